@@ -1,0 +1,547 @@
+// Plain CPU oracle for the explicit finite-volume hydro step.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+// benchmark's CPU-baseline leg may load this code.  It shares nothing with
+// the HIP path: no headers, no helpers, no tables.
+//
+// What it computes (HARD paper, section 2.2.1 "Basic equations" and
+// section 2.2.2 "Numerical algorithms"):
+//   * conserved state U = (rho, rho*v_d, e + rho v^2/2) of the conservation law
+//     d_t U + d_j F^j = 0 (paper equations "conservative form" and "fluxes",
+//     hydro rows, radiation row and sources dropped);
+//   * ideal-gas closure p = (gamma-1) e (the paper's "ideal EoS" of the
+//     temperature-induced shock example, section 3.3);
+//   * finite-volume flux difference on a uniform cell-centred Cartesian mesh
+//     (section 2.2.2, the face-difference formula), summed over axes;
+//   * face states by MUSCL with the minmod limiter on primitive variables,
+//     face fluxes by the HLLC approximate Riemann solver (Toro, "Riemann
+//     Solvers and Numerical Methods for Fluid Dynamics", 3rd ed., section 10.4,
+//     Davis wave-speed estimates);
+//   * Heun's two-stage Runge-Kutta step (paper table "Butcher tableau for
+//     Heun's method") written in Shu-Osher form, which is the same method;
+//   * the CFL time step dt = C / max_i sum_d (|u_d| + c)/dx_d (section 3.5
+//     says only that dt comes from the CFL condition; this is the reading).
+//
+// Everything is a plain loop over cells in FP64.  OpenMP splits the cell
+// loops; every cell is computed by one thread in a fixed order, so the result
+// does not depend on the thread count.
+//
+// The scalar type is a template parameter: `double` gives the values, the
+// forward-mode dual number `Dual` gives the exact directional derivative of
+// the same discrete map (it follows the branch taken at the base point; at a
+// tie min/max/minmod pass the derivative to their first argument and
+// |x| uses sign(0) = +1).
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+namespace hard_oracle {
+
+// ----------------------------------------------------------------------------
+// Forward-mode dual number
+// ----------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+  Dual() : v(0.0), d(0.0) {}
+  Dual(double a) : v(a), d(0.0) {}  // NOLINT: constants promote implicitly
+  Dual(double a, double b) : v(a), d(b) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) {
+  double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+inline Dual sqrt(Dual a) {
+  double s = std::sqrt(a.v);
+  return Dual(s, a.d / (2.0 * s));
+}
+inline Dual fabs(Dual a) { return a.v >= 0.0 ? a : -a; }
+inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
+inline bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
+inline bool operator>(Dual a, Dual b) { return a.v > b.v; }
+inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
+inline double value(double a) { return a; }
+inline double value(Dual a) { return a.v; }
+
+using std::fabs;
+using std::sqrt;
+
+// Status bits reported for a non-physical state.
+enum : int { ST_RHO = 1, ST_PRES = 2, ST_NONFINITE = 4 };
+
+enum : int { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
+
+constexpr int NG = 2;  // ghost layers per side
+
+struct Grid {
+  int ndim;       // 1, 2 or 3
+  int nvar;       // ndim + 2
+  int64_t n[3];   // cells per axis; unused axes have n = 1
+  double dx[3];   // cell width per axis
+  double gamma;   // ratio of specific heats
+  int bc[3][2];   // boundary kind per axis and side (0 = low, 1 = high)
+  int64_t ncell;  // n[0]*n[1]*n[2]
+
+  // padded shape: axes below ndim get NG ghosts on each side
+  int64_t pn[3];
+  int64_t pcell;
+};
+
+static Grid make_grid(int ndim, const int64_t* n, const double* dx, double gamma,
+                      const int* bc) {
+  Grid g;
+  g.ndim = ndim;
+  g.nvar = ndim + 2;
+  g.gamma = gamma;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = d < ndim ? n[d] : 1;
+    g.dx[d] = d < ndim ? dx[d] : 1.0;
+    g.bc[d][0] = d < ndim ? bc[2 * d] : BC_PERIODIC;
+    g.bc[d][1] = d < ndim ? bc[2 * d + 1] : BC_PERIODIC;
+    g.pn[d] = d < ndim ? g.n[d] + 2 * NG : 1;
+  }
+  g.ncell = g.n[0] * g.n[1] * g.n[2];
+  g.pcell = g.pn[0] * g.pn[1] * g.pn[2];
+  return g;
+}
+
+// index of interior cell (i, j, k) in the unpadded array
+static inline int64_t cidx(const Grid& g, int64_t i, int64_t j, int64_t k) {
+  return (k * g.n[1] + j) * g.n[0] + i;
+}
+// index of cell (i, j, k), counted from the first interior cell, in the padded
+// array (negative or >= n indices address ghosts)
+static inline int64_t pidx(const Grid& g, int64_t i, int64_t j, int64_t k) {
+  int64_t oi = i + (g.ndim > 0 ? NG : 0);
+  int64_t oj = j + (g.ndim > 1 ? NG : 0);
+  int64_t ok = k + (g.ndim > 2 ? NG : 0);
+  return (ok * g.pn[1] + oj) * g.pn[0] + oi;
+}
+
+// Source interior index along one axis for ghost position q (q < 0 or q >= n),
+// and whether the normal momentum changes sign (reflecting wall).
+static inline int64_t ghost_source(int64_t q, int64_t n, int bc_lo, int bc_hi, bool* flip) {
+  *flip = false;
+  if (q < 0) {
+    int64_t k = -q;  // 1 or 2
+    if (bc_lo == BC_PERIODIC) return n - k;
+    if (bc_lo == BC_OUTFLOW) return 0;
+    *flip = true;
+    return k - 1;
+  }
+  int64_t k = q - (n - 1);  // 1 or 2
+  if (bc_hi == BC_PERIODIC) return k - 1;
+  if (bc_hi == BC_OUTFLOW) return n - 1;
+  *flip = true;
+  return n - k;
+}
+
+// ----------------------------------------------------------------------------
+// Pieces of the method
+// ----------------------------------------------------------------------------
+
+// minmod(a, b): zero when the one-sided differences disagree in sign (or one
+// is zero), otherwise the one of smaller magnitude; ties pick a.
+template <class T>
+static inline T minmod(T a, T b) {
+  if (a * b <= T(0.0)) return T(0.0);
+  if (fabs(a) <= fabs(b)) return a;
+  return b;
+}
+
+// Primitive state seen by a face along the normal axis:
+// rho, normal velocity un, transverse velocities ut[0..nt-1], pressure p.
+template <class T>
+struct Prim {
+  T rho, un, ut[2], p;
+};
+
+// HLLC flux for the normal direction (Toro section 10.4, Davis speeds).
+// Output order: mass, normal momentum, transverse momenta, energy.
+template <class T>
+static void hllc_flux(const Prim<T>& L, const Prim<T>& R, int nt, double gamma, T* F) {
+  const T g(gamma);
+  const T gm1(gamma - 1.0);
+  T cL = sqrt(g * L.p / L.rho);
+  T cR = sqrt(g * R.p / R.rho);
+  T qL = L.un * L.un;
+  T qR = R.un * R.un;
+  for (int t = 0; t < nt; ++t) {
+    qL = qL + L.ut[t] * L.ut[t];
+    qR = qR + R.ut[t] * R.ut[t];
+  }
+  T EL = L.p / gm1 + T(0.5) * L.rho * qL;
+  T ER = R.p / gm1 + T(0.5) * R.rho * qR;
+
+  // Davis estimates; min/max pass ties to their first argument
+  T aL = L.un - cL, bL = R.un - cR;
+  T SL = aL <= bL ? aL : bL;
+  T aR = L.un + cL, bR = R.un + cR;
+  T SR = aR >= bR ? aR : bR;
+
+  // contact speed
+  T num = R.p - L.p + L.rho * L.un * (SL - L.un) - R.rho * R.un * (SR - R.un);
+  T den = L.rho * (SL - L.un) - R.rho * (SR - R.un);
+  T Ss = num / den;
+
+  const int nv = nt + 3;
+  // physical flux and conserved state of one side
+  auto side = [&](const Prim<T>& W, T E, T* FK, T* UK) {
+    T mn = W.rho * W.un;
+    UK[0] = W.rho;
+    UK[1] = mn;
+    FK[0] = mn;
+    FK[1] = mn * W.un + W.p;
+    for (int t = 0; t < nt; ++t) {
+      UK[2 + t] = W.rho * W.ut[t];
+      FK[2 + t] = mn * W.ut[t];
+    }
+    UK[nv - 1] = E;
+    FK[nv - 1] = (E + W.p) * W.un;
+  };
+  // HLLC star state of one side:
+  //   rho_K r [1, S*, v_K, w_K, E_K/rho_K + (S*-u_K)(S* + p_K/(rho_K (S_K-u_K)))]
+  // with r = (S_K - u_K)/(S_K - S*); the energy entry is expanded as
+  //   r E_K + r (S*-u_K) (rho_K S* + p_K/(S_K-u_K))
+  // so that a stationary contact (u = 0, equal p) maps U_K to itself exactly.
+  auto star = [&](const Prim<T>& W, T E, T S, T* Us) {
+    T r = (S - W.un) / (S - Ss);
+    T fac = W.rho * r;
+    Us[0] = fac;
+    Us[1] = fac * Ss;
+    for (int t = 0; t < nt; ++t) Us[2 + t] = fac * W.ut[t];
+    Us[nv - 1] = r * E + r * (Ss - W.un) * (W.rho * Ss + W.p / (S - W.un));
+  };
+
+  T FK[5], UK[5], Us[5];
+  if (SL >= T(0.0)) {
+    side(L, EL, FK, UK);
+    for (int v = 0; v < nv; ++v) F[v] = FK[v];
+  } else if (Ss >= T(0.0)) {
+    side(L, EL, FK, UK);
+    star(L, EL, SL, Us);
+    for (int v = 0; v < nv; ++v) F[v] = FK[v] + SL * (Us[v] - UK[v]);
+  } else if (SR > T(0.0)) {
+    side(R, ER, FK, UK);
+    star(R, ER, SR, Us);
+    for (int v = 0; v < nv; ++v) F[v] = FK[v] + SR * (Us[v] - UK[v]);
+  } else {
+    side(R, ER, FK, UK);
+    for (int v = 0; v < nv; ++v) F[v] = FK[v];
+  }
+}
+
+// Primitive variables of one conserved state: rho, u_0..u_{ndim-1}, p.
+// Returns status bits.
+template <class T>
+static int primitives(const T* u, int ndim, double gamma, T* w) {
+  T rho = u[0];
+  T q = u[1] * u[1];
+  for (int d = 1; d < ndim; ++d) q = q + u[1 + d] * u[1 + d];
+  T ke = T(0.5) * q / rho;
+  T e = u[ndim + 1] - ke;
+  T p = T(gamma - 1.0) * e;
+  w[0] = rho;
+  for (int d = 0; d < ndim; ++d) w[1 + d] = u[1 + d] / rho;
+  w[ndim + 1] = p;
+  int st = 0;
+  if (!(value(rho) > 0.0)) st |= ST_RHO;
+  if (!(value(p) > 0.0)) st |= ST_PRES;
+  for (int v = 0; v < ndim + 2; ++v)
+    if (!std::isfinite(value(u[v]))) st |= ST_NONFINITE;
+  return st;
+}
+
+// ----------------------------------------------------------------------------
+// L(U) = - sum_d (F_{d,i+1/2} - F_{d,i-1/2}) / dx_d
+// ----------------------------------------------------------------------------
+template <class T>
+static int rhs(const Grid& g, const T* U, T* Lout) {
+  const int nv = g.nvar;
+  const int nd = g.ndim;
+  const int64_t N = g.ncell, PN = g.pcell;
+
+  // 1. ghost-padded conserved copy; corner ghosts stay NaN (never read by the
+  //    star-shaped stencil, so a wrong read shows up as NaN)
+  std::vector<T> G((size_t)nv * PN, T(std::numeric_limits<double>::quiet_NaN()));
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < N; ++c) {
+    int64_t i = c % g.n[0], j = (c / g.n[0]) % g.n[1], k = c / (g.n[0] * g.n[1]);
+    for (int v = 0; v < nv; ++v) G[(size_t)v * PN + pidx(g, i, j, k)] = U[(size_t)v * N + c];
+  }
+  for (int d = 0; d < nd; ++d) {
+    int64_t nd_ = g.n[d];
+    // all cells interior in the other axes, ghost position along d
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < N / nd_; ++c) {
+      int64_t o[3];
+      int64_t rem = c;
+      for (int a = 0; a < 3; ++a) {
+        if (a == d) { o[a] = 0; continue; }
+        o[a] = rem % g.n[a];
+        rem /= g.n[a];
+      }
+      for (int side = 0; side < 2; ++side)
+        for (int kk = 1; kk <= NG; ++kk) {
+          int64_t q = side == 0 ? -kk : nd_ - 1 + kk;
+          bool flip;
+          int64_t s = ghost_source(q, nd_, g.bc[d][0], g.bc[d][1], &flip);
+          int64_t dst[3] = {o[0], o[1], o[2]}, src[3] = {o[0], o[1], o[2]};
+          dst[d] = q;
+          src[d] = s;
+          for (int v = 0; v < nv; ++v) {
+            T val = U[(size_t)v * N + cidx(g, src[0], src[1], src[2])];
+            if (flip && v == 1 + d) val = -val;
+            G[(size_t)v * PN + pidx(g, dst[0], dst[1], dst[2])] = val;
+          }
+        }
+    }
+  }
+
+  // 2. primitives over every padded cell (corners give NaN, unused)
+  std::vector<T> W((size_t)nv * PN);
+  int status = 0;
+#pragma omp parallel for schedule(static) reduction(| : status)
+  for (int64_t c = 0; c < PN; ++c) {
+    T u[5], w[5];
+    for (int v = 0; v < nv; ++v) u[v] = G[(size_t)v * PN + c];
+    int st = primitives(u, nd, g.gamma, w);
+    for (int v = 0; v < nv; ++v) W[(size_t)v * PN + c] = w[v];
+    // validity is judged on interior cells only (ghosts are copies of them)
+    int64_t i = c % g.pn[0], j = (c / g.pn[0]) % g.pn[1], k = c / (g.pn[0] * g.pn[1]);
+    bool interior = true;
+    int64_t ii[3] = {i, j, k};
+    for (int a = 0; a < nd; ++a)
+      if (ii[a] < NG || ii[a] >= NG + g.n[a]) interior = false;
+    if (interior) status |= st;
+  }
+
+  for (int64_t x = 0; x < (int64_t)nv * N; ++x) Lout[x] = T(0.0);
+
+  // 3. faces along each axis in the order x, y, z
+  for (int d = 0; d < nd; ++d) {
+    int64_t nf = g.n[d] + 1;  // faces i-1/2 for i = 0..n
+    int64_t nother = N / g.n[d];
+    std::vector<T> F((size_t)nv * nf * nother);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nother; ++c) {
+      int64_t o[3];
+      int64_t rem = c;
+      for (int a = 0; a < 3; ++a) {
+        if (a == d) { o[a] = 0; continue; }
+        o[a] = rem % g.n[a];
+        rem /= g.n[a];
+      }
+      for (int64_t f = 0; f < nf; ++f) {
+        // face between cells f-1 and f along d; stencil f-2 .. f+1
+        T Wc[4][5];
+        for (int s = 0; s < 4; ++s) {
+          int64_t p[3] = {o[0], o[1], o[2]};
+          p[d] = f - 2 + s;
+          int64_t pi = pidx(g, p[0], p[1], p[2]);
+          for (int v = 0; v < nv; ++v) Wc[s][v] = W[(size_t)v * PN + pi];
+        }
+        T WL[5], WR[5];
+        for (int v = 0; v < nv; ++v) {
+          T sl = minmod(Wc[1][v] - Wc[0][v], Wc[2][v] - Wc[1][v]);  // slope of cell f-1
+          T sr = minmod(Wc[2][v] - Wc[1][v], Wc[3][v] - Wc[2][v]);  // slope of cell f
+          WL[v] = Wc[1][v] + T(0.5) * sl;
+          WR[v] = Wc[2][v] - T(0.5) * sr;
+        }
+        // rotate: normal velocity is axis d, transverse are the others in order
+        Prim<T> PL, PR;
+        PL.rho = WL[0];
+        PR.rho = WR[0];
+        PL.un = WL[1 + d];
+        PR.un = WR[1 + d];
+        int t = 0;
+        for (int a = 0; a < nd; ++a) {
+          if (a == d) continue;
+          PL.ut[t] = WL[1 + a];
+          PR.ut[t] = WR[1 + a];
+          ++t;
+        }
+        PL.p = WL[nd + 1];
+        PR.p = WR[nd + 1];
+        T Fn[5];
+        hllc_flux(PL, PR, nd - 1, g.gamma, Fn);
+        // rotate back to (mass, m_0.., energy)
+        T Fo[5];
+        Fo[0] = Fn[0];
+        Fo[1 + d] = Fn[1];
+        t = 0;
+        for (int a = 0; a < nd; ++a) {
+          if (a == d) continue;
+          Fo[1 + a] = Fn[2 + t];
+          ++t;
+        }
+        Fo[nd + 1] = Fn[nd + 1];
+        for (int v = 0; v < nv; ++v) F[((size_t)v * nother + c) * nf + f] = Fo[v];
+      }
+    }
+    // divergence contribution of axis d
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < N; ++c) {
+      int64_t ii[3] = {c % g.n[0], (c / g.n[0]) % g.n[1], c / (g.n[0] * g.n[1])};
+      // index of this cell's row among the "other" cells
+      int64_t oc = 0, mul = 1;
+      for (int a = 0; a < 3; ++a) {
+        if (a == d) continue;
+        oc += ii[a] * mul;
+        mul *= g.n[a];
+      }
+      int64_t f = ii[d];
+      for (int v = 0; v < nv; ++v) {
+        T Fm = F[((size_t)v * nother + oc) * nf + f];
+        T Fp = F[((size_t)v * nother + oc) * nf + f + 1];
+        Lout[(size_t)v * N + c] = Lout[(size_t)v * N + c] - (Fp - Fm) / T(g.dx[d]);
+      }
+    }
+  }
+  return status;
+}
+
+// One SSP-RK2 (Heun) step, same dt in both stages:
+//   U1 = U + dt L(U);   U_new = 0.5 (U + (U1 + dt L(U1)))
+template <class T>
+static int step(const Grid& g, T* U, T dt) {
+  const int64_t M = (int64_t)g.nvar * g.ncell;
+  std::vector<T> L(M), U1(M);
+  int st = rhs(g, U, L.data());
+#pragma omp parallel for schedule(static)
+  for (int64_t x = 0; x < M; ++x) U1[x] = U[x] + dt * L[x];
+  st |= rhs(g, U1.data(), L.data());
+#pragma omp parallel for schedule(static)
+  for (int64_t x = 0; x < M; ++x) U[x] = T(0.5) * (U[x] + (U1[x] + dt * L[x]));
+  return st;
+}
+
+// Largest signal speed sum over the interior: max_i sum_d (|u_d| + c)/dx_d
+static double max_signal(const Grid& g, const double* U, int* status) {
+  const int nv = g.nvar, nd = g.ndim;
+  const int64_t N = g.ncell;
+  double smax = 0.0;
+  int st = 0;
+#pragma omp parallel for schedule(static) reduction(max : smax) reduction(| : st)
+  for (int64_t c = 0; c < N; ++c) {
+    double u[5], w[5];
+    for (int v = 0; v < nv; ++v) u[v] = U[(size_t)v * N + c];
+    st |= primitives(u, nd, g.gamma, w);
+    double cs = std::sqrt(g.gamma * w[nd + 1] / w[0]);
+    double s = 0.0;
+    for (int d = 0; d < nd; ++d) s = s + (std::fabs(w[1 + d]) + cs) / g.dx[d];
+    if (s > smax) smax = s;
+  }
+  *status = st;
+  return smax;
+}
+
+}  // namespace hard_oracle
+
+// ----------------------------------------------------------------------------
+// C entry points (called from Python through ctypes)
+// ----------------------------------------------------------------------------
+using namespace hard_oracle;
+
+extern "C" {
+
+// L(U) for one state; returns status bits.
+int oracle_rhs(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+               const double* U, double* L) {
+  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  return rhs<double>(g, U, L);
+}
+
+// One SSP-RK2 step in place; returns status bits.
+int oracle_step(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+                double dt, double* U) {
+  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  return step<double>(g, U, dt);
+}
+
+// nsteps SSP-RK2 steps in place with the given dt list; returns OR of status.
+int oracle_steps_fixed(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+                       int64_t nsteps, const double* dts, double* U) {
+  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  int st = 0;
+  for (int64_t s = 0; s < nsteps; ++s) st |= step<double>(g, U, dts[s]);
+  return st;
+}
+
+// dt = cfl / max signal sum; writes the status bits of the state.
+double oracle_cfl_dt(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+                     double cfl, const double* U, int* status) {
+  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  double smax = max_signal(g, U, status);
+  return cfl / smax;
+}
+
+// CFL-driven run to t_end: dt <- min(cfl dt, t_end - t); stops when
+// t >= t_end (1 - 1e-14) or after max_steps.  Records each dt used if
+// dts_out is not null (capacity max_steps).  Returns OR of status bits.
+int oracle_run(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+               double cfl, double t_end, int64_t max_steps, double* U, double* t_out,
+               int64_t* nsteps_out, double* dts_out) {
+  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  double t = 0.0;
+  int64_t s = 0;
+  int st = 0;
+  while (t < t_end * (1.0 - 1e-14) && s < max_steps) {
+    int st_dt = 0;
+    double dt = cfl / max_signal(g, U, &st_dt);
+    st |= st_dt;
+    if (dt > t_end - t) dt = t_end - t;
+    st |= step<double>(g, U, dt);
+    if (dts_out) dts_out[s] = dt;
+    t = t + dt;
+    ++s;
+  }
+  *t_out = t;
+  *nsteps_out = s;
+  return st;
+}
+
+// Forward-mode derivative of nsteps steps with a frozen dt list:
+// (U, dU) -> (U_n, dU_n) in place.  Returns OR of status bits.
+int oracle_steps_tangent(int ndim, const int64_t* n, const double* dx, double gamma,
+                         const int* bc, int64_t nsteps, const double* dts, double* U,
+                         double* dU) {
+  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  const int64_t M = (int64_t)g.nvar * g.ncell;
+  std::vector<Dual> X(M);
+  for (int64_t x = 0; x < M; ++x) X[x] = Dual(U[x], dU[x]);
+  int st = 0;
+  for (int64_t s = 0; s < nsteps; ++s) st |= step<Dual>(g, X.data(), Dual(dts[s]));
+  for (int64_t x = 0; x < M; ++x) {
+    U[x] = X[x].v;
+    dU[x] = X[x].d;
+  }
+  return st;
+}
+
+// HLLC flux for one face: WL, WR = (rho, un, ut[0..nt-1], p); F gets
+// (mass, normal momentum, transverse momenta, energy).
+void oracle_hllc(int nt, double gamma, const double* WL, const double* WR, double* F) {
+  Prim<double> L, R;
+  L.rho = WL[0];
+  L.un = WL[1];
+  R.rho = WR[0];
+  R.un = WR[1];
+  for (int t = 0; t < nt; ++t) {
+    L.ut[t] = WL[2 + t];
+    R.ut[t] = WR[2 + t];
+  }
+  L.p = WL[2 + nt];
+  R.p = WR[2 + nt];
+  hllc_flux(L, R, nt, gamma, F);
+}
+
+double oracle_minmod(double a, double b) { return minmod<double>(a, b); }
+
+}  // extern "C"

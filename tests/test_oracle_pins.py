@@ -1,0 +1,504 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: a printed value (paper or
+textbook), a closed form, an invariant of the method, or brute force.
+"""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle.exact_riemann import RiemannSolution
+from oracle.metrics import exact_sum, fitted_order, l1_error
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+P, O, R = oracle.PERIODIC, oracle.OUTFLOW, oracle.REFLECT
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# exact Riemann solver (the pin of the whole step)
+# --------------------------------------------------------------------------
+def test_exact_riemann_textbook_sod_star_state():
+    """Star state of the Sod data equals the textbook exact solution (5 digits)."""
+    s = gold("sod_paper.json")
+    L, Rr = s["left"], s["right"]
+    ex = RiemannSolution(L["rho"], L["u"], L["p"], Rr["rho"], Rr["u"], Rr["p"], s["gamma"])
+    rsl, rsr = ex.star_densities()
+    assert ex.pstar == pytest.approx(s["p_star"], abs=5e-6)
+    assert ex.ustar == pytest.approx(s["u_star"], abs=5e-6)
+    assert rsl == pytest.approx(s["rho_star_left"], abs=5e-6)
+    assert rsr == pytest.approx(s["rho_star_right"], abs=5e-6)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_exact_riemann_jump_conditions(seed):
+    """Shocks satisfy Rankine-Hugoniot, fans are isentropic with a constant
+    Riemann invariant, and p, u are continuous across the contact."""
+    rng = np.random.default_rng(100 + seed)
+    rL, pL, rR, pR = rng.uniform(0.1, 1.0, 4)
+    uL, uR = rng.uniform(-0.5, 0.5, 2)
+    g = 1.4
+    ex = RiemannSolution(rL, uL, pL, rR, uR, pR, g)
+    w = ex.wave_speeds()
+    eps = 1e-9
+
+    def state(xi):
+        r, u, p = ex.sample(np.array([xi]))
+        return r[0], u[0], p[0]
+
+    def E(r, u, p):
+        return p / (g - 1) + 0.5 * r * u * u
+
+    for side in ("left", "right"):
+        if side + "_shock" in w:
+            S = w[side + "_shock"]
+            a, b = state(S - eps), state(S + eps)
+            for (f, tol) in (
+                (lambda r, u, p: r * (u - S), 1e-12),
+                (lambda r, u, p: r * u * (u - S) + p, 1e-12),
+                (lambda r, u, p: E(r, u, p) * (u - S) + p * u, 1e-12),
+            ):
+                assert f(*a) == pytest.approx(f(*b), rel=tol, abs=tol)
+        else:
+            head, tail = w[side + "_head"], w[side + "_tail"]
+            xs = np.linspace(min(head, tail), max(head, tail), 7)
+            r, u, p = ex.sample(xs)
+            c = np.sqrt(g * p / r)
+            np.testing.assert_allclose(p / r ** g, (p / r ** g)[0], rtol=1e-12)
+            sgn = 1.0 if side == "left" else -1.0
+            inv = u + sgn * 2 * c / (g - 1)
+            np.testing.assert_allclose(inv, inv[0], rtol=1e-12, atol=1e-12)
+    a, b = state(w["contact"] - eps), state(w["contact"] + eps)
+    assert a[1] == pytest.approx(b[1], abs=1e-12)
+    assert a[2] == pytest.approx(b[2], rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# whole step against the exact Riemann solution
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(16))
+def test_two_state_converges_to_exact_solution(seed):
+    """1D two-state problems (outflow, CFL 0.4, t = 0.2) against the exact
+    Riemann solution, cell averages by 10-node Gauss-Legendre.
+
+    Where the contact moves at least two coarse cells, L1(rho) falls
+    monotonically with n and every field converges at the order of a
+    second-order TVD scheme on shocks and contacts (fitted order in
+    [0.6, 1.1]).  A nearly stationary contact is resolved almost exactly by
+    HLLC and its error depends on where it sits inside a cell, so there only
+    the size of the error is checked.
+    """
+    rL, pL, rR, pR = workloads.random_two_state_params(seed)
+    ex = RiemannSolution(rL, 0.0, pL, rR, 0.0, pR)
+    ns = [128, 256, 512, 1024]
+    errs = [[], [], []]
+    for n in ns:
+        g = oracle.Grid((n,), bc=(O, O))
+        U, t, _, st = oracle.run(g, workloads.random_two_state(n, seed), 0.4, 0.2)
+        assert st == 0 and t == pytest.approx(0.2, rel=1e-14)
+        avg = ex.cell_averages(n, t)
+        prim = oracle.primitives(U)
+        for f in range(3):
+            errs[f].append(l1_error(prim[f], avg[f], 1.0 / n))
+    orders = [fitted_order(ns, e) for e in errs]
+    if abs(ex.ustar) * 0.2 >= 2.0 / ns[0]:
+        assert all(b < a for a, b in zip(errs[0], errs[0][1:])), errs[0]
+        for o in orders:
+            assert 0.6 <= o <= 1.1, (orders, errs)
+    else:
+        assert errs[0][-1] < 5e-4, errs[0]
+        assert min(orders[1:]) >= 0.5, orders
+
+
+def test_sod_at_paper_settings():
+    """Sod tube at the paper's settings (t = 0.0669, dx = 2^-10, Courant 0.3).
+
+    The paper's bound L1 < 5e-4 is for WENO5-Z + HLL; MUSCL-minmod + HLLC is a
+    lower-order scheme, so the gate is a factor 2 looser; the value is reported.
+    """
+    s = gold("sod_paper.json")
+    n = int(round(1.0 / s["dx"]))
+    g = oracle.Grid((n,), bc=(O, O))
+    U, t, _, st = oracle.run(g, workloads.sod(n), s["courant"], s["t_final"])
+    ex = RiemannSolution(1.0, 0.0, 1.0, 0.125, 0.0, 0.1)
+    r, u, p = ex.cell_averages(n, t)
+    err = l1_error(U[0], r, s["dx"])
+    print(f"Sod L1(rho) = {err:.3e} (paper, WENO5-Z+HLL: < {s['paper_L1_rho_bound']})")
+    assert st == 0
+    assert err < 2 * s["paper_L1_rho_bound"]
+
+
+def test_acoustic_wave_second_order():
+    """Smooth acoustic wave (closed form of the paper's section 3.5): L1 order >= 1.8."""
+    a = gold("acoustic_paper.json")
+    errs = []
+    for n in a["ns"]:
+        g = oracle.Grid((n,), gamma=a["gamma"], bc=(P, P))
+        U0 = workloads.acoustic_state(n, a["amplitude"], a["gamma"])
+        U, t, _, st = oracle.run(g, U0, a["courant"], a["t_final"])
+        r_ex, u_ex, p_ex = workloads.acoustic_1d(n, a["amplitude"], a["gamma"], t=t)
+        errs.append(l1_error(U[0], r_ex, 1.0 / n))
+    order = fitted_order(a["ns"], errs)
+    assert order >= a["min_order_L1_rho"], (order, errs)
+
+
+def test_heun_tableau():
+    """The step equals Heun's method built from the paper's Butcher tableau."""
+    tab = gold("heun_tableau.json")
+    assert tab["c"] == [0.0, 1.0] and tab["a"][1][0] == 1.0
+    n = 64
+    g = oracle.Grid((n, n), bc=(P, P))
+    U0 = workloads.turbulent_box(n, ndim=2, seed=11)
+    dt, _ = oracle.cfl_dt(g, U0, 0.4)
+    k1, _ = oracle.rhs(g, U0)
+    k2, _ = oracle.rhs(g, U0 + tab["a"][1][0] * dt * k1)
+    heun = U0 + dt * (tab["b"][0] * k1 + tab["b"][1] * k2)
+    U1, _ = oracle.step(g, U0, dt)
+    for v in range(g.nvar):
+        scale = np.abs(U0[v]).max()
+        assert np.abs(U1[v] - heun[v]).max() <= 1e-14 * scale
+
+
+# --------------------------------------------------------------------------
+# HLLC special cases
+# --------------------------------------------------------------------------
+def physical_flux(W, g=1.4):
+    r, un, *ut, p = W
+    E = p / (g - 1) + 0.5 * r * (un * un + sum(v * v for v in ut))
+    return np.array([r * un, r * un * un + p] + [r * un * v for v in ut] + [(E + p) * un])
+
+
+@pytest.mark.parametrize("nt", [0, 1, 2])
+def test_hllc_consistency(nt):
+    """F(W, W) = F(W) to rounding (consistency of the numerical flux)."""
+    rng = np.random.default_rng(7 + nt)
+    for _ in range(200):
+        W = np.concatenate([[rng.uniform(0.1, 2)], rng.uniform(-2, 2, 1 + nt), [rng.uniform(0.1, 2)]])
+        F = oracle.hllc(W, W)
+        np.testing.assert_allclose(F, physical_flux(W), rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("nt", [0, 1, 2])
+def test_hllc_supersonic_upwinding(nt):
+    """All waves moving right (S_L >= 0): the flux is the physical flux of the
+    left state (paper equation "fluxes"); all waves moving left: the right one."""
+    rng = np.random.default_rng(17 + nt)
+    g = 1.4
+    for _ in range(100):
+        rL, pL, rR, pR = rng.uniform(0.5, 1.0, 4)
+        ut = list(rng.uniform(-1, 1, nt))
+        u = 3 * np.sqrt(g * 1.0 / 0.5)  # faster than any sound speed here
+        WL = np.array([rL, u] + ut + [pL])
+        WR = np.array([rR, 1.1 * u] + ut + [pR])
+        np.testing.assert_allclose(oracle.hllc(WL, WR, g), physical_flux(WL, g), rtol=1e-14)
+        WL[1], WR[1] = -u, -1.1 * u
+        np.testing.assert_allclose(oracle.hllc(WL, WR, g), physical_flux(WR, g), rtol=1e-14)
+
+
+def test_hllc_stationary_contact_exact():
+    """u = 0, equal p, density jump: the HLLC flux is exactly (0, p, 0.., 0)."""
+    rng = np.random.default_rng(3)
+    for nt in (0, 1, 2):
+        for _ in range(100):
+            rL, rR, p = rng.uniform(0.1, 2, 3)
+            ut = list(rng.uniform(-1, 1, nt))
+            F = oracle.hllc([rL, 0.0] + ut + [p], [rR, 0.0] + ut + [p])
+            assert F[0] == 0.0 and F[1] == p and F[-1] == 0.0
+            for t in range(nt):
+                assert F[2 + t] == 0.0
+
+
+def test_hllc_mirror_wall_face():
+    """Mirror states (rho, u, p) | (rho, -u, p): contact speed exactly 0, so
+    the mass and energy fluxes vanish to rounding and the transverse
+    momentum flux is zero."""
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        r, u, p = rng.uniform(0.1, 2), rng.uniform(-2, 2), rng.uniform(0.1, 2)
+        F = oracle.hllc([r, u, 0.3, p], [r, -u, 0.3, p])
+        scale = r * (abs(u) + 2) ** 2 + p
+        assert abs(F[0]) <= 1e-14 * scale and abs(F[-1]) <= 1e-14 * scale * 3
+        assert abs(F[2]) <= 1e-14 * scale
+
+
+def test_minmod_truth_table():
+    mm = oracle.minmod
+    assert mm(1.0, 2.0) == 1.0
+    assert mm(2.0, 1.0) == 1.0
+    assert mm(-1.0, -2.0) == -1.0
+    assert mm(-3.0, -2.0) == -2.0
+    assert mm(1.0, -1.0) == 0.0
+    assert mm(-1.0, 1.0) == 0.0
+    assert mm(0.0, 1.0) == 0.0
+    assert mm(1.0, 0.0) == 0.0
+    assert mm(0.0, 0.0) == 0.0
+    assert mm(1.5, 1.5) == 1.5
+    assert mm(-1.5, -1.5) == -1.5
+
+
+# --------------------------------------------------------------------------
+# invariants of the step
+# --------------------------------------------------------------------------
+def uniform_state(shape_n, ndim, vel):
+    shape = tuple(reversed(shape_n))
+    rho = np.full(shape, 0.7)
+    p = np.full(shape, 0.4)
+    return workloads.conserved_from_primitive(rho, [np.full(shape, v) for v in vel], p)
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+@pytest.mark.parametrize("bc", [P, O, R])
+def test_uniform_state_preserved_bitwise(ndim, bc):
+    n = (12, 10, 6)[:ndim]
+    vel = [0.0] * ndim if bc == R else [0.3, -0.2, 0.1][:ndim]
+    U0 = uniform_state(n, ndim, vel)
+    g = oracle.Grid(n, bc=(bc, bc))
+    dt, _ = oracle.cfl_dt(g, U0, 0.4)
+    U, st = oracle.steps(g, U0, [dt] * 3)
+    assert st == 0
+    assert np.array_equal(U, U0)
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+@pytest.mark.parametrize("bc", [P, O, R])
+def test_stationary_contact_preserved_bitwise(ndim, bc):
+    n = (16, 8, 6)[:ndim]
+    shape = tuple(reversed(n))
+    x = workloads.cell_centres(n[0])
+    rho = np.broadcast_to(np.where(x < 0.4, 1.0, 0.2) + 0.1 * (x > 0.7), shape).copy()
+    p = np.full(shape, 0.6)
+    U0 = workloads.conserved_from_primitive(rho, [np.zeros(shape)] * ndim, p)
+    g = oracle.Grid(n, bc=(bc, bc))
+    dt, _ = oracle.cfl_dt(g, U0, 0.4)
+    U, st = oracle.steps(g, U0, [dt] * 4)
+    assert np.array_equal(U, U0)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_conservation_periodic(ndim):
+    n = 48 if ndim == 2 else 20
+    U0 = workloads.turbulent_box(n, ndim=ndim, seed=21)
+    g = oracle.Grid((n,) * ndim, bc=(P, P))
+    dt, _ = oracle.cfl_dt(g, U0, 0.4)
+    U, st = oracle.steps(g, U0, [dt] * 10)
+    assert st == 0
+    assert not np.array_equal(U, U0)
+    for v in range(g.nvar):
+        rel = abs(exact_sum(U[v]) - exact_sum(U0[v])) / exact_sum(np.abs(U0[v]))
+        assert rel <= 1e-12, (v, rel)
+
+
+def symmetric_blast(n, ndim):
+    """Pressure bump at the centre of the box (mirror symmetric in each axis)."""
+    c = workloads.cell_centres(n) - 0.5
+    grids = np.meshgrid(*([c] * ndim), indexing="ij")
+    r2 = sum(a * a for a in grids)
+    shape = (n,) * ndim
+    p = 0.1 + np.exp(-r2 / 0.01)
+    rho = 1.0 + 0.5 * np.exp(-r2 / 0.02)
+    return workloads.conserved_from_primitive(rho, [np.zeros(shape)] * ndim, p)
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_conservation_reflecting(ndim):
+    """Walls: mass and energy are conserved; with mirror-symmetric data the
+    wall impulses cancel, so every momentum total stays zero."""
+    n = {1: 64, 2: 40, 3: 18}[ndim]
+    U0 = symmetric_blast(n, ndim)
+    g = oracle.Grid((n,) * ndim, bc=(R, R))
+    dt, _ = oracle.cfl_dt(g, U0, 0.4)
+    U, st = oracle.steps(g, U0, [dt] * 40)
+    assert st == 0
+    for v in (0, ndim + 1):
+        rel = abs(exact_sum(U[v]) - exact_sum(U0[v])) / exact_sum(np.abs(U0[v]))
+        assert rel <= 1e-12, (v, rel)
+    prims = oracle.primitives(U)
+    cs = np.sqrt(1.4 * prims[-1] / prims[0])
+    scale = exact_sum(prims[0] * (sum(np.abs(u) for u in prims[1:-1]) + cs))
+    for d in range(ndim):
+        assert abs(exact_sum(U[1 + d])) <= 1e-12 * scale
+    assert np.abs(U[1:1 + ndim]).max() > 1e-3  # the flow did move
+
+
+def reflect(U, axis_arr, ndim):
+    """Mirror along array axis axis_arr (array axes are reversed physical axes)."""
+    d = ndim - 1 - axis_arr  # physical axis
+    V = np.flip(U, axis=1 + axis_arr).copy()
+    V[1 + d] = -V[1 + d]
+    return V
+
+
+@pytest.mark.parametrize("ndim,bc", [(1, O), (2, P), (2, R), (3, O), (3, P)])
+def test_mirror_symmetry(ndim, bc):
+    n = {1: 40, 2: 24, 3: 12}[ndim]
+    rng = np.random.default_rng(31)
+    shape = (n,) * ndim
+    rho = rng.uniform(0.5, 1.5, shape)
+    vel = [rng.uniform(-0.3, 0.3, shape) for _ in range(ndim)]
+    p = rng.uniform(0.5, 1.5, shape)
+    U0 = workloads.conserved_from_primitive(rho, vel, p)
+    g = oracle.Grid(shape, bc=(bc, bc))
+    dt, _ = oracle.cfl_dt(g, U0, 0.4)
+    A, _ = oracle.steps(g, U0, [dt] * 2)
+    for ax in range(ndim):
+        B, _ = oracle.steps(g, reflect(U0, ax, ndim), [dt] * 2)
+        RA = reflect(A, ax, ndim)
+        for v in range(g.nvar):
+            assert np.abs(B[v] - RA[v]).max() <= 1e-13 * np.abs(RA[v]).max() + 1e-300
+
+
+def test_axis_permutation_3d():
+    """Swapping x and y (and m_x, m_y) commutes with the step."""
+    n = (12, 10, 8)
+    rng = np.random.default_rng(41)
+    shape = tuple(reversed(n))
+    rho = rng.uniform(0.5, 1.5, shape)
+    vel = [rng.uniform(-0.3, 0.3, shape) for _ in range(3)]
+    p = rng.uniform(0.5, 1.5, shape)
+    U0 = workloads.conserved_from_primitive(rho, vel, p)
+    g = oracle.Grid(n, bc=(P, P, O, O, R, R))
+    dt, _ = oracle.cfl_dt(g, U0, 0.3)
+    A, _ = oracle.steps(g, U0, [dt] * 2)
+
+    def swap(U):
+        V = np.swapaxes(U, 2, 3).copy()  # array axes (v, z, y, x) -> (v, z, x, y)
+        V[[1, 2]] = V[[2, 1]]
+        return V
+
+    gs = oracle.Grid((n[1], n[0], n[2]), bc=(O, O, P, P, R, R))
+    B, _ = oracle.steps(gs, swap(U0), [dt] * 2)
+    SA = swap(A)
+    for v in range(5):
+        assert np.abs(B[v] - SA[v]).max() <= 1e-13 * np.abs(SA[v]).max()
+
+
+@pytest.mark.parametrize("bc", [P, O, R])
+def test_3d_with_1d_data_equals_1d_bitwise(bc):
+    """A 3D grid whose data vary only along x reproduces the 1D step bitwise
+    (transverse flux differences are exactly zero); dt is held fixed."""
+    n = 64
+    rL, pL, rR, pR = workloads.random_two_state_params(3)
+    U1 = workloads.two_state(n, (rL, 0.1, pL), (rR, -0.2, pR))
+    dts = [2e-4] * 5
+    A, _ = oracle.steps(oracle.Grid((n,), bc=(bc, bc)), U1, dts)
+    U3 = np.zeros((5, 3, 4, n))
+    U3[0] = U1[0]
+    U3[1] = U1[1]
+    U3[4] = U1[2]
+    B, _ = oracle.steps(oracle.Grid((n, 4, 3), bc=(bc, bc, P, P, R, R)), U3, dts)
+    for k in range(3):
+        for j in range(4):
+            assert np.array_equal(B[0, k, j], A[0])
+            assert np.array_equal(B[1, k, j], A[1])
+            assert np.array_equal(B[4, k, j], A[2])
+            assert not B[2, k, j].any() and not B[3, k, j].any()
+
+
+def test_cfl_dt_closed_form():
+    """Uniform state: dt = C / sum_d (|u_d| + c)/dx_d."""
+    n = (8, 6, 4)
+    vel = [0.3, -0.2, 0.1]
+    U0 = uniform_state(n, 3, vel)
+    g = oracle.Grid(n, bc=(P, P))
+    dt, st = oracle.cfl_dt(g, U0, 0.4)
+    c = np.sqrt(1.4 * 0.4 / 0.7)
+    expect = 0.4 / sum((abs(v) + c) * nn for v, nn in zip(vel, n))
+    assert st == 0 and dt == pytest.approx(expect, rel=1e-15)
+
+
+def test_status_flags_nonphysical():
+    n = 16
+    U0 = workloads.sod(n)
+    g = oracle.Grid((n,), bc=(O, O))
+    bad = U0.copy()
+    bad[2, 5] = 0.5 * bad[1, 5] ** 2 / bad[0, 5] - 1.0  # negative pressure
+    _, st = oracle.rhs(g, bad)
+    assert st & 2
+    bad = U0.copy()
+    bad[0, 3] = -1.0
+    _, st = oracle.rhs(g, bad)
+    assert st & 1
+    _, st = oracle.rhs(g, U0)
+    assert st == 0
+
+
+def test_thread_count_does_not_change_result():
+    """One OpenMP thread and eight give bitwise identical steps."""
+    code = (
+        "import sys, numpy as np; sys.path.insert(0, %r); import oracle, workloads;"
+        "U0 = workloads.turbulent_box(24, ndim=3, seed=9);"
+        "g = oracle.Grid((24,24,24), bc=(0,0));"
+        "U, st = oracle.steps(g, U0, [1e-3, 1e-3]);"
+        "import hashlib; sys.stdout.write(hashlib.sha256(U.tobytes()).hexdigest())"
+    ) % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    outs = []
+    for nt in ("1", "8"):
+        env = dict(os.environ, OMP_NUM_THREADS=nt)
+        outs.append(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                                   text=True, check=True).stdout)
+    assert outs[0] == outs[1]
+
+
+# --------------------------------------------------------------------------
+# derivative (dual-number) oracle
+# --------------------------------------------------------------------------
+def test_tangent_matches_central_differences():
+    """Forward-mode derivative of three steps vs central differences.
+
+    Minmod switches between its arguments wherever |a| = |b| (inflection
+    points), so a finite step h crosses kinks unless it is tiny; at h = 1e-7
+    (relative) no branch changes and the difference quotient must agree with
+    the dual derivative to its rounding error."""
+    n = 16
+    g = oracle.Grid((n, n), bc=(P, P))
+    # smooth fields with a non-uniform pressure: a uniform field would put every
+    # pressure slope exactly on the minmod kink (a*b = 0), where central
+    # differences and the one-sided branch rule legitimately disagree
+    rng = np.random.default_rng(8)
+    gf = lambda: workloads.gaussian_random_field((n, n), rng, spectral_index=-4.0)
+    U0 = workloads.conserved_from_primitive(1.0 + 0.2 * gf(), [0.3 * gf(), 0.3 * gf()],
+                                            1.0 + 0.2 * gf())
+    dts = [oracle.cfl_dt(g, U0, 0.4)[0]] * 3
+    V = rng.standard_normal(U0.shape) * np.abs(U0).mean(axis=(1, 2), keepdims=True)
+    _, D, _ = oracle.steps_tangent(g, U0, V, dts)
+    for h in (1e-7, 5e-8):
+        Up, _ = oracle.steps(g, U0 + h * V, dts)
+        Um, _ = oracle.steps(g, U0 - h * V, dts)
+        fd = (Up - Um) / (2 * h)
+        assert np.abs(fd - D).max() / np.abs(D).max() < 1e-7
+
+
+def test_tangent_full_jacobian_brute_force_small():
+    """Every column of the one-step Jacobian on a 6x6 grid (forward mode) equals
+    a central difference of the plain step, up to the O(h^2) remainder."""
+    n = 6
+    g = oracle.Grid((n, n), bc=(P, P))
+    rng = np.random.default_rng(12)
+    shape = (n, n)
+    U0 = workloads.conserved_from_primitive(
+        1.0 + 0.2 * rng.standard_normal(shape), [0.1 * rng.standard_normal(shape)] * 2,
+        1.0 + 0.2 * rng.standard_normal(shape))
+    dts = [0.01]
+    M = U0.size
+    h = 1e-6
+    worst = 0.0
+    for col in range(0, M, 7):
+        e = np.zeros(M)
+        e[col] = 1.0
+        e = e.reshape(U0.shape)
+        _, D, _ = oracle.steps_tangent(g, U0, e, dts)
+        Up, _ = oracle.steps(g, U0 + h * e, dts)
+        Um, _ = oracle.steps(g, U0 - h * e, dts)
+        fd = (Up - Um) / (2 * h)
+        worst = max(worst, np.abs(fd - D).max())
+    assert worst < 1e-6
