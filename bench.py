@@ -1,0 +1,165 @@
+"""Throughput of the explicit hydro step on one MI355X.
+
+Workload: the 256^3 FP64 point-energy blast (rho = 1, p = 1e-5, u = 0,
+E0 = 1 over the 32 cells within 2 dx of the centre, gamma = 1.4, reflecting
+walls), CFL 0.4.  One timed step is one full Heun step (stage-1 kernel +
+stage-2 kernel with the next CFL dt folded in), the state resident in HBM.
+After the warmup steps the state is reset to the initial blast, so the timed
+steps are steps 1..K of the blast.
+
+Prints one JSON line: zone-updates/s, the HBM roofline of the dominant kernel
+(stage 2) from HIP events around each launch, and the CPU oracle timed on a
+bounded sample of the same workload on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
+                         "kernel for scaling HBM byte counters)")
+    args = ap.parse_args()
+    if args.copy_probe:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 8, "launches": 5}), flush=True)
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import paper_2509_08971_amd as H
+    import workloads
+
+    n = args.n
+    N = n ** 3
+    nvar, w = 5, 8
+    dev = torch.device("cuda:0")
+    g = H.make_grid((n, n, n), bc=(H.REFLECT, H.REFLECT))
+    U0_host = workloads.blast_3d(n)
+    U0 = torch.from_numpy(U0_host).to(dev)
+    U = U0.clone()
+    U1 = torch.empty_like(U)
+    work = H.workspace(H.hard_workspace_bytes(g), dev)
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        H.hard_hydro_stage(g, 1, U, None, U1, dt, work)
+        if ev is not None:
+            ev[1].record(stream)
+        H.hard_hydro_stage(g, 2, U1, U, U, dt, work, cfl=0.4, next_dt_dev=dt)
+        if ev is not None:
+            ev[2].record(stream)
+
+    log(f"bench: blast {n}^3 fp64, warmup {args.warmup}, steps {args.steps}")
+    H.hard_cfl_dt(g, U, 0.4, dt, work)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # reset to the initial state (untimed)
+    U.copy_(U0)
+    H.hard_cfl_dt(g, U, 0.4, dt, work)
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for k in range(args.steps):
+        step(evs[k])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = start.elapsed_time(stop)
+    flags = H.hard_status_read(work)
+    s1 = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    s2 = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    ms_per_step = ms_total / args.steps
+    zus = N * args.steps / (ms_total * 1e-3)
+    log(f"  {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f}), {zus / 1e9:.2f} G zu/s, "
+        f"stage1 {s1.mean():.3f} ms, stage2 {s2.mean():.3f} ms, flags {flags}")
+
+    b_stage2 = 3 * nvar * w * N  # read U1, read U^n, write U^{n+1}
+    b_stage1 = 2 * nvar * w * N  # read U^n, write U1
+    ach2 = b_stage2 / (s2.mean() * 1e-3) / 1e9
+    ach1 = b_stage1 / (s1.mean() * 1e-3) / 1e9
+    step_gbs = (b_stage1 + b_stage2) / (ms_per_step * 1e-3) / 1e9
+
+    out = {
+        "metric": "zone-updates/s",
+        "value": zus,
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D {n}^3 FP64 point-energy blast, reflecting, CFL 0.4, "
+                               f"MUSCL-minmod + HLLC + SSP-RK2 with fused CFL dt",
+                   "cells": N, "parallelism": "single GPU"},
+        "achieved_hbm_gbs_step": step_gbs,
+        "roofline": {"bound": "hbm", "kernel": "stage_kernel<3,double,2> (stage 2)",
+                     "achieved": ach2, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach2 / HBM_PEAK_GBS, "traffic": None,
+                     "stage1_achieved": ach1, "stage1_ms": float(s1.mean()),
+                     "stage2_ms": float(s2.mean())},
+        "status_flags": flags,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+
+        og = oracle.Grid((n, n, n), bc=(oracle.REFLECT, oracle.REFLECT))
+        ksteps = args.cpu_steps
+        log(f"cpu baseline: oracle, {ksteps} steps of the same blast on {oracle.threads()} threads")
+        dt0, _ = oracle.cfl_dt(og, U0_host, 0.4)
+        t0 = time.perf_counter()
+        Uc = U0_host
+        for _ in range(ksteps):
+            d, _ = oracle.cfl_dt(og, Uc, 0.4)
+            Uc, _ = oracle.step(og, Uc, d)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": N * ksteps / el, "unit": "zone-updates/s",
+                               "cores": oracle.threads(), "kind": "oracle",
+                               "sample": f"{ksteps} steps (CFL dt + step) of the {n}^3 blast from "
+                                         f"its initial state, {el:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * libhard: explicit finite-volume hydro step on one AMD MI355X (gfx950).
+ *
+ * The operation (HARD paper, section 2.2.1 "Basic equations", section 2.2.2
+ * "Numerical algorithms"): the hydro rows of the conservation law
+ * d_t U + d_j F^j = 0 with U = (rho, rho v_d, e + rho v^2/2) and the fluxes of
+ * the paper's equation "fluxes", closed by the ideal-gas law p = (gamma-1) e;
+ * face fluxes F*_{i+-1/2} of the paper's finite-volume difference formula are
+ * HLLC fluxes of MUSCL-minmod face states; time advance is Heun's method
+ * (the paper's Butcher tableau) in Shu-Osher form; the time step comes from
+ * the CFL condition (section 3.5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - State arrays are device pointers (HIP global memory), contiguous,
+ *    structure-of-arrays, field-major with x fastest:
+ *        U[nvar][n2][n1][n0],  nvar = ndim + 2,
+ *    fields (rho, m_x[, m_y[, m_z]], E) with E the total energy density.
+ *    Element type is double (HARD_F64) or float (HARD_F32); the pointer must
+ *    be aligned to the element size.
+ *  - The domain is [0, n_d dx_d] per axis, cell-centred.  Each axis has two
+ *    ghost layers per side generated inside the kernels from the boundary
+ *    kind (periodic wrap, outflow copy of the edge cell, reflecting mirror
+ *    with the normal momentum negated).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *    is enqueued on it; calls return once it is enqueued unless stated.
+ *  - The caller owns every buffer.  The library keeps no pointer after a call
+ *    returns, never allocates device memory on the step path, and does no
+ *    host synchronisation except where stated.  Buffers must stay alive until
+ *    the enqueued work has completed.
+ *  - `work` is a caller-provided device workspace of at least the size the
+ *    matching *_workspace_bytes query returns, 256-byte aligned.  It holds
+ *    the intermediate stage state, reduction slots and the status word.  It
+ *    must be cleared once with hard_workspace_init (or allocated zeroed)
+ *    before first use; the kernels leave its control block ready for the
+ *    next call.  Calls that share one workspace must be stream-ordered.
+ *  - Argument errors are detected on the host before anything is enqueued
+ *    and return HARD_ERR_INVALID_ARG / HARD_ERR_WORKSPACE /
+ *    HARD_ERR_UNSUPPORTED; hard_last_error() then describes the problem.
+ *    Non-physical states (rho <= 0, p <= 0, non-finite values) do not stop
+ *    the kernels: they set bits in the workspace status word, reported as
+ *    HARD_ERR_NONPHYSICAL by the calls that read it back.
+ */
+#ifndef HARD_H
+#define HARD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hard_status_t;
+
+#define HARD_OK 0
+#define HARD_ERR_INVALID_ARG 1
+#define HARD_ERR_UNSUPPORTED 2
+#define HARD_ERR_WORKSPACE 3
+#define HARD_ERR_NONPHYSICAL 4
+#define HARD_ERR_HIP 5
+
+/* Boundary kinds. */
+#define HARD_BC_PERIODIC 0
+#define HARD_BC_OUTFLOW 1
+#define HARD_BC_REFLECT 2
+
+/* Element types.  HARD_F32 stores and computes reconstruction and fluxes in
+ * float; the internal-energy recovery E - |m|^2/(2 rho), the time step and
+ * the conservation sums are computed in double. */
+#define HARD_F64 0
+#define HARD_F32 1
+
+/* Status-word bits (hard_status_read). */
+#define HARD_FLAG_DENSITY 1u   /* rho <= 0 or NaN in some cell */
+#define HARD_FLAG_PRESSURE 2u  /* p <= 0 or NaN in some cell */
+#define HARD_FLAG_NONFINITE 4u /* some conserved value is not finite */
+
+typedef struct hard_grid_t {
+  int32_t ndim;     /* 1, 2 or 3 */
+  int32_t dtype;    /* HARD_F64 or HARD_F32 */
+  int64_t n[3];     /* cells per axis, 2 <= n < 2^31; axes >= ndim must be 1 */
+  double dx[3];     /* cell width per axis, finite and > 0 */
+  double gamma;     /* ratio of specific heats, > 1 */
+  int32_t bc[3][2]; /* boundary kind per axis, [axis][0 = low, 1 = high];
+                       periodic must be set on both sides of an axis */
+} hard_grid_t;
+
+/* Description of the last error on the calling thread ("" if none).  The
+ * string is owned by the library and valid until the next call. */
+const char* hard_last_error(void);
+
+/* Bytes of workspace the single-grid calls (cfl_dt, hydro_step,
+ * conservation_sums, status_read) need for grid g. */
+hard_status_t hard_workspace_bytes(const hard_grid_t* g, size_t* bytes);
+
+/* Clear the workspace control block (enqueued; no memset node is used, so
+ * the call may be captured in a graph). */
+hard_status_t hard_workspace_init(void* work, size_t work_bytes, void* stream);
+
+/* CFL time step (section 3.5; the formula is this library's reading):
+ *     dt = cfl / max_i sum_d (|u_{d,i}| + c_i) / dx_d
+ * over the interior cells of U, c = sqrt(gamma p / rho).  Writes dt to the
+ * device double *dt_dev.  If dt_host is not NULL the call synchronises the
+ * stream, copies dt to *dt_host and returns HARD_ERR_NONPHYSICAL if the
+ * status word has any bit set.  0 < cfl <= 1. */
+hard_status_t hard_cfl_dt(const hard_grid_t* g, const void* U, double cfl, double* dt_dev,
+                          double* dt_host, void* work, size_t work_bytes, void* stream);
+
+/* One Heun (SSP-RK2) step of size *dt_dev (section 2.2.2, Butcher tableau):
+ *     U1 = U + dt L(U),   U_new = (U + (U1 + dt L(U1))) / 2,
+ *     L(U)_i = - sum_d (F_{d,i+1/2} - F_{d,i-1/2}) / dx_d,
+ * with HLLC fluxes of MUSCL-minmod primitive face states.  U is overwritten
+ * with U_new.  If next_dt_dev is not NULL the CFL step of U_new (same
+ * formula as hard_cfl_dt, factor cfl) is written there in the same pass;
+ * next_dt_dev may equal dt_dev.  Stream-ordered, no host synchronisation,
+ * no allocation; graph-capturable. */
+hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_dev, double cfl,
+                              double* next_dt_dev, void* work, size_t work_bytes, void* stream);
+
+/* One stage of hard_hydro_step (stage = 1 or 2), for callers that schedule
+ * the two stages themselves (hard_hydro_step is exactly stage 1 then 2):
+ *   stage 1: dst = src + dt L(src)                      (src = U^n, dst = U^1)
+ *   stage 2: dst = (un + (src + dt L(src))) / 2         (src = U^1, un = U^n)
+ * dst may alias un in stage 2, never src.  next_dt_dev (stage 2 only, may be
+ * NULL) receives the CFL step of dst.  Same layouts and rules as
+ * hard_hydro_step; the workspace provides the control block only. */
+hard_status_t hard_hydro_stage(const hard_grid_t* g, int32_t stage, const void* src,
+                               const void* un, void* dst, const double* dt_dev, double cfl,
+                               double* next_dt_dev, void* work, size_t work_bytes, void* stream);
+
+/* Run to time t_end from U (in place), the time loop of the paper's control
+ * model (section 2.1) with a CFL step each step: dt = min(CFL dt of U,
+ * t_end - t); stops when t >= t_end (1 - 1e-14) or after max_steps steps.
+ * The loop runs on the device in batches (t, dt and the stop flag live in
+ * the workspace; steps after the end are exact no-ops with dt = 0); the host
+ * synchronises once per batch.  Writes the final t and the number of steps
+ * taken; returns HARD_ERR_NONPHYSICAL if the status word has bits set. */
+hard_status_t hard_run(const hard_grid_t* g, void* U, double cfl, double t_end, int64_t max_steps,
+                       double* t_out, int64_t* steps_out, void* work, size_t work_bytes,
+                       void* stream);
+
+/* Read the status word into *flags (HARD_FLAG_* bits), then clear it.
+ * Synchronises the stream.  Returns HARD_ERR_NONPHYSICAL if any bit was set. */
+hard_status_t hard_status_read(void* work, size_t work_bytes, uint32_t* flags, void* stream);
+
+/* Per-field totals sum_i U[v][i] over the interior (v = 0..nvar-1) in
+ * double, from compensated per-thread sums combined in a fixed order
+ * (bitwise reproducible).  sums_dev: device array of nvar doubles. */
+hard_status_t hard_conservation_sums(const hard_grid_t* g, const void* U, double* sums_dev,
+                                     void* work, size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched: many independent problems, each with its own grid and its own
+ * CFL time step, packed into one buffer and advanced by one launch per stage.
+ * ------------------------------------------------------------------------ */
+typedef struct hard_batch_plan hard_batch_plan_t;
+
+/* Build a plan for nprob grids (host array, copied).  All grids must share
+ * dtype and gamma.  Problem p's state occupies elements
+ * [offset[p], offset[p+1]) of the packed buffer, laid out as a single grid.
+ * tune_cache may name a text file of tile choices written by the
+ * autotuner (NULL = built-in defaults).  *out is owned by the library until
+ * hard_batch_plan_destroy.  Allocates device memory for the plan tables
+ * (this is the only allocating call; it synchronises the device). */
+hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
+                                     const char* tune_cache, hard_batch_plan_t** out);
+hard_status_t hard_batch_plan_destroy(hard_batch_plan_t* plan);
+
+/* Element offsets of each problem in the packed buffer (host array of
+ * nprob + 1 int64; offsets[nprob] is the total element count). */
+hard_status_t hard_batch_offsets(const hard_batch_plan_t* plan, int64_t* offsets);
+
+hard_status_t hard_batch_workspace_bytes(const hard_batch_plan_t* plan, size_t* bytes);
+
+/* Per-problem CFL steps dt_dev[p] (device array of nprob doubles). */
+hard_status_t hard_cfl_dt_batched(const hard_batch_plan_t* plan, const void* U, double cfl,
+                                  double* dt_dev, void* work, size_t work_bytes, void* stream);
+
+/* One Heun step of every problem with its own dt_dev[p].  If update_dt is
+ * non-zero, dt_dev[p] is replaced by the CFL step of the new state of
+ * problem p (factor cfl).  Stream-ordered, graph-capturable. */
+hard_status_t hard_hydro_step_batched(const hard_batch_plan_t* plan, void* U, double* dt_dev,
+                                      double cfl, int32_t update_dt, void* work,
+                                      size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Adjoint (vector-Jacobian product) of one step with dt held fixed.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes for hard_hydro_step_adjoint (HARD_F64 only). */
+hard_status_t hard_adjoint_workspace_bytes(const hard_grid_t* g, size_t* bytes);
+
+/* lam <- (d U_new / d U_n)^T lam for the step U_n -> U_new of
+ * hard_hydro_step with the fixed step *dt_dev (the derivative of the branch
+ * taken at U_n: minmod, min/max and HLLC region choices are held).  U_n is
+ * not modified; the intermediate stage is recomputed internally.  lam is a
+ * device array shaped like U. */
+hard_status_t hard_hydro_step_adjoint(const hard_grid_t* g, const void* U_n, const double* dt_dev,
+                                      void* lam, void* work, size_t work_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HARD_H */

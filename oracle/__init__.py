@@ -55,6 +55,8 @@ def lib():
         L.oracle_hllc.restype = None
         L.oracle_minmod.argtypes = [ctypes.c_double, ctypes.c_double]
         L.oracle_minmod.restype = ctypes.c_double
+        L.oracle_threads.argtypes = []
+        L.oracle_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -176,6 +178,11 @@ def hllc(WL, WR, gamma=1.4):
     F = np.empty(nt + 3)
     lib().oracle_hllc(nt, float(gamma), _dptr(WL), _dptr(WR), _dptr(F))
     return F
+
+
+def threads():
+    """OpenMP threads the oracle's loops use."""
+    return lib().oracle_threads()
 
 
 def minmod(a, b):

@@ -544,4 +544,11 @@ void oracle_hllc(int nt, double gamma, const double* WL, const double* WR, doubl
 
 double oracle_minmod(double a, double b) { return minmod<double>(a, b); }
 
+#ifdef _OPENMP
+#include <omp.h>
+int oracle_threads(void) { return omp_get_max_threads(); }
+#else
+int oracle_threads(void) { return 1; }
+#endif
+
 }  // extern "C"

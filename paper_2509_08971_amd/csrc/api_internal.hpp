@@ -1,0 +1,45 @@
+// Host-side helpers shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/hard.h"
+
+namespace hard {
+
+// Validated grid with derived quantities (unused axes: n = 1, dx = 1).
+struct Grid {
+  int ndim, dtype, nvar, wsize;
+  long long ncell;
+  int n[3];
+  double dx[3], inv_dx[3];
+  int bc[3][2];
+  double gamma;
+};
+
+// Byte offsets inside a single-grid workspace.
+struct WorkLayout {
+  size_t ctl;            // Control block (256 B)
+  size_t stage;          // intermediate stage state U^1
+  size_t stage_bytes;
+  size_t partials;       // compensated-sum partials
+  int partials_blocks;
+  size_t total;
+};
+
+hard_status_t fail(hard_status_t code, const char* fmt, ...);
+hard_status_t ok();
+hard_status_t hip_fail(hipError_t e, const char* what);
+hard_status_t check_grid(const hard_grid_t* g, Grid* out);
+hard_status_t check_ptr(const void* p, size_t align, const char* name);
+hard_status_t check_work(void* work, size_t have, size_t need);
+hard_status_t check_cfl(double cfl);
+WorkLayout layout_of(const Grid& g);
+
+// z planes per workgroup for the 3D stage kernel: HARD_STAGE_CZ in the
+// environment overrides the default (read once; 0 = default).
+int stage_cz_override();
+
+}  // namespace hard

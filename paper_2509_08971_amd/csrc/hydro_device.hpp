@@ -1,0 +1,356 @@
+// Device-side building blocks of the hydro step for gfx950.
+//
+// Primitive recovery with the ideal-gas closure, the minmod-limited MUSCL
+// face states and the HLLC flux (HARD paper section 2.2.1 for the equations,
+// section 2.2.2 for the finite-volume face difference; HLLC after Toro,
+// "Riemann Solvers and Numerical Methods for Fluid Dynamics", section 10.4,
+// with Davis wave-speed estimates).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hard {
+
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
+enum : unsigned { FLAG_DENSITY = 1u, FLAG_PRESSURE = 2u, FLAG_NONFINITE = 4u };
+
+// Workspace control block (first 256 bytes of every workspace).
+struct Control {
+  unsigned long long smax_bits;  // running max of the CFL signal sum, as bits of a double >= 0
+  unsigned int counter;          // blocks finished in the current launch
+  unsigned int flags;            // status bits (FLAG_*)
+  double t;                      // simulated time (hard_run)
+  long long steps;               // steps taken (hard_run)
+  int done;                      // hard_run reached t_end or max_steps
+  int pad;
+  double dt;                     // step size slot (hard_run)
+  unsigned long long aux[26];
+};
+static_assert(sizeof(Control) == 256, "control block is 256 bytes");
+
+// Index along one axis of n cells for a (possibly ghost) position q.
+// Periodic wraps, outflow copies the edge cell, reflecting mirrors and sets
+// `flip` (normal momentum changes sign).  Positions further out than the two
+// ghost layers occur only in the overhang of ragged tiles; they are clamped
+// into range and their values never reach an interior result.
+__device__ __forceinline__ int remap(int q, int n, int bclo, int bchi, bool& flip) {
+  flip = false;
+  if (q < 0) {
+    if (bclo == BC_PERIODIC) return q + n >= 0 ? q + n : 0;
+    if (bclo == BC_OUTFLOW) return 0;
+    flip = true;
+    int s = -q - 1;
+    return s < n ? s : n - 1;
+  }
+  if (q >= n) {
+    if (bchi == BC_PERIODIC) return q - n < n ? q - n : n - 1;
+    if (bchi == BC_OUTFLOW) return n - 1;
+    flip = true;
+    int s = 2 * n - 1 - q;
+    return s >= 0 ? s : 0;
+  }
+  return q;
+}
+
+// minmod(a, b): 0 if a and b differ in sign (or one is 0), else the argument
+// of smaller magnitude.  Evaluated as sign(a) max(0, min(|a|, sign(a) b)):
+// the same value (up to the sign of a zero result) without compares/selects.
+template <typename R>
+__device__ __forceinline__ R minmod(R a, R b) {
+  R t = copysign(R(1), a) * b;
+  R m = fmax(fmin(fabs(a), t), R(0));
+  return copysign(m, a);
+}
+
+// Reciprocal and square root used inside the flux.  FP64: hardware
+// v_rcp_f64 / v_rsq_f64 seeds refined by two Newton (resp. Goldschmidt)
+// steps, within about 1 ulp of the correctly rounded value at a third of the
+// instructions of the IEEE sequences.  FP32: the hardware instructions
+// (1 ulp).  The CFL step keeps IEEE division and square root.
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ double fast_sqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  return fma(g, r, g);
+}
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// c = sqrt(gp / rho) = gp * rsq(gp * rho): one reciprocal square root
+// (refined in FP64) instead of a reciprocal and a square root.
+__device__ __forceinline__ double sound_speed(double gp, double rho) {
+  double x = gp * rho;
+  double y = __builtin_amdgcn_rsq(x);
+  // two Newton steps for 1/sqrt(x): y <- y (3 - x y^2) / 2
+  double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return gp * y;
+}
+__device__ __forceinline__ float sound_speed(float gp, float rho) {
+  return gp * __builtin_amdgcn_rsqf(gp * rho);
+}
+
+// Pressure from conserved values.  The internal energy E - |m|^2/(2 rho) is
+// a difference of nearly equal numbers near vacuum and in fast flow, so for
+// float storage it is recovered in double.
+template <int NDIM>
+__device__ __forceinline__ double pressure_f64(const double* U, double inv_rho, double gm1) {
+  double q = U[1] * U[1];
+#pragma unroll
+  for (int d = 1; d < NDIM; ++d) q = q + U[1 + d] * U[1 + d];
+  return gm1 * (U[NDIM + 1] - 0.5 * q * inv_rho);
+}
+// float storage: E - |m|^2/(2 rho) in double (the float inputs are exact in double)
+template <int NDIM>
+__device__ __forceinline__ float pressure_f32(const float* U, double inv_rho, double gm1) {
+  double q = (double)U[1] * (double)U[1];
+#pragma unroll
+  for (int d = 1; d < NDIM; ++d) q = q + (double)U[1 + d] * (double)U[1 + d];
+  double e = (double)U[NDIM + 1] - 0.5 * q * inv_rho;
+  return (float)(gm1 * e);
+}
+
+// Conserved (rho, m_d, E) -> primitive (rho, u_d, p), in place in W.
+template <typename R, int NDIM>
+__device__ __forceinline__ void to_primitive(const R* U, R* W, double gm1);
+
+template <int NDIM>
+__device__ __forceinline__ void to_primitive_f64(const double* U, double* W, double gm1) {
+  double inv = fast_rcp(U[0]);
+  W[0] = U[0];
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) W[1 + d] = U[1 + d] * inv;
+  W[NDIM + 1] = pressure_f64<NDIM>(U, inv, gm1);
+}
+template <int NDIM>
+__device__ __forceinline__ void to_primitive_f32(const float* U, float* W, double gm1) {
+  double inv = fast_rcp((double)U[0]);
+  float invf = (float)inv;
+  W[0] = U[0];
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) W[1 + d] = U[1 + d] * invf;
+  W[NDIM + 1] = pressure_f32<NDIM>(U, inv, gm1);
+}
+template <>
+__device__ __forceinline__ void to_primitive<double, 1>(const double* U, double* W, double g) { to_primitive_f64<1>(U, W, g); }
+template <>
+__device__ __forceinline__ void to_primitive<double, 2>(const double* U, double* W, double g) { to_primitive_f64<2>(U, W, g); }
+template <>
+__device__ __forceinline__ void to_primitive<double, 3>(const double* U, double* W, double g) { to_primitive_f64<3>(U, W, g); }
+template <>
+__device__ __forceinline__ void to_primitive<float, 1>(const float* U, float* W, double g) { to_primitive_f32<1>(U, W, g); }
+template <>
+__device__ __forceinline__ void to_primitive<float, 2>(const float* U, float* W, double g) { to_primitive_f32<2>(U, W, g); }
+template <>
+__device__ __forceinline__ void to_primitive<float, 3>(const float* U, float* W, double g) { to_primitive_f32<3>(U, W, g); }
+
+// Status bits of one interior cell from its conserved values and pressure.
+template <typename R, int NV>
+__device__ __forceinline__ unsigned cell_flags(const R* U, R p) {
+  unsigned f = 0;
+  if (!(U[0] > R(0))) f |= FLAG_DENSITY;
+  if (!(p > R(0))) f |= FLAG_PRESSURE;
+  bool fin = true;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) fin = fin && isfinite(U[v]);
+  if (!fin) f |= FLAG_NONFINITE;
+  return f;
+}
+
+// HLLC flux across a face whose normal velocity is un; NT transverse
+// velocities ut.  Output: mass, normal momentum, NT transverse momenta, energy.
+// Only the side selected by the wave pattern is evaluated:
+//   S_L >= 0         -> F_L
+//   S_L < 0 <= S*    -> F_L + S_L (U*_L - U_L)
+//   S* < 0 < S_R     -> F_R + S_R (U*_R - U_R)
+//   S_R <= 0         -> F_R
+// with U*_K = rho_K r [1, S*, ut_K, E_K/rho_K + (S*-u_K)(S* + p_K/(rho_K (S_K-u_K)))],
+// r = (S_K - u_K)/(S_K - S*), the energy entry expanded as
+// r E_K + r (S* - u_K)(rho_K S* + p_K/(S_K - u_K)).
+template <typename R, int NT>
+__device__ __forceinline__ void hllc(R rL, R unL, const R* utL, R pL, R rR, R unR, const R* utR,
+                                     R pR, R gam, R inv_gm1, R* F) {
+  R cL = sound_speed(gam * pL, rL);
+  R cR = sound_speed(gam * pR, rR);
+  R aL = unL - cL, bL = unR - cR;
+  R SL = (aL <= bL) ? aL : bL;
+  R aR = unL + cL, bR = unR + cR;
+  R SR = (aR >= bR) ? aR : bR;
+  R dL = SL - unL, dR = SR - unR;
+  R mL = rL * dL, mR = rR * dR;  // rho_K (S_K - u_K)
+  R Ss = (pR - pL + mL * unL - mR * unR) * fast_rcp(mL - mR);
+
+  // pick the side
+  bool left = (SL >= R(0)) || (Ss >= R(0));
+  bool star = left ? !(SL >= R(0)) : (SR > R(0));
+  R r = left ? rL : rR;
+  R un = left ? unL : unR;
+  R p = left ? pL : pR;
+  R S = left ? SL : SR;
+  R d = left ? dL : dR;
+  R ut[NT > 0 ? NT : 1];
+  R q = un * un;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    ut[t] = left ? utL[t] : utR[t];
+    q = q + ut[t] * ut[t];
+  }
+  R E = p * inv_gm1 + R(0.5) * r * q;
+
+  // physical flux and conserved state of side K
+  R mn = r * un;
+  R FK[NT + 3], UK[NT + 3], US[NT + 3];
+  FK[0] = mn;
+  FK[1] = mn * un + p;
+  UK[0] = r;
+  UK[1] = mn;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    FK[2 + t] = mn * ut[t];
+    UK[2 + t] = r * ut[t];
+  }
+  FK[NT + 2] = (E + p) * un;
+  UK[NT + 2] = E;
+
+  // star state of side K.  r is an exact quotient: at a stationary contact
+  // (u_K = 0, S* = 0) it is exactly 1, so U*_K = U_K and the contact stays put.
+  R rr = d / (S - Ss);
+  R fac = r * rr;
+  US[0] = fac;
+  US[1] = fac * Ss;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) US[2 + t] = fac * ut[t];
+  US[NT + 2] = rr * E + rr * (Ss - un) * (r * Ss + p * fast_rcp(d));
+
+#pragma unroll
+  for (int v = 0; v < NT + 3; ++v) {
+    R fs = FK[v] + S * (US[v] - UK[v]);
+    F[v] = star ? fs : FK[v];
+  }
+}
+
+// MUSCL-minmod face states from four cell states along the face normal
+// (cells i-1, i | i+1, i+2 around face i+1/2 are w0, w1 | w2, w3).
+template <typename R>
+__device__ __forceinline__ void muscl_pair(R w0, R w1, R w2, R w3, R& wl, R& wr) {
+  R d01 = w1 - w0, d12 = w2 - w1, d23 = w3 - w2;
+  R sl = minmod(d01, d12);
+  R sr = minmod(d12, d23);
+  wl = w1 + R(0.5) * sl;
+  wr = w2 - R(0.5) * sr;
+}
+
+// HLLC flux from primitive face states already ordered (rho, u_n, u_t..., p);
+// output (mass, normal momentum, transverse momenta, energy).
+template <typename R, int NV>
+__device__ __forceinline__ void hllc_ordered(const R* WL, const R* WR, R gam, R inv_gm1, R* F) {
+  constexpr int NT = NV - 3;
+  R utL[NT > 0 ? NT : 1], utR[NT > 0 ? NT : 1];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    utL[t] = WL[2 + t];
+    utR[t] = WR[2 + t];
+  }
+  hllc<R, NT>(WL[0], WL[1], utL, WL[NV - 1], WR[0], WR[1], utR, WR[NV - 1], gam, inv_gm1, F);
+}
+
+// Wave64 reductions
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Map hardware block id to a logical tile id so that the blocks one XCD
+// receives (the dispatcher deals blocks round-robin over the 8 XCDs) form one
+// contiguous run of logical tiles, which share halos through that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int nx = 8;
+  int xcd = b % nx, slot = b / nx;
+  int per = nb / nx, rem = nb % nx;
+  return xcd * per + (xcd < rem ? xcd : rem) + slot;
+}
+
+// CFL signal sum sum_d (|u_d| + c)/dx_d of one conserved state, in double,
+// rounded step by step in the stated order (no contraction) so that it
+// reproduces a plain evaluation of the formula.
+template <int NDIM>
+__device__ __forceinline__ double signal_sum(const double* U, const double* dx, double gamma) {
+#pragma clang fp contract(off)
+  double rho = U[0];
+  double q = U[1] * U[1];
+#pragma unroll
+  for (int d = 1; d < NDIM; ++d) q = q + U[1 + d] * U[1 + d];
+  double ke = 0.5 * q / rho;
+  double e = U[NDIM + 1] - ke;
+  double p = (gamma - 1.0) * e;
+  double cs = sqrt(gamma * p / rho);
+  double s = 0.0;
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) s = s + (fabs(U[1 + d] / rho) + cs) / dx[d];
+  return s;
+}
+
+// Block-wide: OR of status flags and max of CFL sums; one atomic each per
+// block; last block finalises dt.  Must be called by every thread.
+template <int NTHREADS>
+__device__ __forceinline__ void block_finish(unsigned flags, double smax, bool do_cfl,
+                                             Control* ctl, double cfl, double* next_dt) {
+  constexpr int NW = NTHREADS / 64;
+  __shared__ double red_s[NW];
+  __shared__ unsigned red_f[NW];
+  __shared__ int last;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  flags = wave_or(flags);
+  if (do_cfl) smax = wave_max(smax);
+  if (lane == 0) {
+    red_f[w] = flags;
+    red_s[w] = smax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned f = 0;
+    double s = 0.0;
+    for (int i = 0; i < NW; ++i) {
+      f |= red_f[i];
+      s = fmax(s, red_s[i]);
+    }
+    if (f) atomicOr(&ctl->flags, f);
+    last = 0;
+    if (do_cfl) {
+      atomicMax(&ctl->smax_bits, (unsigned long long)__double_as_longlong(s));
+      __threadfence();
+      unsigned prev = atomicAdd(&ctl->counter, 1u);
+      last = (prev == gridDim.x - 1);
+    }
+  }
+  __syncthreads();
+  if (do_cfl && last && threadIdx.x == 0) {
+    __threadfence();
+    unsigned long long bits = atomicAdd(&ctl->smax_bits, 0ull);
+    double s = __longlong_as_double((long long)bits);
+    *next_dt = cfl / s;
+    atomicExch(&ctl->smax_bits, 0ull);
+    atomicExch(&ctl->counter, 0u);
+  }
+}
+
+}  // namespace hard

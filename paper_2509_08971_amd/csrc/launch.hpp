@@ -1,0 +1,46 @@
+// Host-side launch interface between the C ABI (api.hip) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hard {
+
+struct Control;
+
+struct StageArgs {
+  const void* src;       // stencil source: U^n (stage 1) or U^1 (stage 2)
+  const void* un;        // U^n for the stage-2 combine
+  void* dst;             // U^1 (stage 1) or U^{n+1} (stage 2; may alias un)
+  const double* dt;      // device dt
+  int n[3];              // cells per axis (1 for unused axes)
+  int bc[3][2];          // boundary kinds
+  double dx[3];          // cell widths (CFL)
+  double inv_dx[3];      // 1/dx (flux difference)
+  double gamma;
+  double cfl;
+  int fuse_cfl;          // stage 2: fold the CFL max of U^{n+1} into the pass
+  int tiles_x, tiles_y;  // filled by the launcher
+  int cz;                // z planes per workgroup (3D), 0 = default
+  Control* ctl;          // workspace control block
+  double* next_dt;       // fused CFL output (stage 2)
+};
+
+hipError_t launch_stage(int ndim, int dtype, const StageArgs& a, int stage, hipStream_t s);
+
+// Standalone CFL dt (reads U once).
+hipError_t launch_cfl(int ndim, int dtype, const int* n, const double* dx, double gamma,
+                      const void* U, double cfl, double* dt, Control* ctl, hipStream_t s);
+
+// hard_run time control (one thread).
+hipError_t launch_time_control(Control* ctl, double t_end, long long max_steps, hipStream_t s);
+
+// Zero the control block.
+hipError_t launch_control_clear(Control* ctl, hipStream_t s);
+
+// Compensated per-field sums: partials has room for nblocks_max * nvar * 2 doubles.
+hipError_t launch_sums(int ndim, int dtype, const int* n, const void* U, double* partials,
+                       int nblocks_max, double* out, hipStream_t s);
+int sums_blocks(long long ncell);
+
+}  // namespace hard

@@ -1,0 +1,116 @@
+"""C ABI of libhard, checked on the host (no GPU needed): every function
+declared in include/hard.h is exported, and invalid arguments are rejected
+before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+H = pytest.importorskip("paper_2509_08971_amd")
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "hard.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hard_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_function_is_exported():
+    names = declared_functions()
+    assert "hard_hydro_step" in names and "hard_hydro_step_adjoint" in names
+    L = H.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_library_is_gfx950_hip_code():
+    out = open(H.LIB_PATH, "rb").read()
+    assert b"gfx950" in out
+
+
+def grid(**kw):
+    g = H.make_grid((32, 16, 8), bc=(H.PERIODIC, H.PERIODIC))
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+FAKE = 1 << 40  # never dereferenced: every call below fails validation first
+
+
+def call_step(g, U=FAKE, dt=FAKE, cfl=0.4, nxt=None, work=FAKE, nbytes=None):
+    L = H.lib()
+    if nbytes is None:
+        nbytes = 1 << 40
+    return L.hard_hydro_step(ctypes.byref(g) if g is not None else None, U, dt, cfl, nxt, work,
+                             nbytes, None)
+
+
+@pytest.mark.parametrize("mut", [
+    dict(ndim=0), dict(ndim=4), dict(dtype=7), dict(gamma=1.0), dict(gamma=float("nan")),
+])
+def test_invalid_grid_scalar(mut):
+    g = grid(**mut)
+    assert call_step(g, work=None) == H.ERR_INVALID_ARG
+    assert H.hard_last_error()
+
+
+def test_invalid_grid_fields():
+    g = grid()
+    g.n[0] = 1
+    assert call_step(g) == H.ERR_INVALID_ARG
+    g = H.make_grid((32, 16))
+    g.n[2] = 4
+    assert call_step(g) == H.ERR_INVALID_ARG
+    g = grid()
+    g.dx[1] = 0.0
+    assert call_step(g) == H.ERR_INVALID_ARG
+    g = grid()
+    g.dx[2] = float("inf")
+    assert call_step(g) == H.ERR_INVALID_ARG
+    g = grid()
+    g.bc[1][0] = 5
+    assert call_step(g) == H.ERR_INVALID_ARG
+    g = grid()
+    g.bc[0][0] = H.OUTFLOW  # periodic on one side only
+    assert call_step(g) == H.ERR_INVALID_ARG
+    assert call_step(None) == H.ERR_INVALID_ARG
+
+
+def test_invalid_pointers_and_sizes():
+    g = grid()
+    assert call_step(g, U=None) == H.ERR_INVALID_ARG
+    assert call_step(g, U=FAKE + 4) == H.ERR_INVALID_ARG  # misaligned double
+    assert call_step(g, dt=None) == H.ERR_INVALID_ARG
+    assert call_step(g, nxt=FAKE, cfl=0.0) == H.ERR_INVALID_ARG
+    assert call_step(g, nxt=FAKE, cfl=1.5) == H.ERR_INVALID_ARG
+    assert call_step(g, work=None) == H.ERR_INVALID_ARG
+    assert call_step(g, work=FAKE + 8) == H.ERR_INVALID_ARG
+    need = H.hard_workspace_bytes(g)
+    assert call_step(g, nbytes=need - 1) == H.ERR_WORKSPACE
+
+
+def test_workspace_size_formula():
+    g = H.make_grid((256, 256, 256), bc=(H.REFLECT, H.REFLECT))
+    b = H.hard_workspace_bytes(g)
+    state = 5 * 256 ** 3 * 8
+    assert state <= b <= state + 256 * 1024
+    g32 = H.make_grid((64, 64), dtype="f32")
+    assert H.hard_workspace_bytes(g32) >= 4 * 64 * 64 * 4
+
+
+def test_cfl_and_run_argument_checks():
+    L = H.lib()
+    g = grid()
+    host = ctypes.c_double()
+    assert L.hard_cfl_dt(ctypes.byref(g), FAKE, 0.0, FAKE, ctypes.byref(host), FAKE, 1 << 40,
+                         None) == H.ERR_INVALID_ARG
+    t = ctypes.c_double()
+    s = ctypes.c_int64()
+    assert L.hard_run(ctypes.byref(g), FAKE, 0.4, -1.0, 10, ctypes.byref(t), ctypes.byref(s), FAKE,
+                      1 << 40, None) == H.ERR_INVALID_ARG
+    assert L.hard_run(ctypes.byref(g), FAKE, 0.4, 1.0, 0, ctypes.byref(t), ctypes.byref(s), FAKE,
+                      1 << 40, None) == H.ERR_INVALID_ARG

@@ -1,0 +1,232 @@
+"""GPU FP64/FP32 step through the C ABI against the CPU oracle.
+
+Tolerances: FP64 per field max|g - o| / max|o| <= 1e-12; FP32 bulk per field
+sum|g - o| / sum|o| <= 1e-5 against the FP64 oracle run on the same
+(float-rounded) input.  dt: the standalone GPU CFL step equals the oracle's
+bit for bit on the same input (both evaluate the same operations with IEEE
+division and square root and no contraction).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle.metrics import exact_sum, field_rel_l1, field_rel_linf
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+H = pytest.importorskip("paper_2509_08971_amd")
+
+P, O, R = 0, 1, 2
+DEV = "cuda"
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def run_gpu(n, bc, U0, dts=None, cfl=0.4, dtype=torch.float64, fuse=False):
+    """len(dts) steps on the GPU with the given dt list; returns (U, next_dt)."""
+    g = H.make_grid(n, bc=bc, dtype=dtype)
+    U = torch.from_numpy(np.ascontiguousarray(U0)).to(DEV, dtype)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    dt = torch.zeros(1, dtype=torch.float64, device=DEV)
+    nxt = torch.zeros(1, dtype=torch.float64, device=DEV) if fuse else None
+    for d in dts:
+        dt.fill_(d)
+        H.hard_hydro_step(g, U, dt, work, cfl=cfl, next_dt_dev=nxt)
+    torch.cuda.synchronize()
+    flags = H.hard_status_read(work)
+    assert flags == 0, flags
+    return U.double().cpu().numpy(), (nxt.item() if fuse else None)
+
+
+def random_state(n, seed, smooth=False):
+    rng = np.random.default_rng(seed)
+    shape = tuple(reversed(n))
+    if smooth and len(n) == 1:
+        gf = lambda: workloads.gaussian_random_field(shape, rng)
+        return workloads.conserved_from_primitive(np.exp(0.3 * gf()), [0.5 * gf()],
+                                                  1.0 + 0.1 * gf())
+    if smooth:
+        nd = len(n)
+        base = workloads.turbulent_box(max(n), ndim=nd, seed=seed)
+        sl = (slice(None),) + tuple(slice(0, s) for s in shape)
+        return np.ascontiguousarray(base[sl])
+    rho = rng.uniform(0.3, 1.5, shape)
+    vel = [rng.uniform(-0.5, 0.5, shape) for _ in n]
+    p = rng.uniform(0.3, 1.5, shape)
+    return workloads.conserved_from_primitive(rho, vel, p)
+
+
+CASES = [
+    ((1000,), (O, O)),
+    ((37,), (R, R)),
+    ((64,), (P, P)),
+    ((50, 37), (O, O, R, R)),
+    ((33, 40), (P, P, P, P)),
+    ((17, 9), (R, O, O, R)),
+    ((37, 21, 19), (P, P, R, R, O, O)),
+    ((16, 16, 16), (R, R)),
+    ((40, 33, 70), (O, O, P, P, R, R)),
+    ((5, 6, 7), (O, R, P, P, R, O)),
+]
+
+
+@pytest.mark.parametrize("n,bc", CASES)
+def test_cfl_dt_bitwise(n, bc):
+    log("cfl", n, bc)
+    U0 = random_state(n, 1)
+    g = H.make_grid(n, bc=bc)
+    U = torch.from_numpy(U0).to(DEV)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    dt = torch.zeros(1, dtype=torch.float64, device=DEV)
+    got = H.hard_cfl_dt(g, U, 0.4, dt, work, want_host=True)
+    ref, st = oracle.cfl_dt(oracle.Grid(n, bc=bc), U0, 0.4)
+    assert st == 0
+    assert got == ref, (got, ref)
+
+
+@pytest.mark.parametrize("n,bc", CASES)
+def test_step_parity_fp64(n, bc):
+    log("fp64 step", n, bc)
+    U0 = random_state(n, 2)
+    og = oracle.Grid(n, bc=bc)
+    dt, _ = oracle.cfl_dt(og, U0, 0.3)
+    dts = [dt] * 3
+    ref, st = oracle.steps(og, U0, dts)
+    assert st == 0
+    out, nxt = run_gpu(n, bc, U0, dts, fuse=True)
+    for v in range(len(n) + 2):
+        assert field_rel_linf(out[v], ref[v]) <= TOL64, (v, field_rel_linf(out[v], ref[v]))
+    # fused next dt of the GPU state equals the standalone CFL of that state
+    g = H.make_grid(n, bc=bc)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    d = torch.zeros(1, dtype=torch.float64, device=DEV)
+    alone = H.hard_cfl_dt(g, torch.from_numpy(out).to(DEV), 0.4, d, work, want_host=True)
+    assert nxt == alone
+    ref_dt, _ = oracle.cfl_dt(og, ref, 0.4)
+    assert abs(nxt - ref_dt) <= 1e-13 * ref_dt
+
+
+@pytest.mark.parametrize("n,bc", [((1000,), (O, O)), ((50, 37), (O, O, R, R)),
+                                  ((37, 21, 19), (P, P, R, R, O, O)),
+                                  ((64, 40, 24), (P, P, P, P, P, P))])
+def test_step_parity_fp32(n, bc):
+    log("fp32 step", n, bc)
+    U0 = random_state(n, 3, smooth=True)
+    U0 = U0.astype(np.float32).astype(np.float64)
+    og = oracle.Grid(n, bc=bc)
+    dt, _ = oracle.cfl_dt(og, U0, 0.4)
+    dts = [dt] * 4
+    ref, _ = oracle.steps(og, U0, dts)
+    out, _ = run_gpu(n, bc, U0, dts, dtype=torch.float32)
+    for v in range(len(n) + 2):
+        e = field_rel_l1(out[v], ref[v])
+        log("  field", v, "rel L1", e)
+        assert e <= TOL32, (v, e)
+
+
+def test_uniform_and_contact_preserved_bitwise():
+    for n, bc in [((24, 10, 6), (R, R)), ((30, 12), (O, O)), ((50,), (P, P))]:
+        shape = tuple(reversed(n))
+        x = workloads.cell_centres(n[0])
+        rho = np.broadcast_to(np.where(x < 0.4, 1.0, 0.2), shape).copy()
+        U0 = workloads.conserved_from_primitive(rho, [np.zeros(shape)] * len(n),
+                                                np.full(shape, 0.6))
+        out, _ = run_gpu(n, bc, U0, [1e-3] * 5)
+        assert np.array_equal(out, U0)
+
+
+def test_run_to_t_end_config0():
+    """1024-cell two-state problem run to t = 0.2 with the device time loop."""
+    n = 1024
+    for seed in (0, 5):
+        log("run c0 seed", seed)
+        U0 = workloads.random_two_state(n, seed)
+        og = oracle.Grid((n,), bc=(O, O))
+        ref, t_ref, steps_ref, st = oracle.run(og, U0, 0.4, 0.2)
+        g = H.make_grid((n,), bc=(O, O))
+        U = torch.from_numpy(U0).to(DEV)
+        work = H.workspace(H.hard_workspace_bytes(g))
+        t, steps = H.hard_run(g, U, 0.4, 0.2, work)
+        out = U.cpu().numpy()
+        assert steps == steps_ref and t == pytest.approx(t_ref, rel=1e-15, abs=0)
+        for v in range(3):
+            assert field_rel_linf(out[v], ref[v]) <= TOL64, (v, field_rel_linf(out[v], ref[v]))
+
+
+def test_blast_256_full_grid_one_step():
+    """The 256^3 reflecting blast at full size, in the launch the benchmark
+    times: one step against the full oracle step, plus the fused next dt."""
+    n = 256
+    log("blast 256^3")
+    U0 = workloads.blast_3d(n)
+    og = oracle.Grid((n, n, n), bc=(R, R))
+    dt, st = oracle.cfl_dt(og, U0, 0.4)
+    g = H.make_grid((n, n, n), bc=(R, R))
+    U = torch.from_numpy(U0).to(DEV)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    d = torch.zeros(1, dtype=torch.float64, device=DEV)
+    dt_gpu = H.hard_cfl_dt(g, U, 0.4, d, work, want_host=True)
+    assert dt_gpu == dt
+    H.hard_hydro_step(g, U, d, work, cfl=0.4, next_dt_dev=d)
+    torch.cuda.synchronize()
+    ref, st = oracle.step(og, U0, dt)
+    assert st == 0
+    out = U.cpu().numpy()
+    for v in range(5):
+        assert field_rel_linf(out[v], ref[v]) <= TOL64, v
+    nref, _ = oracle.cfl_dt(og, ref, 0.4)
+    assert abs(d.item() - nref) <= 1e-13 * nref
+    assert H.hard_status_read(work) == 0
+
+
+def test_status_flags_nonphysical():
+    n = (40, 20)
+    U0 = random_state(n, 4)
+    U0[3, 5, 7] = 0.5 * (U0[1, 5, 7] ** 2 + U0[2, 5, 7] ** 2) / U0[0, 5, 7] - 0.1  # p < 0
+    g = H.make_grid(n, bc=(P, P))
+    U = torch.from_numpy(U0).to(DEV)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    d = torch.zeros(1, dtype=torch.float64, device=DEV)
+    with pytest.raises(H.HardError) as e:
+        H.hard_cfl_dt(g, U, 0.4, d, work, want_host=True)
+    assert e.value.code == H.ERR_NONPHYSICAL
+    assert H.hard_status_read(work) & H.FLAG_PRESSURE
+    assert H.hard_status_read(work) == 0  # cleared by the read
+
+
+def test_conservation_sums_and_conservation():
+    n = (48, 40, 36)
+    U0 = random_state(n, 5, smooth=True)
+    g = H.make_grid(n, bc=(P, P))
+    U = torch.from_numpy(U0).to(DEV)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    sums = torch.zeros(5, dtype=torch.float64, device=DEV)
+    H.hard_conservation_sums(g, U, sums, work)
+    s0 = sums.cpu().numpy()
+    for v in range(5):
+        ex = exact_sum(U0[v])
+        assert abs(s0[v] - ex) <= 2e-16 * exact_sum(np.abs(U0[v]))
+    d = torch.zeros(1, dtype=torch.float64, device=DEV)
+    H.hard_cfl_dt(g, U, 0.4, d, work)
+    for _ in range(10):
+        H.hard_hydro_step(g, U, d, work, cfl=0.4, next_dt_dev=d)
+    H.hard_conservation_sums(g, U, sums, work)
+    s1 = sums.cpu().numpy()
+    for v in range(5):
+        assert abs(s1[v] - s0[v]) <= 1e-12 * exact_sum(np.abs(U0[v])), v
+
+
+def test_run_to_run_bitwise():
+    n = (64, 48, 40)
+    U0 = random_state(n, 6, smooth=True)
+    a, _ = run_gpu(n, (P, P), U0, [1e-3] * 3, fuse=True)
+    b, _ = run_gpu(n, (P, P), U0, [1e-3] * 3, fuse=True)
+    assert np.array_equal(a, b)

@@ -18,7 +18,12 @@ Workloads (the paper publishes no data; every input here is synthetic):
     relations P_A = c_s^2 rho_A, u_A = c_s rho_A / rho_0);
   * batch_problems: thousands of uneven 1D and 2D two-state problems.
 """
+import os
+
 import numpy as np
+import scipy.fft as sfft
+
+_WORKERS = int(os.environ.get("OMP_NUM_THREADS", "0")) or -1
 
 GAMMA = 1.4
 
@@ -28,9 +33,15 @@ def conserved_from_primitive(rho, vel, p, gamma=GAMMA):
     rho = np.asarray(rho, dtype=np.float64)
     vel = [np.asarray(v, dtype=np.float64) for v in vel]
     p = np.asarray(p, dtype=np.float64)
-    q = sum(v * v for v in vel)
-    E = p / (gamma - 1.0) + 0.5 * rho * q
-    return np.stack([rho] + [rho * v for v in vel] + [E]).astype(np.float64)
+    U = np.empty((len(vel) + 2,) + rho.shape)
+    U[0] = rho
+    q = np.zeros(rho.shape)
+    for d, v in enumerate(vel):
+        np.multiply(rho, v, out=U[1 + d])
+        q += v * v
+    np.multiply(0.5 * rho, q, out=U[-1])
+    U[-1] += p / (gamma - 1.0)
+    return U
 
 
 def cell_centres(n):
@@ -103,7 +114,7 @@ def gaussian_random_field(shape, rng, spectral_index=-2.0):
     """
     d = len(shape)
     white = rng.standard_normal(shape)
-    wk = np.fft.rfftn(white)
+    wk = sfft.rfftn(white, workers=_WORKERS)
     k2 = np.zeros(wk.shape)
     for a, n in enumerate(shape):
         if a == d - 1:
@@ -123,7 +134,7 @@ def gaussian_random_field(shape, rng, spectral_index=-2.0):
             idx[a] = n // 2
             nz[tuple(idx)] = False
     amp[nz] = kk[nz] ** (0.5 * (spectral_index - (d - 1)))
-    field = np.fft.irfftn(wk * amp, s=shape, axes=tuple(range(d)))
+    field = sfft.irfftn(wk * amp, s=shape, axes=tuple(range(d)), workers=_WORKERS)
     field -= field.mean()
     field /= field.std()
     return field
@@ -132,7 +143,8 @@ def gaussian_random_field(shape, rng, spectral_index=-2.0):
 def solenoidal_velocity(shape, rng, spectral_index=-2.0):
     """d independent GRFs projected to zero divergence in Fourier space."""
     d = len(shape)
-    comps = [np.fft.rfftn(gaussian_random_field(shape, rng, spectral_index)) for _ in range(d)]
+    comps = [sfft.rfftn(gaussian_random_field(shape, rng, spectral_index), workers=_WORKERS)
+             for _ in range(d)]
     ks = []
     for a, n in enumerate(shape):
         k = np.fft.rfftfreq(n, 1.0 / n) if a == d - 1 else np.fft.fftfreq(n, 1.0 / n)
@@ -144,7 +156,8 @@ def solenoidal_velocity(shape, rng, spectral_index=-2.0):
     kdotu = sum(ks[a] * comps[a] for a in range(d))
     out = []
     for a in range(d):
-        ua = np.fft.irfftn(comps[a] - ks[a] * kdotu / k2, s=shape, axes=tuple(range(d)))
+        ua = sfft.irfftn(comps[a] - ks[a] * kdotu / k2, s=shape, axes=tuple(range(d)),
+                         workers=_WORKERS)
         ua -= ua.mean()
         out.append(ua)
     return out
