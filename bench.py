@@ -30,6 +30,142 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _time_steps(fn, steps, stream):
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def bench_fp32_turbulent(args, n=512, steps=50):
+    """512^3 periodic turbulent box, FP32 bulk, 50 steps with fused CFL dt."""
+    import paper_2509_08971_amd as H
+    import workloads
+
+    log(f"bench: turbulent {n}^3 fp32, {steps} steps")
+    U = workloads.turbulent_box_torch(n, ndim=3, seed=2, device="cuda", dtype=torch.float32)
+    U0 = U.clone()
+    g = H.make_grid((n, n, n), bc=(H.PERIODIC, H.PERIODIC), dtype=torch.float32)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    H.hard_cfl_dt(g, U, 0.4, dt, work)
+    for _ in range(3):
+        H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=dt)
+    U.copy_(U0)
+    H.hard_cfl_dt(g, U, 0.4, dt, work)
+    ms = _time_steps(lambda: H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=dt), steps,
+                     stream)
+    flags = H.hard_status_read(work)
+    N = n ** 3
+    zus = N * steps / (ms * 1e-3)
+    bytes_step = 5 * 5 * 4 * N
+    log(f"  {ms / steps:.3f} ms/step, {zus / 1e9:.2f} G zu/s")
+    return {"value": zus, "unit": "zone-updates/s", "ms_per_step": ms / steps, "steps": steps,
+            "dtype": "f32 (internal energy, dt in f64)",
+            "workload": f"3D {n}^3 periodic log-normal rho, p = 1, solenoidal u (rms Mach 0.5)",
+            "achieved_hbm_gbs": bytes_step / (ms / steps * 1e-3) / 1e9, "status_flags": flags}
+
+
+def bench_batched(args, steps=100):
+    """4096 two-state problems (3072 1D nx in [64,4096], 1024 2D side in
+    [32,256]), FP32, 100 steps each with per-problem CFL dt, the steps
+    replayed from one captured graph."""
+    import paper_2509_08971_amd as H
+    import workloads
+
+    log(f"bench: batched 4096 problems fp32, {steps} steps")
+    specs = workloads.batch_problem_specs()
+    grids = [H.make_grid((s[1],) * s[0], bc=(H.OUTFLOW, H.OUTFLOW), dtype=torch.float32)
+             for s in specs]
+    plan = H.hard_batch_plan_create(grids, None)
+    try:
+        offs = H.hard_batch_offsets(plan, len(grids))
+        host = np.zeros(offs[-1], dtype=np.float32)
+        cells = 0
+        bytes_step = 0
+        for p, s in enumerate(specs):
+            a = workloads.batch_problem_state(s).astype(np.float32).ravel()
+            host[offs[p]:offs[p] + a.size] = a
+            nv = s[0] + 2
+            cells += a.size // nv
+            bytes_step += 5 * a.size * 4
+        U = torch.from_numpy(host).to("cuda")
+        U0 = U.clone()
+        work = H.workspace(H.hard_batch_workspace_bytes(plan))
+        dt = torch.zeros(len(grids), dtype=torch.float64, device="cuda")
+        H.hard_cfl_dt_batched(plan, U, 0.4, dt, work)
+        dt0 = dt.clone()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            H.hard_hydro_step_batched(plan, U, dt, work, cfl=0.4)
+            side.synchronize()
+            with torch.cuda.graph(graph, stream=side):
+                for _ in range(steps):
+                    H.hard_hydro_step_batched(plan, U, dt, work, cfl=0.4)
+        torch.cuda.synchronize()
+        U.copy_(U0)
+        dt.copy_(dt0)
+        stream = torch.cuda.current_stream()
+        ms = _time_steps(graph.replay, 1, stream)
+        flags = H.hard_status_read(work)
+    finally:
+        H.hard_batch_plan_destroy(plan)
+    zus = cells * steps / (ms * 1e-3)
+    log(f"  {ms / steps:.3f} ms/step, {zus / 1e9:.2f} G zu/s ({cells} cells)")
+    return {"value": zus, "unit": "zone-updates/s", "ms_per_step": ms / steps, "steps": steps,
+            "cells": cells, "problems": len(specs), "dtype": "f32 (internal energy, dt in f64)",
+            "launch": f"{steps} steps x 2 persistent launches replayed from one captured graph",
+            "achieved_hbm_gbs": bytes_step / (ms / steps * 1e-3) / 1e9, "status_flags": flags}
+
+
+def bench_adjoint(args, n=512, nsteps=200, every=20):
+    """Config-4 gradient: 2D 512^2 FP64 periodic, 200 steps, checkpoints every
+    20; gradient of J = dx^2/2 sum (rho_N - rho_T)^2 wrt the initial state."""
+    import time as _t
+
+    import paper_2509_08971_amd as H
+    from paper_2509_08971_amd import autograd as AG
+    import workloads
+
+    log(f"bench: adjoint {n}^2 fp64, {nsteps} steps, checkpoint every {every}")
+    g = H.make_grid((n, n), bc=(H.PERIODIC, H.PERIODIC))
+    U0 = torch.from_numpy(workloads.turbulent_box(n, ndim=2, seed=4)).to("cuda")
+    UT0 = torch.from_numpy(workloads.turbulent_box(n, ndim=2, seed=4,
+                                                   rho_perturb=(0.01, 5))).to("cuda")
+    dts, _ = AG.recorded_dts(U0, g, nsteps)
+    rhoT = AG.run_fixed(UT0, g, dts)[0]
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    AG.recorded_dts(U0, g, nsteps)
+    torch.cuda.synchronize()
+    fwd = _t.perf_counter() - t0
+    X = U0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    UN = AG.rollout(X, g, nsteps, 0.4, every)
+    J = 0.5 * (1.0 / n) ** 2 * ((UN[0] - rhoT) ** 2).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    full = _t.perf_counter() - t0
+    N = n * n
+    log(f"  forward {fwd * 1e3:.1f} ms, forward+gradient {full * 1e3:.1f} ms")
+    return {"forward_ms": fwd * 1e3, "gradient_ms": full * 1e3,
+            "gradient_over_forward": full / fwd,
+            "forward_zone_updates_per_s": N * nsteps / fwd,
+            "gradient_zone_updates_per_s": N * nsteps / full,
+            "workload": f"2D {n}^2 FP64 periodic, {nsteps} steps, checkpoints every {every}, "
+                        f"loss on final rho against a perturbed-start target",
+            "timing": "host wall clock around the whole forward / forward+backward"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -38,6 +174,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--only-main", action="store_true",
+                    help="time only the FP64 blast (skip the FP32 and batched lines)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -140,6 +278,22 @@ def main():
                      "stage2_ms": float(s2.mean())},
         "status_flags": flags,
     }
+
+    if not args.only_main:
+        extras = {}
+        try:
+            extras["fp32_512_turbulent"] = bench_fp32_turbulent(args)
+        except Exception as e:  # reported, never hidden
+            extras["fp32_512_turbulent"] = {"error": repr(e)}
+        try:
+            extras["batched_4096"] = bench_batched(args)
+        except Exception as e:
+            extras["batched_4096"] = {"error": repr(e)}
+        try:
+            extras["adjoint_512"] = bench_adjoint(args)
+        except Exception as e:
+            extras["adjoint_512"] = {"error": repr(e)}
+        out["beside_fp64_step"] = extras
 
     if not args.no_cpu_baseline:
         import oracle

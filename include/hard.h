@@ -184,6 +184,17 @@ hard_status_t hard_hydro_step_batched(const hard_batch_plan_t* plan, void* U, do
                                       double cfl, int32_t update_dt, void* work,
                                       size_t work_bytes, void* stream);
 
+/* Run every problem of the batch to its own t = t_end with its own CFL step
+ * (dt_p = min(CFL dt of problem p, t_end - t_p), the last step clipped; once
+ * a problem reaches t_end its further steps are exact no-ops with dt = 0).
+ * dt_dev is a device array of nprob doubles used as the step buffer.
+ * t_host / steps_host (host arrays of nprob, may be NULL) receive each
+ * problem's final time and step count.  Synchronises the stream once per 32
+ * steps; returns HARD_ERR_NONPHYSICAL if the status word has bits set. */
+hard_status_t hard_run_batched(const hard_batch_plan_t* plan, void* U, double cfl, double t_end,
+                               int64_t max_steps, double* dt_dev, double* t_host,
+                               int64_t* steps_host, void* work, size_t work_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Adjoint (vector-Jacobian product) of one step with dt held fixed.
  * ------------------------------------------------------------------------ */

@@ -21,6 +21,7 @@ __all__ = [
     "hard_hydro_step", "hard_hydro_stage", "hard_run", "hard_status_read", "hard_conservation_sums",
     "hard_batch_plan_create", "hard_batch_plan_destroy", "hard_batch_offsets",
     "hard_batch_workspace_bytes", "hard_cfl_dt_batched", "hard_hydro_step_batched",
+    "hard_run_batched", "batch_pack", "batch_unpack",
     "hard_adjoint_workspace_bytes", "hard_hydro_step_adjoint", "workspace",
     "PERIODIC", "OUTFLOW", "REFLECT", "F64", "F32",
 ]
@@ -87,6 +88,9 @@ def lib():
             "hard_cfl_dt_batched": [_vp, _vp, ctypes.c_double, _vp, _vp, _sz, _vp],
             "hard_hydro_step_batched": [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int32, _vp, _sz,
                                         _vp],
+            "hard_run_batched": [_vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int64, _vp,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                 _vp, _sz, _vp],
             "hard_adjoint_workspace_bytes": [_gp, ctypes.POINTER(_sz)],
             "hard_hydro_step_adjoint": [_gp, _vp, _vp, _vp, _vp, _sz, _vp],
         }
@@ -240,6 +244,38 @@ def hard_hydro_step_batched(plan, U, dt_dev, work, cfl=0.4, update_dt=True, stre
     _check(lib().hard_hydro_step_batched(plan, _ptr(U), _ptr(dt_dev), float(cfl),
                                          1 if update_dt else 0, _ptr(work), work.numel(),
                                          _stream(stream)))
+
+
+def hard_run_batched(plan, nprob, U, cfl, t_end, dt_dev, work, max_steps=10_000_000,
+                     stream=None):
+    """Run every problem to t_end; returns (t list, steps list)."""
+    t = (ctypes.c_double * nprob)()
+    s = (ctypes.c_int64 * nprob)()
+    _check(lib().hard_run_batched(plan, _ptr(U), float(cfl), float(t_end), int(max_steps),
+                                  _ptr(dt_dev), t, s, _ptr(work), work.numel(), _stream(stream)))
+    return list(t), list(s)
+
+
+def batch_pack(states, offsets, dtype=torch.float64, device="cuda"):
+    """Copy per-problem state arrays into one packed device buffer at the
+    plan's element offsets."""
+    total = int(offsets[-1])
+    U = torch.zeros(total, dtype=dtype, device=device)
+    for p, a in enumerate(states):
+        t = torch.as_tensor(a).reshape(-1)
+        U[offsets[p]:offsets[p] + t.numel()] = t.to(device=device, dtype=dtype)
+    return U
+
+
+def batch_unpack(U, offsets, shapes):
+    """Views of the packed buffer as per-problem state arrays."""
+    out = []
+    for p, shp in enumerate(shapes):
+        n = 1
+        for v in shp:
+            n *= int(v)
+        out.append(U[offsets[p]:offsets[p] + n].view(*shp))
+    return out
 
 
 # ---- adjoint ---------------------------------------------------------------

@@ -1,0 +1,85 @@
+"""Gradient of a final-time loss with respect to the initial state.
+
+HydroRollout.apply(U0, grid, nsteps, cfl, every) runs `nsteps` Heun steps
+with the CFL step of each state (the step sizes are recorded and then held
+fixed: the time-step selection is not differentiated), keeping the state
+every `every` steps.  Its backward pass walks the segments in reverse:
+it recomputes the states of one segment from its checkpoint with the
+recorded step sizes, then applies hard_hydro_step_adjoint step by step,
+last step first.  Every state update and every vector-Jacobian product runs
+in libhard's kernels; this module only sequences the calls and keeps the
+checkpoints.
+"""
+import torch
+
+from . import (hard_adjoint_workspace_bytes, hard_cfl_dt, hard_hydro_step,
+               hard_hydro_step_adjoint, hard_workspace_bytes, workspace)
+
+
+class HydroRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U0, grid, nsteps, cfl=0.4, every=20):
+        U = U0.detach().clone().contiguous()
+        dev = U.device
+        work = workspace(hard_workspace_bytes(grid), dev)
+        dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        dts = torch.zeros(nsteps, dtype=torch.float64, device=dev)
+        hard_cfl_dt(grid, U, cfl, dt, work)
+        ckpts = []
+        for n in range(nsteps):
+            if n % every == 0:
+                ckpts.append(U.clone())
+            dts[n:n + 1].copy_(dt)
+            hard_hydro_step(grid, U, dt, work, cfl=cfl, next_dt_dev=dt)
+        ctx.grid = grid
+        ctx.nsteps = nsteps
+        ctx.every = every
+        ctx.save_for_backward(dts, *ckpts)
+        return U
+
+    @staticmethod
+    def backward(ctx, lam_out):
+        dts, *ckpts = ctx.saved_tensors
+        grid, nsteps, every = ctx.grid, ctx.nsteps, ctx.every
+        lam = lam_out.detach().clone().contiguous()
+        dev = lam.device
+        work = workspace(hard_workspace_bytes(grid), dev)
+        awork = workspace(hard_adjoint_workspace_bytes(grid), dev)
+        for seg in reversed(range(len(ckpts))):
+            start = seg * every
+            end = min(start + every, nsteps)
+            states = [ckpts[seg]]
+            for n in range(start, end - 1):
+                U = states[-1].clone()
+                hard_hydro_step(grid, U, dts[n:n + 1], work)
+                states.append(U)
+            for n in reversed(range(start, end)):
+                hard_hydro_step_adjoint(grid, states[n - start], dts[n:n + 1], lam, awork)
+        return lam, None, None, None, None
+
+
+def rollout(U0, grid, nsteps, cfl=0.4, every=20):
+    """Differentiable nsteps-step run (see HydroRollout)."""
+    return HydroRollout.apply(U0, grid, nsteps, cfl, every)
+
+
+def recorded_dts(U0, grid, nsteps, cfl=0.4):
+    """The step sizes a rollout from U0 uses (device tensor of nsteps)."""
+    U = U0.detach().clone().contiguous()
+    work = workspace(hard_workspace_bytes(grid), U.device)
+    dt = torch.zeros(1, dtype=torch.float64, device=U.device)
+    dts = torch.zeros(nsteps, dtype=torch.float64, device=U.device)
+    hard_cfl_dt(grid, U, cfl, dt, work)
+    for n in range(nsteps):
+        dts[n:n + 1].copy_(dt)
+        hard_hydro_step(grid, U, dt, work, cfl=cfl, next_dt_dev=dt)
+    return dts, U
+
+
+def run_fixed(U0, grid, dts):
+    """Steps of the given (device) dt list from U0; returns the final state."""
+    U = U0.detach().clone().contiguous()
+    work = workspace(hard_workspace_bytes(grid), U.device)
+    for n in range(dts.numel()):
+        hard_hydro_step(grid, U, dts[n:n + 1], work)
+    return U

@@ -1,25 +1,630 @@
-// Batched step: placeholder entry points until the batched kernels land.
+// Batched Heun step: thousands of independent 1D/2D/3D problems, each with
+// its own grid, time step and CFL reduction, packed into one buffer.
+//
+// The plan turns every problem into tiles of the kernel's tile shape and
+// lays all tiles of all problems out as one work list, most expensive tile
+// first (longest-processing-time order).  Each stage is one persistent
+// launch: a grid sized to the machine pulls tiles from an atomic work
+// counter, runs the same tile body as the single-grid kernel
+// (stage_tile.hpp), and, in stage 2, folds the tile's CFL max into its
+// problem's slot; the last tile of a problem turns that slot into the
+// problem's next dt.  The last workgroup to run out of work re-arms the
+// counter, so the launch needs no memset and can be captured in a graph.
+// 1D and 2D problems share one launch; 3D problems (heavier tiles, more
+// registers) get their own.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "../../include/hard.h"
 #include "api_internal.hpp"
+#include "hydro_device.hpp"
+#include "launch.hpp"
+#include "stage_tile.hpp"
+
+namespace hard {
+
+struct BatchProblem {
+  long long offset;  // element offset of the problem's state in the packed buffer
+  int n[3];
+  int ndim;
+  int bc[3][2];
+  double dx[3];
+  double inv_dx[3];
+  int tiles_x, tiles_y, nchunk, ntiles;
+};
+
+struct WorkItem {
+  int prob;
+  int tile;
+};
+
+struct BatchQueue {
+  unsigned next;  // next work item to hand out
+  unsigned done;  // workgroups that found the list empty
+  unsigned pad[2];
+};
+
+struct BatchArgs {
+  const void* src;
+  const void* un;
+  void* dst;
+  const BatchProblem* probs;
+  const WorkItem* items;
+  int nitems;
+  double* dt;                    // per-problem dt (read; written by stage 2 when update_dt)
+  unsigned long long* smax;      // per-problem CFL slot
+  unsigned* cnt;                 // per-problem finished-tile counter
+  BatchQueue* q;
+  Control* ctl;                  // status bits
+  double gamma;
+  double cfl;
+  int update_dt;
+  int cz;
+};
+
+constexpr int BT = 256;  // threads per workgroup of the batched kernels
+
+// Tile shapes (x by y) selectable for 2D problems (256 threads each).
+constexpr int kTiles2D[3][2] = {{16, 16}, {32, 8}, {8, 32}};
+
+// Tile-level finish: status bits to the control block, CFL max to the
+// problem's slot; the last tile of the problem writes its dt.
+__device__ __forceinline__ void tile_finish(unsigned flags, double smax, bool do_cfl,
+                                            const BatchArgs& a, int p, int ntiles) {
+  constexpr int NW = BT / 64;
+  __shared__ double red_s[NW];
+  __shared__ unsigned red_f[NW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  flags = wave_or(flags);
+  if (do_cfl) smax = wave_max(smax);
+  if (lane == 0) {
+    red_f[w] = flags;
+    red_s[w] = smax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned f = 0;
+    double s = 0.0;
+    for (int i = 0; i < NW; ++i) {
+      f |= red_f[i];
+      s = fmax(s, red_s[i]);
+    }
+    if (f) atomicOr(&a.ctl->flags, f);
+    if (do_cfl) {
+      atomicMax(&a.smax[p], (unsigned long long)__double_as_longlong(s));
+      __threadfence();
+      unsigned prev = atomicAdd(&a.cnt[p], 1u);
+      if (prev == (unsigned)ntiles - 1) {
+        __threadfence();
+        unsigned long long bits = atomicAdd(&a.smax[p], 0ull);
+        a.dt[p] = a.cfl / __longlong_as_double((long long)bits);
+        atomicExch(&a.smax[p], 0ull);
+        atomicExch(&a.cnt[p], 0u);
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ TileArgs tile_args(const BatchArgs& a, const BatchProblem& P, int wsize) {
+  TileArgs t;
+  const char* s = static_cast<const char*>(a.src) + P.offset * wsize;
+  const char* u = static_cast<const char*>(a.un) + P.offset * wsize;
+  char* d = static_cast<char*>(a.dst) + P.offset * wsize;
+  t.src = s;
+  t.un = u;
+  t.dst = d;
+  for (int k = 0; k < 3; ++k) {
+    t.n[k] = P.n[k];
+    t.bc[k][0] = P.bc[k][0];
+    t.bc[k][1] = P.bc[k][1];
+    t.dx[k] = P.dx[k];
+    t.inv_dx[k] = P.inv_dx[k];
+  }
+  t.gamma = a.gamma;
+  return t;
+}
+
+// Pull the next work item (one per workgroup); -1 when the list is empty.
+__device__ __forceinline__ int next_item(const BatchArgs& a) {
+  __shared__ int item_s;
+  __syncthreads();  // every thread has read the previous item
+  if (threadIdx.x == 0) item_s = (int)atomicAdd(&a.q->next, 1u);
+  __syncthreads();
+  int it = item_s;
+  return it < a.nitems ? it : -1;
+}
+
+__device__ __forceinline__ void queue_exit(const BatchArgs& a) {
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(&a.q->done, 1u);
+    if (prev == gridDim.x - 1) {
+      // every workgroup has drawn its last item: re-arm for the next launch
+      atomicExch(&a.q->next, 0u);
+      atomicExch(&a.q->done, 0u);
+    }
+  }
+}
+
+template <typename R, int STAGE, int TS>
+__global__ __launch_bounds__(BT) void batched_stage_12(BatchArgs a) {
+  constexpr int TX2 = kTiles2D[TS][0], TY2 = kTiles2D[TS][1];
+  constexpr int L1 = TileShape<1, R, BT - 1, 1>::lds_elems;
+  constexpr int L2 = TileShape<2, R, TX2, TY2>::lds_elems;
+  __shared__ R lds[L1 > L2 ? L1 : L2];
+  const bool do_cfl = STAGE == 2 && a.update_dt;
+  for (int it = next_item(a); it >= 0; it = next_item(a)) {
+    const WorkItem w = a.items[it];
+    const BatchProblem P = a.probs[w.prob];
+    TileArgs t = tile_args(a, P, sizeof(R));
+    t.dt = a.dt[w.prob];
+    t.z0 = 0;
+    t.z1 = 1;
+    t.fuse_cfl = do_cfl;
+    unsigned flags = 0;
+    double smax = 0.0;
+    if (P.ndim == 1) {
+      t.x0 = w.tile * (BT - 1);
+      t.y0 = 0;
+      run_tile<1, R, STAGE, BT - 1, 1, BT>(t, lds, flags, smax);
+    } else {
+      t.x0 = (w.tile % P.tiles_x) * TX2;
+      t.y0 = (w.tile / P.tiles_x) * TY2;
+      run_tile<2, R, STAGE, TX2, TY2>(t, lds, flags, smax);
+    }
+    tile_finish(flags, smax, do_cfl, a, w.prob, P.ntiles);
+  }
+  queue_exit(a);
+}
+
+template <typename R, int STAGE, int TS>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 1, 8)))
+void batched_stage_3(BatchArgs a) {
+  constexpr int TX = kTiles2D[TS][0], TY = kTiles2D[TS][1];
+  __shared__ R lds[TileShape<3, R, TX, TY>::lds_elems];
+  const bool do_cfl = STAGE == 2 && a.update_dt;
+  for (int it = next_item(a); it >= 0; it = next_item(a)) {
+    const WorkItem w = a.items[it];
+    const BatchProblem P = a.probs[w.prob];
+    TileArgs t = tile_args(a, P, sizeof(R));
+    t.dt = a.dt[w.prob];
+    int tt = w.tile;
+    const int txi = tt % P.tiles_x;
+    tt /= P.tiles_x;
+    const int tyi = tt % P.tiles_y;
+    const int chunk = tt / P.tiles_y;
+    t.x0 = txi * TX;
+    t.y0 = tyi * TY;
+    t.z0 = chunk * a.cz;
+    t.z1 = min(t.z0 + a.cz, P.n[2]);
+    t.fuse_cfl = do_cfl;
+    unsigned flags = 0;
+    double smax = 0.0;
+    run_tile<3, R, STAGE, TX, TY>(t, lds, flags, smax);
+    tile_finish(flags, smax, do_cfl, a, w.prob, P.ntiles);
+  }
+  queue_exit(a);
+}
+
+// Per-problem CFL dt of the current state (standalone), one tile per item.
+template <typename R>
+__global__ __launch_bounds__(BT) void batched_cfl(BatchArgs a, int tile_cells_x, int tile_cells_y) {
+  for (int it = next_item(a); it >= 0; it = next_item(a)) {
+    const WorkItem w = a.items[it];
+    const BatchProblem P = a.probs[w.prob];
+    const R* U = reinterpret_cast<const R*>(static_cast<const char*>(a.src) + P.offset * sizeof(R));
+    const long long N = (long long)P.n[0] * P.n[1] * P.n[2];
+    int tx_cells = P.ndim == 1 ? BT - 1 : tile_cells_x;
+    int ty_cells = P.ndim == 1 ? 1 : tile_cells_y;
+    int tt = w.tile;
+    const int txi = tt % P.tiles_x;
+    tt /= P.tiles_x;
+    const int tyi = tt % P.tiles_y;
+    const int chunk = tt / P.tiles_y;
+    const int z0 = P.ndim == 3 ? chunk * a.cz : 0;
+    const int z1 = P.ndim == 3 ? min(z0 + a.cz, P.n[2]) : 1;
+    double smax = 0.0;
+    unsigned flags = 0;
+    const int tid = threadIdx.x;
+    const int gx = txi * tx_cells + tid % tx_cells, gy = tyi * ty_cells + tid / tx_cells;
+    if (threadIdx.x < tx_cells * ty_cells && gx < P.n[0] && gy < P.n[1]) {
+      for (int z = z0; z < z1; ++z) {
+        long long c = ((long long)z * P.n[1] + gy) * P.n[0] + gx;
+        double Ud[5];
+        R Ur[5], W[5];
+        const int NV = P.ndim + 2;
+        for (int v = 0; v < 5; ++v) {
+          Ur[v] = v < NV ? U[v * N + c] : R(0);
+          Ud[v] = (double)Ur[v];
+        }
+        if (P.ndim == 1) {
+          to_primitive<R, 1>(Ur, W, a.gamma - 1.0);
+          flags |= cell_flags<R, 3>(Ur, W[2]);
+          smax = fmax(smax, signal_sum<1>(Ud, P.dx, a.gamma));
+        } else if (P.ndim == 2) {
+          to_primitive<R, 2>(Ur, W, a.gamma - 1.0);
+          flags |= cell_flags<R, 4>(Ur, W[3]);
+          smax = fmax(smax, signal_sum<2>(Ud, P.dx, a.gamma));
+        } else {
+          to_primitive<R, 3>(Ur, W, a.gamma - 1.0);
+          flags |= cell_flags<R, 5>(Ur, W[4]);
+          smax = fmax(smax, signal_sum<3>(Ud, P.dx, a.gamma));
+        }
+      }
+    }
+    tile_finish(flags, smax, true, a, w.prob, P.ntiles);
+  }
+  queue_exit(a);
+}
+
+// Per-problem time control of hard_run_batched: clip dt so each problem
+// lands on t_end, advance its t, and turn its steps after the end into dt = 0
+// (exact no-ops).  `active` counts the problems that took a real step.
+__global__ void batched_time_control(int nprob, double* dt, double* t, long long* steps,
+                                     double t_end, long long max_steps, unsigned* active) {
+#pragma clang fp contract(off)
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  double tp = t[p];
+  long long s = steps[p];
+  if (!(tp < t_end * (1.0 - 1e-14)) || s >= max_steps) {
+    dt[p] = 0.0;
+    return;
+  }
+  double d = dt[p];
+  if (d > t_end - tp) d = t_end - tp;
+  dt[p] = d;
+  t[p] = tp + d;
+  steps[p] = s + 1;
+  atomicAdd(active, 1u);
+}
+
+__global__ void batched_run_clear(int nprob, double* t, long long* steps, unsigned* active) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0) *active = 0u;
+  if (p < nprob) {
+    t[p] = 0.0;
+    steps[p] = 0;
+  }
+}
+
+__global__ void counter_clear(unsigned* c) {
+  if (threadIdx.x == 0) *c = 0u;
+}
+
+}  // namespace hard
 
 using namespace hard;
 
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct hard_batch_plan {
+  int nprob = 0;
+  int dtype = 0;
+  double gamma = 0;
+  int wsize = 8;
+  int tile2d = 0;  // index into kTiles2D for 2D and 3D problems (x-y tile)
+  int cz = 32;     // z planes per 3D work item
+  std::vector<int64_t> offsets;
+  long long total_elems = 0;
+  int nitems12 = 0, nitems3 = 0;
+  BatchProblem* d_probs = nullptr;
+  WorkItem* d_items12 = nullptr;
+  WorkItem* d_items3 = nullptr;
+  int grid12 = 0, grid3 = 0;
+  // workspace layout
+  size_t ws_ctl = 0, ws_q12 = 0, ws_q3 = 0, ws_active = 0, ws_smax = 0, ws_cnt = 0, ws_t = 0,
+         ws_steps = 0, ws_stage = 0, ws_total = 0;
+};
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Tile choices from a tune cache: lines "tile2d_f32 = 32x8", "tile2d_f64 = 16x16", "cz = 32".
+static void read_tune_cache(const char* path, int dtype, int* tile2d, int* cz) {
+  if (!path) return;
+  std::ifstream f(path);
+  std::string line;
+  const std::string key = dtype == HARD_F64 ? "tile2d_f64" : "tile2d_f32";
+  while (std::getline(f, line)) {
+    std::istringstream ss(line);
+    std::string k, eq, v;
+    if (!(ss >> k >> eq >> v) || eq != "=") continue;
+    if (k == key) {
+      int x = 0, y = 0;
+      if (std::sscanf(v.c_str(), "%dx%d", &x, &y) == 2)
+        for (int i = 0; i < 3; ++i)
+          if (kTiles2D[i][0] == x && kTiles2D[i][1] == y) *tile2d = i;
+    } else if (k == "cz") {
+      int c = std::atoi(v.c_str());
+      if (c > 0 && c <= 4096) *cz = c;
+    }
+  }
+}
+
+static hard_status_t batch_common(const hard_batch_plan_t* P, const void* U, const double* dt,
+                                  void* work, size_t work_bytes, BatchArgs* a) {
+  if (!P) return fail(HARD_ERR_INVALID_ARG, "plan is NULL");
+  hard_status_t st;
+  if ((st = check_ptr(U, 256, "U"))) return st;
+  if ((st = check_ptr(dt, 8, "dt_dev"))) return st;
+  if ((st = check_work(work, work_bytes, P->ws_total))) return st;
+  char* wb = static_cast<char*>(work);
+  std::memset(a, 0, sizeof *a);
+  a->probs = P->d_probs;
+  a->dt = const_cast<double*>(dt);
+  a->smax = reinterpret_cast<unsigned long long*>(wb + P->ws_smax);
+  a->cnt = reinterpret_cast<unsigned*>(wb + P->ws_cnt);
+  a->ctl = reinterpret_cast<Control*>(wb + P->ws_ctl);
+  a->gamma = P->gamma;
+  a->cz = P->cz;
+  return HARD_OK;
+}
+
+template <typename R, int STAGE>
+static hipError_t launch_batched_stage(const hard_batch_plan_t* P, BatchArgs a, char* wb,
+                                       hipStream_t s) {
+  if (P->nitems12) {
+    BatchArgs b = a;
+    b.items = P->d_items12;
+    b.nitems = P->nitems12;
+    b.q = reinterpret_cast<BatchQueue*>(wb + P->ws_q12);
+    switch (P->tile2d) {
+      case 0: hipLaunchKernelGGL((batched_stage_12<R, STAGE, 0>), dim3(P->grid12), dim3(BT), 0, s, b); break;
+      case 1: hipLaunchKernelGGL((batched_stage_12<R, STAGE, 1>), dim3(P->grid12), dim3(BT), 0, s, b); break;
+      default: hipLaunchKernelGGL((batched_stage_12<R, STAGE, 2>), dim3(P->grid12), dim3(BT), 0, s, b); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (P->nitems3) {
+    BatchArgs b = a;
+    b.items = P->d_items3;
+    b.nitems = P->nitems3;
+    b.q = reinterpret_cast<BatchQueue*>(wb + P->ws_q3);
+    switch (P->tile2d) {
+      case 0: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 0>), dim3(P->grid3), dim3(BT), 0, s, b); break;
+      case 1: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 1>), dim3(P->grid3), dim3(BT), 0, s, b); break;
+      default: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 2>), dim3(P->grid3), dim3(BT), 0, s, b); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 extern "C" {
-hard_status_t hard_batch_plan_create(const hard_grid_t*, int32_t, const char*, hard_batch_plan_t** out) {
-  if (out) *out = nullptr;
-  return fail(HARD_ERR_UNSUPPORTED, "batched step not built");
+
+hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
+                                     const char* tune_cache, hard_batch_plan_t** out) {
+  if (!out) return fail(HARD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!grids || nprob < 1) return fail(HARD_ERR_INVALID_ARG, "need at least one grid");
+  auto* P = new hard_batch_plan;
+  P->nprob = nprob;
+  P->dtype = grids[0].dtype;
+  P->gamma = grids[0].gamma;
+  P->wsize = P->dtype == HARD_F64 ? 8 : 4;
+  P->tile2d = P->dtype == HARD_F64 ? 0 : 1;
+  read_tune_cache(tune_cache, P->dtype, &P->tile2d, &P->cz);
+  const int TX = kTiles2D[P->tile2d][0], TY = kTiles2D[P->tile2d][1];
+  std::vector<BatchProblem> probs(nprob);
+  struct Cost { double c; WorkItem w; };
+  std::vector<Cost> c12, c3;
+  P->offsets.resize(nprob + 1);
+  long long off = 0;
+  for (int p = 0; p < nprob; ++p) {
+    Grid G;
+    hard_status_t st = check_grid(&grids[p], &G);
+    if (st) {
+      delete P;
+      return fail(st, "grid %d: %s", p, hard_last_error());
+    }
+    if (G.dtype != P->dtype || G.gamma != P->gamma) {
+      delete P;
+      return fail(HARD_ERR_INVALID_ARG, "grid %d: all grids must share dtype and gamma", p);
+    }
+    BatchProblem& B = probs[p];
+    B.offset = off;
+    P->offsets[p] = off;
+    B.ndim = G.ndim;
+    for (int d = 0; d < 3; ++d) {
+      B.n[d] = G.n[d];
+      B.bc[d][0] = G.bc[d][0];
+      B.bc[d][1] = G.bc[d][1];
+      B.dx[d] = G.dx[d];
+      B.inv_dx[d] = G.inv_dx[d];
+    }
+    if (G.ndim == 1) {
+      B.tiles_x = (G.n[0] + BT - 2) / (BT - 1);  // 255-cell tiles: 256 faces
+      B.tiles_y = 1;
+      B.nchunk = 1;
+    } else {
+      B.tiles_x = (G.n[0] + TX - 1) / TX;
+      B.tiles_y = (G.n[1] + TY - 1) / TY;
+      B.nchunk = G.ndim == 3 ? (G.n[2] + P->cz - 1) / P->cz : 1;
+    }
+    B.ntiles = B.tiles_x * B.tiles_y * B.nchunk;
+    // tile cost ~ cells x faces per cell
+    double cells = G.ndim == 1 ? BT - 1 : (double)TX * TY * (G.ndim == 3 ? P->cz : 1);
+    double cost = cells * (1.0 + 1.1 * G.ndim);
+    for (int t = 0; t < B.ntiles; ++t) (G.ndim == 3 ? c3 : c12).push_back({cost, {p, t}});
+    // keep every problem 256-byte aligned
+    long long elems = (long long)G.nvar * G.ncell;
+    long long align = 256 / P->wsize;
+    off += (elems + align - 1) / align * align;
+  }
+  P->offsets[nprob] = off;
+  P->total_elems = off;
+  auto lpt = [](std::vector<Cost>& v) {
+    std::stable_sort(v.begin(), v.end(), [](const Cost& a, const Cost& b) { return a.c > b.c; });
+  };
+  lpt(c12);
+  lpt(c3);
+  std::vector<WorkItem> i12, i3;
+  for (auto& c : c12) i12.push_back(c.w);
+  for (auto& c : c3) i3.push_back(c.w);
+  P->nitems12 = (int)i12.size();
+  P->nitems3 = (int)i3.size();
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    ncu = 256;
+  P->grid12 = std::max(1, std::min(P->nitems12, ncu * 8));
+  P->grid3 = std::max(1, std::min(P->nitems3, ncu * 3));
+  hipError_t e;
+  if ((e = hipMalloc(&P->d_probs, sizeof(BatchProblem) * nprob)) != hipSuccess ||
+      (e = hipMalloc(&P->d_items12, sizeof(WorkItem) * std::max(1, P->nitems12))) != hipSuccess ||
+      (e = hipMalloc(&P->d_items3, sizeof(WorkItem) * std::max(1, P->nitems3))) != hipSuccess) {
+    hard_batch_plan_destroy(P);
+    return hip_fail(e, "hard_batch_plan_create alloc");
+  }
+  if ((e = hipMemcpy(P->d_probs, probs.data(), sizeof(BatchProblem) * nprob, hipMemcpyHostToDevice)) != hipSuccess ||
+      (P->nitems12 && (e = hipMemcpy(P->d_items12, i12.data(), sizeof(WorkItem) * P->nitems12, hipMemcpyHostToDevice)) != hipSuccess) ||
+      (P->nitems3 && (e = hipMemcpy(P->d_items3, i3.data(), sizeof(WorkItem) * P->nitems3, hipMemcpyHostToDevice)) != hipSuccess)) {
+    hard_batch_plan_destroy(P);
+    return hip_fail(e, "hard_batch_plan_create copy");
+  }
+  // workspace: control | queue 1D/2D | queue 3D | run counter | smax[nprob] |
+  // cnt[nprob] | t[nprob] | steps[nprob] | stage state
+  P->ws_ctl = 0;
+  P->ws_q12 = 256;
+  P->ws_q3 = 512;
+  P->ws_active = 768;
+  P->ws_smax = 1024;
+  P->ws_cnt = P->ws_smax + al256(sizeof(unsigned long long) * nprob);
+  P->ws_t = P->ws_cnt + al256(sizeof(unsigned) * nprob);
+  P->ws_steps = P->ws_t + al256(sizeof(double) * nprob);
+  P->ws_stage = P->ws_steps + al256(sizeof(long long) * nprob);
+  P->ws_total = P->ws_stage + al256((size_t)P->total_elems * P->wsize);
+  *out = P;
+  return ok();
 }
-hard_status_t hard_batch_plan_destroy(hard_batch_plan_t*) { return ok(); }
-hard_status_t hard_batch_offsets(const hard_batch_plan_t*, int64_t*) {
-  return fail(HARD_ERR_UNSUPPORTED, "batched step not built");
+
+hard_status_t hard_batch_plan_destroy(hard_batch_plan_t* P) {
+  if (!P) return ok();
+  if (P->d_probs) (void)hipFree(P->d_probs);
+  if (P->d_items12) (void)hipFree(P->d_items12);
+  if (P->d_items3) (void)hipFree(P->d_items3);
+  delete P;
+  return ok();
 }
-hard_status_t hard_batch_workspace_bytes(const hard_batch_plan_t*, size_t*) {
-  return fail(HARD_ERR_UNSUPPORTED, "batched step not built");
+
+hard_status_t hard_batch_offsets(const hard_batch_plan_t* P, int64_t* offsets) {
+  if (!P || !offsets) return fail(HARD_ERR_INVALID_ARG, "plan and offsets must not be NULL");
+  std::memcpy(offsets, P->offsets.data(), sizeof(int64_t) * (P->nprob + 1));
+  return ok();
 }
-hard_status_t hard_cfl_dt_batched(const hard_batch_plan_t*, const void*, double, double*, void*, size_t, void*) {
-  return fail(HARD_ERR_UNSUPPORTED, "batched step not built");
+
+hard_status_t hard_batch_workspace_bytes(const hard_batch_plan_t* P, size_t* bytes) {
+  if (!P || !bytes) return fail(HARD_ERR_INVALID_ARG, "plan and bytes must not be NULL");
+  *bytes = P->ws_total;
+  return ok();
 }
-hard_status_t hard_hydro_step_batched(const hard_batch_plan_t*, void*, double*, double, int32_t, void*, size_t, void*) {
-  return fail(HARD_ERR_UNSUPPORTED, "batched step not built");
+
+hard_status_t hard_cfl_dt_batched(const hard_batch_plan_t* P, const void* U, double cfl,
+                                  double* dt_dev, void* work, size_t work_bytes, void* stream) {
+  BatchArgs a;
+  hard_status_t st = batch_common(P, U, dt_dev, work, work_bytes, &a);
+  if (st) return st;
+  if ((st = check_cfl(cfl))) return st;
+  a.src = U;
+  a.cfl = cfl;
+  char* wb = static_cast<char*>(work);
+  hipStream_t s = (hipStream_t)stream;
+  const int TX = kTiles2D[P->tile2d][0], TY = kTiles2D[P->tile2d][1];
+  for (int pass = 0; pass < 2; ++pass) {
+    int n = pass == 0 ? P->nitems12 : P->nitems3;
+    if (!n) continue;
+    BatchArgs b = a;
+    b.items = pass == 0 ? P->d_items12 : P->d_items3;
+    b.nitems = n;
+    b.q = reinterpret_cast<BatchQueue*>(wb + (pass == 0 ? P->ws_q12 : P->ws_q3));
+    int grid = pass == 0 ? P->grid12 : P->grid3;
+    if (P->dtype == HARD_F64)
+      hipLaunchKernelGGL(batched_cfl<double>, dim3(grid), dim3(BT), 0, s, b, TX, TY);
+    else
+      hipLaunchKernelGGL(batched_cfl<float>, dim3(grid), dim3(BT), 0, s, b, TX, TY);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "hard_cfl_dt_batched");
+  }
+  return ok();
 }
+
+hard_status_t hard_hydro_step_batched(const hard_batch_plan_t* P, void* U, double* dt_dev,
+                                      double cfl, int32_t update_dt, void* work,
+                                      size_t work_bytes, void* stream) {
+  BatchArgs a;
+  hard_status_t st = batch_common(P, U, dt_dev, work, work_bytes, &a);
+  if (st) return st;
+  if (update_dt && (st = check_cfl(cfl))) return st;
+  char* wb = static_cast<char*>(work);
+  void* U1 = wb + P->ws_stage;
+  hipStream_t s = (hipStream_t)stream;
+  a.cfl = cfl;
+  a.update_dt = 0;
+  a.src = U;
+  a.un = U;
+  a.dst = U1;
+  hipError_t e = P->dtype == HARD_F64 ? launch_batched_stage<double, 1>(P, a, wb, s)
+                                      : launch_batched_stage<float, 1>(P, a, wb, s);
+  if (e != hipSuccess) return hip_fail(e, "hard_hydro_step_batched stage 1");
+  a.src = U1;
+  a.un = U;
+  a.dst = U;
+  a.update_dt = update_dt ? 1 : 0;
+  e = P->dtype == HARD_F64 ? launch_batched_stage<double, 2>(P, a, wb, s)
+                           : launch_batched_stage<float, 2>(P, a, wb, s);
+  if (e != hipSuccess) return hip_fail(e, "hard_hydro_step_batched stage 2");
+  return ok();
 }
+
+hard_status_t hard_run_batched(const hard_batch_plan_t* P, void* U, double cfl, double t_end,
+                               int64_t max_steps, double* dt_dev, double* t_host,
+                               int64_t* steps_host, void* work, size_t work_bytes, void* stream) {
+  BatchArgs a;
+  hard_status_t st = batch_common(P, U, dt_dev, work, work_bytes, &a);
+  if (st) return st;
+  if ((st = check_cfl(cfl))) return st;
+  if (!(std::isfinite(t_end) && t_end > 0.0)) return fail(HARD_ERR_INVALID_ARG, "t_end must be finite and > 0");
+  if (max_steps < 1) return fail(HARD_ERR_INVALID_ARG, "max_steps must be >= 1");
+  char* wb = static_cast<char*>(work);
+  hipStream_t s = (hipStream_t)stream;
+  double* t = reinterpret_cast<double*>(wb + P->ws_t);
+  long long* steps = reinterpret_cast<long long*>(wb + P->ws_steps);
+  unsigned* active = reinterpret_cast<unsigned*>(wb + P->ws_active);
+  const int nb = (P->nprob + 255) / 256;
+  hipLaunchKernelGGL(batched_run_clear, dim3(nb), dim3(256), 0, s, P->nprob, t, steps, active);
+  if ((st = hard_cfl_dt_batched(P, U, cfl, dt_dev, work, work_bytes, stream))) return st;
+  const int batch = 32;
+  for (;;) {
+    hipLaunchKernelGGL(counter_clear, dim3(1), dim3(64), 0, s, active);
+    for (int i = 0; i < batch; ++i) {
+      hipLaunchKernelGGL(batched_time_control, dim3(nb), dim3(256), 0, s, P->nprob, dt_dev, t, steps,
+                         t_end, (long long)max_steps, active);
+      if ((st = hard_hydro_step_batched(P, U, dt_dev, cfl, 1, work, work_bytes, stream))) return st;
+    }
+    hipError_t e;
+    unsigned act = 0;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hard_run_batched sync");
+    if ((e = hipMemcpy(&act, active, sizeof act, hipMemcpyDeviceToHost)) != hipSuccess)
+      return hip_fail(e, "hard_run_batched read");
+    if (act == 0) break;
+  }
+  hipError_t e;
+  unsigned flags = 0;
+  if ((t_host && (e = hipMemcpy(t_host, t, sizeof(double) * P->nprob, hipMemcpyDeviceToHost)) != hipSuccess) ||
+      (steps_host && (e = hipMemcpy(steps_host, steps, sizeof(long long) * P->nprob, hipMemcpyDeviceToHost)) != hipSuccess) ||
+      (e = hipMemcpy(&flags, &a.ctl->flags, sizeof flags, hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "hard_run_batched read");
+  if (flags) return fail(HARD_ERR_NONPHYSICAL, "non-physical state (flags 0x%x)", flags);
+  return ok();
+}
+
+}  // extern "C"

@@ -1,21 +1,7 @@
-// Fused Heun-stage kernel: primitive recovery -> MUSCL-minmod -> HLLC on
-// every face -> flux difference -> stage combine (HARD paper section 2.2.2:
-// finite-volume face difference and Heun's Butcher tableau in Shu-Osher form).
-//
-// One workgroup owns a TX x TY tile of cells in the x-y plane and walks a
-// chunk of z planes (3D).  For each plane it
-//   1. builds the primitive states of the tile plus a two-cell x/y halo in
-//      LDS (interior cells come from a per-thread register window along z,
-//      halo cells are loaded and converted here; ghost cells are produced by
-//      index remapping, so no ghost arrays exist in HBM),
-//   2. computes every x and y face flux of the tile once, into LDS,
-//   3. computes the z face above each cell from the register window (the face
-//      below was computed in the previous plane),
-//   4. forms L(U) and the stage combine, and stores the cell once.
-// HBM traffic per stage is therefore one read of the stencil source, one
-// write of the result (plus one read of U^n in stage 2); halo re-reads hit
-// the L2 of the XCD that owns the neighbouring tiles.  2D grids use one plane
-// (no z walk), 1D grids one row.
+// Single-grid Heun-stage kernel: one workgroup per (x-y tile, z chunk), the
+// tile body in stage_tile.hpp.  HBM traffic per stage is one read of the
+// stencil source and one write of the result (plus one read of U^n in stage
+// 2); halo re-reads hit the L2 of the XCD that owns the neighbouring tiles.
 //
 // Stage 2 optionally folds the CFL signal-speed max of the new state into
 // the same pass (wave64 shuffle max -> LDS -> one atomicMax per workgroup;
@@ -23,270 +9,54 @@
 
 #include "hydro_device.hpp"
 #include "launch.hpp"
+#include "stage_tile.hpp"
 
 namespace hard {
 
+// Minimum waves per SIMD the register allocator must allow: 3 for the FP64
+// 3D kernels (their natural footprint sits just above the 168-VGPR limit of
+// 3 waves), no constraint otherwise.
 #ifndef HARD_STAGE_WAVES
-#define HARD_STAGE_WAVES 1
+#define HARD_STAGE_WAVES(NDIM, R) ((NDIM) == 3 && sizeof(R) == 8 ? 3 : 1)
 #endif
 
-template <int NDIM, typename R, int STAGE, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(HARD_STAGE_WAVES, 8)))
+template <int NDIM, typename R, int STAGE, int TX, int TY, int NTHR>
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(HARD_STAGE_WAVES(NDIM, R), 8)))
 void stage_kernel(StageArgs a) {
-  constexpr int NV = NDIM + 2;
-  constexpr int NT = TX * TY;
-  constexpr int OY = NDIM >= 2 ? 2 : 0;               // LDS row offset of the tile
-  constexpr int LX = TX + 4;
-  constexpr int LY = NDIM >= 2 ? TY + 4 : 1;
-  constexpr int LXY = LX * LY;
-  constexpr int NFX = (TX + 1) * TY;                  // x faces per plane
-  constexpr int NFY = NDIM >= 2 ? TX * (TY + 1) : 0;  // y faces per plane
-  constexpr int NF = NFX + NFY;
-  constexpr int NHALO = NDIM >= 2 ? 4 * (TX + TY) : 4;
-  static_assert(NDIM >= 2 || TY == 1, "1D tiles are one row");
-
-  // primitive states of the plane (tile + 2-cell x/y halo), variable-major
-  __shared__ R Ws[NV * LXY];
-  // in-plane face fluxes, variable-major; x faces first, then y faces
-  __shared__ R Fs[NV * NF];
-
-  const int tid = threadIdx.x;
-  const int tx = tid % TX, ty = tid / TX;
-  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-  const long long N = (long long)nx * ny * nz;
-
+  __shared__ R lds[TileShape<NDIM, R, TX, TY>::lds_elems];
   int L = xcd_tile(blockIdx.x, gridDim.x);
   const int tile_x = L % a.tiles_x;
   L /= a.tiles_x;
   const int tile_y = L % a.tiles_y;
   const int chunk = L / a.tiles_y;
-  const int x0 = tile_x * TX, y0 = tile_y * TY;
-  const int gx = x0 + tx, gy = y0 + ty;
-  const bool inside = gx < nx && gy < ny;
-  const int z0 = NDIM == 3 ? chunk * a.cz : 0;
-  const int z1 = NDIM == 3 ? min(z0 + a.cz, nz) : 1;
-
-  const R* __restrict__ src = static_cast<const R*>(a.src);
-  const R* __restrict__ un = static_cast<const R*>(a.un);
-  R* __restrict__ dst = static_cast<R*>(a.dst);
-  const double gm1 = a.gamma - 1.0;
-  const R gam = R(a.gamma);
-  const R inv_gm1 = R(1.0 / gm1);
-  const R dt = R(*a.dt);
-  const R idx0 = R(a.inv_dx[0]), idx1 = R(a.inv_dx[1]), idx2 = R(a.inv_dx[2]);
-
-  // this thread's column, clamped (and mirrored past reflecting walls) for
-  // the overhang of ragged tiles; such threads never store
-  bool fx_, fy_;
-  const int cx = remap(gx, nx, a.bc[0][0], a.bc[0][1], fx_);
-  const int cy = remap(gy, ny, a.bc[1][0], a.bc[1][1], fy_);
-  const long long col = (long long)cy * nx + cx;
-
+  TileArgs t;
+  t.src = a.src;
+  t.un = a.un;
+  t.dst = a.dst;
+  for (int d = 0; d < 3; ++d) {
+    t.n[d] = a.n[d];
+    t.bc[d][0] = a.bc[d][0];
+    t.bc[d][1] = a.bc[d][1];
+    t.dx[d] = a.dx[d];
+    t.inv_dx[d] = a.inv_dx[d];
+  }
+  t.gamma = a.gamma;
+  t.dt = *a.dt;
+  t.x0 = tile_x * TX;
+  t.y0 = tile_y * TY;
+  t.z0 = NDIM == 3 ? chunk * a.cz : 0;
+  t.z1 = NDIM == 3 ? min(t.z0 + a.cz, a.n[2]) : 1;
+  t.fuse_cfl = STAGE == 2 && a.fuse_cfl;
   unsigned flags = 0;
   double smax = 0.0;
-
-  auto zplane = [&](int q, bool& fz) -> long long {
-    int z = NDIM == 3 ? remap(q, nz, a.bc[2][0], a.bc[2][1], fz) : 0;
-    return (long long)z * nx * ny;
-  };
-  auto load_cons = [&](long long c, R* Uc) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Uc[v] = src[v * N + c];
-  };
-  // primitive state of this thread's column from conserved values
-  auto col_prim = [&](const R* Uc, bool fz, R* W) {
-    to_primitive<R, NDIM>(Uc, W, gm1);
-    if (fx_) W[1] = -W[1];
-    if (NDIM >= 2 && fy_) W[2] = -W[2];
-    if (NDIM == 3 && fz) W[3] = -W[3];
-  };
-
-  // z register window (3D): P0 = plane z, P1 = z+1, S0 = slope at z, Fm = flux
-  // through the face z-1/2 (variables in the order rho, u_z, u_x, u_y, p)
-  R P0[NV], P1[NV], S0[NV], Fm[NV];
-  // conserved values of this column at planes z and z+1 (each cell is loaded
-  // from memory once per stage; the combine uses them from registers)
-  R Ucur[NV], Uc1[NV];
-  if (NDIM < 3) load_cons(col, Ucur);
-  if (NDIM == 3) {
-    R Pm2[NV], Pm1[NV], Ut[NV];
-    bool fz;
-    long long zo;
-    zo = zplane(z0 - 2, fz); load_cons(zo + col, Ut); col_prim(Ut, fz, Pm2);
-    zo = zplane(z0 - 1, fz); load_cons(zo + col, Ut); col_prim(Ut, fz, Pm1);
-    zo = zplane(z0, fz);     load_cons(zo + col, Ucur); col_prim(Ucur, fz, P0);
-    zo = zplane(z0 + 1, fz); load_cons(zo + col, Uc1); col_prim(Uc1, fz, P1);
-    R WL[NV], WR[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      R d0 = Pm1[v] - Pm2[v], d1 = P0[v] - Pm1[v], d2 = P1[v] - P0[v];
-      R sm1 = minmod(d0, d1);
-      S0[v] = minmod(d1, d2);
-      WL[v] = Pm1[v] + R(0.5) * sm1;
-      WR[v] = P0[v] - R(0.5) * S0[v];
-    }
-    R A[NV], B[NV], Fn[NV];
-    A[0] = WL[0]; A[1] = WL[3]; A[2] = WL[1]; A[3] = WL[2]; A[4] = WL[4];
-    B[0] = WR[0]; B[1] = WR[3]; B[2] = WR[1]; B[3] = WR[2]; B[4] = WR[4];
-    hllc_ordered<R, NV>(A, B, gam, inv_gm1, Fn);
-    Fm[0] = Fn[0]; Fm[1] = Fn[2]; Fm[2] = Fn[3]; Fm[3] = Fn[1]; Fm[4] = Fn[4];
-  }
-
-  for (int z = z0; z < z1; ++z) {
-    // ---- 0. issue the z+2 plane's column load early
-    R Unext[NV];
-    bool fz_next = false;
-    if (NDIM == 3) {
-      long long zn = zplane(z + 2, fz_next);
-      load_cons(zn + col, Unext);
-    }
-    if (NDIM < 3) {
-      col_prim(Ucur, false, P0);
-    }
-    // ---- 1. primitives of plane z: interior from the window, halo loaded
-    for (int h = tid; h < NHALO; h += NT) {
-      int lx, ly;
-      if (NDIM >= 2) {
-        if (h < 4 * TY) {
-          int side = h / (2 * TY), r = h % (2 * TY);
-          ly = r / 2 + 2;
-          lx = side ? TX + 2 + (r % 2) : (r % 2);
-        } else {
-          int hh = h - 4 * TY;
-          int side = hh / (2 * TX), r = hh % (2 * TX);
-          lx = r % TX + 2;
-          ly = side ? TY + 2 + r / TX : r / TX;
-        }
-      } else {
-        ly = 0;
-        lx = h < 2 ? h : TX + h;
-      }
-      bool flx, fly = false, flz = false;
-      int qx = remap(x0 + lx - 2, nx, a.bc[0][0], a.bc[0][1], flx);
-      int qy = NDIM >= 2 ? remap(y0 + ly - 2, ny, a.bc[1][0], a.bc[1][1], fly) : 0;
-      long long c = zplane(z, flz) + (long long)qy * nx + qx;
-      R Uh[NV], Wh[NV];
-      load_cons(c, Uh);
-      to_primitive<R, NDIM>(Uh, Wh, gm1);
-      if (flx) Wh[1] = -Wh[1];
-      if (NDIM >= 2 && fly) Wh[2] = -Wh[2];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Ws[v * LXY + ly * LX + lx] = Wh[v];
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Ws[v * LXY + (ty + OY) * LX + tx + 2] = P0[v];
-    if (inside) flags |= cell_flags<R, NV>(Ucur, P0[NV - 1]);
-    __syncthreads();
-
-    // ---- 2. in-plane faces.  The normal velocity of a y face is variable
-    // slot 2 and its first transverse velocity slot 1: the swap is done in
-    // the LDS addresses, so one code path serves both axes.
-    for (int f = tid; f < NF; f += NT) {
-      int base, stride;
-      bool yface = f >= NFX;
-      if (!yface) {
-        int fxx = f % (TX + 1), fyy = f / (TX + 1);
-        base = (fyy + OY) * LX + fxx;
-        stride = 1;
-      } else {
-        int g = f - NFX;
-        int fxx = g % TX, fyy = g / TX;
-        base = fyy * LX + fxx + 2;
-        stride = LX;
-      }
-      int slot[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) slot[v] = v;
-      if (NDIM >= 2) {
-        slot[1] = yface ? 2 : 1;
-        slot[2] = yface ? 1 : 2;
-      }
-      R WL[NV], WR[NV], Fn[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const R* w = Ws + slot[v] * LXY + base;
-        muscl_pair(w[0], w[stride], w[2 * stride], w[3 * stride], WL[v], WR[v]);
-      }
-      hllc_ordered<R, NV>(WL, WR, gam, inv_gm1, Fn);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Fs[slot[v] * NF + f] = Fn[v];
-    }
-
-    // ---- 3. face z+1/2 from the register window
-    R Fp[NV];
-    R P2[NV];
-    if (NDIM == 3) {
-      col_prim(Unext, fz_next, P2);
-      R S1[NV], A[NV], B[NV], Fn[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        R d1 = P1[v] - P0[v], d2 = P2[v] - P1[v];
-        S1[v] = minmod(d1, d2);
-      }
-      // reorder to (rho, u_z, u_x, u_y, p)
-      const int perm[5] = {0, 3, 1, 2, 4};
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        int q = perm[v];
-        A[v] = P0[q] + R(0.5) * S0[q];
-        B[v] = P1[q] - R(0.5) * S1[q];
-      }
-      hllc_ordered<R, NV>(A, B, gam, inv_gm1, Fn);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Fp[perm[v]] = Fn[v];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) S0[v] = S1[v];
-    }
-    __syncthreads();
-
-    // ---- 4. flux difference and stage combine
-    if (inside) {
-      long long c = (long long)z * nx * ny + (long long)gy * nx + gx;
-      const int fxl = ty * (TX + 1) + tx;
-      const int fyl = NFX + ty * TX + tx;
-      R Out[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        R l = R(0) - (Fs[v * NF + fxl + 1] - Fs[v * NF + fxl]) * idx0;
-        if (NDIM >= 2) l = l - (Fs[v * NF + fyl + TX] - Fs[v * NF + fyl]) * idx1;
-        if (NDIM == 3) l = l - (Fp[v] - Fm[v]) * idx2;
-        if (STAGE == 1) {
-          Out[v] = Ucur[v] + dt * l;
-        } else {
-          R u0 = un[v * N + c];
-          Out[v] = R(0.5) * (u0 + (Ucur[v] + dt * l));
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) dst[v * N + c] = Out[v];
-      if (STAGE == 2 && a.fuse_cfl) {
-        double Ud[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) Ud[v] = (double)Out[v];
-        smax = fmax(smax, signal_sum<NDIM>(Ud, a.dx, a.gamma));
-      }
-    }
-
-    // ---- 5. slide the window
-    if (NDIM == 3) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        Fm[v] = Fp[v];
-        P0[v] = P1[v];
-        P1[v] = P2[v];
-        Ucur[v] = Uc1[v];
-        Uc1[v] = Unext[v];
-      }
-    }
-  }
-
-  block_finish<NT>(flags, smax, STAGE == 2 && a.fuse_cfl, a.ctl, a.cfl, a.next_dt);
+  run_tile<NDIM, R, STAGE, TX, TY, NTHR>(t, lds, flags, smax);
+  block_finish<NTHR>(flags, smax, STAGE == 2 && a.fuse_cfl, a.ctl, a.cfl, a.next_dt);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int NDIM, typename R, int TX, int TY>
+template <int NDIM, typename R, int TX, int TY, int NTHR = TX * TY>
 static hipError_t launch_stage_t(const StageArgs& a0, int stage, hipStream_t s) {
   StageArgs a = a0;
   a.tiles_x = (int)((a.n[0] + TX - 1) / TX);
@@ -298,11 +68,11 @@ static hipError_t launch_stage_t(const StageArgs& a0, int stage, hipStream_t s) 
   } else {
     a.cz = 1;
   }
-  dim3 grid((unsigned)(a.tiles_x * a.tiles_y * nchunk)), block(TX * TY);
+  dim3 grid((unsigned)(a.tiles_x * a.tiles_y * nchunk)), block(NTHR);
   if (stage == 1)
-    hipLaunchKernelGGL((stage_kernel<NDIM, R, 1, TX, TY>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<NDIM, R, 1, TX, TY, NTHR>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((stage_kernel<NDIM, R, 2, TX, TY>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<NDIM, R, 2, TX, TY, NTHR>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 
@@ -317,13 +87,13 @@ static hipError_t launch_stage_t(const StageArgs& a0, int stage, hipStream_t s) 
 hipError_t launch_stage(int ndim, int dtype, const StageArgs& a, int stage, hipStream_t s) {
   if (dtype == 0) {
     switch (ndim) {
-      case 1: return launch_stage_t<1, double, 256, 1>(a, stage, s);
+      case 1: return launch_stage_t<1, double, 255, 1, 256>(a, stage, s);
       case 2: return launch_stage_t<2, double, 16, 16>(a, stage, s);
       case 3: return launch_stage_t<3, double, HARD_TILE64>(a, stage, s);
     }
   } else {
     switch (ndim) {
-      case 1: return launch_stage_t<1, float, 256, 1>(a, stage, s);
+      case 1: return launch_stage_t<1, float, 255, 1, 256>(a, stage, s);
       case 2: return launch_stage_t<2, float, 32, 8>(a, stage, s);
       case 3: return launch_stage_t<3, float, HARD_TILE32>(a, stage, s);
     }

@@ -114,3 +114,21 @@ def test_cfl_and_run_argument_checks():
                       1 << 40, None) == H.ERR_INVALID_ARG
     assert L.hard_run(ctypes.byref(g), FAKE, 0.4, 1.0, 0, ctypes.byref(t), ctypes.byref(s), FAKE,
                       1 << 40, None) == H.ERR_INVALID_ARG
+
+
+def test_adjoint_is_fp64_only():
+    g = H.make_grid((16, 16), dtype="f32")
+    L = H.lib()
+    b = ctypes.c_size_t()
+    assert L.hard_adjoint_workspace_bytes(ctypes.byref(g), ctypes.byref(b)) == H.ERR_UNSUPPORTED
+    g = H.make_grid((16, 16))
+    assert L.hard_adjoint_workspace_bytes(ctypes.byref(g), ctypes.byref(b)) == H.OK
+    assert b.value >= 3 * 4 * 16 * 16 * 8
+
+
+def test_batched_plan_rejects_mixed_dtypes():
+    grids = [H.make_grid((64,)), H.make_grid((32, 32), dtype="f32")]
+    arr = (H.hard_grid_t * 2)(*grids)
+    plan = ctypes.c_void_p()
+    assert H.lib().hard_batch_plan_create(arr, 2, None, ctypes.byref(plan)) == H.ERR_INVALID_ARG
+    assert not plan.value

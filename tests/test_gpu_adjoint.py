@@ -1,0 +1,162 @@
+"""Adjoint of the Heun step (dt held fixed) and the checkpointed rollout.
+
+* One step: <Adjoint(lam), v> equals <lam, Tangent(v)> where the tangent is
+  the oracle's forward-mode dual derivative of the same step (relative
+  1e-10).  The GPU adjoint and the oracle tangent are independent
+  implementations (reverse mode on the GPU, forward mode on the CPU).
+* Rollout, config-4 recipe (2D periodic, log-normal rho, p = 1, solenoidal u;
+  loss J = dx^2/2 sum (rho_N - rho_T)^2, target from rho (1 + 0.01 g')):
+  <grad J, v> against the oracle's dual directional derivative (each side
+  with its own CFL step list), and against central differences of the GPU
+  forward map with O(h^2) remainders.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+H = pytest.importorskip("paper_2509_08971_amd")
+AG = pytest.importorskip("paper_2509_08971_amd.autograd")
+
+P, O, R = 0, 1, 2
+DEV = "cuda"
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def smooth_state(n, seed):
+    rng = np.random.default_rng(seed)
+    shape = tuple(reversed(n))
+    gf = lambda: workloads.gaussian_random_field(shape, rng, spectral_index=-3.0)
+    vel = [0.3 * gf() for _ in n]
+    return workloads.conserved_from_primitive(np.exp(0.2 * gf()), vel, 1.0 + 0.2 * gf()), rng
+
+
+@pytest.mark.parametrize("n,bc", [((64,), (O, O)), ((48,), (R, R)), ((40, 32), (P, P, R, R)),
+                                  ((32, 24), (O, O, P, P)), ((16, 12, 10), (P, P, R, R, O, O))])
+def test_one_step_adjoint_dot_product(n, bc):
+    log("adjoint dot product", n, bc)
+    U0, rng = smooth_state(n, 3)
+    og = oracle.Grid(n, bc=bc)
+    dt, _ = oracle.cfl_dt(og, U0, 0.4)
+    g = H.make_grid(n, bc=bc)
+    U = torch.from_numpy(U0).to(DEV)
+    dtd = torch.full((1,), dt, dtype=torch.float64, device=DEV)
+    aw = H.workspace(H.hard_adjoint_workspace_bytes(g))
+    for trial in range(3):
+        lam = rng.standard_normal(U0.shape)
+        v = rng.standard_normal(U0.shape) * np.abs(U0).mean(axis=tuple(range(1, U0.ndim)),
+                                                           keepdims=True)
+        lt = torch.from_numpy(lam.copy()).to(DEV)
+        H.hard_hydro_step_adjoint(g, U, dtd, lt, aw)
+        lhs = float((lt.cpu().numpy() * v).sum())
+        _, dU, _ = oracle.steps_tangent(og, U0, v, [dt])
+        rhs = float((lam * dU).sum())
+        scale = np.abs(lt.cpu().numpy() * v).sum()
+        assert abs(lhs - rhs) <= 1e-10 * scale, (trial, lhs, rhs)
+
+
+def c4_state(n, seed=4):
+    return workloads.turbulent_box(n, ndim=2, seed=seed)
+
+
+def c4_target_state(n, seed=4, seed2=5):
+    return workloads.turbulent_box(n, ndim=2, seed=seed, rho_perturb=(0.01, seed2))
+
+
+def gpu_grad(n, nsteps, every):
+    """(J, grad J wrt U0) on the GPU through HydroRollout."""
+    g = H.make_grid((n, n), bc=(P, P))
+    U0 = torch.from_numpy(c4_state(n)).to(DEV)
+    UT0 = torch.from_numpy(c4_target_state(n)).to(DEV)
+    dts, _ = AG.recorded_dts(U0, g, nsteps)
+    rhoT = AG.run_fixed(UT0, g, dts)[0]
+    X = U0.clone().requires_grad_(True)
+    UN = AG.rollout(X, g, nsteps, 0.4, every)
+    dx2 = (1.0 / n) ** 2
+    J = 0.5 * dx2 * ((UN[0] - rhoT) ** 2).sum()
+    J.backward()
+    return J.item(), X.grad.cpu().numpy(), g, dts
+
+
+def oracle_dir_deriv(n, nsteps, V):
+    """Oracle J and D_V J with the oracle's own recorded CFL steps."""
+    og = oracle.Grid((n, n), bc=(P, P))
+    U0 = c4_state(n)
+    UT0 = c4_target_state(n)
+    _, _, _, _, dts = oracle.run(og, U0, 0.4, 1e9, max_steps=nsteps, record_dts=True)
+    rhoT = oracle.steps(og, UT0, dts)[0][0]
+    out = []
+    for v in V:
+        UN, dUN, _ = oracle.steps_tangent(og, U0, v, dts)
+        out.append((1.0 / n) ** 2 * float(((UN[0] - rhoT) * dUN[0]).sum()))
+    return out
+
+
+def test_rollout_gradient_vs_oracle_dual_64():
+    """64x64, 200 steps, checkpoints every 20, eight random directions."""
+    n, nsteps = 64, 200
+    J, grad, g, _ = gpu_grad(n, nsteps, 20)
+    rng = np.random.default_rng(9)
+    U0 = c4_state(n)
+    V = [rng.standard_normal(U0.shape) * np.abs(U0).mean(axis=(1, 2), keepdims=True)
+         for _ in range(8)]
+    ref = oracle_dir_deriv(n, nsteps, V)
+    for k, v in enumerate(V):
+        got = float((grad * v).sum())
+        scale = float(np.abs(grad * v).sum())
+        log(f"  dir {k}: gpu {got:.12e} oracle {ref[k]:.12e}")
+        assert abs(got - ref[k]) <= 1e-10 * scale + 1e-14 * abs(ref[k]), (k, got, ref[k])
+
+
+def test_rollout_gradient_vs_oracle_dual_512_short():
+    """The 512x512 config-4 grid at full size, 20 steps (checkpoints every 5),
+    one direction."""
+    n, nsteps = 512, 20
+    J, grad, g, _ = gpu_grad(n, nsteps, 5)
+    rng = np.random.default_rng(10)
+    U0 = c4_state(n)
+    v = rng.standard_normal(U0.shape) * np.abs(U0).mean(axis=(1, 2), keepdims=True)
+    ref = oracle_dir_deriv(n, nsteps, [v])[0]
+    got = float((grad * v).sum())
+    scale = float(np.abs(grad * v).sum())
+    assert abs(got - ref) <= 1e-10 * scale, (got, ref)
+
+
+def test_rollout_gradient_vs_finite_differences_64():
+    """Central differences of J along smooth density perturbations at fixed
+    velocity and pressure (these never sit on the uniform-pressure minmod
+    kink); the remainder shrinks like h^2."""
+    n, nsteps = 64, 200
+    J, grad, g, dts = gpu_grad(n, nsteps, 20)
+    U0 = c4_state(n)
+    rho, ux, uy, p = oracle.primitives(U0)
+    rng = np.random.default_rng(11)
+    UT0 = torch.from_numpy(c4_target_state(n)).to(DEV)
+    rhoT = AG.run_fixed(UT0, g, dts)[0]
+
+    def Jof(Uh):
+        UN = AG.run_fixed(torch.from_numpy(Uh).to(DEV), g, dts)
+        return 0.5 * (1.0 / n) ** 2 * float(((UN[0] - rhoT) ** 2).sum())
+
+    for k in range(3):
+        w = workloads.gaussian_random_field((n, n), rng, spectral_index=-3.0)
+        errs = []
+        for h in (1e-4, 5e-5):
+            Up = workloads.conserved_from_primitive(rho * (1 + h * w), [ux, uy], p)
+            Um = workloads.conserved_from_primitive(rho * (1 - h * w), [ux, uy], p)
+            fd = (Jof(Up) - Jof(Um)) / 2.0
+            # the same perturbation to first order: dU = d/dh U(rho (1 + h w), u, p)
+            rw = rho * w
+            dU = np.stack([rw, rw * ux, rw * uy, 0.5 * rw * (ux * ux + uy * uy)])
+            pred = h * float((grad * dU).sum())
+            errs.append(abs(fd - pred) / abs(pred))
+        log(f"  direction {k}: relative FD remainders {errs}")
+        assert errs[-1] < 1e-6
+        assert errs[1] < errs[0] or errs[1] < 1e-9
