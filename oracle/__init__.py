@@ -27,13 +27,23 @@ PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
 _lib = None
 
 
-def lib():
+def use_library(path):
+    """Load the oracle from another build of hydro_oracle.cpp (the mutation
+    tests compile deliberately broken copies and check that the pins fail)."""
+    global _lib
+    _lib = None
+    return lib(path)
+
+
+def lib(path=None):
     """Load liboracle.so, compiling it only if it is not there."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
-            _build.build()
-        L = ctypes.CDLL(_build.LIB)
+        if path is None:
+            path = _build.LIB
+            if not os.path.exists(path):
+                _build.build()
+        L = ctypes.CDLL(path)
         i64p = ctypes.POINTER(ctypes.c_int64)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)

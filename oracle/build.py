@@ -12,14 +12,16 @@ LIB = os.path.join(HERE, "liboracle.so")
 SRC = [os.path.join(HERE, "hydro_oracle.cpp")]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, src=None, out=None) -> str:
+    """Compile hydro_oracle.cpp (or `src`) into liboracle.so (or `out`)."""
+    out = out or LIB
     cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp"] + SRC
+           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", out + ".tmp"] + ([src] if src else SRC)
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

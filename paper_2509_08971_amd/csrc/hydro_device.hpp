@@ -210,36 +210,24 @@ __device__ __forceinline__ void hllc(R rL, R unL, const R* utL, R pL, R rR, R un
   }
   R E = p * inv_gm1 + R(0.5) * r * q;
 
-  // physical flux and conserved state of side K
+  // physical flux and conserved state of side K, star state, and the flux.
+  // The transverse momentum fluxes are u_t times the mass flux in every
+  // region (rho u u_t + S (rho* - rho) u_t), so only mass, normal momentum
+  // and energy go through the star-state formula.
   R mn = r * un;
-  R FK[NT + 3], UK[NT + 3], US[NT + 3];
-  FK[0] = mn;
-  FK[1] = mn * un + p;
-  UK[0] = r;
-  UK[1] = mn;
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    FK[2 + t] = mn * ut[t];
-    UK[2 + t] = r * ut[t];
-  }
-  FK[NT + 2] = (E + p) * un;
-  UK[NT + 2] = E;
-
-  // star state of side K.  r is an exact quotient: at a stationary contact
-  // (u_K = 0, S* = 0) it is exactly 1, so U*_K = U_K and the contact stays put.
-  R rr = d / (S - Ss);
+  R rr = d / (S - Ss);  // exact quotient: 1 at a stationary contact, so U*_K = U_K
   R fac = r * rr;
-  US[0] = fac;
-  US[1] = fac * Ss;
+  R F0s = mn + S * (fac - r);
+  R F1s = (mn * un + p) + S * (fac * Ss - mn);
+  R E_s = rr * E + rr * (Ss - un) * (r * Ss + p * fast_rcp(d));
+  R FE = (E + p) * un;
+  R FEs = FE + S * (E_s - E);
+  R F0 = star ? F0s : mn;
+  F[0] = F0;
+  F[1] = star ? F1s : mn * un + p;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) US[2 + t] = fac * ut[t];
-  US[NT + 2] = rr * E + rr * (Ss - un) * (r * Ss + p * fast_rcp(d));
-
-#pragma unroll
-  for (int v = 0; v < NT + 3; ++v) {
-    R fs = FK[v] + S * (US[v] - UK[v]);
-    F[v] = star ? fs : FK[v];
-  }
+  for (int t = 0; t < NT; ++t) F[2 + t] = ut[t] * F0;
+  F[NT + 2] = star ? FEs : FE;
 }
 
 // MUSCL-minmod face states from four cell states along the face normal

@@ -3,8 +3,9 @@
 * Every problem of a mixed batch equals the single-grid GPU step bit for bit,
   state and fused dt (the tile body and the per-cell arithmetic are shared).
 * Every tile shape the autotuner may pick gives the same bits.
-* A subset of the 4096-problem workload, run to t = 0.2 with per-problem dt,
-  against the FP64 oracle per problem (FP32: relative L1 <= 1e-5 per field).
+* A subset of the 4096-problem workload: 100 steps with per-problem dt
+  against the FP64 oracle per problem (FP32: relative L1 <= 1e-5 per field),
+  and runs to t = 0.2 against the exact Riemann solution.
 * Graph capture: replays of captured batched steps equal eager steps.
 """
 import os
@@ -107,15 +108,16 @@ def test_batched_tile_shapes_bitwise():
         assert got_dt == base_dt
 
 
-def test_batched_run_to_t_end_vs_oracle_fp32():
-    """40 problems of the 4096-problem recipe (every 100th plus 2D ones), each
-    run to t = 0.2 with its own CFL dt, against the FP64 oracle run of the
-    same float-rounded initial state."""
+def _subset():
     specs_all = workloads.batch_problem_specs()
     pick = list(range(0, 3072, 160)) + list(range(3072, 4096, 52))
     specs = [specs_all[i] for i in pick]
     states = [workloads.batch_problem_state(s).astype(np.float32).astype(np.float64)
               for s in specs]
+    return pick, specs, states
+
+
+def _run_subset(specs, states, t_end, max_steps):
     grids = [H.make_grid((s[1],) * s[0], bc=(O, O), dtype=torch.float32) for s in specs]
     plan = H.hard_batch_plan_create(grids)
     try:
@@ -123,23 +125,56 @@ def test_batched_run_to_t_end_vs_oracle_fp32():
         U = H.batch_pack(states, offs, torch.float32)
         work = H.workspace(H.hard_batch_workspace_bytes(plan))
         dt = torch.zeros(len(grids), dtype=torch.float64, device=DEV)
-        ts, steps = H.hard_run_batched(plan, len(grids), U, 0.4, 0.2, dt, work)
+        ts, steps = H.hard_run_batched(plan, len(grids), U, 0.4, t_end, dt, work,
+                                       max_steps=max_steps)
         outs = [t.double().cpu().numpy() for t in
                 H.batch_unpack(U, offs, [s.shape for s in states])]
     finally:
         H.hard_batch_plan_destroy(plan)
+    return ts, steps, outs
+
+
+def test_batched_100_steps_vs_oracle_fp32():
+    """40 problems of the 4096-problem recipe (every 160th 1D, every 52nd 2D),
+    100 steps each with its own CFL dt (the workload's step count), against
+    the FP64 oracle run of the same float-rounded initial state with its own
+    CFL steps: relative L1 <= 1e-5 per field."""
+    pick, specs, states = _subset()
+    ts, steps, outs = _run_subset(specs, states, 1e9, 100)
     worst = 0.0
     for k, (s, U0) in enumerate(zip(specs, states)):
         og = oracle.Grid((s[1],) * s[0], bc=(O, O))
-        ref, t_ref, n_ref, st = oracle.run(og, U0, 0.4, 0.2)
-        assert st == 0
-        assert ts[k] == pytest.approx(0.2, rel=1e-14)
-        assert abs(steps[k] - n_ref) <= 1
+        ref, t_ref, n_ref, st = oracle.run(og, U0, 0.4, 1e9, max_steps=100)
+        assert st == 0 and steps[k] == 100 and n_ref == 100
         for v in range(s[0] + 2):
             e = field_rel_l1(outs[k][v], ref[v])
             worst = max(worst, e)
             assert e <= 1e-5, (pick[k], v, e)
-    log("worst FP32 relative L1 over the subset", worst)
+    log("worst FP32 relative L1 over the subset (100 steps)", worst)
+
+
+def test_batched_run_to_t_end_vs_exact_riemann():
+    """The same 40 problems run to t = 0.2 with per-problem clipping: every
+    problem lands on t = 0.2, and its density error against the exact Riemann
+    solution matches the FP64 oracle's own error (FP32 rounding is far below
+    the discretisation error)."""
+    from oracle.exact_riemann import RiemannSolution
+    from oracle.metrics import l1_error
+    pick, specs, states = _subset()
+    ts, steps, outs = _run_subset(specs, states, 0.2, 10_000_000)
+    for k, (s, U0) in enumerate(zip(specs, states)):
+        assert ts[k] == pytest.approx(0.2, rel=1e-14)
+        ndim, n, (rL, pL, rR, pR) = s
+        og = oracle.Grid((n,) * ndim, bc=(O, O))
+        ref, t_ref, n_ref, st = oracle.run(og, U0, 0.4, 0.2)
+        assert abs(steps[k] - n_ref) <= 1
+        ex = RiemannSolution(rL, 0.0, pL, rR, 0.0, pR)
+        r_ex, _, _ = ex.cell_averages(n, 0.2)
+        rho_gpu = outs[k][0] if ndim == 1 else outs[k][0].mean(axis=0)
+        rho_ref = ref[0] if ndim == 1 else ref[0].mean(axis=0)
+        e_gpu = l1_error(rho_gpu, r_ex, 1.0 / n)
+        e_ref = l1_error(rho_ref, r_ex, 1.0 / n)
+        assert abs(e_gpu - e_ref) <= 0.02 * e_ref + 1e-6, (pick[k], e_gpu, e_ref)
 
 
 def test_batched_graph_replay():
