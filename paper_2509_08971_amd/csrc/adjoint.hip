@@ -557,6 +557,7 @@ hard_status_t hard_hydro_step_adjoint(const hard_grid_t* g, const void* U_n, con
     a.n[d] = G.n[d];
     a.dx[d] = G.dx[d];
     a.inv_dx[d] = G.inv_dx[d];
+    a.dx_pow2 = G.dx_pow2;
     a.bc[d][0] = G.bc[d][0];
     a.bc[d][1] = G.bc[d][1];
   }

@@ -77,6 +77,11 @@ hard_status_t check_grid(const hard_grid_t* g, Grid* out) {
       out->bc[d][1] = d < g->ndim ? g->bc[d][1] : HARD_BC_PERIODIC;
     }
     out->gamma = g->gamma;
+    out->dx_pow2 = 1;
+    for (int d = 0; d < g->ndim; ++d) {
+      int e;
+      if (std::frexp(g->dx[d], &e) != 0.5) out->dx_pow2 = 0;
+    }
   }
   return HARD_OK;
 }
@@ -159,7 +164,8 @@ hard_status_t hard_cfl_dt(const hard_grid_t* g, const void* U, double cfl, doubl
   if ((st = check_work(work, work_bytes, L.total))) return st;
   hipStream_t s = (hipStream_t)stream;
   Control* ctl = reinterpret_cast<Control*>(static_cast<char*>(work) + L.ctl);
-  hipError_t e = launch_cfl(G.ndim, G.dtype, G.n, G.dx, G.gamma, U, cfl, dt_dev, ctl, s);
+  hipError_t e = launch_cfl(G.ndim, G.dtype, G.n, G.dx, G.inv_dx, G.dx_pow2, G.gamma, U, cfl, dt_dev,
+                                ctl, s);
   if (e != hipSuccess) return hip_fail(e, "hard_cfl_dt launch");
   if (dt_host) {
     unsigned flags = 0;
@@ -194,6 +200,7 @@ hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_de
     a.n[d] = G.n[d];
     a.dx[d] = G.dx[d];
     a.inv_dx[d] = G.inv_dx[d];
+    a.dx_pow2 = G.dx_pow2;
     a.bc[d][0] = G.bc[d][0];
     a.bc[d][1] = G.bc[d][1];
   }
@@ -244,6 +251,7 @@ hard_status_t hard_hydro_stage(const hard_grid_t* g, int32_t stage, const void* 
     a.n[d] = G.n[d];
     a.dx[d] = G.dx[d];
     a.inv_dx[d] = G.inv_dx[d];
+    a.dx_pow2 = G.dx_pow2;
     a.bc[d][0] = G.bc[d][0];
     a.bc[d][1] = G.bc[d][1];
   }
@@ -280,7 +288,8 @@ hard_status_t hard_run(const hard_grid_t* g, void* U, double cfl, double t_end,
   hipError_t e = launch_control_clear(ctl, s);
   if (e != hipSuccess) return hip_fail(e, "hard_run clear");
   double* dt = &ctl->dt;
-  if ((e = launch_cfl(G.ndim, G.dtype, G.n, G.dx, G.gamma, U, cfl, dt, ctl, s)) != hipSuccess)
+  if ((e = launch_cfl(G.ndim, G.dtype, G.n, G.dx, G.inv_dx, G.dx_pow2, G.gamma, U, cfl, dt,
+                      ctl, s)) != hipSuccess)
     return hip_fail(e, "hard_run cfl");
   const int batch = 64;
   int done = 0;

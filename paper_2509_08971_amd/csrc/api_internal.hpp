@@ -17,6 +17,7 @@ struct Grid {
   double dx[3], inv_dx[3];
   int bc[3][2];
   double gamma;
+  int dx_pow2;  // every dx is a power of two (x/dx == x*(1/dx) exactly)
 };
 
 // Byte offsets inside a single-grid workspace.

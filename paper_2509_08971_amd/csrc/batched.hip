@@ -37,7 +37,9 @@ struct BatchProblem {
   int bc[3][2];
   double dx[3];
   double inv_dx[3];
-  int tiles_x, tiles_y, nchunk, ntiles;
+  int dx_pow2;
+  int tiles_x, tiles_y, nchunk, ntiles;  // work items of this problem
+  int walk;                              // walk positions per work item (2D rows, 3D planes)
 };
 
 struct WorkItem {
@@ -60,25 +62,29 @@ struct BatchArgs {
   int nitems;
   double* dt;                    // per-problem dt (read; written by stage 2 when update_dt)
   unsigned long long* smax;      // per-problem CFL slot
-  unsigned* cnt;                 // per-problem finished-tile counter
+  unsigned* cnt;                 // per-problem finished-item counter
   BatchQueue* q;
   Control* ctl;                  // status bits
   double gamma;
   double cfl;
   int update_dt;
-  int cz;
 };
 
-constexpr int BT = 256;  // threads per workgroup of the batched kernels
+// 1D and 2D problems: one wave per work item.  A 1D item is a row of 63
+// cells (64 faces, one per lane); a 2D item is a row segment of 63 cells
+// walking along y over `walk` rows.
+constexpr int BT12 = 64;
+constexpr int ROW = BT12 - 1;
+// 3D problems: 256-thread workgroups, x-y tiles walking along z.
+constexpr int BT3 = 256;
+constexpr int kTiles3D[3][2] = {{16, 16}, {32, 8}, {8, 32}};
 
-// Tile shapes (x by y) selectable for 2D problems (256 threads each).
-constexpr int kTiles2D[3][2] = {{16, 16}, {32, 8}, {8, 32}};
-
-// Tile-level finish: status bits to the control block, CFL max to the
-// problem's slot; the last tile of the problem writes its dt.
+// Item-level finish: status bits to the control block, CFL max to the
+// problem's slot; the last item of the problem writes its dt.
+template <int NTHR>
 __device__ __forceinline__ void tile_finish(unsigned flags, double smax, bool do_cfl,
-                                            const BatchArgs& a, int p, int ntiles) {
-  constexpr int NW = BT / 64;
+                                            const BatchArgs& a, int p, int nitems_p) {
+  constexpr int NW = NTHR / 64;
   __shared__ double red_s[NW];
   __shared__ unsigned red_f[NW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -101,7 +107,7 @@ __device__ __forceinline__ void tile_finish(unsigned flags, double smax, bool do
       atomicMax(&a.smax[p], (unsigned long long)__double_as_longlong(s));
       __threadfence();
       unsigned prev = atomicAdd(&a.cnt[p], 1u);
-      if (prev == (unsigned)ntiles - 1) {
+      if (prev == (unsigned)nitems_p - 1) {
         __threadfence();
         unsigned long long bits = atomicAdd(&a.smax[p], 0ull);
         a.dt[p] = a.cfl / __longlong_as_double((long long)bits);
@@ -114,12 +120,9 @@ __device__ __forceinline__ void tile_finish(unsigned flags, double smax, bool do
 
 __device__ __forceinline__ TileArgs tile_args(const BatchArgs& a, const BatchProblem& P, int wsize) {
   TileArgs t;
-  const char* s = static_cast<const char*>(a.src) + P.offset * wsize;
-  const char* u = static_cast<const char*>(a.un) + P.offset * wsize;
-  char* d = static_cast<char*>(a.dst) + P.offset * wsize;
-  t.src = s;
-  t.un = u;
-  t.dst = d;
+  t.src = static_cast<const char*>(a.src) + P.offset * wsize;
+  t.un = static_cast<const char*>(a.un) + P.offset * wsize;
+  t.dst = static_cast<char*>(a.dst) + P.offset * wsize;
   for (int k = 0; k < 3; ++k) {
     t.n[k] = P.n[k];
     t.bc[k][0] = P.bc[k][0];
@@ -127,8 +130,24 @@ __device__ __forceinline__ TileArgs tile_args(const BatchArgs& a, const BatchPro
     t.dx[k] = P.dx[k];
     t.inv_dx[k] = P.inv_dx[k];
   }
+  t.dx_pow2 = P.dx_pow2;
   t.gamma = a.gamma;
   return t;
+}
+
+// Work item -> tile origin and walk range.  1D: x row; 2D: x row segment and
+// a range of rows; 3D: x-y tile and a range of planes.
+__device__ __forceinline__ void item_geometry(const BatchProblem& P, int tile, int tx_cells,
+                                              int ty_cells, TileArgs& t) {
+  const int txi = tile % P.tiles_x;
+  const int rest = tile / P.tiles_x;
+  const int tyi = rest % P.tiles_y;
+  const int chunk = rest / P.tiles_y;
+  t.x0 = txi * tx_cells;
+  t.y0 = P.ndim == 3 ? tyi * ty_cells : 0;
+  const int nwalk = P.ndim == 3 ? P.n[2] : (P.ndim == 2 ? P.n[1] : 1);
+  t.w0 = P.ndim >= 2 ? chunk * P.walk : 0;
+  t.w1 = P.ndim >= 2 ? min(t.w0 + P.walk, nwalk) : 1;
 }
 
 // Pull the next work item (one per workgroup); -1 when the list is empty.
@@ -152,11 +171,10 @@ __device__ __forceinline__ void queue_exit(const BatchArgs& a) {
   }
 }
 
-template <typename R, int STAGE, int TS>
-__global__ __launch_bounds__(BT) void batched_stage_12(BatchArgs a) {
-  constexpr int TX2 = kTiles2D[TS][0], TY2 = kTiles2D[TS][1];
-  constexpr int L1 = TileShape<1, R, BT - 1, 1>::lds_elems;
-  constexpr int L2 = TileShape<2, R, TX2, TY2>::lds_elems;
+template <typename R, int STAGE>
+__global__ __launch_bounds__(BT12) void batched_stage_12(BatchArgs a) {
+  constexpr int L1 = TileShape<1, R, ROW, 1>::lds_elems;
+  constexpr int L2 = TileShape<2, R, ROW, 1>::lds_elems;
   __shared__ R lds[L1 > L2 ? L1 : L2];
   const bool do_cfl = STAGE == 2 && a.update_dt;
   for (int it = next_item(a); it >= 0; it = next_item(a)) {
@@ -164,29 +182,23 @@ __global__ __launch_bounds__(BT) void batched_stage_12(BatchArgs a) {
     const BatchProblem P = a.probs[w.prob];
     TileArgs t = tile_args(a, P, sizeof(R));
     t.dt = a.dt[w.prob];
-    t.z0 = 0;
-    t.z1 = 1;
     t.fuse_cfl = do_cfl;
+    item_geometry(P, w.tile, ROW, 1, t);
     unsigned flags = 0;
     double smax = 0.0;
-    if (P.ndim == 1) {
-      t.x0 = w.tile * (BT - 1);
-      t.y0 = 0;
-      run_tile<1, R, STAGE, BT - 1, 1, BT>(t, lds, flags, smax);
-    } else {
-      t.x0 = (w.tile % P.tiles_x) * TX2;
-      t.y0 = (w.tile / P.tiles_x) * TY2;
-      run_tile<2, R, STAGE, TX2, TY2>(t, lds, flags, smax);
-    }
-    tile_finish(flags, smax, do_cfl, a, w.prob, P.ntiles);
+    if (P.ndim == 1)
+      run_tile<1, R, STAGE, ROW, 1, BT12>(t, lds, flags, smax);
+    else
+      run_tile<2, R, STAGE, ROW, 1, BT12>(t, lds, flags, smax);
+    tile_finish<BT12>(flags, smax, do_cfl, a, w.prob, P.ntiles);
   }
   queue_exit(a);
 }
 
 template <typename R, int STAGE, int TS>
-__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 1, 8)))
+__global__ __launch_bounds__(BT3) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 1, 8)))
 void batched_stage_3(BatchArgs a) {
-  constexpr int TX = kTiles2D[TS][0], TY = kTiles2D[TS][1];
+  constexpr int TX = kTiles3D[TS][0], TY = kTiles3D[TS][1];
   __shared__ R lds[TileShape<3, R, TX, TY>::lds_elems];
   const bool do_cfl = STAGE == 2 && a.update_dt;
   for (int it = next_item(a); it >= 0; it = next_item(a)) {
@@ -194,51 +206,39 @@ void batched_stage_3(BatchArgs a) {
     const BatchProblem P = a.probs[w.prob];
     TileArgs t = tile_args(a, P, sizeof(R));
     t.dt = a.dt[w.prob];
-    int tt = w.tile;
-    const int txi = tt % P.tiles_x;
-    tt /= P.tiles_x;
-    const int tyi = tt % P.tiles_y;
-    const int chunk = tt / P.tiles_y;
-    t.x0 = txi * TX;
-    t.y0 = tyi * TY;
-    t.z0 = chunk * a.cz;
-    t.z1 = min(t.z0 + a.cz, P.n[2]);
     t.fuse_cfl = do_cfl;
+    item_geometry(P, w.tile, TX, TY, t);
     unsigned flags = 0;
     double smax = 0.0;
-    run_tile<3, R, STAGE, TX, TY>(t, lds, flags, smax);
-    tile_finish(flags, smax, do_cfl, a, w.prob, P.ntiles);
+    run_tile<3, R, STAGE, TX, TY, BT3>(t, lds, flags, smax);
+    tile_finish<BT3>(flags, smax, do_cfl, a, w.prob, P.ntiles);
   }
   queue_exit(a);
 }
 
-// Per-problem CFL dt of the current state (standalone), one tile per item.
-template <typename R>
-__global__ __launch_bounds__(BT) void batched_cfl(BatchArgs a, int tile_cells_x, int tile_cells_y) {
+// Per-problem CFL dt of the current state (standalone), item by item.
+template <typename R, int NTHR>
+__global__ __launch_bounds__(NTHR) void batched_cfl(BatchArgs a, int tx3, int ty3) {
   for (int it = next_item(a); it >= 0; it = next_item(a)) {
     const WorkItem w = a.items[it];
     const BatchProblem P = a.probs[w.prob];
     const R* U = reinterpret_cast<const R*>(static_cast<const char*>(a.src) + P.offset * sizeof(R));
     const long long N = (long long)P.n[0] * P.n[1] * P.n[2];
-    int tx_cells = P.ndim == 1 ? BT - 1 : tile_cells_x;
-    int ty_cells = P.ndim == 1 ? 1 : tile_cells_y;
-    int tt = w.tile;
-    const int txi = tt % P.tiles_x;
-    tt /= P.tiles_x;
-    const int tyi = tt % P.tiles_y;
-    const int chunk = tt / P.tiles_y;
-    const int z0 = P.ndim == 3 ? chunk * a.cz : 0;
-    const int z1 = P.ndim == 3 ? min(z0 + a.cz, P.n[2]) : 1;
+    const int txc = P.ndim == 3 ? tx3 : ROW;
+    const int tyc = P.ndim == 3 ? ty3 : 1;
+    TileArgs t;
+    item_geometry(P, w.tile, txc, tyc, t);
     double smax = 0.0;
     unsigned flags = 0;
     const int tid = threadIdx.x;
-    const int gx = txi * tx_cells + tid % tx_cells, gy = tyi * ty_cells + tid / tx_cells;
-    if (threadIdx.x < tx_cells * ty_cells && gx < P.n[0] && gy < P.n[1]) {
-      for (int z = z0; z < z1; ++z) {
-        long long c = ((long long)z * P.n[1] + gy) * P.n[0] + gx;
+    const int gx = t.x0 + tid % txc, gy = P.ndim == 3 ? t.y0 + tid / txc : 0;
+    const int NV = P.ndim + 2;
+    if (tid < txc * tyc && gx < P.n[0] && (P.ndim != 3 || gy < P.n[1])) {
+      for (int ww = t.w0; ww < t.w1; ++ww) {
+        long long c = P.ndim == 3 ? ((long long)ww * P.n[1] + gy) * P.n[0] + gx
+                                  : (long long)ww * P.n[0] + gx;
         double Ud[5];
         R Ur[5], W[5];
-        const int NV = P.ndim + 2;
         for (int v = 0; v < 5; ++v) {
           Ur[v] = v < NV ? U[v * N + c] : R(0);
           Ud[v] = (double)Ur[v];
@@ -246,19 +246,19 @@ __global__ __launch_bounds__(BT) void batched_cfl(BatchArgs a, int tile_cells_x,
         if (P.ndim == 1) {
           to_primitive<R, 1>(Ur, W, a.gamma - 1.0);
           flags |= cell_flags<R, 3>(Ur, W[2]);
-          smax = fmax(smax, signal_sum<1>(Ud, P.dx, a.gamma));
+          smax = fmax(smax, signal_sum<1>(Ud, P.dx, P.inv_dx, P.dx_pow2, a.gamma));
         } else if (P.ndim == 2) {
           to_primitive<R, 2>(Ur, W, a.gamma - 1.0);
           flags |= cell_flags<R, 4>(Ur, W[3]);
-          smax = fmax(smax, signal_sum<2>(Ud, P.dx, a.gamma));
+          smax = fmax(smax, signal_sum<2>(Ud, P.dx, P.inv_dx, P.dx_pow2, a.gamma));
         } else {
           to_primitive<R, 3>(Ur, W, a.gamma - 1.0);
           flags |= cell_flags<R, 5>(Ur, W[4]);
-          smax = fmax(smax, signal_sum<3>(Ud, P.dx, a.gamma));
+          smax = fmax(smax, signal_sum<3>(Ud, P.dx, P.inv_dx, P.dx_pow2, a.gamma));
         }
       }
     }
-    tile_finish(flags, smax, true, a, w.prob, P.ntiles);
+    tile_finish<NTHR>(flags, smax, true, a, w.prob, P.ntiles);
   }
   queue_exit(a);
 }
@@ -310,8 +310,9 @@ struct hard_batch_plan {
   int dtype = 0;
   double gamma = 0;
   int wsize = 8;
-  int tile2d = 0;  // index into kTiles2D for 2D and 3D problems (x-y tile)
-  int cz = 32;     // z planes per 3D work item
+  int tile3d = 0;   // index into kTiles3D (x-y tile of 3D problems)
+  int walk2d = 32;  // rows per 2D work item
+  int cz = 32;      // planes per 3D work item
   std::vector<int64_t> offsets;
   long long total_elems = 0;
   int nitems12 = 0, nitems3 = 0;
@@ -326,24 +327,30 @@ struct hard_batch_plan {
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Tile choices from a tune cache: lines "tile2d_f32 = 32x8", "tile2d_f64 = 16x16", "cz = 32".
-static void read_tune_cache(const char* path, int dtype, int* tile2d, int* cz) {
+// Tile choices from a tune cache, lines "key = value":
+//   walk2d = 32          rows per 2D work item
+//   tile3d_f64 = 16x16   x-y tile of 3D problems (tile3d_f32 for float)
+//   cz = 32              planes per 3D work item
+static void read_tune_cache(const char* path, hard_batch_plan* P) {
   if (!path) return;
   std::ifstream f(path);
   std::string line;
-  const std::string key = dtype == HARD_F64 ? "tile2d_f64" : "tile2d_f32";
+  const std::string key3 = P->dtype == HARD_F64 ? "tile3d_f64" : "tile3d_f32";
   while (std::getline(f, line)) {
     std::istringstream ss(line);
     std::string k, eq, v;
     if (!(ss >> k >> eq >> v) || eq != "=") continue;
-    if (k == key) {
+    if (k == key3) {
       int x = 0, y = 0;
       if (std::sscanf(v.c_str(), "%dx%d", &x, &y) == 2)
         for (int i = 0; i < 3; ++i)
-          if (kTiles2D[i][0] == x && kTiles2D[i][1] == y) *tile2d = i;
+          if (kTiles3D[i][0] == x && kTiles3D[i][1] == y) P->tile3d = i;
+    } else if (k == "walk2d") {
+      int c = std::atoi(v.c_str());
+      if (c > 0 && c <= 65536) P->walk2d = c;
     } else if (k == "cz") {
       int c = std::atoi(v.c_str());
-      if (c > 0 && c <= 4096) *cz = c;
+      if (c > 0 && c <= 65536) P->cz = c;
     }
   }
 }
@@ -363,7 +370,6 @@ static hard_status_t batch_common(const hard_batch_plan_t* P, const void* U, con
   a->cnt = reinterpret_cast<unsigned*>(wb + P->ws_cnt);
   a->ctl = reinterpret_cast<Control*>(wb + P->ws_ctl);
   a->gamma = P->gamma;
-  a->cz = P->cz;
   return HARD_OK;
 }
 
@@ -375,11 +381,7 @@ static hipError_t launch_batched_stage(const hard_batch_plan_t* P, BatchArgs a, 
     b.items = P->d_items12;
     b.nitems = P->nitems12;
     b.q = reinterpret_cast<BatchQueue*>(wb + P->ws_q12);
-    switch (P->tile2d) {
-      case 0: hipLaunchKernelGGL((batched_stage_12<R, STAGE, 0>), dim3(P->grid12), dim3(BT), 0, s, b); break;
-      case 1: hipLaunchKernelGGL((batched_stage_12<R, STAGE, 1>), dim3(P->grid12), dim3(BT), 0, s, b); break;
-      default: hipLaunchKernelGGL((batched_stage_12<R, STAGE, 2>), dim3(P->grid12), dim3(BT), 0, s, b); break;
-    }
+    hipLaunchKernelGGL((batched_stage_12<R, STAGE>), dim3(P->grid12), dim3(BT12), 0, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -388,10 +390,10 @@ static hipError_t launch_batched_stage(const hard_batch_plan_t* P, BatchArgs a, 
     b.items = P->d_items3;
     b.nitems = P->nitems3;
     b.q = reinterpret_cast<BatchQueue*>(wb + P->ws_q3);
-    switch (P->tile2d) {
-      case 0: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 0>), dim3(P->grid3), dim3(BT), 0, s, b); break;
-      case 1: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 1>), dim3(P->grid3), dim3(BT), 0, s, b); break;
-      default: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 2>), dim3(P->grid3), dim3(BT), 0, s, b); break;
+    switch (P->tile3d) {
+      case 0: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 0>), dim3(P->grid3), dim3(BT3), 0, s, b); break;
+      case 1: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 1>), dim3(P->grid3), dim3(BT3), 0, s, b); break;
+      default: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 2>), dim3(P->grid3), dim3(BT3), 0, s, b); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -411,9 +413,9 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
   P->dtype = grids[0].dtype;
   P->gamma = grids[0].gamma;
   P->wsize = P->dtype == HARD_F64 ? 8 : 4;
-  P->tile2d = P->dtype == HARD_F64 ? 0 : 1;
-  read_tune_cache(tune_cache, P->dtype, &P->tile2d, &P->cz);
-  const int TX = kTiles2D[P->tile2d][0], TY = kTiles2D[P->tile2d][1];
+  P->tile3d = P->dtype == HARD_F64 ? 0 : 1;
+  read_tune_cache(tune_cache, P);
+  const int TX3 = kTiles3D[P->tile3d][0], TY3 = kTiles3D[P->tile3d][1];
   std::vector<BatchProblem> probs(nprob);
   struct Cost { double c; WorkItem w; };
   std::vector<Cost> c12, c3;
@@ -441,19 +443,29 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
       B.dx[d] = G.dx[d];
       B.inv_dx[d] = G.inv_dx[d];
     }
+    B.dx_pow2 = G.dx_pow2;
+    double cells;  // cells of one work item, for the cost order
     if (G.ndim == 1) {
-      B.tiles_x = (G.n[0] + BT - 2) / (BT - 1);  // 255-cell tiles: 256 faces
+      B.tiles_x = (G.n[0] + ROW - 1) / ROW;
       B.tiles_y = 1;
+      B.walk = 1;
       B.nchunk = 1;
+      cells = ROW;
+    } else if (G.ndim == 2) {
+      B.tiles_x = (G.n[0] + ROW - 1) / ROW;
+      B.tiles_y = 1;
+      B.walk = P->walk2d;
+      B.nchunk = (G.n[1] + B.walk - 1) / B.walk;
+      cells = (double)ROW * std::min(B.walk, G.n[1]);
     } else {
-      B.tiles_x = (G.n[0] + TX - 1) / TX;
-      B.tiles_y = (G.n[1] + TY - 1) / TY;
-      B.nchunk = G.ndim == 3 ? (G.n[2] + P->cz - 1) / P->cz : 1;
+      B.tiles_x = (G.n[0] + TX3 - 1) / TX3;
+      B.tiles_y = (G.n[1] + TY3 - 1) / TY3;
+      B.walk = P->cz;
+      B.nchunk = (G.n[2] + B.walk - 1) / B.walk;
+      cells = (double)TX3 * TY3 * std::min(B.walk, G.n[2]);
     }
     B.ntiles = B.tiles_x * B.tiles_y * B.nchunk;
-    // tile cost ~ cells x faces per cell
-    double cells = G.ndim == 1 ? BT - 1 : (double)TX * TY * (G.ndim == 3 ? P->cz : 1);
-    double cost = cells * (1.0 + 1.1 * G.ndim);
+    const double cost = cells * G.ndim;  // faces per cell ~ ndim
     for (int t = 0; t < B.ntiles; ++t) (G.ndim == 3 ? c3 : c12).push_back({cost, {p, t}});
     // keep every problem 256-byte aligned
     long long elems = (long long)G.nvar * G.ncell;
@@ -476,7 +488,7 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     ncu = 256;
-  P->grid12 = std::max(1, std::min(P->nitems12, ncu * 8));
+  P->grid12 = std::max(1, std::min(P->nitems12, ncu * 32));
   P->grid3 = std::max(1, std::min(P->nitems3, ncu * 3));
   hipError_t e;
   if ((e = hipMalloc(&P->d_probs, sizeof(BatchProblem) * nprob)) != hipSuccess ||
@@ -538,19 +550,28 @@ hard_status_t hard_cfl_dt_batched(const hard_batch_plan_t* P, const void* U, dou
   a.cfl = cfl;
   char* wb = static_cast<char*>(work);
   hipStream_t s = (hipStream_t)stream;
-  const int TX = kTiles2D[P->tile2d][0], TY = kTiles2D[P->tile2d][1];
-  for (int pass = 0; pass < 2; ++pass) {
-    int n = pass == 0 ? P->nitems12 : P->nitems3;
-    if (!n) continue;
+  const int TX3 = kTiles3D[P->tile3d][0], TY3 = kTiles3D[P->tile3d][1];
+  if (P->nitems12) {
     BatchArgs b = a;
-    b.items = pass == 0 ? P->d_items12 : P->d_items3;
-    b.nitems = n;
-    b.q = reinterpret_cast<BatchQueue*>(wb + (pass == 0 ? P->ws_q12 : P->ws_q3));
-    int grid = pass == 0 ? P->grid12 : P->grid3;
+    b.items = P->d_items12;
+    b.nitems = P->nitems12;
+    b.q = reinterpret_cast<BatchQueue*>(wb + P->ws_q12);
     if (P->dtype == HARD_F64)
-      hipLaunchKernelGGL(batched_cfl<double>, dim3(grid), dim3(BT), 0, s, b, TX, TY);
+      hipLaunchKernelGGL((batched_cfl<double, BT12>), dim3(P->grid12), dim3(BT12), 0, s, b, TX3, TY3);
     else
-      hipLaunchKernelGGL(batched_cfl<float>, dim3(grid), dim3(BT), 0, s, b, TX, TY);
+      hipLaunchKernelGGL((batched_cfl<float, BT12>), dim3(P->grid12), dim3(BT12), 0, s, b, TX3, TY3);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "hard_cfl_dt_batched");
+  }
+  if (P->nitems3) {
+    BatchArgs b = a;
+    b.items = P->d_items3;
+    b.nitems = P->nitems3;
+    b.q = reinterpret_cast<BatchQueue*>(wb + P->ws_q3);
+    if (P->dtype == HARD_F64)
+      hipLaunchKernelGGL((batched_cfl<double, BT3>), dim3(P->grid3), dim3(BT3), 0, s, b, TX3, TY3);
+    else
+      hipLaunchKernelGGL((batched_cfl<float, BT3>), dim3(P->grid3), dim3(BT3), 0, s, b, TX3, TY3);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "hard_cfl_dt_batched");
   }

@@ -279,9 +279,11 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 // CFL signal sum sum_d (|u_d| + c)/dx_d of one conserved state, in double,
 // rounded step by step in the stated order (no contraction) so that it
-// reproduces a plain evaluation of the formula.
+// reproduces a plain evaluation of the formula.  When every dx is a power of
+// two, x/dx equals x*(1/dx) exactly and the multiply is used.
 template <int NDIM>
-__device__ __forceinline__ double signal_sum(const double* U, const double* dx, double gamma) {
+__device__ __forceinline__ double signal_sum(const double* U, const double* dx,
+                                             const double* inv_dx, int dx_pow2, double gamma) {
 #pragma clang fp contract(off)
   double rho = U[0];
   double q = U[1] * U[1];
@@ -293,7 +295,10 @@ __device__ __forceinline__ double signal_sum(const double* U, const double* dx, 
   double cs = sqrt(gamma * p / rho);
   double s = 0.0;
 #pragma unroll
-  for (int d = 0; d < NDIM; ++d) s = s + (fabs(U[1 + d] / rho) + cs) / dx[d];
+  for (int d = 0; d < NDIM; ++d) {
+    double t = fabs(U[1 + d] / rho) + cs;
+    s = s + (dx_pow2 ? t * inv_dx[d] : t / dx[d]);
+  }
   return s;
 }
 

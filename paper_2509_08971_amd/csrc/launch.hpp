@@ -17,11 +17,12 @@ struct StageArgs {
   int bc[3][2];          // boundary kinds
   double dx[3];          // cell widths (CFL)
   double inv_dx[3];      // 1/dx (flux difference)
+  int dx_pow2;           // every dx is a power of two
   double gamma;
   double cfl;
   int fuse_cfl;          // stage 2: fold the CFL max of U^{n+1} into the pass
   int tiles_x, tiles_y;  // filled by the launcher
-  int cz;                // z planes per workgroup (3D), 0 = default
+  int cz;                // walk positions per workgroup (z in 3D, y in 2D), 0 = default
   Control* ctl;          // workspace control block
   double* next_dt;       // fused CFL output (stage 2)
 };
@@ -29,8 +30,9 @@ struct StageArgs {
 hipError_t launch_stage(int ndim, int dtype, const StageArgs& a, int stage, hipStream_t s);
 
 // Standalone CFL dt (reads U once).
-hipError_t launch_cfl(int ndim, int dtype, const int* n, const double* dx, double gamma,
-                      const void* U, double cfl, double* dt, Control* ctl, hipStream_t s);
+hipError_t launch_cfl(int ndim, int dtype, const int* n, const double* dx, const double* inv_dx,
+                      int dx_pow2, double gamma, const void* U, double cfl, double* dt,
+                      Control* ctl, hipStream_t s);
 
 // hard_run time control (one thread).
 hipError_t launch_time_control(Control* ctl, double t_end, long long max_steps, hipStream_t s);

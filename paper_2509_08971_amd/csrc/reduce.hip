@@ -11,14 +11,18 @@ constexpr int RED_THREADS = 256;
 // dt = cfl / max_i sum_d (|u_d| + c)/dx_d over the interior (the paper's
 // section 3.5 says only that dt follows the CFL condition; this is the
 // library's reading).  Grid-stride over cells; also ORs the status bits.
+struct CflGeo {
+  int n[3];
+  double dx[3], inv_dx[3];
+  int dx_pow2;
+};
+
 template <int NDIM, typename R>
-__global__ __launch_bounds__(RED_THREADS) void cfl_kernel(const R* __restrict__ U, int nx, int ny,
-                                                          int nz, double dx0, double dx1,
-                                                          double dx2, double gamma, double cfl,
-                                                          double* dt, Control* ctl) {
+__global__ __launch_bounds__(RED_THREADS) void cfl_kernel(const R* __restrict__ U, CflGeo g,
+                                                          double gamma, double cfl, double* dt,
+                                                          Control* ctl) {
   constexpr int NV = NDIM + 2;
-  const long long N = (long long)nx * ny * nz;
-  const double dx[3] = {dx0, dx1, dx2};
+  const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
   double smax = 0.0;
   unsigned flags = 0;
   for (long long c = (long long)blockIdx.x * RED_THREADS + threadIdx.x; c < N;
@@ -33,7 +37,7 @@ __global__ __launch_bounds__(RED_THREADS) void cfl_kernel(const R* __restrict__ 
     R W[NV];
     to_primitive<R, NDIM>(Ur, W, gamma - 1.0);
     flags |= cell_flags<R, NV>(Ur, W[NV - 1]);
-    smax = fmax(smax, signal_sum<NDIM>(Ud, dx, gamma));
+    smax = fmax(smax, signal_sum<NDIM>(Ud, g.dx, g.inv_dx, g.dx_pow2, gamma));
   }
   block_finish<RED_THREADS>(flags, smax, true, ctl, cfl, dt);
 }
@@ -45,13 +49,21 @@ static int cfl_blocks(long long N) {
   return (int)b;
 }
 
-hipError_t launch_cfl(int ndim, int dtype, const int* n, const double* dx, double gamma,
-                      const void* U, double cfl, double* dt, Control* ctl, hipStream_t s) {
+hipError_t launch_cfl(int ndim, int dtype, const int* n, const double* dx, const double* inv_dx,
+                      int dx_pow2, double gamma, const void* U, double cfl, double* dt,
+                      Control* ctl, hipStream_t s) {
   long long N = (long long)n[0] * n[1] * n[2];
   dim3 grid(cfl_blocks(N)), block(RED_THREADS);
+  CflGeo g;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = n[d];
+    g.dx[d] = dx[d];
+    g.inv_dx[d] = inv_dx[d];
+  }
+  g.dx_pow2 = dx_pow2;
 #define HARD_CFL(D, T)                                                                      \
-  hipLaunchKernelGGL((cfl_kernel<D, T>), grid, block, 0, s, static_cast<const T*>(U), n[0], \
-                     n[1], n[2], dx[0], dx[1], dx[2], gamma, cfl, dt, ctl)
+  hipLaunchKernelGGL((cfl_kernel<D, T>), grid, block, 0, s, static_cast<const T*>(U), g, gamma, \
+                     cfl, dt, ctl)
   if (dtype == 0) {
     if (ndim == 1) HARD_CFL(1, double);
     else if (ndim == 2) HARD_CFL(2, double);

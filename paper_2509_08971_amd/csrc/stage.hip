@@ -40,12 +40,14 @@ void stage_kernel(StageArgs a) {
     t.dx[d] = a.dx[d];
     t.inv_dx[d] = a.inv_dx[d];
   }
+  t.dx_pow2 = a.dx_pow2;
   t.gamma = a.gamma;
   t.dt = *a.dt;
   t.x0 = tile_x * TX;
   t.y0 = tile_y * TY;
-  t.z0 = NDIM == 3 ? chunk * a.cz : 0;
-  t.z1 = NDIM == 3 ? min(t.z0 + a.cz, a.n[2]) : 1;
+  const int nwalk = NDIM == 3 ? a.n[2] : (NDIM == 2 ? a.n[1] : 1);
+  t.w0 = NDIM >= 2 ? chunk * a.cz : 0;
+  t.w1 = NDIM >= 2 ? min(t.w0 + a.cz, nwalk) : 1;
   t.fuse_cfl = STAGE == 2 && a.fuse_cfl;
   unsigned flags = 0;
   double smax = 0.0;
@@ -56,15 +58,18 @@ void stage_kernel(StageArgs a) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int NDIM, typename R, int TX, int TY, int NTHR = TX * TY>
-static hipError_t launch_stage_t(const StageArgs& a0, int stage, hipStream_t s) {
+// TX x TY cells per tile (3D), or a row of TX cells (1D, 2D); NTHR threads;
+// a.cz positions per walk chunk (0 = default).
+template <int NDIM, typename R, int TX, int TY, int NTHR>
+static hipError_t launch_stage_t(const StageArgs& a0, int stage, int cz_default, hipStream_t s) {
   StageArgs a = a0;
   a.tiles_x = (int)((a.n[0] + TX - 1) / TX);
-  a.tiles_y = NDIM >= 2 ? (int)((a.n[1] + TY - 1) / TY) : 1;
+  a.tiles_y = NDIM == 3 ? (int)((a.n[1] + TY - 1) / TY) : 1;
   int nchunk = 1;
-  if (NDIM == 3) {
-    if (a.cz <= 0) a.cz = 32;
-    nchunk = (int)((a.n[2] + a.cz - 1) / a.cz);
+  if (NDIM >= 2) {
+    const int nwalk = NDIM == 3 ? a.n[2] : a.n[1];
+    if (a.cz <= 0) a.cz = cz_default;
+    nchunk = (nwalk + a.cz - 1) / a.cz;
   } else {
     a.cz = 1;
   }
@@ -84,18 +89,34 @@ static hipError_t launch_stage_t(const StageArgs& a0, int stage, hipStream_t s) 
 #define HARD_TILE32 32, 8
 #endif
 
+// 2D grids: rows of 255, 127 or 63 cells (one face per thread per row) and
+// enough walk chunks to give the machine a few thousand workgroups.
+template <typename R>
+static hipError_t launch_stage_2d(const StageArgs& a, int stage, hipStream_t s) {
+  const int nx = a.n[0], ny = a.n[1];
+  auto chunk_for = [&](int tx) {
+    long long tiles = (nx + tx - 1) / tx;
+    long long want = 4096;
+    long long c = (tiles * ny + want - 1) / want;
+    return (int)(c < 4 ? 4 : (c > 64 ? 64 : c));
+  };
+  if (nx >= 1024) return launch_stage_t<2, R, 255, 1, 256>(a, stage, chunk_for(255), s);
+  if (nx >= 256) return launch_stage_t<2, R, 127, 1, 128>(a, stage, chunk_for(127), s);
+  return launch_stage_t<2, R, 63, 1, 64>(a, stage, chunk_for(63), s);
+}
+
 hipError_t launch_stage(int ndim, int dtype, const StageArgs& a, int stage, hipStream_t s) {
   if (dtype == 0) {
     switch (ndim) {
-      case 1: return launch_stage_t<1, double, 255, 1, 256>(a, stage, s);
-      case 2: return launch_stage_t<2, double, 16, 16>(a, stage, s);
-      case 3: return launch_stage_t<3, double, HARD_TILE64>(a, stage, s);
+      case 1: return launch_stage_t<1, double, 255, 1, 256>(a, stage, 1, s);
+      case 2: return launch_stage_2d<double>(a, stage, s);
+      case 3: return launch_stage_t<3, double, HARD_TILE64, 256>(a, stage, 32, s);
     }
   } else {
     switch (ndim) {
-      case 1: return launch_stage_t<1, float, 255, 1, 256>(a, stage, s);
-      case 2: return launch_stage_t<2, float, 32, 8>(a, stage, s);
-      case 3: return launch_stage_t<3, float, HARD_TILE32>(a, stage, s);
+      case 1: return launch_stage_t<1, float, 255, 1, 256>(a, stage, 1, s);
+      case 2: return launch_stage_2d<float>(a, stage, s);
+      case 3: return launch_stage_t<3, float, HARD_TILE32, 256>(a, stage, 32, s);
     }
   }
   return hipErrorInvalidValue;

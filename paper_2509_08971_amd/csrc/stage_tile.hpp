@@ -1,18 +1,22 @@
 // One tile of a Heun stage: the shared body of the single-grid stage kernel
-// and the batched kernel (HARD paper section 2.2.2: finite-volume face
+// and the batched kernels (HARD paper section 2.2.2: finite-volume face
 // difference, Heun's Butcher tableau in Shu-Osher form).
 //
-// A workgroup of TX x TY threads owns a TX x TY tile of cells in the x-y
-// plane and walks the z planes [z0, z1) (3D).  For each plane it
-//   1. builds the primitive states of the tile plus a two-cell x/y halo in
-//      LDS (interior cells come from a per-thread register window along z,
-//      halo cells are loaded and converted here; ghost cells are produced by
-//      index remapping, so no ghost arrays exist in HBM),
-//   2. computes every x and y face flux of the tile once, into LDS,
-//   3. computes the z face above each cell from the register window (the face
-//      below was computed in the previous plane),
+// A tile is a plane of cells held in LDS that walks along the last axis:
+//   1D: a row of TX cells in x (no walk);
+//   2D: a row of TX cells in x walking along y over [w0, w1);
+//   3D: a TX x TY tile in x-y walking along z over [w0, w1).
+// For each position of the walk it
+//   1. puts the primitive states of the plane plus a two-cell halo in LDS
+//      (the thread's own cell comes from a register window along the walk
+//      axis, the halo cells were loaded during the previous position; ghost
+//      cells are produced by index remapping, so no ghost arrays exist),
+//   2. computes every in-plane face flux once, into LDS,
+//   3. computes the face ahead along the walk axis from the register window
+//      (the face behind was computed at the previous position),
 //   4. forms L(U) and the stage combine, and stores the cell once.
-// 2D grids use one plane (no z walk), 1D grids one row.
+// Each cell is read from memory once per stage (plus the halo re-reads of
+// neighbouring tiles, which are served by L2), written once.
 #pragma once
 
 #include "hydro_device.hpp"
@@ -27,131 +31,142 @@ struct TileArgs {
   int bc[3][2];
   double dx[3];
   double inv_dx[3];
+  int dx_pow2;      // every dx is a power of two: x / dx == x * (1/dx) exactly
   double gamma;
   double dt;
-  int x0, y0, z0, z1;  // tile origin and z range
-  int fuse_cfl;        // stage 2: accumulate the CFL signal max of the output
+  int x0, y0;       // tile origin (y0: 3D only)
+  int w0, w1;       // walk range (y in 2D, z in 3D; [0, 1) in 1D)
+  int fuse_cfl;     // stage 2: accumulate the CFL signal max of the output
 };
 
-// LDS elements (of type R) one tile needs.
 template <int NDIM, typename R, int TX, int TY>
 struct TileShape {
   static constexpr int NV = NDIM + 2;
+  static constexpr int PD = NDIM == 3 ? 2 : 1;  // dimensions of the plane in LDS
   static constexpr int LX = TX + 4;
-  static constexpr int LY = NDIM >= 2 ? TY + 4 : 1;
-  static constexpr int NF = (TX + 1) * TY + (NDIM >= 2 ? TX * (TY + 1) : 0);
-  static constexpr int lds_elems = NV * (LX * LY + NF);
+  static constexpr int LY = PD == 2 ? TY + 4 : 1;
+  static constexpr int LXY = LX * LY;
+  static constexpr int NFX = (TX + 1) * TY;                // x faces per plane
+  static constexpr int NFY = PD == 2 ? TX * (TY + 1) : 0;  // y faces per plane (3D)
+  static constexpr int NF = NFX + NFY;
+  static constexpr int NHALO = PD == 2 ? 4 * (TX + TY) : 4;
+  static constexpr int lds_elems = NV * (LXY + NF);
+  static_assert(PD == 2 || TY == 1, "1D and 2D planes are one row");
 };
 
 // Runs one tile; ORs status bits into `flags` and maxes the CFL signal sum of
 // the stored cells into `smax` (when a.fuse_cfl).  Every thread of the
-// workgroup must call it (it contains barriers).
-//
-// NTHR (>= TX*TY) is the workgroup size; threads beyond TX*TY own no cell but
-// take part in the face and halo loops (a 1D tile of 255 cells has exactly
-// 256 faces, one per thread of a 256-thread workgroup).
+// workgroup must call it (it contains barriers).  NTHR (>= TX*TY) is the
+// workgroup size; threads beyond TX*TY own no cell but take part in the face
+// and halo loops (a row of 63 cells has exactly 64 faces, one per lane).
 template <int NDIM, typename R, int STAGE, int TX, int TY, int NTHR = TX * TY>
 __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& flags, double& smax) {
-  constexpr int NV = NDIM + 2;
+  using S = TileShape<NDIM, R, TX, TY>;
+  constexpr int NV = S::NV, PD = S::PD, LX = S::LX, LXY = S::LXY;
+  constexpr int NFX = S::NFX, NF = S::NF, NHALO = S::NHALO;
+  constexpr bool WALK = NDIM >= 2;
+  constexpr int WA = NDIM - 1;          // walk axis
+  constexpr int OY = PD == 2 ? 2 : 0;   // LDS row of the tile's first row
   constexpr int NT = NTHR;
   static_assert(NTHR >= TX * TY, "one thread per cell at least");
-  constexpr int OY = NDIM >= 2 ? 2 : 0;               // LDS row offset of the tile
-  constexpr int LX = TX + 4;
-  constexpr int LY = NDIM >= 2 ? TY + 4 : 1;
-  constexpr int LXY = LX * LY;
-  constexpr int NFX = (TX + 1) * TY;                  // x faces per plane
-  constexpr int NFY = NDIM >= 2 ? TX * (TY + 1) : 0;  // y faces per plane
-  constexpr int NF = NFX + NFY;
-  constexpr int NHALO = NDIM >= 2 ? 4 * (TX + TY) : 4;
-  static_assert(NDIM >= 2 || TY == 1, "1D tiles are one row");
+  static_assert(NHALO <= NT, "one halo cell per thread at most");
 
-  R* Ws = lds;            // NV * LXY: primitives of the plane (tile + halo)
-  R* Fs = lds + NV * LXY; // NV * NF: in-plane face fluxes, x faces then y faces
+  R* Ws = lds;             // NV * LXY: primitives of the plane (tile + halo)
+  R* Fs = lds + NV * LXY;  // NV * NF: in-plane face fluxes, x faces then y faces
 
   const int tid = threadIdx.x;
   const bool owner = tid < TX * TY;  // this thread owns a cell column of the tile
   const int tx = owner ? tid % TX : 0, ty = owner ? tid / TX : 0;
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const long long N = (long long)nx * ny * nz;
+  const int nwalk = NDIM == 3 ? nz : (NDIM == 2 ? ny : 1);
+  const long long WS = NDIM == 3 ? (long long)nx * ny : nx;  // stride along the walk axis
 
   const int x0 = a.x0, y0 = a.y0;
-  const int gx = x0 + tx, gy = y0 + ty;
-  const bool inside = owner && gx < nx && gy < ny;
-  const int z0 = a.z0, z1 = a.z1;
+  const int gx = x0 + tx, gy = PD == 2 ? y0 + ty : 0;
+  const bool inside = owner && gx < nx && (PD == 1 || gy < ny);
+  const int w0 = a.w0, w1 = a.w1;
 
+  // src never aliases dst (the stage state lives in its own buffer); un and
+  // dst may be the same array, each thread reading its own cell before
+  // storing it, so neither of them is restrict.
   const R* __restrict__ src = static_cast<const R*>(a.src);
-  const R* __restrict__ un = static_cast<const R*>(a.un);
-  R* __restrict__ dst = static_cast<R*>(a.dst);
+  const R* un = static_cast<const R*>(a.un);
+  R* dst = static_cast<R*>(a.dst);
   const double gm1 = a.gamma - 1.0;
   const R gam = R(a.gamma);
   const R inv_gm1 = R(1.0 / gm1);
   const R dt = R(a.dt);
-  const R idx0 = R(a.inv_dx[0]), idx1 = R(a.inv_dx[1]), idx2 = R(a.inv_dx[2]);
+  const R idx0 = R(a.inv_dx[0]), idx1 = R(a.inv_dx[1]), idxw = R(a.inv_dx[WA]);
 
   // this thread's column, clamped (and mirrored past reflecting walls) for
   // the overhang of ragged tiles; such threads never store
-  bool fx_, fy_;
+  bool fx_ = false, fy_ = false;
   const int cx = remap(gx, nx, a.bc[0][0], a.bc[0][1], fx_);
-  const int cy = remap(gy, ny, a.bc[1][0], a.bc[1][1], fy_);
+  const int cy = PD == 2 ? remap(gy, ny, a.bc[1][0], a.bc[1][1], fy_) : 0;
   const long long col = (long long)cy * nx + cx;
 
-  auto zplane = [&](int q, bool& fz) -> long long {
-    int z = NDIM == 3 ? remap(q, nz, a.bc[2][0], a.bc[2][1], fz) : 0;
-    return (long long)z * nx * ny;
+  // offset of walk position q (ghost-mapped along the walk axis)
+  auto wplane = [&](int q, bool& fw) -> long long {
+    fw = false;
+    if constexpr (!WALK) {
+      return 0;
+    } else {
+      int w = remap(q, nwalk, a.bc[WA][0], a.bc[WA][1], fw);
+      return (long long)w * WS;
+    }
   };
   auto load_cons = [&](long long c, R* Uc) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) Uc[v] = src[v * N + c];
   };
   // primitive state of this thread's column from conserved values
-  auto col_prim = [&](const R* Uc, bool fz, R* W) {
+  auto col_prim = [&](const R* Uc, bool fw, R* W) {
     to_primitive<R, NDIM>(Uc, W, gm1);
     if (fx_) W[1] = -W[1];
-    if (NDIM >= 2 && fy_) W[2] = -W[2];
-    if (NDIM == 3 && fz) W[3] = -W[3];
+    if (PD == 2 && fy_) W[2] = -W[2];
+    if (WALK && fw) W[1 + WA] = -W[1 + WA];
   };
+  // variable order of a face normal to the walk axis: (rho, u_n, u_t..., p)
+  constexpr int wperm[5] = {0, 1 + WA, 1, NDIM == 3 ? 2 : NV - 1, NV - 1};
 
-  // z register window (3D): P0 = plane z, P1 = z+1, S0 = slope at z, Fm = flux
-  // through the face z-1/2 (variables in the order rho, u_z, u_x, u_y, p)
+  // walk-axis register window: P0 = position w, P1 = w+1, S0 = slope at w,
+  // Fm = flux through the face w-1/2; conserved values Ucur (w) and Uc1 (w+1)
   R P0[NV], P1[NV], S0[NV], Fm[NV];
-  // conserved values of this column at planes z and z+1 (each cell is loaded
-  // from memory once per stage; the combine uses them from registers)
   R Ucur[NV], Uc1[NV];
-  if (NDIM < 3) load_cons(col, Ucur);
-  if constexpr (NDIM == 3) {
+  if constexpr (!WALK) load_cons(col, Ucur);
+  if constexpr (WALK) {
     R Pm2[NV], Pm1[NV], Ut[NV];
-    bool fz;
-    long long zo;
-    zo = zplane(z0 - 2, fz); load_cons(zo + col, Ut); col_prim(Ut, fz, Pm2);
-    zo = zplane(z0 - 1, fz); load_cons(zo + col, Ut); col_prim(Ut, fz, Pm1);
-    zo = zplane(z0, fz);     load_cons(zo + col, Ucur); col_prim(Ucur, fz, P0);
-    zo = zplane(z0 + 1, fz); load_cons(zo + col, Uc1); col_prim(Uc1, fz, P1);
-    R WL[NV], WR[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      R d0 = Pm1[v] - Pm2[v], d1 = P0[v] - Pm1[v], d2 = P1[v] - P0[v];
-      R sm1 = minmod(d0, d1);
-      S0[v] = minmod(d1, d2);
-      WL[v] = Pm1[v] + R(0.5) * sm1;
-      WR[v] = P0[v] - R(0.5) * S0[v];
-    }
+    bool fw;
+    long long wo;
+    wo = wplane(w0 - 2, fw); load_cons(wo + col, Ut); col_prim(Ut, fw, Pm2);
+    wo = wplane(w0 - 1, fw); load_cons(wo + col, Ut); col_prim(Ut, fw, Pm1);
+    wo = wplane(w0, fw);     load_cons(wo + col, Ucur); col_prim(Ucur, fw, P0);
+    wo = wplane(w0 + 1, fw); load_cons(wo + col, Uc1); col_prim(Uc1, fw, P1);
     R A[NV], B[NV], Fn[NV];
-    A[0] = WL[0]; A[1] = WL[3]; A[2] = WL[1]; A[3] = WL[2]; A[4] = WL[4];
-    B[0] = WR[0]; B[1] = WR[3]; B[2] = WR[1]; B[3] = WR[2]; B[4] = WR[4];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) S0[v] = minmod(P0[v] - Pm1[v], P1[v] - P0[v]);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int q = wperm[k];
+      R sm1 = minmod(Pm1[q] - Pm2[q], P0[q] - Pm1[q]);
+      A[k] = Pm1[q] + R(0.5) * sm1;
+      B[k] = P0[q] - R(0.5) * S0[q];
+    }
     hllc_ordered<R, NV>(A, B, gam, inv_gm1, Fn);
-    Fm[0] = Fn[0]; Fm[1] = Fn[2]; Fm[2] = Fn[3]; Fm[3] = Fn[1]; Fm[4] = Fn[4];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) Fm[wperm[k]] = Fn[k];
   }
 
   // Halo slot of this thread: NHALO <= NT, so each thread owns at most one
-  // halo cell of the plane, at the same x-y position on every plane.
-  static_assert(NHALO <= NT, "one halo cell per thread at most");
+  // halo cell of the plane, at the same in-plane position on every plane.
   const bool has_halo = tid < NHALO;
   int hlx = 0, hly = 0;
   bool hflx = false, hfly = false;
   long long hcol = 0;
   if (has_halo) {
     const int h = tid;
-    if (NDIM >= 2) {
+    if constexpr (PD == 2) {
       if (h < 4 * TY) {
         int side = h / (2 * TY), r = h % (2 * TY);
         hly = r / 2 + 2;
@@ -167,40 +182,42 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
       hlx = h < 2 ? h : TX + h;
     }
     int qx = remap(x0 + hlx - 2, nx, a.bc[0][0], a.bc[0][1], hflx);
-    int qy = NDIM >= 2 ? remap(y0 + hly - 2, ny, a.bc[1][0], a.bc[1][1], hfly) : 0;
+    int qy = PD == 2 ? remap(y0 + hly - 2, ny, a.bc[1][0], a.bc[1][1], hfly) : 0;
     hcol = (long long)qy * nx + qx;
   }
-  // conserved values of this thread's halo cell on the current plane; the
-  // next plane's are loaded while the current plane's faces are computed
+  // conserved values of this thread's halo cell at the current position; the
+  // next position's are loaded while the current plane's faces are computed
   R Hc[NV];
   if (has_halo) {
     bool f;
-    load_cons(zplane(z0, f) + hcol, Hc);
+    load_cons(wplane(w0, f) + hcol, Hc);
   }
 
-  for (int z = z0; z < z1; ++z) {
-    // ---- 0. issue the z+2 plane's column load early
-    R Unext[NV];
-    bool fz_next = false;
-    if (NDIM == 3) {
-      long long zn = zplane(z + 2, fz_next);
-      load_cons(zn + col, Unext);
+  for (int w = w0; w < w1; ++w) {
+    // ---- 0. issue the loads this position needs later: the column two
+    // positions ahead, and (stage 2) U^n of this thread's cell
+    R Unext[NV], Un0[NV];
+    bool fw_next = false;
+    if constexpr (WALK) load_cons(wplane(w + 2, fw_next) + col, Unext);
+    const long long cidx = (long long)w * WS + col;
+    if (STAGE == 2 && inside) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Un0[v] = un[v * N + cidx];
     }
-    if (NDIM < 3) {
-      col_prim(Ucur, false, P0);
-    }
-    // ---- 1. primitives of plane z: interior from the window, halo from Hc
+    if constexpr (!WALK) col_prim(Ucur, false, P0);
+
+    // ---- 1. primitives of the plane: own cell from the window, halo from Hc
     R Hn[NV];
     if (has_halo) {
       R Wh[NV];
       to_primitive<R, NDIM>(Hc, Wh, gm1);
       if (hflx) Wh[1] = -Wh[1];
-      if (NDIM >= 2 && hfly) Wh[2] = -Wh[2];
+      if (PD == 2 && hfly) Wh[2] = -Wh[2];
 #pragma unroll
       for (int v = 0; v < NV; ++v) Ws[v * LXY + hly * LX + hlx] = Wh[v];
-      if (NDIM == 3 && z + 1 < z1) {
+      if (WALK && w + 1 < w1) {
         bool f;
-        load_cons(zplane(z + 1, f) + hcol, Hn);
+        load_cons(wplane(w + 1, f) + hcol, Hn);
       }
     }
     if (owner) {
@@ -210,12 +227,12 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
     if (inside) flags |= cell_flags<R, NV>(Ucur, P0[NV - 1]);
     __syncthreads();
 
-    // ---- 2. in-plane faces.  The normal velocity of a y face is variable
-    // slot 2 and its first transverse velocity slot 1: the swap is done in
-    // the LDS addresses, so one code path serves both axes.
+    // ---- 2. in-plane faces.  In 3D the normal velocity of a y face is
+    // variable slot 2 and its first transverse velocity slot 1: the swap is
+    // done in the LDS addresses, so one code path serves both axes.
     for (int f = tid; f < NF; f += NT) {
       int base, stride;
-      bool yface = f >= NFX;
+      const bool yface = PD == 2 && f >= NFX;
       if (!yface) {
         int fxx = f % (TX + 1), fyy = f / (TX + 1);
         base = (fyy + OY) * LX + fxx;
@@ -229,78 +246,71 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
       int slot[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) slot[v] = v;
-      if (NDIM >= 2) {
+      if (PD == 2) {
         slot[1] = yface ? 2 : 1;
         slot[2] = yface ? 1 : 2;
       }
       R WL[NV], WR[NV], Fn[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const R* w = Ws + slot[v] * LXY + base;
-        muscl_pair(w[0], w[stride], w[2 * stride], w[3 * stride], WL[v], WR[v]);
+        const R* wp = Ws + slot[v] * LXY + base;
+        muscl_pair(wp[0], wp[stride], wp[2 * stride], wp[3 * stride], WL[v], WR[v]);
       }
       hllc_ordered<R, NV>(WL, WR, gam, inv_gm1, Fn);
 #pragma unroll
       for (int v = 0; v < NV; ++v) Fs[slot[v] * NF + f] = Fn[v];
     }
 
-    // ---- 3. face z+1/2 from the register window
+    // ---- 3. face w+1/2 from the register window
     R Fp[NV];
     R P2[NV];
-    if constexpr (NDIM == 3) {
-      col_prim(Unext, fz_next, P2);
+    if constexpr (WALK) {
+      col_prim(Unext, fw_next, P2);
       R S1[NV], A[NV], B[NV], Fn[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        R d1 = P1[v] - P0[v], d2 = P2[v] - P1[v];
-        S1[v] = minmod(d1, d2);
-      }
-      // reorder to (rho, u_z, u_x, u_y, p)
-      const int perm[5] = {0, 3, 1, 2, 4};
+      for (int v = 0; v < NV; ++v) S1[v] = minmod(P1[v] - P0[v], P2[v] - P1[v]);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        int q = perm[v];
-        A[v] = P0[q] + R(0.5) * S0[q];
-        B[v] = P1[q] - R(0.5) * S1[q];
+      for (int k = 0; k < NV; ++k) {
+        const int q = wperm[k];
+        A[k] = P0[q] + R(0.5) * S0[q];
+        B[k] = P1[q] - R(0.5) * S1[q];
       }
       hllc_ordered<R, NV>(A, B, gam, inv_gm1, Fn);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Fp[perm[v]] = Fn[v];
+      for (int k = 0; k < NV; ++k) Fp[wperm[k]] = Fn[k];
 #pragma unroll
       for (int v = 0; v < NV; ++v) S0[v] = S1[v];
     }
     __syncthreads();
 
-    // ---- 4. flux difference and stage combine
+    // ---- 4. flux difference (x, then y, then z) and stage combine
     if (inside) {
-      long long c = (long long)z * nx * ny + (long long)gy * nx + gx;
       const int fxl = ty * (TX + 1) + tx;
       const int fyl = NFX + ty * TX + tx;
       R Out[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         R l = R(0) - (Fs[v * NF + fxl + 1] - Fs[v * NF + fxl]) * idx0;
-        if (NDIM >= 2) l = l - (Fs[v * NF + fyl + TX] - Fs[v * NF + fyl]) * idx1;
-        if (NDIM == 3) l = l - (Fp[v] - Fm[v]) * idx2;
+        if (PD == 2) l = l - (Fs[v * NF + fyl + TX] - Fs[v * NF + fyl]) * idx1;
+        if (WALK) l = l - (Fp[v] - Fm[v]) * idxw;
         if (STAGE == 1) {
           Out[v] = Ucur[v] + dt * l;
         } else {
-          R u0 = un[v * N + c];
-          Out[v] = R(0.5) * (u0 + (Ucur[v] + dt * l));
+          Out[v] = R(0.5) * (Un0[v] + (Ucur[v] + dt * l));
         }
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) dst[v * N + c] = Out[v];
+      for (int v = 0; v < NV; ++v) dst[v * N + cidx] = Out[v];
       if (STAGE == 2 && a.fuse_cfl) {
         double Ud[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) Ud[v] = (double)Out[v];
-        smax = fmax(smax, signal_sum<NDIM>(Ud, a.dx, a.gamma));
+        smax = fmax(smax, signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
       }
     }
 
     // ---- 5. slide the window
-    if (NDIM == 3) {
+    if constexpr (WALK) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         Fm[v] = Fp[v];
@@ -312,7 +322,6 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
       }
     }
   }
-
 }
 
 }  // namespace hard

@@ -2,7 +2,7 @@
 
 * Every problem of a mixed batch equals the single-grid GPU step bit for bit,
   state and fused dt (the tile body and the per-cell arithmetic are shared).
-* Every tile shape the autotuner may pick gives the same bits.
+* Every work-item shape the autotuner may pick gives the same bits.
 * A subset of the 4096-problem workload: 100 steps with per-problem dt
   against the FP64 oracle per problem (FP32: relative L1 <= 1e-5 per field),
   and runs to t = 0.2 against the exact Riemann solution.
@@ -92,15 +92,21 @@ def test_batched_equals_single_bitwise(dtype):
         assert got_dt[p] == ref_dt[p], (p, got_dt[p], ref_dt[p])
 
 
-def test_batched_tile_shapes_bitwise():
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batched_tile_shapes_bitwise(dtype):
+    """Every setting the autotuner may write gives the same bits."""
     specs, states = mixed_batch()
-    base, base_dt = batched_run(specs, states, torch.float32, 3)
-    for cand in ("16x16", "8x32"):
+    base, base_dt = batched_run(specs, states, dtype, 3)
+    k3 = "tile3d_f64" if dtype == torch.float64 else "tile3d_f32"
+    settings = ["walk2d = 8", "walk2d = 64\ncz = 5", f"{k3} = 8x32\ncz = 3",
+                f"{k3} = 32x8\nwalk2d = 1", f"{k3} = 16x16\ncz = 64"]
+    for cand in settings:
+        log("tune setting", repr(cand), dtype)
         fd, path = tempfile.mkstemp(suffix=".tune")
         with os.fdopen(fd, "w") as f:
-            f.write(f"tile2d_f32 = {cand}\n")
+            f.write(cand + "\n")
         try:
-            got, got_dt = batched_run(specs, states, torch.float32, 3, tune=path)
+            got, got_dt = batched_run(specs, states, dtype, 3, tune=path)
         finally:
             os.unlink(path)
         for p in range(len(specs)):
