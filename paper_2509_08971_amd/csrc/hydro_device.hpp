@@ -54,13 +54,16 @@ __device__ __forceinline__ int remap(int q, int n, int bclo, int bchi, bool& fli
 }
 
 // minmod(a, b): 0 if a and b differ in sign (or one is 0), else the argument
-// of smaller magnitude.  Evaluated as sign(a) max(0, min(|a|, sign(a) b)):
-// the same value (up to the sign of a zero result) without compares/selects.
+// of smaller magnitude -- which is the median of a, b and 0 (up to the sign
+// of a zero result): max(min(a, b), min(max(a, b), 0)), no compares or
+// selects; one v_med3 in float.
 template <typename R>
 __device__ __forceinline__ R minmod(R a, R b) {
-  R t = copysign(R(1), a) * b;
-  R m = fmax(fmin(fabs(a), t), R(0));
-  return copysign(m, a);
+  return fmax(fmin(a, b), fmin(fmax(a, b), R(0)));
+}
+template <>
+__device__ __forceinline__ float minmod<float>(float a, float b) {
+  return __builtin_amdgcn_fmed3f(a, b, 0.0f);
 }
 
 // Reciprocal and square root used inside the flux.  FP64: hardware
@@ -177,9 +180,15 @@ __device__ __forceinline__ unsigned cell_flags(const R* U, R p) {
 //   S_L < 0 <= S*    -> F_L + S_L (U*_L - U_L)
 //   S* < 0 < S_R     -> F_R + S_R (U*_R - U_R)
 //   S_R <= 0         -> F_R
-// with U*_K = rho_K r [1, S*, ut_K, E_K/rho_K + (S*-u_K)(S* + p_K/(rho_K (S_K-u_K)))],
-// r = (S_K - u_K)/(S_K - S*), the energy entry expanded as
-// r E_K + r (S* - u_K)(rho_K S* + p_K/(S_K - u_K)).
+// With q = (S* - u_K)/(S_K - S*) (so that (S_K - u_K)/(S_K - S*) = 1 + q), the
+// jumps U*_K - U_K of the star state are formed directly:
+//   mass              rho q
+//   normal momentum   rho (S* - u_K + q S*)
+//   transverse        rho q ut
+//   energy            q (E + p + rho (S_K - u_K) S*)
+// which is Toro's star state rearranged: one reciprocal per face for q (plus
+// one for S*), and q = 0 exactly at a stationary contact (S* = u_K), where
+// the flux reduces to the physical flux.
 template <typename R, int NT>
 __device__ __forceinline__ void hllc(R rL, R unL, const R* utL, R pL, R rR, R unR, const R* utR,
                                      R pR, R gam, R inv_gm1, R* F) {
@@ -202,32 +211,28 @@ __device__ __forceinline__ void hllc(R rL, R unL, const R* utL, R pL, R rR, R un
   R S = left ? SL : SR;
   R d = left ? dL : dR;
   R ut[NT > 0 ? NT : 1];
-  R q = un * un;
+  R k2 = un * un;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     ut[t] = left ? utL[t] : utR[t];
-    q = q + ut[t] * ut[t];
+    k2 = k2 + ut[t] * ut[t];
   }
-  R E = p * inv_gm1 + R(0.5) * r * q;
+  R Ep = p * inv_gm1 + R(0.5) * r * k2 + p;  // E + p
 
-  // physical flux and conserved state of side K, star state, and the flux.
-  // The transverse momentum fluxes are u_t times the mass flux in every
-  // region (rho u u_t + S (rho* - rho) u_t), so only mass, normal momentum
-  // and energy go through the star-state formula.
+  // star jump factors; outside the star regions they are 0, which leaves
+  // the physical flux (S_K - S* may vanish there, so q is masked, not used)
+  R g = Ss - un;
+  R q = g * fast_rcp(S - Ss);
+  g = star ? g : R(0);
+  q = star ? q : R(0);
   R mn = r * un;
-  R rr = d / (S - Ss);  // exact quotient: 1 at a stationary contact, so U*_K = U_K
-  R fac = r * rr;
-  R F0s = mn + S * (fac - r);
-  R F1s = (mn * un + p) + S * (fac * Ss - mn);
-  R E_s = rr * E + rr * (Ss - un) * (r * Ss + p * fast_rcp(d));
-  R FE = (E + p) * un;
-  R FEs = FE + S * (E_s - E);
-  R F0 = star ? F0s : mn;
+  R Sr = S * r;
+  R F0 = mn + Sr * q;
   F[0] = F0;
-  F[1] = star ? F1s : mn * un + p;
+  F[1] = (mn * un + p) + Sr * (g + q * Ss);
 #pragma unroll
   for (int t = 0; t < NT; ++t) F[2 + t] = ut[t] * F0;
-  F[NT + 2] = star ? FEs : FE;
+  F[NT + 2] = Ep * un + (S * q) * (Ep + r * d * Ss);
 }
 
 // MUSCL-minmod face states from four cell states along the face normal

@@ -19,6 +19,8 @@
 // neighbouring tiles, which are served by L2), written once.
 #pragma once
 
+#include <type_traits>
+
 #include "hydro_device.hpp"
 
 namespace hard {
@@ -75,7 +77,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
   R* Fs = lds + NV * LXY;  // NV * NF: in-plane face fluxes, x faces then y faces
 
   const int tid = threadIdx.x;
-  const bool owner = tid < TX * TY;  // this thread owns a cell column of the tile
+  const bool owner = NT == TX * TY || tid < TX * TY;  // this thread owns a cell column of the tile
   const int tx = owner ? tid % TX : 0, ty = owner ? tid / TX : 0;
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const long long N = (long long)nx * ny * nz;
@@ -227,38 +229,53 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
     if (inside) flags |= cell_flags<R, NV>(Ucur, P0[NV - 1]);
     __syncthreads();
 
-    // ---- 2. in-plane faces.  In 3D the normal velocity of a y face is
+    // ---- 2. in-plane faces.  Each owner thread takes the low x face of
+    // its cell (and, in 3D, the low y face); the far faces (x = TX of every
+    // row, y = TY of every column) go to the threads that own no cell, or to
+    // a short third round.  In 3D the normal velocity of a y face is
     // variable slot 2 and its first transverse velocity slot 1: the swap is
     // done in the LDS addresses, so one code path serves both axes.
-    for (int f = tid; f < NF; f += NT) {
-      int base, stride;
-      const bool yface = PD == 2 && f >= NFX;
-      if (!yface) {
-        int fxx = f % (TX + 1), fyy = f / (TX + 1);
-        base = (fyy + OY) * LX + fxx;
-        stride = 1;
-      } else {
-        int g = f - NFX;
-        int fxx = g % TX, fyy = g / TX;
-        base = fyy * LX + fxx + 2;
-        stride = LX;
-      }
-      int slot[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) slot[v] = v;
-      if (PD == 2) {
-        slot[1] = yface ? 2 : 1;
-        slot[2] = yface ? 1 : 2;
-      }
+    auto face = [&](int base, int fidx, auto yface_c) {
+      constexpr bool YF = decltype(yface_c)::value;
+      constexpr int stride = YF ? LX : 1;
       R WL[NV], WR[NV], Fn[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const R* wp = Ws + slot[v] * LXY + base;
+        const int sv = (PD == 2 && YF && (v == 1 || v == 2)) ? 3 - v : v;
+        const R* wp = Ws + sv * LXY + base;
         muscl_pair(wp[0], wp[stride], wp[2 * stride], wp[3 * stride], WL[v], WR[v]);
       }
       hllc_ordered<R, NV>(WL, WR, gam, inv_gm1, Fn);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Fs[slot[v] * NF + f] = Fn[v];
+      for (int v = 0; v < NV; ++v) {
+        const int sv = (PD == 2 && YF && (v == 1 || v == 2)) ? 3 - v : v;
+        Fs[sv * NF + fidx] = Fn[v];
+      }
+    };
+    using XF = std::integral_constant<bool, false>;
+    using YF = std::integral_constant<bool, true>;
+    if constexpr (PD == 1) {
+      // a row: TX + 1 faces, face f between tile cells f - 1 and f
+      for (int f = tid; f < TX + 1; f += NT) face(f, f, XF{});
+    } else {
+      constexpr int NSPARE = NT - TX * TY;
+      const int sp = tid - TX * TY;  // spare-thread index (< 0 for owners)
+      if (owner) face((ty + OY) * LX + tx, ty * (TX + 1) + tx, XF{});
+      else if (sp < TY) face((sp + OY) * LX + TX, sp * (TX + 1) + TX, XF{});
+      if (owner) face(ty * LX + tx + 2, NFX + ty * TX + tx, YF{});
+      else if (sp < TX) face(TY * LX + sp + 2, NFX + TY * TX + sp, YF{});
+      if constexpr (NSPARE < TY || NSPARE < TX) {
+        // far faces the spare threads did not cover
+        constexpr int RX = NSPARE < TY ? TY - NSPARE : 0;
+        constexpr int RY = NSPARE < TX ? TX - NSPARE : 0;
+        if (tid < RX) {
+          const int j = NSPARE + tid;
+          face((j + OY) * LX + TX, j * (TX + 1) + TX, XF{});
+        } else if (tid < RX + RY) {
+          const int j = NSPARE + tid - RX;
+          face(TY * LX + j + 2, NFX + TY * TX + j, YF{});
+        }
+      }
     }
 
     // ---- 3. face w+1/2 from the register window
