@@ -26,6 +26,42 @@ import torch  # noqa: E402
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
+# Sources of the stage kernel; HBM byte counts taken with rocprofv3 are
+# reported only while these files are unchanged since the counters were read.
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_08971_amd", "csrc", f)
+                  for f in ("hydro_device.hpp", "stage_tile.hpp", "stage.hip", "launch.hpp")]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "stage_kernel_blast256_fp64_hbm_counters.md")
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Stage-2 HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    copy-kernel factor), from the committed counter summary, or None if the
+    kernel sources changed since it was taken."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            kv = dict(l.split(":", 1) for l in f.read().splitlines() if ":" in l and
+                      l.split(":", 1)[0].strip().startswith(("kernel-source-sha256", "stage2-")))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel-source-sha256") != kernel_source_hash():
+        return None
+    try:
+        return (int(kv["stage2-fetch-bytes-per-launch"]), int(kv["stage2-write-bytes-per-launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -253,6 +289,7 @@ def main():
     ach2 = b_stage2 / (s2.mean() * 1e-3) / 1e9
     ach1 = b_stage1 / (s1.mean() * 1e-3) / 1e9
     step_gbs = (b_stage1 + b_stage2) / (ms_per_step * 1e-3) / 1e9
+    traffic = measured_traffic() if n == 256 else None
 
     out = {
         "metric": "zone-updates/s",
@@ -273,7 +310,9 @@ def main():
         "achieved_hbm_gbs_step": step_gbs,
         "roofline": {"bound": "hbm", "kernel": "stage_kernel<3,double,2> (stage 2)",
                      "achieved": ach2, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach2 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": ach2 / HBM_PEAK_GBS,
+                     "traffic": (sum(traffic) if traffic else None),
+                     "traffic_fetch_write": traffic, "algorithmic_bytes": b_stage2,
                      "stage1_achieved": ach1, "stage1_ms": float(s1.mean()),
                      "stage2_ms": float(s2.mean())},
         "status_flags": flags,

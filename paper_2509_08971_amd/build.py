@@ -2,7 +2,11 @@
 
 Every .hip file under csrc/ is compiled to an object and linked into one
 shared library next to this file.  Packed FP32 instructions are disabled
-(-packed-fp32-ops) for all device code.
+(-packed-fp32-ops) for all device code.  Multiply-adds are fused only
+within one source expression (-ffp-contract=on), so the rounding of a
+formula is fixed by its source and does not depend on where the optimizer
+places it: the same tile body inlined into different kernels (or into the
+prologue and the loop of a walk) gives the same bits.
 """
 import concurrent.futures as cf
 import glob
@@ -18,7 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 FLAGS = [
-    "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
+    "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I", os.path.join(HERE, "..", "include"),

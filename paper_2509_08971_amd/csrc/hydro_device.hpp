@@ -66,11 +66,16 @@ __device__ __forceinline__ float minmod<float>(float a, float b) {
   return __builtin_amdgcn_fmed3f(a, b, 0.0f);
 }
 
-// Reciprocal and square root used inside the flux.  FP64: hardware
-// v_rcp_f64 / v_rsq_f64 seeds refined by two Newton (resp. Goldschmidt)
-// steps, within about 1 ulp of the correctly rounded value at a third of the
-// instructions of the IEEE sequences.  FP32: the hardware instructions
-// (1 ulp).  The CFL step keeps IEEE division and square root.
+// Reciprocal and square root.  FP64: the hardware v_rcp_f64 / v_rsq_f64
+// seeds (relative error about 5e-8 on gfx950) refined by Newton steps; each
+// step squares the error.  FP32: the hardware instructions (about 1 ulp).
+// The CFL sum keeps IEEE division and square root.
+//   fast_rcp   two steps, within about 1 ulp: primitive recovery (1/rho).
+//   flux_rcp   one step, within about 1e-14: the two quotients of the HLLC
+//              flux (S* and the star factor q).
+//   sound_speed  one step, within about 1e-14.
+// The flux tolerances are far below the 1e-12 parity bar and cost a third
+// of the instructions of the IEEE sequences.
 __device__ __forceinline__ double fast_rcp(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
@@ -80,25 +85,19 @@ __device__ __forceinline__ double fast_rcp(double x) {
 }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-__device__ __forceinline__ double fast_sqrt(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double g = x * y, h = 0.5 * y;
-  double r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  r = fma(-g, h, 0.5);
-  return fma(g, r, g);
+__device__ __forceinline__ double flux_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 }
-__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float flux_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // c = sqrt(gp / rho) = gp * rsq(gp * rho): one reciprocal square root
-// (refined in FP64) instead of a reciprocal and a square root.
+// instead of a reciprocal and a square root.
 __device__ __forceinline__ double sound_speed(double gp, double rho) {
   double x = gp * rho;
   double y = __builtin_amdgcn_rsq(x);
-  // two Newton steps for 1/sqrt(x): y <- y (3 - x y^2) / 2
+  // one Newton step for 1/sqrt(x): y <- y (3 - x y^2) / 2
   double h = 0.5 * x;
-  y = y * fma(-h * y, y, 1.5);
   y = y * fma(-h * y, y, 1.5);
   return gp * y;
 }
@@ -200,7 +199,7 @@ __device__ __forceinline__ void hllc(R rL, R unL, const R* utL, R pL, R rR, R un
   R SR = (aR >= bR) ? aR : bR;
   R dL = SL - unL, dR = SR - unR;
   R mL = rL * dL, mR = rR * dR;  // rho_K (S_K - u_K)
-  R Ss = (pR - pL + mL * unL - mR * unR) * fast_rcp(mL - mR);
+  R Ss = (pR - pL + mL * unL - mR * unR) * flux_rcp(mL - mR);
 
   // pick the side
   bool left = (SL >= R(0)) || (Ss >= R(0));
@@ -222,7 +221,7 @@ __device__ __forceinline__ void hllc(R rL, R unL, const R* utL, R pL, R rR, R un
   // star jump factors; outside the star regions they are 0, which leaves
   // the physical flux (S_K - S* may vanish there, so q is masked, not used)
   R g = Ss - un;
-  R q = g * fast_rcp(S - Ss);
+  R q = g * flux_rcp(S - Ss);
   g = star ? g : R(0);
   q = star ? q : R(0);
   R mn = r * un;
