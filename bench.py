@@ -158,7 +158,8 @@ def bench_batched(args, steps=100):
     log(f"  {ms / steps:.3f} ms/step, {zus / 1e9:.2f} G zu/s ({cells} cells)")
     return {"value": zus, "unit": "zone-updates/s", "ms_per_step": ms / steps, "steps": steps,
             "cells": cells, "problems": len(specs), "dtype": "f32 (internal energy, dt in f64)",
-            "launch": f"{steps} steps x 2 persistent launches replayed from one captured graph",
+            "launch": f"{steps} steps x (2 persistent stage launches + 1 per-problem dt "
+                      f"launch) replayed from one captured graph",
             "achieved_hbm_gbs": bytes_step / (ms / steps * 1e-3) / 1e9, "status_flags": flags}
 
 

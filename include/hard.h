@@ -159,7 +159,7 @@ typedef struct hard_batch_plan hard_batch_plan_t;
 /* Build a plan for nprob grids (host array, copied).  All grids must share
  * dtype and gamma.  Problem p's state occupies elements
  * [offset[p], offset[p+1]) of the packed buffer, laid out as a single grid.
- * tune_cache may name a text file of tile choices written by the
+ * tune_cache may name a text file of work-item shapes written by the
  * autotuner (NULL = built-in defaults).  *out is owned by the library until
  * hard_batch_plan_destroy.  Allocates device memory for the plan tables
  * (this is the only allocating call; it synchronises the device). */

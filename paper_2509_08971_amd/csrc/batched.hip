@@ -1,17 +1,19 @@
 // Batched Heun step: thousands of independent 1D/2D/3D problems, each with
 // its own grid, time step and CFL reduction, packed into one buffer.
 //
-// The plan turns every problem into tiles of the kernel's tile shape and
-// lays all tiles of all problems out as one work list, most expensive tile
-// first (longest-processing-time order).  Each stage is one persistent
-// launch: a grid sized to the machine pulls tiles from an atomic work
-// counter, runs the same tile body as the single-grid kernel
-// (stage_tile.hpp), and, in stage 2, folds the tile's CFL max into its
-// problem's slot; the last tile of a problem turns that slot into the
-// problem's next dt.  The last workgroup to run out of work re-arms the
-// counter, so the launch needs no memset and can be captured in a graph.
-// 1D and 2D problems share one launch; 3D problems (heavier tiles, more
-// registers) get their own.
+// The plan cuts every problem into work items (1D: rows of 63 cells; 2D:
+// 63-cell row segments walking a range of rows; 3D: x-y tiles walking a
+// range of z planes) and lays all items of all problems out as one list,
+// most expensive first (longest-processing-time order).  Each stage is one
+// persistent launch sized to the resident capacity of the machine; workgroup
+// b runs items b, b + G, b + 2G, ... of the list (static striding: no shared
+// counter, no atomics to hand out work).  The item body is the single-grid
+// tile body (stage_tile.hpp).  In stage 2 each item stores the CFL signal
+// max of its cells into its own slot; a small kernel then reduces the slots
+// of each problem into the problem's next dt.  Nothing needs clearing
+// between launches, so the step can be captured in a graph.  1D and 2D
+// problems share one launch (one wave per item); 3D problems (heavier
+// tiles, more registers) get their own.
 
 #include <algorithm>
 #include <cmath>
@@ -40,17 +42,12 @@ struct BatchProblem {
   int dx_pow2;
   int tiles_x, tiles_y, nchunk, ntiles;  // work items of this problem
   int walk;                              // walk positions per work item (2D rows, 3D planes)
+  int slot0;                             // first CFL slot of the problem (one per item)
 };
 
 struct WorkItem {
   int prob;
   int tile;
-};
-
-struct BatchQueue {
-  unsigned next;  // next work item to hand out
-  unsigned done;  // workgroups that found the list empty
-  unsigned pad[2];
 };
 
 struct BatchArgs {
@@ -60,14 +57,11 @@ struct BatchArgs {
   const BatchProblem* probs;
   const WorkItem* items;
   int nitems;
-  double* dt;                    // per-problem dt (read; written by stage 2 when update_dt)
-  unsigned long long* smax;      // per-problem CFL slot
-  unsigned* cnt;                 // per-problem finished-item counter
-  BatchQueue* q;
-  Control* ctl;                  // status bits
+  double* dt;        // per-problem dt (read)
+  double* slot;      // per-item CFL signal max (written when the item computes it)
+  Control* ctl;      // status bits
   double gamma;
-  double cfl;
-  int update_dt;
+  int fuse_cfl;      // stage 2: store the CFL signal max of the new state
 };
 
 // 1D and 2D problems: one wave per work item.  A 1D item is a row of 63
@@ -79,42 +73,39 @@ constexpr int ROW = BT12 - 1;
 constexpr int BT3 = 256;
 constexpr int kTiles3D[3][2] = {{16, 16}, {32, 8}, {8, 32}};
 
-// Item-level finish: status bits to the control block, CFL max to the
-// problem's slot; the last item of the problem writes its dt.
+// Item-level finish: status bits to the control block, the item's CFL
+// signal max to its slot.
 template <int NTHR>
 __device__ __forceinline__ void tile_finish(unsigned flags, double smax, bool do_cfl,
-                                            const BatchArgs& a, int p, int nitems_p) {
+                                            const BatchArgs& a, int slot) {
   constexpr int NW = NTHR / 64;
-  __shared__ double red_s[NW];
-  __shared__ unsigned red_f[NW];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   flags = wave_or(flags);
   if (do_cfl) smax = wave_max(smax);
-  if (lane == 0) {
-    red_f[w] = flags;
-    red_s[w] = smax;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned f = 0;
-    double s = 0.0;
-    for (int i = 0; i < NW; ++i) {
-      f |= red_f[i];
-      s = fmax(s, red_s[i]);
+  if constexpr (NW == 1) {
+    if (threadIdx.x == 0) {
+      if (flags) atomicOr(&a.ctl->flags, flags);
+      if (do_cfl) a.slot[slot] = smax;
     }
-    if (f) atomicOr(&a.ctl->flags, f);
-    if (do_cfl) {
-      atomicMax(&a.smax[p], (unsigned long long)__double_as_longlong(s));
-      __threadfence();
-      unsigned prev = atomicAdd(&a.cnt[p], 1u);
-      if (prev == (unsigned)nitems_p - 1) {
-        __threadfence();
-        unsigned long long bits = atomicAdd(&a.smax[p], 0ull);
-        a.dt[p] = a.cfl / __longlong_as_double((long long)bits);
-        atomicExch(&a.smax[p], 0ull);
-        atomicExch(&a.cnt[p], 0u);
+  } else {
+    __shared__ double red_s[NW];
+    __shared__ unsigned red_f[NW];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+      red_f[w] = flags;
+      red_s[w] = smax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned f = 0;
+      double m = 0.0;
+      for (int i = 0; i < NW; ++i) {
+        f |= red_f[i];
+        m = fmax(m, red_s[i]);
       }
+      if (f) atomicOr(&a.ctl->flags, f);
+      if (do_cfl) a.slot[slot] = m;
     }
+    __syncthreads();  // red_* are reused by the next item
   }
 }
 
@@ -150,34 +141,13 @@ __device__ __forceinline__ void item_geometry(const BatchProblem& P, int tile, i
   t.w1 = P.ndim >= 2 ? min(t.w0 + P.walk, nwalk) : 1;
 }
 
-// Pull the next work item (one per workgroup); -1 when the list is empty.
-__device__ __forceinline__ int next_item(const BatchArgs& a) {
-  __shared__ int item_s;
-  __syncthreads();  // every thread has read the previous item
-  if (threadIdx.x == 0) item_s = (int)atomicAdd(&a.q->next, 1u);
-  __syncthreads();
-  int it = item_s;
-  return it < a.nitems ? it : -1;
-}
-
-__device__ __forceinline__ void queue_exit(const BatchArgs& a) {
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(&a.q->done, 1u);
-    if (prev == gridDim.x - 1) {
-      // every workgroup has drawn its last item: re-arm for the next launch
-      atomicExch(&a.q->next, 0u);
-      atomicExch(&a.q->done, 0u);
-    }
-  }
-}
-
 template <typename R, int STAGE>
 __global__ __launch_bounds__(BT12) void batched_stage_12(BatchArgs a) {
   constexpr int L1 = TileShape<1, R, ROW, 1>::lds_elems;
   constexpr int L2 = TileShape<2, R, ROW, 1>::lds_elems;
   __shared__ R lds[L1 > L2 ? L1 : L2];
-  const bool do_cfl = STAGE == 2 && a.update_dt;
-  for (int it = next_item(a); it >= 0; it = next_item(a)) {
+  const bool do_cfl = STAGE == 2 && a.fuse_cfl;
+  for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
     const WorkItem w = a.items[it];
     const BatchProblem P = a.probs[w.prob];
     TileArgs t = tile_args(a, P, sizeof(R));
@@ -190,9 +160,9 @@ __global__ __launch_bounds__(BT12) void batched_stage_12(BatchArgs a) {
       run_tile<1, R, STAGE, ROW, 1, BT12>(t, lds, flags, smax);
     else
       run_tile<2, R, STAGE, ROW, 1, BT12>(t, lds, flags, smax);
-    tile_finish<BT12>(flags, smax, do_cfl, a, w.prob, P.ntiles);
+    tile_finish<BT12>(flags, smax, do_cfl, a, P.slot0 + w.tile);
+    __syncthreads();  // the next item rewrites lds
   }
-  queue_exit(a);
 }
 
 template <typename R, int STAGE, int TS>
@@ -200,8 +170,8 @@ __global__ __launch_bounds__(BT3) __attribute__((amdgpu_waves_per_eu(sizeof(R) =
 void batched_stage_3(BatchArgs a) {
   constexpr int TX = kTiles3D[TS][0], TY = kTiles3D[TS][1];
   __shared__ R lds[TileShape<3, R, TX, TY>::lds_elems];
-  const bool do_cfl = STAGE == 2 && a.update_dt;
-  for (int it = next_item(a); it >= 0; it = next_item(a)) {
+  const bool do_cfl = STAGE == 2 && a.fuse_cfl;
+  for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
     const WorkItem w = a.items[it];
     const BatchProblem P = a.probs[w.prob];
     TileArgs t = tile_args(a, P, sizeof(R));
@@ -211,15 +181,16 @@ void batched_stage_3(BatchArgs a) {
     unsigned flags = 0;
     double smax = 0.0;
     run_tile<3, R, STAGE, TX, TY, BT3>(t, lds, flags, smax);
-    tile_finish<BT3>(flags, smax, do_cfl, a, w.prob, P.ntiles);
+    tile_finish<BT3>(flags, smax, do_cfl, a, P.slot0 + w.tile);
+    __syncthreads();
   }
-  queue_exit(a);
 }
 
-// Per-problem CFL dt of the current state (standalone), item by item.
+// CFL signal max of the current state (standalone), item by item, into the
+// items' slots.
 template <typename R, int NTHR>
 __global__ __launch_bounds__(NTHR) void batched_cfl(BatchArgs a, int tx3, int ty3) {
-  for (int it = next_item(a); it >= 0; it = next_item(a)) {
+  for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
     const WorkItem w = a.items[it];
     const BatchProblem P = a.probs[w.prob];
     const R* U = reinterpret_cast<const R*>(static_cast<const char*>(a.src) + P.offset * sizeof(R));
@@ -258,9 +229,19 @@ __global__ __launch_bounds__(NTHR) void batched_cfl(BatchArgs a, int tx3, int ty
         }
       }
     }
-    tile_finish<NTHR>(flags, smax, true, a, w.prob, P.ntiles);
+    tile_finish<NTHR>(flags, smax, true, a, P.slot0 + w.tile);
   }
-  queue_exit(a);
+}
+
+// dt of every problem from its items' slots: cfl / max(slot).
+__global__ void batched_dt_final(int nprob, const BatchProblem* probs, const double* slot,
+                                 double cfl, double* dt) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  const int s0 = probs[p].slot0, ns = probs[p].ntiles;
+  double m = 0.0;
+  for (int i = 0; i < ns; ++i) m = fmax(m, slot[s0 + i]);
+  dt[p] = cfl / m;
 }
 
 // Per-problem time control of hard_run_batched: clip dt so each problem
@@ -321,8 +302,8 @@ struct hard_batch_plan {
   WorkItem* d_items3 = nullptr;
   int grid12 = 0, grid3 = 0;
   // workspace layout
-  size_t ws_ctl = 0, ws_q12 = 0, ws_q3 = 0, ws_active = 0, ws_smax = 0, ws_cnt = 0, ws_t = 0,
-         ws_steps = 0, ws_stage = 0, ws_total = 0;
+  size_t ws_ctl = 0, ws_active = 0, ws_slot = 0, ws_t = 0, ws_steps = 0, ws_stage = 0,
+         ws_total = 0;
 };
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -366,11 +347,18 @@ static hard_status_t batch_common(const hard_batch_plan_t* P, const void* U, con
   std::memset(a, 0, sizeof *a);
   a->probs = P->d_probs;
   a->dt = const_cast<double*>(dt);
-  a->smax = reinterpret_cast<unsigned long long*>(wb + P->ws_smax);
-  a->cnt = reinterpret_cast<unsigned*>(wb + P->ws_cnt);
+  a->slot = reinterpret_cast<double*>(wb + P->ws_slot);
   a->ctl = reinterpret_cast<Control*>(wb + P->ws_ctl);
   a->gamma = P->gamma;
   return HARD_OK;
+}
+
+static hipError_t launch_dt_final(const hard_batch_plan_t* P, const BatchArgs& a, double cfl,
+                                  hipStream_t s) {
+  const int nb = (P->nprob + 255) / 256;
+  hipLaunchKernelGGL(batched_dt_final, dim3(nb), dim3(256), 0, s, P->nprob,
+                     (const BatchProblem*)P->d_probs, (const double*)a.slot, cfl, a.dt);
+  return hipGetLastError();
 }
 
 template <typename R, int STAGE>
@@ -380,7 +368,6 @@ static hipError_t launch_batched_stage(const hard_batch_plan_t* P, BatchArgs a, 
     BatchArgs b = a;
     b.items = P->d_items12;
     b.nitems = P->nitems12;
-    b.q = reinterpret_cast<BatchQueue*>(wb + P->ws_q12);
     hipLaunchKernelGGL((batched_stage_12<R, STAGE>), dim3(P->grid12), dim3(BT12), 0, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -389,7 +376,6 @@ static hipError_t launch_batched_stage(const hard_batch_plan_t* P, BatchArgs a, 
     BatchArgs b = a;
     b.items = P->d_items3;
     b.nitems = P->nitems3;
-    b.q = reinterpret_cast<BatchQueue*>(wb + P->ws_q3);
     switch (P->tile3d) {
       case 0: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 0>), dim3(P->grid3), dim3(BT3), 0, s, b); break;
       case 1: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 1>), dim3(P->grid3), dim3(BT3), 0, s, b); break;
@@ -420,7 +406,7 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
   struct Cost { double c; WorkItem w; };
   std::vector<Cost> c12, c3;
   P->offsets.resize(nprob + 1);
-  long long off = 0;
+  long long off = 0, nslot = 0;
   for (int p = 0; p < nprob; ++p) {
     Grid G;
     hard_status_t st = check_grid(&grids[p], &G);
@@ -465,6 +451,12 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
       cells = (double)TX3 * TY3 * std::min(B.walk, G.n[2]);
     }
     B.ntiles = B.tiles_x * B.tiles_y * B.nchunk;
+    B.slot0 = (int)nslot;
+    nslot += B.ntiles;
+    if (nslot > (1LL << 30)) {
+      delete P;
+      return fail(HARD_ERR_INVALID_ARG, "batch has more than 2^30 work items");
+    }
     const double cost = cells * G.ndim;  // faces per cell ~ ndim
     for (int t = 0; t < B.ntiles; ++t) (G.ndim == 3 ? c3 : c12).push_back({cost, {p, t}});
     // keep every problem 256-byte aligned
@@ -484,12 +476,24 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
   for (auto& c : c3) i3.push_back(c.w);
   P->nitems12 = (int)i12.size();
   P->nitems3 = (int)i3.size();
+  // persistent grids: the resident capacity of the machine for the stage-2
+  // kernel (the larger register footprint), at most one workgroup per item
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     ncu = 256;
-  P->grid12 = std::max(1, std::min(P->nitems12, ncu * 32));
-  P->grid3 = std::max(1, std::min(P->nitems3, ncu * 3));
+  int occ12 = 0, occ3 = 0;
+  if (P->dtype == HARD_F64) {
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ12, batched_stage_12<double, 2>, BT12, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ3, batched_stage_3<double, 2, 0>, BT3, 0);
+  } else {
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ12, batched_stage_12<float, 2>, BT12, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ3, batched_stage_3<float, 2, 1>, BT3, 0);
+  }
+  occ12 = std::max(1, std::min(occ12, 32));
+  occ3 = std::max(1, std::min(occ3, 8));
+  P->grid12 = std::max(1, std::min(P->nitems12, ncu * occ12));
+  P->grid3 = std::max(1, std::min(P->nitems3, ncu * occ3));
   hipError_t e;
   if ((e = hipMalloc(&P->d_probs, sizeof(BatchProblem) * nprob)) != hipSuccess ||
       (e = hipMalloc(&P->d_items12, sizeof(WorkItem) * std::max(1, P->nitems12))) != hipSuccess ||
@@ -503,15 +507,12 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
     hard_batch_plan_destroy(P);
     return hip_fail(e, "hard_batch_plan_create copy");
   }
-  // workspace: control | queue 1D/2D | queue 3D | run counter | smax[nprob] |
-  // cnt[nprob] | t[nprob] | steps[nprob] | stage state
+  // workspace: control | run counter | slot[items] | t[nprob] | steps[nprob] |
+  // stage state
   P->ws_ctl = 0;
-  P->ws_q12 = 256;
-  P->ws_q3 = 512;
-  P->ws_active = 768;
-  P->ws_smax = 1024;
-  P->ws_cnt = P->ws_smax + al256(sizeof(unsigned long long) * nprob);
-  P->ws_t = P->ws_cnt + al256(sizeof(unsigned) * nprob);
+  P->ws_active = 256;
+  P->ws_slot = 512;
+  P->ws_t = P->ws_slot + al256(sizeof(double) * (size_t)nslot);
   P->ws_steps = P->ws_t + al256(sizeof(double) * nprob);
   P->ws_stage = P->ws_steps + al256(sizeof(long long) * nprob);
   P->ws_total = P->ws_stage + al256((size_t)P->total_elems * P->wsize);
@@ -547,15 +548,12 @@ hard_status_t hard_cfl_dt_batched(const hard_batch_plan_t* P, const void* U, dou
   if (st) return st;
   if ((st = check_cfl(cfl))) return st;
   a.src = U;
-  a.cfl = cfl;
-  char* wb = static_cast<char*>(work);
   hipStream_t s = (hipStream_t)stream;
   const int TX3 = kTiles3D[P->tile3d][0], TY3 = kTiles3D[P->tile3d][1];
   if (P->nitems12) {
     BatchArgs b = a;
     b.items = P->d_items12;
     b.nitems = P->nitems12;
-    b.q = reinterpret_cast<BatchQueue*>(wb + P->ws_q12);
     if (P->dtype == HARD_F64)
       hipLaunchKernelGGL((batched_cfl<double, BT12>), dim3(P->grid12), dim3(BT12), 0, s, b, TX3, TY3);
     else
@@ -567,7 +565,6 @@ hard_status_t hard_cfl_dt_batched(const hard_batch_plan_t* P, const void* U, dou
     BatchArgs b = a;
     b.items = P->d_items3;
     b.nitems = P->nitems3;
-    b.q = reinterpret_cast<BatchQueue*>(wb + P->ws_q3);
     if (P->dtype == HARD_F64)
       hipLaunchKernelGGL((batched_cfl<double, BT3>), dim3(P->grid3), dim3(BT3), 0, s, b, TX3, TY3);
     else
@@ -575,6 +572,8 @@ hard_status_t hard_cfl_dt_batched(const hard_batch_plan_t* P, const void* U, dou
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "hard_cfl_dt_batched");
   }
+  hipError_t e = launch_dt_final(P, a, cfl, s);
+  if (e != hipSuccess) return hip_fail(e, "hard_cfl_dt_batched final");
   return ok();
 }
 
@@ -588,8 +587,7 @@ hard_status_t hard_hydro_step_batched(const hard_batch_plan_t* P, void* U, doubl
   char* wb = static_cast<char*>(work);
   void* U1 = wb + P->ws_stage;
   hipStream_t s = (hipStream_t)stream;
-  a.cfl = cfl;
-  a.update_dt = 0;
+  a.fuse_cfl = 0;
   a.src = U;
   a.un = U;
   a.dst = U1;
@@ -599,10 +597,12 @@ hard_status_t hard_hydro_step_batched(const hard_batch_plan_t* P, void* U, doubl
   a.src = U1;
   a.un = U;
   a.dst = U;
-  a.update_dt = update_dt ? 1 : 0;
+  a.fuse_cfl = update_dt ? 1 : 0;
   e = P->dtype == HARD_F64 ? launch_batched_stage<double, 2>(P, a, wb, s)
                            : launch_batched_stage<float, 2>(P, a, wb, s);
   if (e != hipSuccess) return hip_fail(e, "hard_hydro_step_batched stage 2");
+  if (update_dt && (e = launch_dt_final(P, a, cfl, s)) != hipSuccess)
+    return hip_fail(e, "hard_hydro_step_batched dt");
   return ok();
 }
 
