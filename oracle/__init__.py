@@ -67,6 +67,8 @@ def lib(path=None):
         L.oracle_minmod.restype = ctypes.c_double
         L.oracle_threads.argtypes = []
         L.oracle_threads.restype = ctypes.c_int
+        L.oracle_count_ops.argtypes = common + [ctypes.c_double, dp, i64p]
+        L.oracle_count_ops.restype = None
         _lib = L
     return _lib
 
@@ -188,6 +190,35 @@ def hllc(WL, WR, gamma=1.4):
     F = np.empty(nt + 3)
     lib().oracle_hllc(nt, float(gamma), _dptr(WL), _dptr(WR), _dptr(F))
     return F
+
+
+OP_KINDS = ("add", "mul", "div", "sqrt", "cmp", "abs")
+
+
+def count_ops(g: Grid, U, dt):
+    """Floating-point operations of one CFL dt plus one SSP-RK2 step of U, by
+    kind (add/sub, mul, div, sqrt, compare, abs), as the oracle evaluates them
+    (ghost cells included).  Runs on one thread."""
+    U = _as_state(g, U)
+    out = (ctypes.c_int64 * 6)()
+    lib().oracle_count_ops(*g._args(), float(dt), _dptr(U), out)
+    return dict(zip(OP_KINDS, list(out)))
+
+
+def ops_per_zone_update(ndim, U_of_n, n_small, n_large, bc=None, dt=1e-4):
+    """Operations per zone-update without the ghost-layer overhead: counts on
+    an n_small^d and an n_large^d grid, with ops(n) = a n^d + b n^(d-1) solved
+    for a per kind (the ghost-cell and extra-face work grows with n^(d-1))."""
+    out = {}
+    res = []
+    for n in (n_small, n_large):
+        g = Grid((n,) * ndim, bc=bc or (PERIODIC, PERIODIC))
+        res.append(count_ops(g, U_of_n(n), dt))
+    a, b = float(n_small), float(n_large)
+    for k in OP_KINDS:
+        c1, c2 = res[0][k] / a ** (ndim - 1), res[1][k] / b ** (ndim - 1)
+        out[k] = (c2 - c1) / (b - a)
+    return out
 
 
 def threads():

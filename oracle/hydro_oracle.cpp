@@ -72,6 +72,35 @@ inline double value(Dual a) { return a.v; }
 using std::fabs;
 using std::sqrt;
 
+// ----------------------------------------------------------------------------
+// Operation-counting scalar: a double that tallies the floating-point
+// operations applied to it (for the algorithmic operation count per
+// zone-update).  The tallies are plain globals, so counting runs use one
+// thread.
+// ----------------------------------------------------------------------------
+struct OpTally {
+  long long add, mul, div, sqrt, cmp, abs;
+};
+static OpTally g_ops;
+
+struct Cnt {
+  double v;
+  Cnt() : v(0.0) {}
+  Cnt(double a) : v(a) {}  // NOLINT: constants promote implicitly
+};
+inline Cnt operator+(Cnt a, Cnt b) { ++g_ops.add; return Cnt(a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { ++g_ops.add; return Cnt(a.v - b.v); }
+inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
+inline Cnt operator*(Cnt a, Cnt b) { ++g_ops.mul; return Cnt(a.v * b.v); }
+inline Cnt operator/(Cnt a, Cnt b) { ++g_ops.div; return Cnt(a.v / b.v); }
+inline Cnt sqrt(Cnt a) { ++g_ops.sqrt; return Cnt(std::sqrt(a.v)); }
+inline Cnt fabs(Cnt a) { ++g_ops.abs; return Cnt(std::fabs(a.v)); }
+inline bool operator<(Cnt a, Cnt b) { ++g_ops.cmp; return a.v < b.v; }
+inline bool operator<=(Cnt a, Cnt b) { ++g_ops.cmp; return a.v <= b.v; }
+inline bool operator>(Cnt a, Cnt b) { ++g_ops.cmp; return a.v > b.v; }
+inline bool operator>=(Cnt a, Cnt b) { ++g_ops.cmp; return a.v >= b.v; }
+inline double value(Cnt a) { return a.v; }
+
 // Status bits reported for a non-physical state.
 enum : int { ST_RHO = 1, ST_PRES = 2, ST_NONFINITE = 4 };
 
@@ -423,20 +452,21 @@ static int step(const Grid& g, T* U, T dt) {
 }
 
 // Largest signal speed sum over the interior: max_i sum_d (|u_d| + c)/dx_d
-static double max_signal(const Grid& g, const double* U, int* status) {
+template <class T>
+static double max_signal(const Grid& g, const T* U, int* status) {
   const int nv = g.nvar, nd = g.ndim;
   const int64_t N = g.ncell;
   double smax = 0.0;
   int st = 0;
 #pragma omp parallel for schedule(static) reduction(max : smax) reduction(| : st)
   for (int64_t c = 0; c < N; ++c) {
-    double u[5], w[5];
+    T u[5], w[5];
     for (int v = 0; v < nv; ++v) u[v] = U[(size_t)v * N + c];
     st |= primitives(u, nd, g.gamma, w);
-    double cs = std::sqrt(g.gamma * w[nd + 1] / w[0]);
-    double s = 0.0;
-    for (int d = 0; d < nd; ++d) s = s + (std::fabs(w[1 + d]) + cs) / g.dx[d];
-    if (s > smax) smax = s;
+    T cs = sqrt(T(g.gamma) * w[nd + 1] / w[0]);
+    T s(0.0);
+    for (int d = 0; d < nd; ++d) s = s + (fabs(w[1 + d]) + cs) / T(g.dx[d]);
+    if (value(s) > smax) smax = value(s);
   }
   *status = st;
   return smax;
@@ -544,11 +574,40 @@ void oracle_hllc(int nt, double gamma, const double* WL, const double* WR, doubl
 
 double oracle_minmod(double a, double b) { return minmod<double>(a, b); }
 
+// Floating-point operations of one CFL dt plus one SSP-RK2 step of U (left
+// unchanged), tallied by kind: out[0..5] = add/sub, mul, div, sqrt, compare,
+// abs.  Runs on one thread.
+void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+                      double dt, const double* U, int64_t* out);
+
 #ifdef _OPENMP
 #include <omp.h>
 int oracle_threads(void) { return omp_get_max_threads(); }
 #else
 int oracle_threads(void) { return 1; }
+static void omp_set_num_threads(int) {}
+static int omp_get_max_threads(void) { return 1; }
 #endif
+
+void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+                      double dt, const double* U, int64_t* out) {
+  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  const int64_t M = (int64_t)g.nvar * g.ncell;
+  std::vector<Cnt> X(M);
+  for (int64_t x = 0; x < M; ++x) X[x] = Cnt(U[x]);
+  const int threads = omp_get_max_threads();
+  omp_set_num_threads(1);
+  g_ops = OpTally{0, 0, 0, 0, 0, 0};
+  int st = 0;
+  (void)max_signal(g, X.data(), &st);
+  (void)step<Cnt>(g, X.data(), Cnt(dt));
+  omp_set_num_threads(threads);
+  out[0] = g_ops.add;
+  out[1] = g_ops.mul;
+  out[2] = g_ops.div;
+  out[3] = g_ops.sqrt;
+  out[4] = g_ops.cmp;
+  out[5] = g_ops.abs;
+}
 
 }  // extern "C"

@@ -118,8 +118,10 @@ __device__ __forceinline__ TileArgs tile_args(const BatchArgs& a, const BatchPro
     t.n[k] = P.n[k];
     t.bc[k][0] = P.bc[k][0];
     t.bc[k][1] = P.bc[k][1];
+    t.dx[k] = P.dx[k];
     t.inv_dx[k] = P.inv_dx[k];
   }
+  t.dx_pow2 = P.dx_pow2;
   t.gamma = a.gamma;
   return t;
 }

@@ -306,26 +306,6 @@ __device__ __forceinline__ double signal_sum(const double* U, const double* dx,
   return s;
 }
 
-// The same signal sum for the fused CFL of stage 2, from the refined
-// hardware reciprocal and reciprocal square root (fast_rcp, sound_speed) and
-// 1/dx: within about 1e-14 relative of the IEEE evaluation above, at a third
-// of its instructions.  The standalone CFL (the first dt of a run) keeps the
-// IEEE form.
-template <int NDIM>
-__device__ __forceinline__ double signal_sum_fast(const double* U, const double* inv_dx,
-                                                  double gamma) {
-  const double inv = fast_rcp(U[0]);
-  double q = U[1] * U[1];
-#pragma unroll
-  for (int d = 1; d < NDIM; ++d) q = q + U[1 + d] * U[1 + d];
-  const double p = (gamma - 1.0) * (U[NDIM + 1] - 0.5 * q * inv);
-  const double cs = sound_speed(gamma * p, U[0]);
-  double s = 0.0;
-#pragma unroll
-  for (int d = 0; d < NDIM; ++d) s = s + (fabs(U[1 + d]) * inv + cs) * inv_dx[d];
-  return s;
-}
-
 // Block-wide: OR of status flags and max of CFL sums; one atomic each per
 // block; last block finalises dt.  Must be called by every thread.
 template <int NTHREADS>

@@ -37,8 +37,10 @@ void stage_kernel(StageArgs a) {
     t.n[d] = a.n[d];
     t.bc[d][0] = a.bc[d][0];
     t.bc[d][1] = a.bc[d][1];
+    t.dx[d] = a.dx[d];
     t.inv_dx[d] = a.inv_dx[d];
   }
+  t.dx_pow2 = a.dx_pow2;
   t.gamma = a.gamma;
   t.dt = *a.dt;
   t.x0 = tile_x * TX;

@@ -31,7 +31,9 @@ struct TileArgs {
   void* dst;        // U^1 (stage 1) or U^{n+1} (stage 2; may alias un)
   int n[3];
   int bc[3][2];
+  double dx[3];
   double inv_dx[3];
+  int dx_pow2;      // every dx is a power of two: x / dx == x * (1/dx) exactly
   double gamma;
   double dt;
   int x0, y0;       // tile origin (y0: 3D only)
@@ -320,7 +322,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
         double Ud[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) Ud[v] = (double)Out[v];
-        smax = fmax(smax, signal_sum_fast<NDIM>(Ud, a.inv_dx, a.gamma));
+        smax = fmax(smax, signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
       }
     }
 
