@@ -71,6 +71,16 @@ typedef int32_t hard_status_t;
 #define HARD_F64 0
 #define HARD_F32 1
 
+/* Face schemes.  HARD_SCHEME_MUSCL_HLLC: MUSCL-minmod face states of the
+ * primitive variables with the HLLC flux (two ghost layers), in the fused
+ * tile kernels.  HARD_SCHEME_WENO5Z_HLL: the paper's own choice (section
+ * 2.2.2), WENO5-Z face states of the primitive variables (Borges et al.
+ * 2008) with the HLL flux (three ghost layers), as a pipeline of per-axis
+ * face kernels; single-grid calls only (the batched and adjoint calls return
+ * HARD_ERR_UNSUPPORTED for it). */
+#define HARD_SCHEME_MUSCL_HLLC 0
+#define HARD_SCHEME_WENO5Z_HLL 1
+
 /* Status-word bits (hard_status_read). */
 #define HARD_FLAG_DENSITY 1u   /* rho <= 0 or NaN in some cell */
 #define HARD_FLAG_PRESSURE 2u  /* p <= 0 or NaN in some cell */
@@ -84,6 +94,9 @@ typedef struct hard_grid_t {
   double gamma;     /* ratio of specific heats, > 1 */
   int32_t bc[3][2]; /* boundary kind per axis, [axis][0 = low, 1 = high];
                        periodic must be set on both sides of an axis */
+  int32_t scheme;   /* face scheme: HARD_SCHEME_MUSCL_HLLC (0, the default of a
+                       zero-initialised struct) or HARD_SCHEME_WENO5Z_HLL (1,
+                       needs n >= 3 on every axis) */
 } hard_grid_t;
 
 /* Description of the last error on the calling thread ("" if none).  The
@@ -110,7 +123,7 @@ hard_status_t hard_cfl_dt(const hard_grid_t* g, const void* U, double cfl, doubl
 /* One Heun (SSP-RK2) step of size *dt_dev (section 2.2.2, Butcher tableau):
  *     U1 = U + dt L(U),   U_new = (U + (U1 + dt L(U1))) / 2,
  *     L(U)_i = - sum_d (F_{d,i+1/2} - F_{d,i-1/2}) / dx_d,
- * with HLLC fluxes of MUSCL-minmod primitive face states.  U is overwritten
+ * with the face states and fluxes of g->scheme.  U is overwritten
  * with U_new.  If next_dt_dev is not NULL the CFL step of U_new (same
  * formula as hard_cfl_dt, factor cfl) is written there in the same pass;
  * next_dt_dev may equal dt_dev.  Stream-ordered, no host synchronisation,
@@ -124,7 +137,9 @@ hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_de
  *   stage 2: dst = (un + (src + dt L(src))) / 2         (src = U^1, un = U^n)
  * dst may alias un in stage 2, never src.  next_dt_dev (stage 2 only, may be
  * NULL) receives the CFL step of dst.  Same layouts and rules as
- * hard_hydro_step; the workspace provides the control block only. */
+ * hard_hydro_step; for HARD_SCHEME_MUSCL_HLLC the workspace needs only the
+ * control block (256 bytes), for HARD_SCHEME_WENO5Z_HLL the full
+ * hard_workspace_bytes. */
 hard_status_t hard_hydro_stage(const hard_grid_t* g, int32_t stage, const void* src,
                                const void* un, void* dst, const double* dt_dev, double cfl,
                                double* next_dt_dev, void* work, size_t work_bytes, void* stream);

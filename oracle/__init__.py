@@ -23,6 +23,7 @@ import numpy as np
 from . import build as _build
 
 PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
+MUSCL_HLLC, WENO5Z_HLL = 0, 1  # face reconstruction + flux schemes
 
 _lib = None
 
@@ -47,7 +48,7 @@ def lib(path=None):
         i64p = ctypes.POINTER(ctypes.c_int64)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
-        common = [ctypes.c_int, i64p, dp, ctypes.c_double, ip]
+        common = [ctypes.c_int, i64p, dp, ctypes.c_double, ip, ctypes.c_int]
         L.oracle_rhs.argtypes = common + [dp, dp]
         L.oracle_rhs.restype = ctypes.c_int
         L.oracle_step.argtypes = common + [ctypes.c_double, dp]
@@ -65,6 +66,10 @@ def lib(path=None):
         L.oracle_hllc.restype = None
         L.oracle_minmod.argtypes = [ctypes.c_double, ctypes.c_double]
         L.oracle_minmod.restype = ctypes.c_double
+        L.oracle_hll.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp]
+        L.oracle_hll.restype = None
+        L.oracle_weno5z.argtypes = [dp]
+        L.oracle_weno5z.restype = ctypes.c_double
         L.oracle_threads.argtypes = []
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_count_ops.argtypes = common + [ctypes.c_double, dp, i64p]
@@ -80,6 +85,7 @@ class Grid:
     gamma: float = 1.4
     bc: Sequence[int] = (OUTFLOW, OUTFLOW)  # (lo, hi) per axis, flattened
     dx: Sequence[float] = field(default=None)
+    scheme: int = 0  # MUSCL_HLLC or WENO5Z_HLL
 
     def __post_init__(self):
         self.n = tuple(int(v) for v in self.n)
@@ -91,6 +97,9 @@ class Grid:
             bc = bc * self.ndim
         self.bc = bc
         assert len(self.bc) == 2 * self.ndim
+        assert self.scheme in (MUSCL_HLLC, WENO5Z_HLL)
+        ng = 3 if self.scheme == WENO5Z_HLL else 2
+        assert min(self.n) >= ng, f"need at least {ng} cells per axis"
 
     @property
     def ndim(self):
@@ -109,7 +118,7 @@ class Grid:
         n3 = (ctypes.c_int64 * 3)(*(list(self.n) + [1] * (3 - self.ndim)))
         dx3 = (ctypes.c_double * 3)(*(list(self.dx) + [1.0] * (3 - self.ndim)))
         bc6 = (ctypes.c_int * 6)(*(list(self.bc) + [0] * (6 - 2 * self.ndim)))
-        return [self.ndim, n3, dx3, self.gamma, bc6]
+        return [self.ndim, n3, dx3, self.gamma, bc6, int(self.scheme)]
 
 
 def _dptr(a):
@@ -228,6 +237,23 @@ def threads():
 
 def minmod(a, b):
     return lib().oracle_minmod(float(a), float(b))
+
+
+def hll(WL, WR, gamma=1.4):
+    """HLL flux for face states (rho, un, ut..., p) -> (mass, mom_n, mom_t..., energy)."""
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    nt = WL.size - 3
+    F = np.empty(nt + 3)
+    lib().oracle_hll(nt, float(gamma), _dptr(WL), _dptr(WR), _dptr(F))
+    return F
+
+
+def weno5z(v):
+    """WENO5-Z value at the right face of the middle cell of five cell values."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert v.size == 5
+    return lib().oracle_weno5z(_dptr(v))
 
 
 def primitives(U, gamma=1.4):

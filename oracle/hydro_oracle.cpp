@@ -17,6 +17,10 @@
 //     face fluxes by the HLLC approximate Riemann solver (Toro, "Riemann
 //     Solvers and Numerical Methods for Fluid Dynamics", 3rd ed., section 10.4,
 //     Davis wave-speed estimates);
+//   * or, as a second scheme, the paper's own choice (section 2.2.2): WENO5-Z
+//     face states (Borges, Carmona, Costa and Don 2008) on primitive
+//     variables with the HLL flux (Harten, Lax and van Leer 1983; Davis
+//     speeds), which needs three ghost layers instead of two;
 //   * Heun's two-stage Runge-Kutta step (paper table "Butcher tableau for
 //     Heun's method") written in Shu-Osher form, which is the same method;
 //   * the CFL time step dt = C / max_i sum_d (|u_d| + c)/dx_d (section 3.5
@@ -106,7 +110,7 @@ enum : int { ST_RHO = 1, ST_PRES = 2, ST_NONFINITE = 4 };
 
 enum : int { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
 
-constexpr int NG = 2;  // ghost layers per side
+enum : int { SCHEME_MUSCL_HLLC = 0, SCHEME_WENO5Z_HLL = 1 };
 
 struct Grid {
   int ndim;       // 1, 2 or 3
@@ -116,15 +120,19 @@ struct Grid {
   double gamma;   // ratio of specific heats
   int bc[3][2];   // boundary kind per axis and side (0 = low, 1 = high)
   int64_t ncell;  // n[0]*n[1]*n[2]
+  int scheme;     // SCHEME_MUSCL_HLLC or SCHEME_WENO5Z_HLL
+  int ng;         // ghost layers per side: 2 (MUSCL) or 3 (WENO5-Z)
 
-  // padded shape: axes below ndim get NG ghosts on each side
+  // padded shape: axes below ndim get ng ghosts on each side
   int64_t pn[3];
   int64_t pcell;
 };
 
 static Grid make_grid(int ndim, const int64_t* n, const double* dx, double gamma,
-                      const int* bc) {
+                      const int* bc, int scheme) {
   Grid g;
+  g.scheme = scheme;
+  g.ng = scheme == SCHEME_WENO5Z_HLL ? 3 : 2;
   g.ndim = ndim;
   g.nvar = ndim + 2;
   g.gamma = gamma;
@@ -133,7 +141,7 @@ static Grid make_grid(int ndim, const int64_t* n, const double* dx, double gamma
     g.dx[d] = d < ndim ? dx[d] : 1.0;
     g.bc[d][0] = d < ndim ? bc[2 * d] : BC_PERIODIC;
     g.bc[d][1] = d < ndim ? bc[2 * d + 1] : BC_PERIODIC;
-    g.pn[d] = d < ndim ? g.n[d] + 2 * NG : 1;
+    g.pn[d] = d < ndim ? g.n[d] + 2 * g.ng : 1;
   }
   g.ncell = g.n[0] * g.n[1] * g.n[2];
   g.pcell = g.pn[0] * g.pn[1] * g.pn[2];
@@ -147,24 +155,25 @@ static inline int64_t cidx(const Grid& g, int64_t i, int64_t j, int64_t k) {
 // index of cell (i, j, k), counted from the first interior cell, in the padded
 // array (negative or >= n indices address ghosts)
 static inline int64_t pidx(const Grid& g, int64_t i, int64_t j, int64_t k) {
-  int64_t oi = i + (g.ndim > 0 ? NG : 0);
-  int64_t oj = j + (g.ndim > 1 ? NG : 0);
-  int64_t ok = k + (g.ndim > 2 ? NG : 0);
+  int64_t oi = i + (g.ndim > 0 ? g.ng : 0);
+  int64_t oj = j + (g.ndim > 1 ? g.ng : 0);
+  int64_t ok = k + (g.ndim > 2 ? g.ng : 0);
   return (ok * g.pn[1] + oj) * g.pn[0] + oi;
 }
 
-// Source interior index along one axis for ghost position q (q < 0 or q >= n),
-// and whether the normal momentum changes sign (reflecting wall).
+// Source interior index along one axis for ghost position q (q < 0 or q >= n,
+// at most ng <= n cells out), and whether the normal momentum changes sign
+// (reflecting wall).
 static inline int64_t ghost_source(int64_t q, int64_t n, int bc_lo, int bc_hi, bool* flip) {
   *flip = false;
   if (q < 0) {
-    int64_t k = -q;  // 1 or 2
+    int64_t k = -q;  // 1 .. ng
     if (bc_lo == BC_PERIODIC) return n - k;
     if (bc_lo == BC_OUTFLOW) return 0;
     *flip = true;
     return k - 1;
   }
-  int64_t k = q - (n - 1);  // 1 or 2
+  int64_t k = q - (n - 1);  // 1 .. ng
   if (bc_hi == BC_PERIODIC) return k - 1;
   if (bc_hi == BC_OUTFLOW) return n - 1;
   *flip = true;
@@ -190,6 +199,25 @@ template <class T>
 struct Prim {
   T rho, un, ut[2], p;
 };
+
+// Physical flux F_K and conserved state U_K of one face state (normal axis
+// first): F = (rho u, rho u^2 + p, rho u u_t, (E + p) u), U = (rho, rho u,
+// rho u_t, E), with E the total energy density.
+template <class T>
+static void physical_flux(const Prim<T>& W, T E, int nt, T* FK, T* UK) {
+  const int nv = nt + 3;
+  T mn = W.rho * W.un;
+  UK[0] = W.rho;
+  UK[1] = mn;
+  FK[0] = mn;
+  FK[1] = mn * W.un + W.p;
+  for (int t = 0; t < nt; ++t) {
+    UK[2 + t] = W.rho * W.ut[t];
+    FK[2 + t] = mn * W.ut[t];
+  }
+  UK[nv - 1] = E;
+  FK[nv - 1] = (E + W.p) * W.un;
+}
 
 // HLLC flux for the normal direction (Toro section 10.4, Davis speeds).
 // Output order: mass, normal momentum, transverse momenta, energy.
@@ -220,20 +248,7 @@ static void hllc_flux(const Prim<T>& L, const Prim<T>& R, int nt, double gamma, 
   T Ss = num / den;
 
   const int nv = nt + 3;
-  // physical flux and conserved state of one side
-  auto side = [&](const Prim<T>& W, T E, T* FK, T* UK) {
-    T mn = W.rho * W.un;
-    UK[0] = W.rho;
-    UK[1] = mn;
-    FK[0] = mn;
-    FK[1] = mn * W.un + W.p;
-    for (int t = 0; t < nt; ++t) {
-      UK[2 + t] = W.rho * W.ut[t];
-      FK[2 + t] = mn * W.ut[t];
-    }
-    UK[nv - 1] = E;
-    FK[nv - 1] = (E + W.p) * W.un;
-  };
+  auto side = [&](const Prim<T>& W, T E, T* FK, T* UK) { physical_flux(W, E, nt, FK, UK); };
   // HLLC star state of one side:
   //   rho_K r [1, S*, v_K, w_K, E_K/rho_K + (S*-u_K)(S* + p_K/(rho_K (S_K-u_K)))]
   // with r = (S_K - u_K)/(S_K - S*); the energy entry is expanded as
@@ -264,6 +279,71 @@ static void hllc_flux(const Prim<T>& L, const Prim<T>& R, int nt, double gamma, 
     side(R, ER, FK, UK);
     for (int v = 0; v < nv; ++v) F[v] = FK[v];
   }
+}
+
+// HLL flux (Harten, Lax and van Leer 1983) with the Davis wave speeds:
+//   F_L if S_L >= 0;  F_R if S_R <= 0;  otherwise
+//   (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) / (S_R - S_L).
+template <class T>
+static void hll_flux(const Prim<T>& L, const Prim<T>& R, int nt, double gamma, T* F) {
+  const T g(gamma);
+  const T gm1(gamma - 1.0);
+  T cL = sqrt(g * L.p / L.rho);
+  T cR = sqrt(g * R.p / R.rho);
+  T qL = L.un * L.un;
+  T qR = R.un * R.un;
+  for (int t = 0; t < nt; ++t) {
+    qL = qL + L.ut[t] * L.ut[t];
+    qR = qR + R.ut[t] * R.ut[t];
+  }
+  T EL = L.p / gm1 + T(0.5) * L.rho * qL;
+  T ER = R.p / gm1 + T(0.5) * R.rho * qR;
+  T aL = L.un - cL, bL = R.un - cR;
+  T SL = aL <= bL ? aL : bL;
+  T aR = L.un + cL, bR = R.un + cR;
+  T SR = aR >= bR ? aR : bR;
+  const int nv = nt + 3;
+  T FL[5], UL[5], FR[5], UR[5];
+  physical_flux(L, EL, nt, FL, UL);
+  physical_flux(R, ER, nt, FR, UR);
+  if (SL >= T(0.0)) {
+    for (int v = 0; v < nv; ++v) F[v] = FL[v];
+  } else if (SR <= T(0.0)) {
+    for (int v = 0; v < nv; ++v) F[v] = FR[v];
+  } else {
+    for (int v = 0; v < nv; ++v)
+      F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) / (SR - SL);
+  }
+}
+
+// WENO5-Z value at the right face of the middle cell of v[0..4] (cells
+// i-2 .. i+2), Borges et al. 2008: the three third-order candidate values on
+// the stencils {i-2,i-1,i}, {i-1,i,i+1}, {i,i+1,i+2}; the Jiang-Shu
+// smoothness indicators beta_k; tau5 = |beta_0 - beta_2|; the weights
+// alpha_k = d_k (1 + tau5 / (beta_k + eps)) with the optimal weights
+// d = (1/10, 6/10, 3/10) and eps = 1e-40; the value sum alpha_k q_k / sum alpha_k.
+// The left face of cell i is the same function of the mirrored cells
+// (i+2, i+1, i, i-1, i-2).
+template <class T>
+static T weno5z(const T* v) {
+  T q0 = (T(2.0) * v[0] - T(7.0) * v[1] + T(11.0) * v[2]) / T(6.0);
+  T q1 = (-v[1] + T(5.0) * v[2] + T(2.0) * v[3]) / T(6.0);
+  T q2 = (T(2.0) * v[2] + T(5.0) * v[3] - v[4]) / T(6.0);
+  T s0 = v[0] - T(2.0) * v[1] + v[2];
+  T t0 = v[0] - T(4.0) * v[1] + T(3.0) * v[2];
+  T s1 = v[1] - T(2.0) * v[2] + v[3];
+  T t1 = v[1] - v[3];
+  T s2 = v[2] - T(2.0) * v[3] + v[4];
+  T t2 = T(3.0) * v[2] - T(4.0) * v[3] + v[4];
+  const T c1(13.0 / 12.0), c2(0.25), eps(1e-40);
+  T b0 = c1 * s0 * s0 + c2 * t0 * t0;
+  T b1 = c1 * s1 * s1 + c2 * t1 * t1;
+  T b2 = c1 * s2 * s2 + c2 * t2 * t2;
+  T tau = fabs(b0 - b2);
+  T a0 = T(0.1) * (T(1.0) + tau / (b0 + eps));
+  T a1 = T(0.6) * (T(1.0) + tau / (b1 + eps));
+  T a2 = T(0.3) * (T(1.0) + tau / (b2 + eps));
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 
 // Primitive variables of one conserved state: rho, u_0..u_{ndim-1}, p.
@@ -317,7 +397,7 @@ static int rhs(const Grid& g, const T* U, T* Lout) {
         rem /= g.n[a];
       }
       for (int side = 0; side < 2; ++side)
-        for (int kk = 1; kk <= NG; ++kk) {
+        for (int kk = 1; kk <= g.ng; ++kk) {
           int64_t q = side == 0 ? -kk : nd_ - 1 + kk;
           bool flip;
           int64_t s = ghost_source(q, nd_, g.bc[d][0], g.bc[d][1], &flip);
@@ -347,7 +427,7 @@ static int rhs(const Grid& g, const T* U, T* Lout) {
     bool interior = true;
     int64_t ii[3] = {i, j, k};
     for (int a = 0; a < nd; ++a)
-      if (ii[a] < NG || ii[a] >= NG + g.n[a]) interior = false;
+      if (ii[a] < g.ng || ii[a] >= g.ng + g.n[a]) interior = false;
     if (interior) status |= st;
   }
 
@@ -367,21 +447,35 @@ static int rhs(const Grid& g, const T* U, T* Lout) {
         o[a] = rem % g.n[a];
         rem /= g.n[a];
       }
+      const int ns = 2 * g.ng;  // stencil cells f-ng .. f+ng-1
       for (int64_t f = 0; f < nf; ++f) {
-        // face between cells f-1 and f along d; stencil f-2 .. f+1
-        T Wc[4][5];
-        for (int s = 0; s < 4; ++s) {
+        // face between cells f-1 and f along d
+        T Wst[6][5];
+        for (int s = 0; s < ns; ++s) {
           int64_t p[3] = {o[0], o[1], o[2]};
-          p[d] = f - 2 + s;
+          p[d] = f - g.ng + s;
           int64_t pi = pidx(g, p[0], p[1], p[2]);
-          for (int v = 0; v < nv; ++v) Wc[s][v] = W[(size_t)v * PN + pi];
+          for (int v = 0; v < nv; ++v) Wst[s][v] = W[(size_t)v * PN + pi];
         }
         T WL[5], WR[5];
-        for (int v = 0; v < nv; ++v) {
-          T sl = minmod(Wc[1][v] - Wc[0][v], Wc[2][v] - Wc[1][v]);  // slope of cell f-1
-          T sr = minmod(Wc[2][v] - Wc[1][v], Wc[3][v] - Wc[2][v]);  // slope of cell f
-          WL[v] = Wc[1][v] + T(0.5) * sl;
-          WR[v] = Wc[2][v] - T(0.5) * sr;
+        if (g.scheme == SCHEME_MUSCL_HLLC) {
+          // Wc[0..3] = cells f-2 .. f+1
+          T (*Wc)[5] = Wst;
+          for (int v = 0; v < nv; ++v) {
+            T sl = minmod(Wc[1][v] - Wc[0][v], Wc[2][v] - Wc[1][v]);  // slope of cell f-1
+            T sr = minmod(Wc[2][v] - Wc[1][v], Wc[3][v] - Wc[2][v]);  // slope of cell f
+            WL[v] = Wc[1][v] + T(0.5) * sl;
+            WR[v] = Wc[2][v] - T(0.5) * sr;
+          }
+        } else {
+          // Wst[0..5] = cells f-3 .. f+2: the right face of cell f-1 from
+          // cells f-3..f+1, the left face of cell f from f+2..f-2 (mirrored)
+          for (int v = 0; v < nv; ++v) {
+            T a[5] = {Wst[0][v], Wst[1][v], Wst[2][v], Wst[3][v], Wst[4][v]};
+            T b[5] = {Wst[5][v], Wst[4][v], Wst[3][v], Wst[2][v], Wst[1][v]};
+            WL[v] = weno5z(a);
+            WR[v] = weno5z(b);
+          }
         }
         // rotate: normal velocity is axis d, transverse are the others in order
         Prim<T> PL, PR;
@@ -399,7 +493,10 @@ static int rhs(const Grid& g, const T* U, T* Lout) {
         PL.p = WL[nd + 1];
         PR.p = WR[nd + 1];
         T Fn[5];
-        hllc_flux(PL, PR, nd - 1, g.gamma, Fn);
+        if (g.scheme == SCHEME_MUSCL_HLLC)
+          hllc_flux(PL, PR, nd - 1, g.gamma, Fn);
+        else
+          hll_flux(PL, PR, nd - 1, g.gamma, Fn);
         // rotate back to (mass, m_0.., energy)
         T Fo[5];
         Fo[0] = Fn[0];
@@ -482,32 +579,32 @@ using namespace hard_oracle;
 extern "C" {
 
 // L(U) for one state; returns status bits.
-int oracle_rhs(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+int oracle_rhs(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
                const double* U, double* L) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
   return rhs<double>(g, U, L);
 }
 
 // One SSP-RK2 step in place; returns status bits.
-int oracle_step(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+int oracle_step(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
                 double dt, double* U) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
   return step<double>(g, U, dt);
 }
 
 // nsteps SSP-RK2 steps in place with the given dt list; returns OR of status.
-int oracle_steps_fixed(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+int oracle_steps_fixed(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
                        int64_t nsteps, const double* dts, double* U) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
   int st = 0;
   for (int64_t s = 0; s < nsteps; ++s) st |= step<double>(g, U, dts[s]);
   return st;
 }
 
 // dt = cfl / max signal sum; writes the status bits of the state.
-double oracle_cfl_dt(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+double oracle_cfl_dt(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
                      double cfl, const double* U, int* status) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
   double smax = max_signal(g, U, status);
   return cfl / smax;
 }
@@ -515,10 +612,10 @@ double oracle_cfl_dt(int ndim, const int64_t* n, const double* dx, double gamma,
 // CFL-driven run to t_end: dt <- min(cfl dt, t_end - t); stops when
 // t >= t_end (1 - 1e-14) or after max_steps.  Records each dt used if
 // dts_out is not null (capacity max_steps).  Returns OR of status bits.
-int oracle_run(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+int oracle_run(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
                double cfl, double t_end, int64_t max_steps, double* U, double* t_out,
                int64_t* nsteps_out, double* dts_out) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
   double t = 0.0;
   int64_t s = 0;
   int st = 0;
@@ -540,9 +637,9 @@ int oracle_run(int ndim, const int64_t* n, const double* dx, double gamma, const
 // Forward-mode derivative of nsteps steps with a frozen dt list:
 // (U, dU) -> (U_n, dU_n) in place.  Returns OR of status bits.
 int oracle_steps_tangent(int ndim, const int64_t* n, const double* dx, double gamma,
-                         const int* bc, int64_t nsteps, const double* dts, double* U,
+                         const int* bc, int scheme, int64_t nsteps, const double* dts, double* U,
                          double* dU) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
   const int64_t M = (int64_t)g.nvar * g.ncell;
   std::vector<Dual> X(M);
   for (int64_t x = 0; x < M; ++x) X[x] = Dual(U[x], dU[x]);
@@ -574,10 +671,29 @@ void oracle_hllc(int nt, double gamma, const double* WL, const double* WR, doubl
 
 double oracle_minmod(double a, double b) { return minmod<double>(a, b); }
 
+// HLL flux for one face (same layout as oracle_hllc).
+void oracle_hll(int nt, double gamma, const double* WL, const double* WR, double* F) {
+  Prim<double> L, R;
+  L.rho = WL[0];
+  L.un = WL[1];
+  R.rho = WR[0];
+  R.un = WR[1];
+  for (int t = 0; t < nt; ++t) {
+    L.ut[t] = WL[2 + t];
+    R.ut[t] = WR[2 + t];
+  }
+  L.p = WL[2 + nt];
+  R.p = WR[2 + nt];
+  hll_flux(L, R, nt, gamma, F);
+}
+
+// WENO5-Z value at the right face of the middle cell of v[0..4].
+double oracle_weno5z(const double* v) { return weno5z<double>(v); }
+
 // Floating-point operations of one CFL dt plus one SSP-RK2 step of U (left
 // unchanged), tallied by kind: out[0..5] = add/sub, mul, div, sqrt, compare,
 // abs.  Runs on one thread.
-void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
                       double dt, const double* U, int64_t* out);
 
 #ifdef _OPENMP
@@ -589,9 +705,9 @@ static void omp_set_num_threads(int) {}
 static int omp_get_max_threads(void) { return 1; }
 #endif
 
-void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
                       double dt, const double* U, int64_t* out) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
   const int64_t M = (int64_t)g.nvar * g.ncell;
   std::vector<Cnt> X(M);
   for (int64_t x = 0; x < M; ++x) X[x] = Cnt(U[x]);

@@ -31,6 +31,7 @@ LIB_PATH = os.path.join(HERE, "libhard.so")
 
 PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
 F64, F32 = 0, 1
+MUSCL_HLLC, WENO5Z_HLL = 0, 1  # face schemes (HARD_SCHEME_*)
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_NONPHYSICAL, ERR_HIP = range(6)
 FLAG_DENSITY, FLAG_PRESSURE, FLAG_NONFINITE = 1, 2, 4
 
@@ -49,6 +50,7 @@ class hard_grid_t(ctypes.Structure):
         ("dx", ctypes.c_double * 3),
         ("gamma", ctypes.c_double),
         ("bc", (ctypes.c_int32 * 2) * 3),
+        ("scheme", ctypes.c_int32),
     ]
 
 
@@ -111,9 +113,11 @@ def _check(code):
         raise HardError(code, hard_last_error())
 
 
-def make_grid(n, dx=None, gamma=1.4, bc=(OUTFLOW, OUTFLOW), dtype=torch.float64):
+def make_grid(n, dx=None, gamma=1.4, bc=(OUTFLOW, OUTFLOW), dtype=torch.float64,
+              scheme=0):
     """hard_grid_t for n = (nx[, ny[, nz]]); bc is (lo, hi) per axis, flattened
-    (a single pair applies to every axis); dx defaults to 1/n (unit box)."""
+    (a single pair applies to every axis); dx defaults to 1/n (unit box);
+    scheme is MUSCL_HLLC (default) or WENO5Z_HLL."""
     n = tuple(int(v) for v in n)
     nd = len(n)
     if dx is None:
@@ -130,6 +134,7 @@ def make_grid(n, dx=None, gamma=1.4, bc=(OUTFLOW, OUTFLOW), dtype=torch.float64)
         g.bc[d][0] = bc[2 * d] if d < nd else 0
         g.bc[d][1] = bc[2 * d + 1] if d < nd else 0
     g.gamma = float(gamma)
+    g.scheme = int(scheme)
     return g
 
 

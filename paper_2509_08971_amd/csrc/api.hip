@@ -63,6 +63,11 @@ hard_status_t check_grid(const hard_grid_t* g, Grid* out) {
   if (ncell >= (1LL << 31)) return fail(HARD_ERR_INVALID_ARG, "more than 2^31 - 1 cells");
   if (!(std::isfinite(g->gamma) && g->gamma > 1.0))
     return fail(HARD_ERR_INVALID_ARG, "gamma must be finite and > 1");
+  if (g->scheme != HARD_SCHEME_MUSCL_HLLC && g->scheme != HARD_SCHEME_WENO5Z_HLL)
+    return fail(HARD_ERR_INVALID_ARG, "scheme must be HARD_SCHEME_MUSCL_HLLC or HARD_SCHEME_WENO5Z_HLL");
+  if (g->scheme == HARD_SCHEME_WENO5Z_HLL)
+    for (int d = 0; d < g->ndim; ++d)
+      if (g->n[d] < 3) return fail(HARD_ERR_INVALID_ARG, "WENO5-Z needs n[%d] >= 3", d);
   if (out) {
     out->ndim = g->ndim;
     out->dtype = g->dtype;
@@ -77,6 +82,7 @@ hard_status_t check_grid(const hard_grid_t* g, Grid* out) {
       out->bc[d][1] = d < g->ndim ? g->bc[d][1] : HARD_BC_PERIODIC;
     }
     out->gamma = g->gamma;
+    out->scheme = g->scheme;
     out->dx_pow2 = 1;
     for (int d = 0; d < g->ndim; ++d) {
       int e;
@@ -96,6 +102,16 @@ WorkLayout layout_of(const Grid& g) {
   w.partials = w.stage + w.stage_bytes;
   w.partials_blocks = sums_blocks(g.ncell);
   w.total = w.partials + align256((size_t)w.partials_blocks * g.nvar * 2 * sizeof(double));
+  w.weno_w = 0;
+  w.weno_f[0] = w.weno_f[1] = w.weno_f[2] = 0;
+  if (g.scheme == HARD_SCHEME_WENO5Z_HLL) {
+    w.weno_w = w.total;
+    w.total += align256((size_t)g.nvar * g.ncell * g.wsize);
+    for (int d = 0; d < g.ndim; ++d) {
+      w.weno_f[d] = w.total;
+      w.total += align256((size_t)g.nvar * (g.ncell / g.n[d]) * (g.n[d] + 1) * g.wsize);
+    }
+  }
   return w;
 }
 
@@ -110,6 +126,35 @@ hard_status_t check_work(void* work, size_t have, size_t need) {
   if (((uintptr_t)work) % 256) return fail(HARD_ERR_INVALID_ARG, "work is not 256-byte aligned");
   if (have < need) return fail(HARD_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", have, need);
   return HARD_OK;
+}
+
+// One stage of the grid's scheme: the fused tile kernel (MUSCL-HLLC) or the
+// WENO5-Z + HLL pipeline over the workspace arrays of layout L.
+hipError_t launch_scheme_stage(const Grid& G, const WorkLayout& L, char* wb, const StageArgs& a,
+                               int stage, hipStream_t s) {
+  if (G.scheme == HARD_SCHEME_MUSCL_HLLC) return launch_stage(G.ndim, G.dtype, a, stage, s);
+  WenoArgs w;
+  std::memset(&w, 0, sizeof w);
+  w.src = a.src;
+  w.un = a.un;
+  w.dst = a.dst;
+  w.dt = a.dt;
+  for (int d = 0; d < 3; ++d) {
+    w.n[d] = a.n[d];
+    w.bc[d][0] = a.bc[d][0];
+    w.bc[d][1] = a.bc[d][1];
+    w.dx[d] = a.dx[d];
+    w.inv_dx[d] = a.inv_dx[d];
+    w.F[d] = L.weno_f[d] ? wb + L.weno_f[d] : nullptr;
+  }
+  w.dx_pow2 = a.dx_pow2;
+  w.gamma = a.gamma;
+  w.cfl = a.cfl;
+  w.fuse_cfl = a.fuse_cfl;
+  w.ctl = a.ctl;
+  w.next_dt = a.next_dt;
+  w.W = wb + L.weno_w;
+  return launch_weno_stage(G.ndim, G.dtype, w, stage, s);
 }
 
 int stage_cz_override() {
@@ -215,7 +260,7 @@ hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_de
   a.un = U;
   a.dst = U1;
   a.fuse_cfl = 0;
-  hipError_t e = launch_stage(G.ndim, G.dtype, a, 1, s);
+  hipError_t e = launch_scheme_stage(G, L, wb, a, 1, s);
   if (e != hipSuccess) return hip_fail(e, "hard_hydro_step stage 1");
   // stage 2: U = (U + (U1 + dt L(U1))) / 2, optionally with the next dt
   a.src = U1;
@@ -223,7 +268,7 @@ hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_de
   a.dst = U;
   a.fuse_cfl = next_dt_dev != nullptr;
   a.next_dt = next_dt_dev;
-  e = launch_stage(G.ndim, G.dtype, a, 2, s);
+  e = launch_scheme_stage(G, L, wb, a, 2, s);
   if (e != hipSuccess) return hip_fail(e, "hard_hydro_step stage 2");
   return ok();
 }
@@ -244,7 +289,9 @@ hard_status_t hard_hydro_stage(const hard_grid_t* g, int32_t stage, const void* 
     if ((st = check_ptr(next_dt_dev, 8, "next_dt_dev"))) return st;
     if ((st = check_cfl(cfl))) return st;
   }
-  if ((st = check_work(work, work_bytes, sizeof(Control)))) return st;
+  WorkLayout L = layout_of(G);
+  const size_t need = G.scheme == HARD_SCHEME_MUSCL_HLLC ? sizeof(Control) : L.total;
+  if ((st = check_work(work, work_bytes, need))) return st;
   StageArgs a;
   std::memset(&a, 0, sizeof a);
   for (int d = 0; d < 3; ++d) {
@@ -265,7 +312,7 @@ hard_status_t hard_hydro_stage(const hard_grid_t* g, int32_t stage, const void* 
   a.dst = dst;
   a.fuse_cfl = stage == 2 && next_dt_dev != nullptr;
   a.next_dt = next_dt_dev;
-  hipError_t e = launch_stage(G.ndim, G.dtype, a, stage, (hipStream_t)stream);
+  hipError_t e = launch_scheme_stage(G, L, static_cast<char*>(work), a, stage, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "hard_hydro_stage");
   return ok();
 }

@@ -18,6 +18,7 @@ struct Grid {
   int bc[3][2];
   double gamma;
   int dx_pow2;  // every dx is a power of two (x/dx == x*(1/dx) exactly)
+  int scheme;   // HARD_SCHEME_*
 };
 
 // Byte offsets inside a single-grid workspace.
@@ -27,6 +28,8 @@ struct WorkLayout {
   size_t stage_bytes;
   size_t partials;       // compensated-sum partials
   int partials_blocks;
+  size_t weno_w;         // WENO5-Z pipeline: primitives (0 if unused)
+  size_t weno_f[3];      // WENO5-Z pipeline: face fluxes per axis
   size_t total;
 };
 
@@ -38,6 +41,9 @@ hard_status_t check_ptr(const void* p, size_t align, const char* name);
 hard_status_t check_work(void* work, size_t have, size_t need);
 hard_status_t check_cfl(double cfl);
 WorkLayout layout_of(const Grid& g);
+struct StageArgs;
+hipError_t launch_scheme_stage(const Grid& G, const WorkLayout& L, char* wb, const StageArgs& a,
+                               int stage, hipStream_t s);
 
 // z planes per workgroup for the 3D stage kernel: HARD_STAGE_CZ in the
 // environment overrides the default (read once; 0 = default).

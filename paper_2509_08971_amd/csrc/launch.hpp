@@ -29,6 +29,29 @@ struct StageArgs {
 
 hipError_t launch_stage(int ndim, int dtype, const StageArgs& a, int stage, hipStream_t s);
 
+// WENO5-Z + HLL stage (weno.hip): same stage semantics as StageArgs, with the
+// workspace arrays of the pipeline.
+struct WenoArgs {
+  const void* src;
+  const void* un;
+  void* dst;
+  const double* dt;
+  int n[3];
+  int bc[3][2];
+  double dx[3];
+  double inv_dx[3];
+  int dx_pow2;
+  double gamma;
+  double cfl;
+  int fuse_cfl;
+  Control* ctl;
+  double* next_dt;
+  void* W;      // primitives of the stage source, [nvar][N]
+  void* F[3];   // face fluxes per axis, [nvar][faces along that axis]
+};
+
+hipError_t launch_weno_stage(int ndim, int dtype, const WenoArgs& a, int stage, hipStream_t s);
+
 // Standalone CFL dt (reads U once).
 hipError_t launch_cfl(int ndim, int dtype, const int* n, const double* dx, const double* inv_dx,
                       int dx_pow2, double gamma, const void* U, double cfl, double* dt,

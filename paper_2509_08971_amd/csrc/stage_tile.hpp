@@ -41,6 +41,30 @@ struct TileArgs {
   int fuse_cfl;     // stage 2: accumulate the CFL signal max of the output
 };
 
+// Streams that no other workgroup reads again within the launch -- the
+// stored result and, in stage 2, U^n of the own cell -- go through the cache
+// as non-temporal accesses, so that they do not push the halo lines that
+// neighbouring tiles re-read out of the XCD's L2.
+#ifndef HARD_NT_STREAMS
+#define HARD_NT_STREAMS 1
+#endif
+template <typename R>
+__device__ __forceinline__ R stream_load(const R* p) {
+#if HARD_NT_STREAMS
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+template <typename R>
+__device__ __forceinline__ void stream_store(R* p, R v) {
+#if HARD_NT_STREAMS
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
 template <int NDIM, typename R, int TX, int TY>
 struct TileShape {
   static constexpr int NV = NDIM + 2;
@@ -204,7 +228,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
     const long long cidx = (long long)w * WS + col;
     if (STAGE == 2 && inside) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Un0[v] = un[v * N + cidx];
+      for (int v = 0; v < NV; ++v) Un0[v] = stream_load(un + v * N + cidx);
     }
     if constexpr (!WALK) col_prim(Ucur, false, P0);
 
@@ -317,7 +341,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
         }
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) dst[v * N + cidx] = Out[v];
+      for (int v = 0; v < NV; ++v) stream_store(dst + v * N + cidx, Out[v]);
       if (STAGE == 2 && a.fuse_cfl) {
         double Ud[NV];
 #pragma unroll

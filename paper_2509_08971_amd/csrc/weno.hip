@@ -1,0 +1,284 @@
+// The paper's own face scheme (section 2.2.2): WENO5-Z face states of the
+// primitive variables (Borges, Carmona, Costa and Don 2008) with the HLL flux
+// (Harten, Lax and van Leer 1983; Davis wave speeds), inside the same Heun
+// stages as the MUSCL-HLLC path.  Three ghost layers per side.
+//
+// This path is a plain pipeline per stage, not the fused tile kernel:
+//   weno_prim    one thread per cell: primitives W of the stage source into
+//                the workspace (and the status bits);
+//   weno_face    one thread per face, one launch per axis: six W cells along
+//                the axis (ghosts by index remap), WENO5-Z left and right
+//                states, HLL flux into a per-axis face array;
+//   weno_update  one thread per cell: L(U) = -sum_d (F+ - F-)/dx_d in the order
+//                x, y, z, the stage combine, and in stage 2 the fused CFL step.
+// Bytes per cell and stage: the fused MUSCL kernel moves 2-3 nvar words; this
+// pipeline about 6 + 4 ndim nvar words (W and the face arrays round-trip
+// through memory).
+
+#include "hydro_device.hpp"
+#include "launch.hpp"
+
+namespace hard {
+
+// WENO5-Z value at the right face of the middle cell of v0..v4 (cells
+// i-2..i+2): third-order candidates on the three sub-stencils, Jiang-Shu
+// smoothness indicators, tau5 = |beta0 - beta2|, weights
+// d_k (1 + tau5 / (beta_k + eps)) with d = (1/10, 6/10, 3/10), eps = 1e-40.
+// Evaluated in double for both storage types: the weight ratios reach
+// 1e40 and beyond at a jump, out of float range (and the FP64 vector rate
+// of gfx950 equals its unpacked FP32 rate).
+__device__ __forceinline__ double weno5z_d(double v0, double v1, double v2, double v3, double v4) {
+  const double inv6 = 1.0 / 6.0;
+  double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * inv6;
+  double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * inv6;
+  double q2 = (2.0 * v2 + 5.0 * v3 - v4) * inv6;
+  double s0 = v0 - 2.0 * v1 + v2, t0 = v0 - 4.0 * v1 + 3.0 * v2;
+  double s1 = v1 - 2.0 * v2 + v3, t1 = v1 - v3;
+  double s2 = v2 - 2.0 * v3 + v4, t2 = 3.0 * v2 - 4.0 * v3 + v4;
+  const double c1 = 13.0 / 12.0, c2 = 0.25, eps = 1e-40;
+  double b0 = c1 * s0 * s0 + c2 * t0 * t0;
+  double b1 = c1 * s1 * s1 + c2 * t1 * t1;
+  double b2 = c1 * s2 * s2 + c2 * t2 * t2;
+  double tau = fabs(b0 - b2);
+  double a0 = 0.1 * (1.0 + tau * fast_rcp(b0 + eps));
+  double a1 = 0.6 * (1.0 + tau * fast_rcp(b1 + eps));
+  double a2 = 0.3 * (1.0 + tau * fast_rcp(b2 + eps));
+  return (a0 * q0 + a1 * q1 + a2 * q2) * fast_rcp(a0 + a1 + a2);
+}
+template <typename R>
+__device__ __forceinline__ R weno5z(R v0, R v1, R v2, R v3, R v4) {
+  return R(weno5z_d(v0, v1, v2, v3, v4));
+}
+
+// HLL flux of face states ordered (rho, u_n, u_t..., p); output (mass,
+// normal momentum, transverse momenta, energy).
+template <typename R, int NV>
+__device__ __forceinline__ void hll_ordered(const R* WL, const R* WR, R gam, R inv_gm1, R* F) {
+  constexpr int NT = NV - 3;
+  const R rL = WL[0], uL = WL[1], pL = WL[NV - 1];
+  const R rR = WR[0], uR = WR[1], pR = WR[NV - 1];
+  R cL = sound_speed(gam * pL, rL);
+  R cR = sound_speed(gam * pR, rR);
+  R aL = uL - cL, bL = uR - cR;
+  R SL = (aL <= bL) ? aL : bL;
+  R aR = uL + cL, bR = uR + cR;
+  R SR = (aR >= bR) ? aR : bR;
+  R qL = uL * uL, qR = uR * uR;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    qL = qL + WL[2 + t] * WL[2 + t];
+    qR = qR + WR[2 + t] * WR[2 + t];
+  }
+  const R EL = pL * inv_gm1 + R(0.5) * rL * qL;
+  const R ER = pR * inv_gm1 + R(0.5) * rR * qR;
+  const R mL = rL * uL, mR = rR * uR;
+  R FL[NV], FR[NV], UL[NV], UR[NV];
+  FL[0] = mL;
+  FR[0] = mR;
+  UL[0] = rL;
+  UR[0] = rR;
+  FL[1] = mL * uL + pL;
+  FR[1] = mR * uR + pR;
+  UL[1] = mL;
+  UR[1] = mR;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    FL[2 + t] = mL * WL[2 + t];
+    FR[2 + t] = mR * WR[2 + t];
+    UL[2 + t] = rL * WL[2 + t];
+    UR[2 + t] = rR * WR[2 + t];
+  }
+  FL[NV - 1] = (EL + pL) * uL;
+  FR[NV - 1] = (ER + pR) * uR;
+  UL[NV - 1] = EL;
+  UR[NV - 1] = ER;
+  if (SL >= R(0)) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = FL[v];
+  } else if (SR <= R(0)) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = FR[v];
+  } else {
+    const R inv = fast_rcp(SR - SL);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) * inv;
+  }
+}
+
+template <typename R, int NDIM>
+__global__ __launch_bounds__(256) void weno_prim(WenoArgs a) {
+  constexpr int NV = NDIM + 2;
+  const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned flags = 0;
+  if (c < N) {
+    const R* U = static_cast<const R*>(a.src);
+    R* W = static_cast<R*>(a.W);
+    R u[NV], w[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = U[v * N + c];
+    to_primitive<R, NDIM>(u, w, a.gamma - 1.0);
+    flags = cell_flags<R, NV>(u, w[NV - 1]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) W[v * N + c] = w[v];
+  }
+  flags = wave_or(flags);
+  if ((threadIdx.x & 63) == 0 && flags) atomicOr(&a.ctl->flags, flags);
+}
+
+// Faces along axis AX: face f (0..n_AX) lies between cells f-1 and f.
+// Linear face index, x fastest: AX = 0: (f, j, k); AX = 1: (i, f, k);
+// AX = 2: (i, j, f).
+template <typename R, int NDIM, int AX>
+__global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
+  constexpr int NV = NDIM + 2;
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const long long N = (long long)nx * ny * nz;
+  const long long nface = N / a.n[AX] * (a.n[AX] + 1);
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nface) return;
+  int i, j, k, f;
+  if constexpr (AX == 0) {
+    f = (int)(idx % (nx + 1));
+    long long r = idx / (nx + 1);
+    j = (int)(r % ny);
+    k = (int)(r / ny);
+    i = 0;
+  } else if constexpr (AX == 1) {
+    i = (int)(idx % nx);
+    long long r = idx / nx;
+    f = (int)(r % (ny + 1));
+    k = (int)(r / (ny + 1));
+    j = 0;
+  } else {
+    i = (int)(idx % nx);
+    long long r = idx / nx;
+    j = (int)(r % ny);
+    f = (int)(r / ny);
+    k = 0;
+  }
+  const R* W = static_cast<const R*>(a.W);
+  // six cells f-3 .. f+2 along AX, primitives with the wall flip applied
+  R c[6][NV];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    bool flip;
+    const int q = remap(f - 3 + s, a.n[AX], a.bc[AX][0], a.bc[AX][1], flip);
+    const int ii = AX == 0 ? q : i, jj = AX == 1 ? q : j, kk = AX == 2 ? q : k;
+    const long long cell = ((long long)kk * ny + jj) * nx + ii;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) c[s][v] = W[v * N + cell];
+    if (flip) c[s][1 + AX] = -c[s][1 + AX];
+  }
+  // face states ordered (rho, u_n, u_t in axis order, p)
+  int perm[NV];
+  perm[0] = 0;
+  perm[1] = 1 + AX;
+  {
+    int t = 2;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d)
+      if (d != AX) perm[t++] = 1 + d;
+  }
+  perm[NV - 1] = NV - 1;
+  R WL[NV], WR[NV], Fn[NV];
+#pragma unroll
+  for (int m = 0; m < NV; ++m) {
+    const int v = perm[m];
+    WL[m] = weno5z<R>(c[0][v], c[1][v], c[2][v], c[3][v], c[4][v]);
+    WR[m] = weno5z<R>(c[5][v], c[4][v], c[3][v], c[2][v], c[1][v]);
+  }
+  const R gam = R(a.gamma), inv_gm1 = R(1.0 / (a.gamma - 1.0));
+  hll_ordered<R, NV>(WL, WR, gam, inv_gm1, Fn);
+  R* F = static_cast<R*>(a.F[AX]);
+#pragma unroll
+  for (int m = 0; m < NV; ++m) F[perm[m] * nface + idx] = Fn[m];
+}
+
+template <typename R, int NDIM, int STAGE>
+__global__ __launch_bounds__(256) void weno_update(WenoArgs a) {
+  constexpr int NV = NDIM + 2;
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const long long N = (long long)nx * ny * nz;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool fuse = STAGE == 2 && a.fuse_cfl;
+  double smax = 0.0;
+  if (c < N) {
+    const int i = (int)(c % nx);
+    const long long r = c / nx;
+    const int j = (int)(r % ny), k = (int)(r / ny);
+    const R* src = static_cast<const R*>(a.src);
+    const R* un = static_cast<const R*>(a.un);
+    R* dst = static_cast<R*>(a.dst);
+    const R dt = R(*a.dt);
+    long long fm[3], step[3], nf[3];
+    fm[0] = ((long long)k * ny + j) * (nx + 1) + i;
+    step[0] = 1;
+    nf[0] = (long long)(nx + 1) * ny * nz;
+    fm[1] = ((long long)k * (ny + 1) + j) * nx + i;
+    step[1] = nx;
+    nf[1] = (long long)nx * (ny + 1) * nz;
+    fm[2] = ((long long)k * ny + j) * nx + i;
+    step[2] = (long long)nx * ny;
+    nf[2] = (long long)nx * ny * (nz + 1);
+    R Out[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      R l = R(0);
+#pragma unroll
+      for (int d = 0; d < NDIM; ++d) {
+        const R* F = static_cast<const R*>(a.F[d]) + v * nf[d];
+        l = l - (F[fm[d] + step[d]] - F[fm[d]]) * R(a.inv_dx[d]);
+      }
+      const R u = src[v * N + c];
+      if (STAGE == 1)
+        Out[v] = u + dt * l;
+      else
+        Out[v] = R(0.5) * (un[v * N + c] + (u + dt * l));
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dst[v * N + c] = Out[v];
+    if (fuse) {
+      double Ud[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Ud[v] = (double)Out[v];
+      smax = signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma);
+    }
+  }
+  block_finish<256>(0u, smax, fuse, a.ctl, a.cfl, a.next_dt);
+}
+
+template <typename R, int NDIM>
+static hipError_t weno_stage_t(const WenoArgs& a, int stage, hipStream_t s) {
+  const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
+  const unsigned nb = (unsigned)((N + 255) / 256);
+  hipLaunchKernelGGL((weno_prim<R, NDIM>), dim3(nb), dim3(256), 0, s, a);
+  auto faces = [&](int d) { return (unsigned)((N / a.n[d] * (a.n[d] + 1) + 255) / 256); };
+  hipLaunchKernelGGL((weno_face<R, NDIM, 0>), dim3(faces(0)), dim3(256), 0, s, a);
+  if constexpr (NDIM >= 2) hipLaunchKernelGGL((weno_face<R, NDIM, 1>), dim3(faces(1)), dim3(256), 0, s, a);
+  if constexpr (NDIM >= 3) hipLaunchKernelGGL((weno_face<R, NDIM, 2>), dim3(faces(2)), dim3(256), 0, s, a);
+  if (stage == 1)
+    hipLaunchKernelGGL((weno_update<R, NDIM, 1>), dim3(nb), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((weno_update<R, NDIM, 2>), dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_weno_stage(int ndim, int dtype, const WenoArgs& a, int stage, hipStream_t s) {
+  if (dtype == 0) {
+    switch (ndim) {
+      case 1: return weno_stage_t<double, 1>(a, stage, s);
+      case 2: return weno_stage_t<double, 2>(a, stage, s);
+      case 3: return weno_stage_t<double, 3>(a, stage, s);
+    }
+  } else {
+    switch (ndim) {
+      case 1: return weno_stage_t<float, 1>(a, stage, s);
+      case 2: return weno_stage_t<float, 2>(a, stage, s);
+      case 3: return weno_stage_t<float, 3>(a, stage, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace hard

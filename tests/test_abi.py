@@ -132,3 +132,24 @@ def test_batched_plan_rejects_mixed_dtypes():
     plan = ctypes.c_void_p()
     assert H.lib().hard_batch_plan_create(arr, 2, None, ctypes.byref(plan)) == H.ERR_INVALID_ARG
     assert not plan.value
+
+
+def test_scheme_checks():
+    """The face scheme is validated; WENO5-Z needs three cells per axis, its
+    pipeline arrays are part of the workspace, and the batched and adjoint
+    calls reject it."""
+    L = H.lib()
+    assert call_step(grid(scheme=2), work=None) == H.ERR_INVALID_ARG
+    g = H.make_grid((2, 16), scheme=H.WENO5Z_HLL)
+    assert call_step(g, work=None) == H.ERR_INVALID_ARG
+    n = 64
+    gm = H.make_grid((n, n, n))
+    gw = H.make_grid((n, n, n), scheme=H.WENO5Z_HLL)
+    extra = H.hard_workspace_bytes(gw) - H.hard_workspace_bytes(gm)
+    assert extra >= 5 * 8 * (n ** 3 + 3 * n * n * (n + 1))  # W and three face arrays
+    b = ctypes.c_size_t()
+    assert L.hard_adjoint_workspace_bytes(ctypes.byref(gw), ctypes.byref(b)) == H.ERR_UNSUPPORTED
+    arr = (H.hard_grid_t * 1)(H.make_grid((64,), scheme=H.WENO5Z_HLL))
+    plan = ctypes.c_void_p()
+    assert L.hard_batch_plan_create(arr, 1, None, ctypes.byref(plan)) == H.ERR_UNSUPPORTED
+    assert not plan.value

@@ -1,0 +1,146 @@
+"""GPU WENO5-Z + HLL scheme (the paper's own face scheme) through the C ABI
+against the CPU oracle's second scheme.
+
+Tolerances as for the MUSCL-HLLC path: FP64 per field max|g - o| / max|o|
+<= 1e-12; FP32 bulk per field sum|g - o| / sum|o| <= 1e-5 against the FP64
+oracle on the float-rounded input.  The fused CFL step equals the oracle's
+bit for bit.  The paper's Sod figure (L1(rho) < 5e-4 at t = 0.0669, dx =
+2^-10, Courant 0.3) is also checked on the GPU run.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle.exact_riemann import RiemannSolution
+from oracle.metrics import field_rel_l1, field_rel_linf, l1_error
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+H = pytest.importorskip("paper_2509_08971_amd")
+
+P, O, R = 0, 1, 2
+W5 = 1
+DEV = "cuda"
+TOL64 = 1e-12
+TOL32 = 1e-5
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def random_state(n, seed):
+    rng = np.random.default_rng(seed)
+    shape = tuple(reversed(n))
+    return workloads.conserved_from_primitive(rng.uniform(0.3, 1.5, shape),
+                                              [rng.uniform(-0.5, 0.5, shape) for _ in n],
+                                              rng.uniform(0.3, 1.5, shape))
+
+
+def run_gpu(n, bc, U0, dts, dtype=torch.float64):
+    g = H.make_grid(n, bc=bc, dtype=dtype, scheme=W5)
+    U = torch.from_numpy(np.ascontiguousarray(U0)).to(DEV, dtype)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    dt = torch.zeros(1, dtype=torch.float64, device=DEV)
+    nxt = torch.zeros(1, dtype=torch.float64, device=DEV)
+    for d in dts:
+        dt.fill_(d)
+        H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=nxt)
+    torch.cuda.synchronize()
+    assert H.hard_status_read(work) == 0
+    return U.double().cpu().numpy(), nxt.item()
+
+
+CASES = [
+    ((300,), (O, O)),
+    ((37,), (R, R)),
+    ((64,), (P, P)),
+    ((50, 37), (O, O, R, R)),
+    ((33, 40), (P, P, P, P)),
+    ((3, 9), (R, O, O, R)),
+    ((37, 21, 19), (P, P, R, R, O, O)),
+    ((16, 16, 16), (R, R)),
+    ((5, 6, 7), (O, R, P, P, R, O)),
+]
+
+
+@pytest.mark.parametrize("n,bc", CASES)
+def test_step_parity_fp64(n, bc):
+    log("weno fp64", n, bc)
+    U0 = random_state(n, 3)
+    og = oracle.Grid(n, bc=bc, scheme=W5)
+    dt, _ = oracle.cfl_dt(og, U0, 0.3)
+    ref, st = oracle.steps(og, U0, [dt] * 3)
+    assert st == 0
+    out, nxt = run_gpu(n, bc, U0, [dt] * 3)
+    for v in range(len(n) + 2):
+        assert field_rel_linf(out[v], ref[v]) <= TOL64, (v, field_rel_linf(out[v], ref[v]))
+    nref, _ = oracle.cfl_dt(og, out, 0.4)
+    assert nxt == nref
+
+
+@pytest.mark.parametrize("n,bc", [((1000,), (O, O)), ((50, 37), (O, O, R, R)),
+                                  ((37, 21, 19), (P, P, R, R, O, O))])
+def test_step_parity_fp32(n, bc):
+    log("weno fp32", n, bc)
+    U0 = random_state(n, 4).astype(np.float32).astype(np.float64)
+    og = oracle.Grid(n, bc=bc, scheme=W5)
+    dt, _ = oracle.cfl_dt(og, U0, 0.3)
+    ref, _ = oracle.steps(og, U0, [dt] * 3)
+    out, _ = run_gpu(n, bc, U0, [dt] * 3, dtype=torch.float32)
+    for v in range(len(n) + 2):
+        assert field_rel_l1(out[v], ref[v]) <= TOL32, (v, field_rel_l1(out[v], ref[v]))
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_uniform_state_preserved_bitwise(ndim):
+    n = (12, 10, 6)[:ndim]
+    shape = tuple(reversed(n))
+    U0 = workloads.conserved_from_primitive(np.full(shape, 0.7),
+                                            [np.full(shape, v) for v in (0.3, -0.2, 0.1)[:ndim]],
+                                            np.full(shape, 0.4))
+    out, _ = run_gpu(n, (P, P), U0, [1e-3] * 3)
+    assert np.array_equal(out, U0)
+
+
+def test_sod_paper_figure_on_gpu():
+    """The paper's Sod run on the GPU with the device time loop: the same
+    number of steps as the oracle, fields within 1e-12, and L1(rho) below
+    the paper's 5e-4."""
+    with open(os.path.join(GOLD, "sod_paper.json")) as f:
+        s = json.load(f)
+    n = int(round(1.0 / s["dx"]))
+    U0 = workloads.sod(n)
+    og = oracle.Grid((n,), bc=(O, O), scheme=W5)
+    ref, t_ref, steps_ref, st = oracle.run(og, U0, s["courant"], s["t_final"])
+    g = H.make_grid((n,), bc=(O, O), scheme=W5)
+    U = torch.from_numpy(U0).to(DEV)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    t, steps = H.hard_run(g, U, s["courant"], s["t_final"], work)
+    out = U.cpu().numpy()
+    assert steps == steps_ref and t == pytest.approx(t_ref, rel=1e-15, abs=0)
+    for v in range(3):
+        assert field_rel_linf(out[v], ref[v]) <= 1e-11, (v, field_rel_linf(out[v], ref[v]))
+    ex = RiemannSolution(1.0, 0.0, 1.0, 0.125, 0.0, 0.1)
+    r, _, _ = ex.cell_averages(n, t)
+    err = l1_error(out[0], r, s["dx"])
+    log(f"GPU WENO5-Z + HLL Sod L1(rho) = {err:.3e}")
+    assert err < s["paper_L1_rho_bound"]
+
+
+def test_turbulent_64_periodic_one_step():
+    n = 64
+    U0 = workloads.turbulent_box(n, ndim=3, seed=2)
+    og = oracle.Grid((n, n, n), bc=(P, P), scheme=W5)
+    dt, _ = oracle.cfl_dt(og, U0, 0.4)
+    ref, st = oracle.step(og, U0, dt)
+    assert st == 0
+    out, nxt = run_gpu((n, n, n), (P, P), U0, [dt])
+    for v in range(5):
+        assert field_rel_linf(out[v], ref[v]) <= TOL64, v

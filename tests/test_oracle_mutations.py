@@ -138,8 +138,8 @@ MUTATIONS = {
     "Heun combine uses U1 twice": ("U[x] = T(0.5) * (U[x] + (U1[x] + dt * L[x]));",
                                    "U[x] = T(0.5) * (U1[x] + (U1[x] + dt * L[x]));"),
     "flux difference sign": ("- (Fp - Fm) / T(g.dx[d]);", "- (Fm - Fp) / T(g.dx[d]);"),
-    "CFL takes the max over axes": ("s = s + (std::fabs(w[1 + d]) + cs) / g.dx[d];",
-                                    "s = std::max(s, (std::fabs(w[1 + d]) + cs) / g.dx[d]);"),
+    "CFL takes the max over axes": ("s = s + (fabs(w[1 + d]) + cs) / T(g.dx[d]);",
+                                    "s = std::max(s, (fabs(w[1 + d]) + cs) / T(g.dx[d]));"),
     "transverse momentum flux": ("FK[2 + t] = mn * W.ut[t];", "FK[2 + t] = W.rho * W.ut[t];"),
     "slope dropped (first order)": ("WL[v] = Wc[1][v] + T(0.5) * sl;",
                                     "WL[v] = Wc[1][v] + T(0.0) * sl;"),
@@ -161,9 +161,11 @@ def test_unmodified_oracle_passes_quick_pins(restore_oracle):
 def test_planted_mistake_is_caught(name, restore_oracle, tmp_path):
     old, new = MUTATIONS[name]
     src = open(obuild.SRC[0]).read()
-    assert src.count(old) == 1, f"mutation site not unique: {old}"
+    # the first occurrence is the MUSCL-HLLC path the quick pins run (the
+    # HLL flux of the second scheme repeats the wave-speed lines)
+    assert src.count(old) >= 1, f"mutation site missing: {old}"
     mutated = tmp_path / "hydro_oracle_mutant.cpp"
-    mutated.write_text(src.replace(old, new))
+    mutated.write_text(src.replace(old, new, 1))
     lib = obuild.build(src=str(mutated), out=str(tmp_path / "liboracle_mutant.so"))
     oracle.use_library(lib)
     try:
