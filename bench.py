@@ -163,6 +163,40 @@ def bench_batched(args, steps=100):
             "achieved_hbm_gbs": bytes_step / (ms / steps * 1e-3) / 1e9, "status_flags": flags}
 
 
+def bench_weno(args, n=256, steps=10):
+    """The paper's own face scheme (WENO5-Z + HLL) on the 256^3 FP64 blast:
+    the same step, as the per-axis pipeline (primitives, three face-flux
+    kernels, update with the fused CFL step)."""
+    import paper_2509_08971_amd as H
+    import workloads
+
+    log(f"bench: WENO5-Z + HLL blast {n}^3 fp64, {steps} steps")
+    g = H.make_grid((n, n, n), bc=(H.REFLECT, H.REFLECT), scheme=H.WENO5Z_HLL)
+    U = torch.from_numpy(workloads.blast_3d(n)).to("cuda")
+    work = H.workspace(H.hard_workspace_bytes(g))
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    H.hard_cfl_dt(g, U, 0.4, dt, work)
+    for _ in range(2):
+        H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=dt)
+    ms = _time_steps(lambda: H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=dt), steps,
+                     stream)
+    flags = H.hard_status_read(work)
+    N = n ** 3
+    zus = N * steps / (ms * 1e-3)
+    # pipeline words per cell and stage: prim (read U, write W), 3 x face
+    # (read W, write F), update (read 3 F, read src, write dst; stage 2 also
+    # reads U^n): 2 + 6 + 5 (+1) words of nvar; both stages
+    words = (2 + 6 + 5) + (2 + 6 + 6)
+    pipe_bytes = words * 5 * 8
+    log(f"  {ms / steps:.3f} ms/step, {zus / 1e9:.2f} G zu/s")
+    return {"value": zus, "unit": "zone-updates/s", "ms_per_step": ms / steps, "steps": steps,
+            "dtype": "f64", "workload": f"3D {n}^3 FP64 point-energy blast, reflecting, CFL 0.4, "
+                                         f"WENO5-Z + HLL (the paper's scheme) + SSP-RK2",
+            "pipeline_bytes_per_zone_update": pipe_bytes,
+            "achieved_hbm_gbs_pipeline": pipe_bytes * zus / 1e9, "status_flags": flags}
+
+
 def bench_adjoint(args, n=512, nsteps=200, every=20):
     """Config-4 gradient: 2D 512^2 FP64 periodic, 200 steps, checkpoints every
     20; gradient of J = dx^2/2 sum (rho_N - rho_T)^2 wrt the initial state."""
@@ -333,6 +367,10 @@ def main():
             extras["adjoint_512"] = bench_adjoint(args)
         except Exception as e:
             extras["adjoint_512"] = {"error": repr(e)}
+        try:
+            extras["weno5z_hll_256"] = bench_weno(args)
+        except Exception as e:
+            extras["weno5z_hll_256"] = {"error": repr(e)}
         out["beside_fp64_step"] = extras
 
     if not args.no_cpu_baseline:

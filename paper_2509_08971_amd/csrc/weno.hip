@@ -14,6 +14,12 @@
 // Bytes per cell and stage: the fused MUSCL kernel moves 2-3 nvar words; this
 // pipeline about 6 + 4 ndim nvar words (W and the face arrays round-trip
 // through memory).
+//
+// The arithmetic is plain: IEEE division and square root, no contraction,
+// the operations in the order of the formulas.  The WENO weights react to
+// the last bits of the smoothness indicators near a jump, and a pipeline
+// bound by memory traffic loses nothing by it, so over a run of hundreds of
+// steps the GPU stays within rounding of a plain evaluation.
 
 #include "hydro_device.hpp"
 #include "launch.hpp"
@@ -24,14 +30,14 @@ namespace hard {
 // i-2..i+2): third-order candidates on the three sub-stencils, Jiang-Shu
 // smoothness indicators, tau5 = |beta0 - beta2|, weights
 // d_k (1 + tau5 / (beta_k + eps)) with d = (1/10, 6/10, 3/10), eps = 1e-40.
-// Evaluated in double for both storage types: the weight ratios reach
-// 1e40 and beyond at a jump, out of float range (and the FP64 vector rate
-// of gfx950 equals its unpacked FP32 rate).
+// Evaluated in double for both storage types: at a jump the weight ratios
+// reach 1e40 and beyond, out of float range (and the FP64 vector rate of
+// gfx950 equals its unpacked FP32 rate).
 __device__ __forceinline__ double weno5z_d(double v0, double v1, double v2, double v3, double v4) {
-  const double inv6 = 1.0 / 6.0;
-  double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * inv6;
-  double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * inv6;
-  double q2 = (2.0 * v2 + 5.0 * v3 - v4) * inv6;
+#pragma clang fp contract(off)
+  double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) / 6.0;
+  double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) / 6.0;
+  double q2 = (2.0 * v2 + 5.0 * v3 - v4) / 6.0;
   double s0 = v0 - 2.0 * v1 + v2, t0 = v0 - 4.0 * v1 + 3.0 * v2;
   double s1 = v1 - 2.0 * v2 + v3, t1 = v1 - v3;
   double s2 = v2 - 2.0 * v3 + v4, t2 = 3.0 * v2 - 4.0 * v3 + v4;
@@ -40,10 +46,10 @@ __device__ __forceinline__ double weno5z_d(double v0, double v1, double v2, doub
   double b1 = c1 * s1 * s1 + c2 * t1 * t1;
   double b2 = c1 * s2 * s2 + c2 * t2 * t2;
   double tau = fabs(b0 - b2);
-  double a0 = 0.1 * (1.0 + tau * fast_rcp(b0 + eps));
-  double a1 = 0.6 * (1.0 + tau * fast_rcp(b1 + eps));
-  double a2 = 0.3 * (1.0 + tau * fast_rcp(b2 + eps));
-  return (a0 * q0 + a1 * q1 + a2 * q2) * fast_rcp(a0 + a1 + a2);
+  double a0 = 0.1 * (1.0 + tau / (b0 + eps));
+  double a1 = 0.6 * (1.0 + tau / (b1 + eps));
+  double a2 = 0.3 * (1.0 + tau / (b2 + eps));
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 template <typename R>
 __device__ __forceinline__ R weno5z(R v0, R v1, R v2, R v3, R v4) {
@@ -51,26 +57,29 @@ __device__ __forceinline__ R weno5z(R v0, R v1, R v2, R v3, R v4) {
 }
 
 // HLL flux of face states ordered (rho, u_n, u_t..., p); output (mass,
-// normal momentum, transverse momenta, energy).
+// normal momentum, transverse momenta, energy).  Davis wave speeds; F_L if
+// S_L >= 0, F_R if S_R <= 0, else (S_R F_L - S_L F_R + S_L S_R (U_R - U_L)) /
+// (S_R - S_L).
 template <typename R, int NV>
-__device__ __forceinline__ void hll_ordered(const R* WL, const R* WR, R gam, R inv_gm1, R* F) {
+__device__ __forceinline__ void hll_ordered(const R* WL, const R* WR, R gam, R gm1, R* F) {
+#pragma clang fp contract(off)
   constexpr int NT = NV - 3;
   const R rL = WL[0], uL = WL[1], pL = WL[NV - 1];
   const R rR = WR[0], uR = WR[1], pR = WR[NV - 1];
-  R cL = sound_speed(gam * pL, rL);
-  R cR = sound_speed(gam * pR, rR);
-  R aL = uL - cL, bL = uR - cR;
-  R SL = (aL <= bL) ? aL : bL;
-  R aR = uL + cL, bR = uR + cR;
-  R SR = (aR >= bR) ? aR : bR;
+  R cL = sqrt(gam * pL / rL);
+  R cR = sqrt(gam * pR / rR);
   R qL = uL * uL, qR = uR * uR;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     qL = qL + WL[2 + t] * WL[2 + t];
     qR = qR + WR[2 + t] * WR[2 + t];
   }
-  const R EL = pL * inv_gm1 + R(0.5) * rL * qL;
-  const R ER = pR * inv_gm1 + R(0.5) * rR * qR;
+  const R EL = pL / gm1 + R(0.5) * rL * qL;
+  const R ER = pR / gm1 + R(0.5) * rR * qR;
+  R aL = uL - cL, bL = uR - cR;
+  R SL = (aL <= bL) ? aL : bL;
+  R aR = uL + cL, bR = uR + cR;
+  R SR = (aR >= bR) ? aR : bR;
   const R mL = rL * uL, mR = rR * uR;
   R FL[NV], FR[NV], UL[NV], UR[NV];
   FL[0] = mL;
@@ -99,10 +108,28 @@ __device__ __forceinline__ void hll_ordered(const R* WL, const R* WR, R gam, R i
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v] = FR[v];
   } else {
-    const R inv = fast_rcp(SR - SL);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) * inv;
+    for (int v = 0; v < NV; ++v)
+      F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) / (SR - SL);
   }
+}
+
+// Primitives of one conserved state in the order of the formulas: ke =
+// 0.5 |m|^2 / rho, e = E - ke, p = (gamma - 1) e, u_d = m_d / rho.  Float
+// storage recovers e in double.
+template <typename R, int NDIM>
+__device__ __forceinline__ void primitives_plain(const R* u, double gamma, R* w) {
+#pragma clang fp contract(off)
+  const double rho = (double)u[0];
+  double q = (double)u[1] * (double)u[1];
+#pragma unroll
+  for (int d = 1; d < NDIM; ++d) q = q + (double)u[1 + d] * (double)u[1 + d];
+  const double ke = 0.5 * q / rho;
+  const double e = (double)u[NDIM + 1] - ke;
+  w[0] = u[0];
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) w[1 + d] = u[1 + d] / u[0];
+  w[NDIM + 1] = R((gamma - 1.0) * e);
 }
 
 template <typename R, int NDIM>
@@ -117,7 +144,7 @@ __global__ __launch_bounds__(256) void weno_prim(WenoArgs a) {
     R u[NV], w[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[v] = U[v * N + c];
-    to_primitive<R, NDIM>(u, w, a.gamma - 1.0);
+    primitives_plain<R, NDIM>(u, a.gamma, w);
     flags = cell_flags<R, NV>(u, w[NV - 1]);
 #pragma unroll
     for (int v = 0; v < NV; ++v) W[v * N + c] = w[v];
@@ -188,8 +215,8 @@ __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
     WL[m] = weno5z<R>(c[0][v], c[1][v], c[2][v], c[3][v], c[4][v]);
     WR[m] = weno5z<R>(c[5][v], c[4][v], c[3][v], c[2][v], c[1][v]);
   }
-  const R gam = R(a.gamma), inv_gm1 = R(1.0 / (a.gamma - 1.0));
-  hll_ordered<R, NV>(WL, WR, gam, inv_gm1, Fn);
+  const R gam = R(a.gamma), gm1 = R(a.gamma - 1.0);
+  hll_ordered<R, NV>(WL, WR, gam, gm1, Fn);
   R* F = static_cast<R*>(a.F[AX]);
 #pragma unroll
   for (int m = 0; m < NV; ++m) F[perm[m] * nface + idx] = Fn[m];
@@ -197,6 +224,7 @@ __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
 
 template <typename R, int NDIM, int STAGE>
 __global__ __launch_bounds__(256) void weno_update(WenoArgs a) {
+#pragma clang fp contract(off)
   constexpr int NV = NDIM + 2;
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const long long N = (long long)nx * ny * nz;
@@ -228,7 +256,8 @@ __global__ __launch_bounds__(256) void weno_update(WenoArgs a) {
 #pragma unroll
       for (int d = 0; d < NDIM; ++d) {
         const R* F = static_cast<const R*>(a.F[d]) + v * nf[d];
-        l = l - (F[fm[d] + step[d]] - F[fm[d]]) * R(a.inv_dx[d]);
+        const R df = F[fm[d] + step[d]] - F[fm[d]];
+        l = l - (a.dx_pow2 ? df * R(a.inv_dx[d]) : df / R(a.dx[d]));
       }
       const R u = src[v * N + c];
       if (STAGE == 1)
