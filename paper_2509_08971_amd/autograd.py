@@ -12,7 +12,7 @@ checkpoints.
 """
 import torch
 
-from . import (hard_adjoint_workspace_bytes, hard_cfl_dt, hard_hydro_step,
+from . import (hard_adjoint_workspace_bytes, hard_cfl_dt, hard_hydro_stage, hard_hydro_step,
                hard_hydro_step_adjoint, hard_workspace_bytes, workspace)
 
 
@@ -22,15 +22,17 @@ class HydroRollout(torch.autograd.Function):
         U = U0.detach().clone().contiguous()
         dev = U.device
         work = workspace(hard_workspace_bytes(grid), dev)
-        dt = torch.zeros(1, dtype=torch.float64, device=dev)
-        dts = torch.zeros(nsteps, dtype=torch.float64, device=dev)
-        hard_cfl_dt(grid, U, cfl, dt, work)
+        # dts[n] is the step buffer of step n; the fused CFL of step n writes
+        # dts[n + 1] directly (the last one goes to a spare slot)
+        dts_buf = torch.zeros(nsteps + 1, dtype=torch.float64, device=dev)
+        hard_cfl_dt(grid, U, cfl, dts_buf[0:1], work)
         ckpts = []
         for n in range(nsteps):
             if n % every == 0:
                 ckpts.append(U.clone())
-            dts[n:n + 1].copy_(dt)
-            hard_hydro_step(grid, U, dt, work, cfl=cfl, next_dt_dev=dt)
+            hard_hydro_step(grid, U, dts_buf[n:n + 1], work, cfl=cfl,
+                            next_dt_dev=dts_buf[n + 1:n + 2])
+        dts = dts_buf[:nsteps]
         ctx.grid = grid
         ctx.nsteps = nsteps
         ctx.every = every
@@ -45,13 +47,17 @@ class HydroRollout(torch.autograd.Function):
         dev = lam.device
         work = workspace(hard_workspace_bytes(grid), dev)
         awork = workspace(hard_adjoint_workspace_bytes(grid), dev)
+        U1 = torch.empty_like(lam)
         for seg in reversed(range(len(ckpts))):
             start = seg * every
             end = min(start + every, nsteps)
             states = [ckpts[seg]]
             for n in range(start, end - 1):
-                U = states[-1].clone()
-                hard_hydro_step(grid, U, dts[n:n + 1], work)
+                # recompute the segment's states: stage 1 into a scratch state,
+                # stage 2 straight into the new state (no copy of U^n)
+                U = torch.empty_like(lam)
+                hard_hydro_stage(grid, 1, states[-1], None, U1, dts[n:n + 1], work)
+                hard_hydro_stage(grid, 2, U1, states[-1], U, dts[n:n + 1], work)
                 states.append(U)
             for n in reversed(range(start, end)):
                 hard_hydro_step_adjoint(grid, states[n - start], dts[n:n + 1], lam, awork)
@@ -67,13 +73,11 @@ def recorded_dts(U0, grid, nsteps, cfl=0.4):
     """The step sizes a rollout from U0 uses (device tensor of nsteps)."""
     U = U0.detach().clone().contiguous()
     work = workspace(hard_workspace_bytes(grid), U.device)
-    dt = torch.zeros(1, dtype=torch.float64, device=U.device)
-    dts = torch.zeros(nsteps, dtype=torch.float64, device=U.device)
-    hard_cfl_dt(grid, U, cfl, dt, work)
+    dts = torch.zeros(nsteps + 1, dtype=torch.float64, device=U.device)
+    hard_cfl_dt(grid, U, cfl, dts[0:1], work)
     for n in range(nsteps):
-        dts[n:n + 1].copy_(dt)
-        hard_hydro_step(grid, U, dt, work, cfl=cfl, next_dt_dev=dt)
-    return dts, U
+        hard_hydro_step(grid, U, dts[n:n + 1], work, cfl=cfl, next_dt_dev=dts[n + 1:n + 2])
+    return dts[:nsteps], U
 
 
 def run_fixed(U0, grid, dts):

@@ -256,8 +256,8 @@ __device__ __forceinline__ void hllc_vjp(const double* WL, const double* WR, dou
 }
 
 // One face along `axis`: contributions of its flux adjoint to the primitive
-// adjoints of its four stencil cells, written to C[face][slot][var]
-// (primitive order, before any ghost fold).
+// adjoints of its four stencil cells, written to C[slot][var][face]
+// (primitive order, before any ghost fold; faces numbered x fastest).
 template <int NDIM, int axis>
 __global__ __launch_bounds__(256) void adj_face(const double* __restrict__ X,
                                                 const double* __restrict__ mu,
@@ -268,15 +268,17 @@ __global__ __launch_bounds__(256) void adj_face(const double* __restrict__ X,
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const long long N = (long long)nx * ny * nz;
   const int nd = g.n[axis];
-  const long long nother = N / nd;
+  // faces form a grid of n + 1 positions along `axis` and n along the others,
+  // x fastest (so that neighbouring threads touch neighbouring cells)
+  const int m0 = nx + (axis == 0), m1 = ny + (axis == 1);
+  const long long NF = (long long)m0 * m1 * (nz + (axis == 2));
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= nother * (nd + 1)) return;
-  const int f = (int)(id % (nd + 1));
-  const long long o = id / (nd + 1);
-  int c0[3] = {0, 0, 0};
-  if constexpr (axis == 0) { c0[1] = (int)(o % ny); c0[2] = (int)(o / ny); }
-  else if constexpr (axis == 1) { c0[0] = (int)(o % nx); c0[2] = (int)(o / nx); }
-  else { c0[0] = (int)(o % nx); c0[1] = (int)(o / nx); }
+  if (id >= NF) return;
+  int c0[3];
+  c0[0] = (int)(id % m0);
+  c0[1] = (int)((id / m0) % m1);
+  c0[2] = (int)(id / ((long long)m0 * m1));
+  const int f = c0[axis];
   auto cell = [&](int q, bool& flip) -> long long {
     int c[3] = {c0[0], c0[1], c0[2]};
     c[axis] = remap(q, nd, g.bc[axis][0], g.bc[axis][1], flip);
@@ -353,11 +355,10 @@ __global__ __launch_bounds__(256) void adj_face(const double* __restrict__ X,
     if (pr[v] == 1) { Cb[2][v] += srb; Cb[1][v] -= srb; }
     else if (pr[v] == 2) { Cb[3][v] += srb; Cb[2][v] -= srb; }
   }
-  double* out = C + (o * (nd + 1) + f) * 4 * NV;
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int v = 0; v < NV; ++v) out[s * NV + v] = Cb[s][v];
+    for (int v = 0; v < NV; ++v) C[(s * NV + v) * NF + id] = Cb[s][v];
 }
 
 // Per cell: sum the contributions of every face stencil that reads it along
@@ -373,11 +374,13 @@ __global__ __launch_bounds__(256) void adj_gather(AdjGeo g, int axis, const doub
   if (c >= N) return;
   const int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((long long)nx * ny));
   const int nd = g.n[axis];
-  int j;
-  long long o;
-  if (axis == 0) { j = x; o = (long long)z * ny + y; }
-  else if (axis == 1) { j = y; o = (long long)z * nx + x; }
-  else { j = z; o = (long long)y * nx + x; }
+  const int j = axis == 0 ? x : (axis == 1 ? y : z);
+  // the face grid of `axis` (see adj_face): index of face position f on this
+  // cell's line, f = 0 .. nd
+  const int m0 = nx + (axis == 0), m1 = ny + (axis == 1);
+  const long long NF = (long long)m0 * m1 * (nz + (axis == 2));
+  const long long fstride = axis == 0 ? 1 : (axis == 1 ? (long long)m0 : (long long)m0 * m1);
+  const long long fbase = ((long long)z * m1 + y) * m0 + x - (long long)j * fstride;
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
@@ -392,10 +395,10 @@ __global__ __launch_bounds__(256) void adj_gather(AdjGeo g, int axis, const doub
     const int f0 = q - 1 > 0 ? q - 1 : 0;
     const int f1 = q + 2 < nd ? q + 2 : nd;
     for (int f = f0; f <= f1; ++f) {
-      const double* in = C + (o * (nd + 1) + f) * 4 * NV + (q - f + 2) * NV;
+      const double* in = C + (long long)(q - f + 2) * NV * NF + fbase + f * fstride;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        double val = in[v];
+        double val = in[v * NF];
         if (flip && v == 1 + axis) val = -val;
         acc[v] += val;
       }

@@ -51,7 +51,7 @@ void stage_kernel(StageArgs a) {
   t.fuse_cfl = STAGE == 2 && a.fuse_cfl;
   unsigned flags = 0;
   double smax = 0.0;
-  run_tile<NDIM, R, STAGE, TX, TY, NTHR>(t, lds, flags, smax);
+  run_tile<NDIM, R, STAGE, TX, TY, NTHR, NDIM == 3>(t, lds, flags, smax);
   block_finish<NTHR>(flags, smax, STAGE == 2 && a.fuse_cfl, a.ctl, a.cfl, a.next_dt);
 }
 

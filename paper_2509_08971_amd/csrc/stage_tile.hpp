@@ -42,27 +42,21 @@ struct TileArgs {
 };
 
 // Streams that no other workgroup reads again within the launch -- the
-// stored result and, in stage 2, U^n of the own cell -- go through the cache
-// as non-temporal accesses, so that they do not push the halo lines that
-// neighbouring tiles re-read out of the XCD's L2.
-#ifndef HARD_NT_STREAMS
-#define HARD_NT_STREAMS 1
-#endif
-template <typename R>
+// stored result and, in stage 2, U^n of the own cell -- can go through the
+// cache as non-temporal accesses (NTS), so that they do not push the halo
+// lines that neighbouring tiles re-read out of the XCD's L2.  That pays for
+// 3D tiles, whose rows are whole 128-byte lines; the batched kernels store
+// 63-cell rows that straddle lines, which the L2 must merge before they
+// reach memory, so they keep ordinary stores.
+template <bool NTS, typename R>
 __device__ __forceinline__ R stream_load(const R* p) {
-#if HARD_NT_STREAMS
-  return __builtin_nontemporal_load(p);
-#else
-  return *p;
-#endif
+  if constexpr (NTS) return __builtin_nontemporal_load(p);
+  else return *p;
 }
-template <typename R>
+template <bool NTS, typename R>
 __device__ __forceinline__ void stream_store(R* p, R v) {
-#if HARD_NT_STREAMS
-  __builtin_nontemporal_store(v, p);
-#else
-  *p = v;
-#endif
+  if constexpr (NTS) __builtin_nontemporal_store(v, p);
+  else *p = v;
 }
 
 template <int NDIM, typename R, int TX, int TY>
@@ -85,7 +79,7 @@ struct TileShape {
 // workgroup must call it (it contains barriers).  NTHR (>= TX*TY) is the
 // workgroup size; threads beyond TX*TY own no cell but take part in the face
 // and halo loops (a row of 63 cells has exactly 64 faces, one per lane).
-template <int NDIM, typename R, int STAGE, int TX, int TY, int NTHR = TX * TY>
+template <int NDIM, typename R, int STAGE, int TX, int TY, int NTHR = TX * TY, bool NTS = false>
 __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& flags, double& smax) {
   using S = TileShape<NDIM, R, TX, TY>;
   constexpr int NV = S::NV, PD = S::PD, LX = S::LX, LXY = S::LXY;
@@ -228,7 +222,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
     const long long cidx = (long long)w * WS + col;
     if (STAGE == 2 && inside) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Un0[v] = stream_load(un + v * N + cidx);
+      for (int v = 0; v < NV; ++v) Un0[v] = stream_load<NTS>(un + v * N + cidx);
     }
     if constexpr (!WALK) col_prim(Ucur, false, P0);
 
@@ -341,7 +335,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
         }
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) stream_store(dst + v * N + cidx, Out[v]);
+      for (int v = 0; v < NV; ++v) stream_store<NTS>(dst + v * N + cidx, Out[v]);
       if (STAGE == 2 && a.fuse_cfl) {
         double Ud[NV];
 #pragma unroll
