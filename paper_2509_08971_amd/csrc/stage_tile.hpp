@@ -286,12 +286,25 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
         // far faces the spare threads did not cover
         constexpr int RX = NSPARE < TY ? TY - NSPARE : 0;
         constexpr int RY = NSPARE < TX ? TX - NSPARE : 0;
-        if (tid < RX) {
-          const int j = NSPARE + tid;
-          face((j + OY) * LX + TX, j * (TX + 1) + TX, XF{});
-        } else if (tid < RX + RY) {
-          const int j = NSPARE + tid - RX;
-          face(TY * LX + j + 2, NFX + TY * TX + j, YF{});
+        // one far-face computation per wave (a few lanes each): the x faces
+        // on the first half of the waves, the y faces on the second half, so
+        // that no wave does two and the others wait for it at the barrier
+        constexpr int NW = NT / 64;
+        static_assert(NW >= 2 && NW % 2 == 0, "far-face split needs an even number of waves");
+        constexpr int PX = (RX + NW / 2 - 1) / (NW / 2), PY = (RY + NW / 2 - 1) / (NW / 2);
+        const int wv = tid >> 6, ln = tid & 63;
+        if (wv < NW / 2) {
+          const int r = wv * PX + ln;
+          if (ln < PX && r < RX) {
+            const int j = NSPARE + r;
+            face((j + OY) * LX + TX, j * (TX + 1) + TX, XF{});
+          }
+        } else {
+          const int r = (wv - NW / 2) * PY + ln;
+          if (ln < PY && r < RY) {
+            const int j = NSPARE + r;
+            face(TY * LX + j + 2, NFX + TY * TX + j, YF{});
+          }
         }
       }
     }
