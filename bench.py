@@ -24,6 +24,10 @@ import numpy as np  # noqa: E402
 import torch  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# floating-point operations of one zone-update in 3D as the oracle evaluates
+# them (oracle.ops_per_zone_update: 485 add, 378 mul, 87 div, 13 sqrt, 118
+# compare, 64 abs); tests/test_oracle_opcount.py recomputes it
+OPS_PER_ZU_3D = 1145
 
 
 # Sources of the stage kernel; HBM byte counts taken with rocprofv3 are
@@ -43,21 +47,38 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def _counter_lines():
+    """Machine-readable lines of the committed counter summary, or {} if the
+    kernel sources changed since the counters were taken."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            kv = dict(l.split(":", 1) for l in f.read().splitlines() if ":" in l and
+                      l.split(":", 1)[0].strip().startswith(("kernel-source-sha256", "stage1-",
+                                                             "stage2-")))
+    except OSError:
+        return {}
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel-source-sha256") != kernel_source_hash():
+        return {}
+    return kv
+
+
 def measured_traffic():
     """Stage-2 HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, each scaled by the
     copy-kernel factor), from the committed counter summary, or None if the
     kernel sources changed since it was taken."""
-    try:
-        with open(COUNTERS_FILE) as f:
-            kv = dict(l.split(":", 1) for l in f.read().splitlines() if ":" in l and
-                      l.split(":", 1)[0].strip().startswith(("kernel-source-sha256", "stage2-")))
-    except OSError:
-        return None
-    kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("kernel-source-sha256") != kernel_source_hash():
-        return None
+    kv = _counter_lines()
     try:
         return (int(kv["stage2-fetch-bytes-per-launch"]), int(kv["stage2-write-bytes-per-launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_valu():
+    """SQ_INSTS_VALU per 64 cells of stage 1 and stage 2 (same rule as above)."""
+    kv = _counter_lines()
+    try:
+        return (float(kv["stage1-valu-per-64-cells"]), float(kv["stage2-valu-per-64-cells"]))
     except (KeyError, ValueError):
         return None
 
@@ -218,12 +239,17 @@ def bench_adjoint(args, n=512, nsteps=200, every=20):
     AG.recorded_dts(U0, g, nsteps)
     torch.cuda.synchronize()
     fwd = _t.perf_counter() - t0
-    X = U0.clone().requires_grad_(True)
+    def gradient():
+        X = U0.clone().requires_grad_(True)
+        UN = AG.rollout(X, g, nsteps, 0.4, every)
+        J = 0.5 * (1.0 / n) ** 2 * ((UN[0] - rhoT) ** 2).sum()
+        J.backward()
+        return X.grad
+
+    gradient()  # untimed: the allocator's first requests for the checkpoints and buffers
     torch.cuda.synchronize()
     t0 = _t.perf_counter()
-    UN = AG.rollout(X, g, nsteps, 0.4, every)
-    J = 0.5 * (1.0 / n) ** 2 * ((UN[0] - rhoT) ** 2).sum()
-    J.backward()
+    gradient()
     torch.cuda.synchronize()
     full = _t.perf_counter() - t0
     N = n * n
@@ -234,7 +260,8 @@ def bench_adjoint(args, n=512, nsteps=200, every=20):
             "gradient_zone_updates_per_s": N * nsteps / full,
             "workload": f"2D {n}^2 FP64 periodic, {nsteps} steps, checkpoints every {every}, "
                         f"loss on final rho against a perturbed-start target",
-            "timing": "host wall clock around the whole forward / forward+backward"}
+            "timing": "host wall clock around the whole forward / forward+backward, after "
+                      "one untimed forward+backward (allocator warm-up)"}
 
 
 def main():
@@ -325,6 +352,7 @@ def main():
     ach1 = b_stage1 / (s1.mean() * 1e-3) / 1e9
     step_gbs = (b_stage1 + b_stage2) / (ms_per_step * 1e-3) / 1e9
     traffic = measured_traffic() if n == 256 else None
+    valu = measured_valu() if n == 256 else None
 
     out = {
         "metric": "zone-updates/s",
@@ -352,6 +380,16 @@ def main():
                      "stage2_ms": float(s2.mean())},
         "status_flags": flags,
     }
+    # the VALU ceiling beside the byte roofline: one wave64 FP64 instruction
+    # per 4 cycles on each of 1024 SIMDs at 2.4 GHz = 39.3 T lane-instr/s
+    lane_peak = 256 * 4 * 16 * 2.4e9
+    alu = {"bound": "alu", "unit": "lane-instr/s", "peak": lane_peak,
+           "oracle_ops_per_zone_update": OPS_PER_ZU_3D}
+    if valu:
+        per_zu = valu[0] + valu[1]  # lane-instructions per zone-update, both stages
+        alu.update({"valu_per_zone_update": per_zu, "achieved": zus * per_zu,
+                    "frac": zus * per_zu / lane_peak, "ceiling_zone_updates_per_s": lane_peak / per_zu})
+    out["alu_beside"] = alu
 
     if not args.only_main:
         extras = {}

@@ -32,3 +32,13 @@ def test_ops_per_zone_update_3d():
     # two stages x three faces x two sound speeds + one for the CFL step
     assert r["sqrt"] == 13.0
     assert 900 < sum(r.values()) < 1500
+
+
+def test_bench_reports_the_oracle_count():
+    """bench.py quotes the count beside its VALU figures; it must be the oracle's."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    r = oracle.ops_per_zone_update(3, lambda n: workloads.turbulent_box(n, ndim=3, seed=2), 16, 32)
+    assert bench.OPS_PER_ZU_3D == round(sum(r.values()))
