@@ -231,3 +231,44 @@ def test_run_to_run_bitwise():
     a, _ = run_gpu(n, (P, P), U0, [1e-3] * 3, fuse=True)
     b, _ = run_gpu(n, (P, P), U0, [1e-3] * 3, fuse=True)
     assert np.array_equal(a, b)
+
+
+def test_turbulent_512_fp32_full_size_sampled():
+    """The 512^3 FP32 periodic turbulent box at full size, in the launch the
+    benchmark times (hard_hydro_step with the fused dt): one step, checked on
+    sampled cells.  A cell's new value depends only on the cells within 4 of
+    it (two stages of a 2-cell stencil), so the oracle steps a 9^3 window
+    around each sample (periodic wrap, any boundary at the window's edge) and
+    the window's centre must match.  FP32 bar: relative L1 over the samples
+    <= 1e-5 per field against the FP64 oracle on the float-rounded input."""
+    n = 512
+    log("turbulent 512^3 fp32 sampled")
+    U = workloads.turbulent_box_torch(n, ndim=3, seed=2, device=DEV, dtype=torch.float32)
+    U0 = U.clone()
+    g = H.make_grid((n, n, n), bc=(P, P), dtype=torch.float32)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    dt = torch.zeros(1, dtype=torch.float64, device=DEV)
+    H.hard_cfl_dt(g, U, 0.4, dt, work)
+    dtv = dt.item()
+    H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=dt)
+    torch.cuda.synchronize()
+    assert H.hard_status_read(work) == 0
+    rng = np.random.default_rng(17)
+    pts = rng.integers(0, n, size=(48, 3))
+    # corner and edge cells exercise the periodic wrap
+    pts[:4] = [[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 5], [n - 1, 3, 0]]
+    r = np.arange(-4, 5)
+    got, ref = [], []
+    og = oracle.Grid((9, 9, 9), bc=(O, O), dx=(1.0 / n,) * 3)
+    for z, y, x in pts:
+        iz = torch.from_numpy((z + r) % n).to(DEV)
+        iy = torch.from_numpy((y + r) % n).to(DEV)
+        ix = torch.from_numpy((x + r) % n).to(DEV)
+        win = U0[:, iz][:, :, iy][:, :, :, ix].double().cpu().numpy()
+        out, _ = oracle.step(og, win, dtv)
+        ref.append(out[:, 4, 4, 4])
+        got.append(U[:, z, y, x].double().cpu().numpy())
+    got, ref = np.array(got), np.array(ref)
+    for v in range(5):
+        rel = np.abs(got[:, v] - ref[:, v]).sum() / np.abs(ref[:, v]).sum()
+        assert rel <= TOL32, (v, rel)

@@ -502,3 +502,21 @@ def test_tangent_full_jacobian_brute_force_small():
         fd = (Up - Um) / (2 * h)
         worst = max(worst, np.abs(fd - D).max())
     assert worst < 1e-6
+
+
+def test_step_is_local_within_radius_4():
+    """A cell's new value depends only on the cells within 4 of it (two stages
+    of a 2-cell stencil): stepping a 9^3 window cut around it (periodic wrap,
+    outflow at the window's edge) reproduces it bitwise.  The full-size GPU
+    parity tests sample cells this way."""
+    n = 20
+    U0 = workloads.turbulent_box(n, ndim=3, seed=6)
+    g = oracle.Grid((n, n, n), bc=(P, P))
+    dt, _ = oracle.cfl_dt(g, U0, 0.4)
+    full, _ = oracle.step(g, U0, dt)
+    r = np.arange(-4, 5)
+    og = oracle.Grid((9, 9, 9), bc=(O, O), dx=(1.0 / n,) * 3)
+    for z, y, x in [(0, 0, 0), (n - 1, n - 1, n - 1), (5, 17, 2), (12, 0, n - 1)]:
+        win = np.ascontiguousarray(U0[:, (z + r) % n][:, :, (y + r) % n][:, :, :, (x + r) % n])
+        out, _ = oracle.step(og, win, dt)
+        assert np.array_equal(out[:, 4, 4, 4], full[:, z, y, x])
