@@ -48,7 +48,7 @@ def lib(path=None):
         i64p = ctypes.POINTER(ctypes.c_int64)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
-        common = [ctypes.c_int, i64p, dp, ctypes.c_double, ip, ctypes.c_int]
+        common = [ctypes.c_int, i64p, dp, ctypes.c_double, ip, ctypes.c_int, dp]
         L.oracle_rhs.argtypes = common + [dp, dp]
         L.oracle_rhs.restype = ctypes.c_int
         L.oracle_step.argtypes = common + [ctypes.c_double, dp]
@@ -86,6 +86,7 @@ class Grid:
     bc: Sequence[int] = (OUTFLOW, OUTFLOW)  # (lo, hi) per axis, flattened
     dx: Sequence[float] = field(default=None)
     scheme: int = 0  # MUSCL_HLLC or WENO5Z_HLL
+    rad: Sequence[float] = None  # (kappa, mu): radiation energy density as one more field
 
     def __post_init__(self):
         self.n = tuple(int(v) for v in self.n)
@@ -107,7 +108,7 @@ class Grid:
 
     @property
     def nvar(self):
-        return self.ndim + 2
+        return self.ndim + 2 + (self.rad is not None)
 
     @property
     def shape(self):
@@ -118,7 +119,8 @@ class Grid:
         n3 = (ctypes.c_int64 * 3)(*(list(self.n) + [1] * (3 - self.ndim)))
         dx3 = (ctypes.c_double * 3)(*(list(self.dx) + [1.0] * (3 - self.ndim)))
         bc6 = (ctypes.c_int * 6)(*(list(self.bc) + [0] * (6 - 2 * self.ndim)))
-        return [self.ndim, n3, dx3, self.gamma, bc6, int(self.scheme)]
+        radp = None if self.rad is None else (ctypes.c_double * 2)(*[float(v) for v in self.rad])
+        return [self.ndim, n3, dx3, self.gamma, bc6, int(self.scheme), radp]
 
 
 def _dptr(a):

@@ -17,6 +17,13 @@
 //     face fluxes by the HLLC approximate Riemann solver (Toro, "Riemann
 //     Solvers and Numerical Methods for Fluid Dynamics", 3rd ed., section 10.4,
 //     Davis wave-speed estimates);
+//   * optionally the radiation energy density E as one more conserved field
+//     (section 2.2.1: the fourth row of the conservation law and its source):
+//     advected with the fluid velocity through the local Lax-Friedrichs
+//     (Rusanov) flux (section 2.2.2), and exchanged with the fluid internal
+//     energy by the heating rate qdot = c kappa rho (E - a T^4) (equation
+//     "heating-cooling"), integrated implicitly after each step; the
+//     diffusion flux and the radiation pressure work are not part of it;
 //   * or, as a second scheme, the paper's own choice (section 2.2.2): WENO5-Z
 //     face states (Borges, Carmona, Costa and Don 2008) on primitive
 //     variables with the HLL flux (Harten, Lax and van Leer 1983; Davis
@@ -40,6 +47,7 @@
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <type_traits>
 #include <vector>
 
 namespace hard_oracle {
@@ -114,7 +122,11 @@ enum : int { SCHEME_MUSCL_HLLC = 0, SCHEME_WENO5Z_HLL = 1 };
 
 struct Grid {
   int ndim;       // 1, 2 or 3
-  int nvar;       // ndim + 2
+  int nvar;       // ndim + 2 (+1 with radiation)
+  int nh;         // hydro fields: ndim + 2
+  int rad;        // 1: field nh is the radiation energy density E
+  double kappa;   // opacity (cm^2/g), radiation only
+  double mu;      // mean molecular weight, radiation only
   int64_t n[3];   // cells per axis; unused axes have n = 1
   double dx[3];   // cell width per axis
   double gamma;   // ratio of specific heats
@@ -129,12 +141,16 @@ struct Grid {
 };
 
 static Grid make_grid(int ndim, const int64_t* n, const double* dx, double gamma,
-                      const int* bc, int scheme) {
+                      const int* bc, int scheme, const double* radp) {
   Grid g;
   g.scheme = scheme;
   g.ng = scheme == SCHEME_WENO5Z_HLL ? 3 : 2;
   g.ndim = ndim;
-  g.nvar = ndim + 2;
+  g.nh = ndim + 2;
+  g.rad = radp != nullptr;
+  g.kappa = radp ? radp[0] : 0.0;
+  g.mu = radp ? radp[1] : 1.0;
+  g.nvar = g.nh + g.rad;
   g.gamma = gamma;
   for (int d = 0; d < 3; ++d) {
     g.n[d] = d < ndim ? n[d] : 1;
@@ -349,7 +365,8 @@ static T weno5z(const T* v) {
 // Primitive variables of one conserved state: rho, u_0..u_{ndim-1}, p.
 // Returns status bits.
 template <class T>
-static int primitives(const T* u, int ndim, double gamma, T* w) {
+static int primitives(const T* u, int ndim, double gamma, T* w, int nextra = 0) {
+  for (int x = 0; x < nextra; ++x) w[ndim + 2 + x] = u[ndim + 2 + x];
   T rho = u[0];
   T q = u[1] * u[1];
   for (int d = 1; d < ndim; ++d) q = q + u[1 + d] * u[1 + d];
@@ -362,9 +379,63 @@ static int primitives(const T* u, int ndim, double gamma, T* w) {
   int st = 0;
   if (!(value(rho) > 0.0)) st |= ST_RHO;
   if (!(value(p) > 0.0)) st |= ST_PRES;
-  for (int v = 0; v < ndim + 2; ++v)
+  for (int v = 0; v < ndim + 2 + nextra; ++v)
     if (!std::isfinite(value(u[v]))) st |= ST_NONFINITE;
   return st;
+}
+
+// Local Lax-Friedrichs (Rusanov) flux of the radiation energy density E
+// advected with the normal fluid velocity: (E_L u_L + E_R u_R)/2 -
+// s (E_R - E_L)/2, s = max(|u_L| + c_L, |u_R| + c_R), from the same face
+// states as the hydro flux.
+template <class T>
+static T rusanov_E(const Prim<T>& L, const Prim<T>& R, T EL, T ER, double gamma) {
+  const T g(gamma);
+  T cL = sqrt(g * L.p / L.rho);
+  T cR = sqrt(g * R.p / R.rho);
+  T sL = fabs(L.un) + cL, sR = fabs(R.un) + cR;
+  T s = sL >= sR ? sL : sR;
+  return T(0.5) * (EL * L.un + ER * R.un) - T(0.5) * s * (ER - EL);
+}
+
+// Physical constants (CGS; CODATA 2018): speed of light, radiation constant
+// a = 4 sigma / c, Boltzmann constant, atomic mass unit.
+constexpr double C_LIGHT = 2.99792458e10;
+constexpr double A_RAD = 4.0 * 5.670374419e-5 / 2.99792458e10;
+constexpr double K_BOLTZ = 1.380649e-16;
+constexpr double M_U = 1.66053906660e-24;
+
+// Radiation-matter exchange of one cell over dt, backward Euler on
+//   de/dt = qdot,  dE/dt = -qdot,  qdot = c kappa rho (E - a T^4),
+// with T = e / C_v, C_v = rho k_B / (mu m_u (gamma - 1)) the ideal-gas heat
+// capacity per volume.  e + E = W is conserved; with E' = (E + dt q a T'^4) /
+// (1 + dt q), q = c kappa rho, the new temperature is the root of the
+// increasing convex f(T) = C_v T + E'(T) - W, found by Newton iterations from
+// an upper bound (so they decrease monotonically onto the root).  The
+// kinetic energy is untouched: the total fluid energy changes by e' - e.
+static void exchange(double rho, double ke, double& Ef, double& Er, double dt,
+                     const Grid& g) {
+  const double q = C_LIGHT * g.kappa * rho;
+  const double dq = dt * q;
+  if (!(dq > 0.0)) return;
+  const double e = Ef - ke;
+  const double Cv = rho * K_BOLTZ / (g.mu * M_U * (g.gamma - 1.0));
+  const double W = e + Er;
+  // upper bounds: all energy in the fluid; or none of it (C_v T dropped)
+  const double t1 = W / Cv;
+  const double t2 = std::sqrt(std::sqrt((W * (1.0 + dq) - Er) / (dq * A_RAD)));
+  double T = t1 < t2 ? t1 : t2;
+  for (int it = 0; it < 200; ++it) {
+    const double T3 = T * T * T;
+    const double f = Cv * T + (Er + dq * A_RAD * (T3 * T)) / (1.0 + dq) - W;
+    const double fp = Cv + 4.0 * dq * A_RAD * T3 / (1.0 + dq);
+    const double Tn = T - f / fp;
+    if (!(Tn < T)) break;  // monotone from above: stop when it no longer decreases
+    T = Tn;
+  }
+  const double e_new = Cv * T;
+  Ef = Ef + (e_new - e);
+  Er = W - e_new;
 }
 
 // ----------------------------------------------------------------------------
@@ -418,9 +489,9 @@ static int rhs(const Grid& g, const T* U, T* Lout) {
   int status = 0;
 #pragma omp parallel for schedule(static) reduction(| : status)
   for (int64_t c = 0; c < PN; ++c) {
-    T u[5], w[5];
+    T u[6], w[6];
     for (int v = 0; v < nv; ++v) u[v] = G[(size_t)v * PN + c];
-    int st = primitives(u, nd, g.gamma, w);
+    int st = primitives(u, nd, g.gamma, w, g.rad);
     for (int v = 0; v < nv; ++v) W[(size_t)v * PN + c] = w[v];
     // validity is judged on interior cells only (ghosts are copies of them)
     int64_t i = c % g.pn[0], j = (c / g.pn[0]) % g.pn[1], k = c / (g.pn[0] * g.pn[1]);
@@ -450,17 +521,17 @@ static int rhs(const Grid& g, const T* U, T* Lout) {
       const int ns = 2 * g.ng;  // stencil cells f-ng .. f+ng-1
       for (int64_t f = 0; f < nf; ++f) {
         // face between cells f-1 and f along d
-        T Wst[6][5];
+        T Wst[6][6];
         for (int s = 0; s < ns; ++s) {
           int64_t p[3] = {o[0], o[1], o[2]};
           p[d] = f - g.ng + s;
           int64_t pi = pidx(g, p[0], p[1], p[2]);
           for (int v = 0; v < nv; ++v) Wst[s][v] = W[(size_t)v * PN + pi];
         }
-        T WL[5], WR[5];
+        T WL[6], WR[6];
         if (g.scheme == SCHEME_MUSCL_HLLC) {
           // Wc[0..3] = cells f-2 .. f+1
-          T (*Wc)[5] = Wst;
+          T (*Wc)[6] = Wst;
           for (int v = 0; v < nv; ++v) {
             T sl = minmod(Wc[1][v] - Wc[0][v], Wc[2][v] - Wc[1][v]);  // slope of cell f-1
             T sr = minmod(Wc[2][v] - Wc[1][v], Wc[3][v] - Wc[2][v]);  // slope of cell f
@@ -492,13 +563,13 @@ static int rhs(const Grid& g, const T* U, T* Lout) {
         }
         PL.p = WL[nd + 1];
         PR.p = WR[nd + 1];
-        T Fn[5];
+        T Fn[6];
         if (g.scheme == SCHEME_MUSCL_HLLC)
           hllc_flux(PL, PR, nd - 1, g.gamma, Fn);
         else
           hll_flux(PL, PR, nd - 1, g.gamma, Fn);
         // rotate back to (mass, m_0.., energy)
-        T Fo[5];
+        T Fo[6];
         Fo[0] = Fn[0];
         Fo[1 + d] = Fn[1];
         t = 0;
@@ -508,6 +579,7 @@ static int rhs(const Grid& g, const T* U, T* Lout) {
           ++t;
         }
         Fo[nd + 1] = Fn[nd + 1];
+        if (g.rad) Fo[g.nh] = rusanov_E(PL, PR, WL[g.nh], WR[g.nh], g.gamma);
         for (int v = 0; v < nv; ++v) F[((size_t)v * nother + c) * nf + f] = Fo[v];
       }
     }
@@ -545,6 +617,20 @@ static int step(const Grid& g, T* U, T dt) {
   st |= rhs(g, U1.data(), L.data());
 #pragma omp parallel for schedule(static)
   for (int64_t x = 0; x < M; ++x) U[x] = T(0.5) * (U[x] + (U1[x] + dt * L[x]));
+  if constexpr (std::is_same<T, double>::value) {
+    if (g.rad) {
+      const int nd = g.ndim;
+      const int64_t N = g.ncell;
+#pragma omp parallel for schedule(static)
+      for (int64_t c = 0; c < N; ++c) {
+        const double rho = U[c];
+        double q = U[N + c] * U[N + c];
+        for (int d = 1; d < nd; ++d) q = q + U[(size_t)(1 + d) * N + c] * U[(size_t)(1 + d) * N + c];
+        const double ke = 0.5 * q / rho;
+        exchange(rho, ke, U[(size_t)(nd + 1) * N + c], U[(size_t)(nd + 2) * N + c], value(dt), g);
+      }
+    }
+  }
   return st;
 }
 
@@ -557,9 +643,9 @@ static double max_signal(const Grid& g, const T* U, int* status) {
   int st = 0;
 #pragma omp parallel for schedule(static) reduction(max : smax) reduction(| : st)
   for (int64_t c = 0; c < N; ++c) {
-    T u[5], w[5];
+    T u[6], w[6];
     for (int v = 0; v < nv; ++v) u[v] = U[(size_t)v * N + c];
-    st |= primitives(u, nd, g.gamma, w);
+    st |= primitives(u, nd, g.gamma, w, g.rad);
     T cs = sqrt(T(g.gamma) * w[nd + 1] / w[0]);
     T s(0.0);
     for (int d = 0; d < nd; ++d) s = s + (fabs(w[1 + d]) + cs) / T(g.dx[d]);
@@ -579,32 +665,32 @@ using namespace hard_oracle;
 extern "C" {
 
 // L(U) for one state; returns status bits.
-int oracle_rhs(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
+int oracle_rhs(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
                const double* U, double* L) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   return rhs<double>(g, U, L);
 }
 
 // One SSP-RK2 step in place; returns status bits.
-int oracle_step(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
+int oracle_step(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
                 double dt, double* U) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   return step<double>(g, U, dt);
 }
 
 // nsteps SSP-RK2 steps in place with the given dt list; returns OR of status.
-int oracle_steps_fixed(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
+int oracle_steps_fixed(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
                        int64_t nsteps, const double* dts, double* U) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   int st = 0;
   for (int64_t s = 0; s < nsteps; ++s) st |= step<double>(g, U, dts[s]);
   return st;
 }
 
 // dt = cfl / max signal sum; writes the status bits of the state.
-double oracle_cfl_dt(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
+double oracle_cfl_dt(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
                      double cfl, const double* U, int* status) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   double smax = max_signal(g, U, status);
   return cfl / smax;
 }
@@ -612,10 +698,10 @@ double oracle_cfl_dt(int ndim, const int64_t* n, const double* dx, double gamma,
 // CFL-driven run to t_end: dt <- min(cfl dt, t_end - t); stops when
 // t >= t_end (1 - 1e-14) or after max_steps.  Records each dt used if
 // dts_out is not null (capacity max_steps).  Returns OR of status bits.
-int oracle_run(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
+int oracle_run(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
                double cfl, double t_end, int64_t max_steps, double* U, double* t_out,
                int64_t* nsteps_out, double* dts_out) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   double t = 0.0;
   int64_t s = 0;
   int st = 0;
@@ -637,9 +723,9 @@ int oracle_run(int ndim, const int64_t* n, const double* dx, double gamma, const
 // Forward-mode derivative of nsteps steps with a frozen dt list:
 // (U, dU) -> (U_n, dU_n) in place.  Returns OR of status bits.
 int oracle_steps_tangent(int ndim, const int64_t* n, const double* dx, double gamma,
-                         const int* bc, int scheme, int64_t nsteps, const double* dts, double* U,
+                         const int* bc, int scheme, const double* radp, int64_t nsteps, const double* dts, double* U,
                          double* dU) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   const int64_t M = (int64_t)g.nvar * g.ncell;
   std::vector<Dual> X(M);
   for (int64_t x = 0; x < M; ++x) X[x] = Dual(U[x], dU[x]);
@@ -693,7 +779,7 @@ double oracle_weno5z(const double* v) { return weno5z<double>(v); }
 // Floating-point operations of one CFL dt plus one SSP-RK2 step of U (left
 // unchanged), tallied by kind: out[0..5] = add/sub, mul, div, sqrt, compare,
 // abs.  Runs on one thread.
-void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
+void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
                       double dt, const double* U, int64_t* out);
 
 #ifdef _OPENMP
@@ -705,9 +791,9 @@ static void omp_set_num_threads(int) {}
 static int omp_get_max_threads(void) { return 1; }
 #endif
 
-void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme,
+void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
                       double dt, const double* U, int64_t* out) {
-  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme);
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   const int64_t M = (int64_t)g.nvar * g.ncell;
   std::vector<Cnt> X(M);
   for (int64_t x = 0; x < M; ++x) X[x] = Cnt(U[x]);
