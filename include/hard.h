@@ -81,6 +81,21 @@ typedef int32_t hard_status_t;
 #define HARD_SCHEME_MUSCL_HLLC 0
 #define HARD_SCHEME_WENO5Z_HLL 1
 
+/* Radiation (rad = 1; section 2.2.1, the fourth row of the conservation law
+ * and its heating source).  The state has nvar = ndim + 3 fields, E_r last.
+ * Each Heun stage advects E_r with the fluid velocity through the local
+ * Lax-Friedrichs (Rusanov) flux of its MUSCL-minmod face states (section
+ * 2.2.2), with the signal speed max(|u_L| + c_L, |u_R| + c_R) of the hydro
+ * face states; E_r does not act on the hydro fields.  After stage 2 every
+ * cell exchanges energy between the fluid and the radiation by the heating
+ * rate qdot = c kappa rho (E_r - a T^4) (equation "heating-cooling"), T =
+ * (gamma - 1) e mu m_u / (rho k_B), integrated by backward Euler (Newton on
+ * the new temperature; e + E_r is conserved); the fused next dt is that of
+ * the state after the exchange.  CGS units for the constants (c, a, k_B,
+ * m_u).  Single-grid calls with HARD_SCHEME_MUSCL_HLLC only:
+ * hard_hydro_stage, the batched and the adjoint calls return
+ * HARD_ERR_UNSUPPORTED for rad = 1. */
+
 /* Status-word bits (hard_status_read). */
 #define HARD_FLAG_DENSITY 1u   /* rho <= 0 or NaN in some cell */
 #define HARD_FLAG_PRESSURE 2u  /* p <= 0 or NaN in some cell */
@@ -97,6 +112,10 @@ typedef struct hard_grid_t {
   int32_t scheme;   /* face scheme: HARD_SCHEME_MUSCL_HLLC (0, the default of a
                        zero-initialised struct) or HARD_SCHEME_WENO5Z_HLL (1,
                        needs n >= 3 on every axis) */
+  int32_t rad;      /* 1: the state carries the radiation energy density E_r
+                       as field ndim + 2 (see "Radiation" below); 0: hydro only */
+  double kappa;     /* rad = 1: mean opacity (cm^2/g), finite and >= 0 */
+  double mu;        /* rad = 1: mean molecular weight, finite and > 0 */
 } hard_grid_t;
 
 /* Description of the last error on the calling thread ("" if none).  The

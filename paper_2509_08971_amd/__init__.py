@@ -51,6 +51,9 @@ class hard_grid_t(ctypes.Structure):
         ("gamma", ctypes.c_double),
         ("bc", (ctypes.c_int32 * 2) * 3),
         ("scheme", ctypes.c_int32),
+        ("rad", ctypes.c_int32),
+        ("kappa", ctypes.c_double),
+        ("mu", ctypes.c_double),
     ]
 
 
@@ -114,10 +117,11 @@ def _check(code):
 
 
 def make_grid(n, dx=None, gamma=1.4, bc=(OUTFLOW, OUTFLOW), dtype=torch.float64,
-              scheme=0):
+              scheme=0, rad=None):
     """hard_grid_t for n = (nx[, ny[, nz]]); bc is (lo, hi) per axis, flattened
     (a single pair applies to every axis); dx defaults to 1/n (unit box);
-    scheme is MUSCL_HLLC (default) or WENO5Z_HLL."""
+    scheme is MUSCL_HLLC (default) or WENO5Z_HLL; rad = (kappa, mu) adds the
+    radiation energy density as the last field."""
     n = tuple(int(v) for v in n)
     nd = len(n)
     if dx is None:
@@ -135,6 +139,11 @@ def make_grid(n, dx=None, gamma=1.4, bc=(OUTFLOW, OUTFLOW), dtype=torch.float64,
         g.bc[d][1] = bc[2 * d + 1] if d < nd else 0
     g.gamma = float(gamma)
     g.scheme = int(scheme)
+    if rad is not None:
+        g.rad = 1
+        g.kappa, g.mu = float(rad[0]), float(rad[1])
+    else:
+        g.rad, g.kappa, g.mu = 0, 0.0, 1.0
     return g
 
 

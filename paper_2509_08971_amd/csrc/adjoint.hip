@@ -535,8 +535,8 @@ hard_status_t hard_adjoint_workspace_bytes(const hard_grid_t* g, size_t* bytes) 
   if (st) return st;
   if (!bytes) return fail(HARD_ERR_INVALID_ARG, "bytes is NULL");
   if (G.dtype != HARD_F64) return fail(HARD_ERR_UNSUPPORTED, "the adjoint is built for HARD_F64");
-  if (G.scheme != HARD_SCHEME_MUSCL_HLLC)
-    return fail(HARD_ERR_UNSUPPORTED, "the adjoint is built for HARD_SCHEME_MUSCL_HLLC");
+  if (G.scheme != HARD_SCHEME_MUSCL_HLLC || G.rad)
+    return fail(HARD_ERR_UNSUPPORTED, "the adjoint is built for HARD_SCHEME_MUSCL_HLLC without radiation");
   *bytes = adj_layout(G).total;
   return ok();
 }
@@ -547,8 +547,8 @@ hard_status_t hard_hydro_step_adjoint(const hard_grid_t* g, const void* U_n, con
   hard_status_t st = check_grid(g, &G);
   if (st) return st;
   if (G.dtype != HARD_F64) return fail(HARD_ERR_UNSUPPORTED, "the adjoint is built for HARD_F64");
-  if (G.scheme != HARD_SCHEME_MUSCL_HLLC)
-    return fail(HARD_ERR_UNSUPPORTED, "the adjoint is built for HARD_SCHEME_MUSCL_HLLC");
+  if (G.scheme != HARD_SCHEME_MUSCL_HLLC || G.rad)
+    return fail(HARD_ERR_UNSUPPORTED, "the adjoint is built for HARD_SCHEME_MUSCL_HLLC without radiation");
   if ((st = check_ptr(U_n, 8, "U_n"))) return st;
   if ((st = check_ptr(lam, 8, "lam"))) return st;
   if ((st = check_ptr(dt_dev, 8, "dt_dev"))) return st;

@@ -68,10 +68,22 @@ hard_status_t check_grid(const hard_grid_t* g, Grid* out) {
   if (g->scheme == HARD_SCHEME_WENO5Z_HLL)
     for (int d = 0; d < g->ndim; ++d)
       if (g->n[d] < 3) return fail(HARD_ERR_INVALID_ARG, "WENO5-Z needs n[%d] >= 3", d);
+  if (g->rad != 0 && g->rad != 1) return fail(HARD_ERR_INVALID_ARG, "rad must be 0 or 1");
+  if (g->rad) {
+    if (!(std::isfinite(g->kappa) && g->kappa >= 0.0))
+      return fail(HARD_ERR_INVALID_ARG, "kappa must be finite and >= 0");
+    if (!(std::isfinite(g->mu) && g->mu > 0.0))
+      return fail(HARD_ERR_INVALID_ARG, "mu must be finite and > 0");
+    if (g->scheme != HARD_SCHEME_MUSCL_HLLC)
+      return fail(HARD_ERR_UNSUPPORTED, "radiation is built for HARD_SCHEME_MUSCL_HLLC");
+  }
   if (out) {
     out->ndim = g->ndim;
     out->dtype = g->dtype;
-    out->nvar = g->ndim + 2;
+    out->nvar = g->ndim + 2 + (g->rad ? 1 : 0);
+    out->rad = g->rad;
+    out->kappa = g->rad ? g->kappa : 0.0;
+    out->mu = g->rad ? g->mu : 1.0;
     out->wsize = g->dtype == HARD_F64 ? 8 : 4;
     out->ncell = ncell;
     for (int d = 0; d < 3; ++d) {
@@ -155,6 +167,31 @@ hipError_t launch_scheme_stage(const Grid& G, const WorkLayout& L, char* wb, con
   w.next_dt = a.next_dt;
   w.W = wb + L.weno_w;
   return launch_weno_stage(G.ndim, G.dtype, w, stage, s);
+}
+
+// Radiation arguments of a stage from the hydro stage arguments.
+RadArgs rad_args(const Grid& G, const StageArgs& a) {
+  RadArgs r;
+  std::memset(&r, 0, sizeof r);
+  r.src = a.src;
+  r.un = a.un;
+  r.dst = a.dst;
+  r.dt = a.dt;
+  for (int d = 0; d < 3; ++d) {
+    r.n[d] = a.n[d];
+    r.bc[d][0] = a.bc[d][0];
+    r.bc[d][1] = a.bc[d][1];
+    r.dx[d] = a.dx[d];
+    r.inv_dx[d] = a.inv_dx[d];
+  }
+  r.dx_pow2 = a.dx_pow2;
+  r.gamma = a.gamma;
+  r.kappa = G.kappa;
+  r.mu = G.mu;
+  r.cfl = a.cfl;
+  r.ctl = a.ctl;
+  r.next_dt = a.next_dt;
+  return r;
 }
 
 int stage_cz_override() {
@@ -262,14 +299,25 @@ hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_de
   a.fuse_cfl = 0;
   hipError_t e = launch_scheme_stage(G, L, wb, a, 1, s);
   if (e != hipSuccess) return hip_fail(e, "hard_hydro_step stage 1");
+  if (G.rad && (e = launch_rad_advect(G.ndim, G.dtype, rad_args(G, a), 1, s)) != hipSuccess)
+    return hip_fail(e, "hard_hydro_step radiation stage 1");
   // stage 2: U = (U + (U1 + dt L(U1))) / 2, optionally with the next dt
+  // (with radiation the next dt comes after the exchange instead)
   a.src = U1;
   a.un = U;
   a.dst = U;
-  a.fuse_cfl = next_dt_dev != nullptr;
+  a.fuse_cfl = next_dt_dev != nullptr && !G.rad;
   a.next_dt = next_dt_dev;
   e = launch_scheme_stage(G, L, wb, a, 2, s);
   if (e != hipSuccess) return hip_fail(e, "hard_hydro_step stage 2");
+  if (G.rad) {
+    RadArgs r = rad_args(G, a);
+    if ((e = launch_rad_advect(G.ndim, G.dtype, r, 2, s)) != hipSuccess)
+      return hip_fail(e, "hard_hydro_step radiation stage 2");
+    r.fuse_cfl = next_dt_dev != nullptr;
+    if ((e = launch_rad_source(G.ndim, G.dtype, r, s)) != hipSuccess)
+      return hip_fail(e, "hard_hydro_step radiation exchange");
+  }
   return ok();
 }
 
@@ -280,6 +328,8 @@ hard_status_t hard_hydro_stage(const hard_grid_t* g, int32_t stage, const void* 
   hard_status_t st = check_grid(g, &G);
   if (st) return st;
   if (stage != 1 && stage != 2) return fail(HARD_ERR_INVALID_ARG, "stage must be 1 or 2");
+  if (G.rad)
+    return fail(HARD_ERR_UNSUPPORTED, "with radiation the step is not a pair of stages; use hard_hydro_step");
   if ((st = check_ptr(src, G.wsize, "src"))) return st;
   if ((st = check_ptr(dst, G.wsize, "dst"))) return st;
   if (stage == 2 && (st = check_ptr(un, G.wsize, "un"))) return st;
@@ -390,7 +440,7 @@ hard_status_t hard_conservation_sums(const hard_grid_t* g, const void* U, double
   WorkLayout L = layout_of(G);
   if ((st = check_work(work, work_bytes, L.total))) return st;
   double* partials = reinterpret_cast<double*>(static_cast<char*>(work) + L.partials);
-  hipError_t e = launch_sums(G.ndim, G.dtype, G.n, U, partials, L.partials_blocks, sums_dev,
+  hipError_t e = launch_sums(G.nvar, G.dtype, G.n, U, partials, L.partials_blocks, sums_dev,
                              (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "hard_conservation_sums");
   return ok();

@@ -19,6 +19,8 @@ struct Grid {
   double gamma;
   int dx_pow2;  // every dx is a power of two (x/dx == x*(1/dx) exactly)
   int scheme;   // HARD_SCHEME_*
+  int rad;      // 1: field ndim + 2 is the radiation energy density
+  double kappa, mu;
 };
 
 // Byte offsets inside a single-grid workspace.
@@ -42,6 +44,8 @@ hard_status_t check_work(void* work, size_t have, size_t need);
 hard_status_t check_cfl(double cfl);
 WorkLayout layout_of(const Grid& g);
 struct StageArgs;
+struct RadArgs;
+RadArgs rad_args(const Grid& G, const StageArgs& a);
 hipError_t launch_scheme_stage(const Grid& G, const WorkLayout& L, char* wb, const StageArgs& a,
                                int stage, hipStream_t s);
 

@@ -414,9 +414,9 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
       delete P;
       return fail(st, "grid %d: %s", p, hard_last_error());
     }
-    if (G.scheme != HARD_SCHEME_MUSCL_HLLC) {
+    if (G.scheme != HARD_SCHEME_MUSCL_HLLC || G.rad) {
       delete P;
-      return fail(HARD_ERR_UNSUPPORTED, "grid %d: the batched step is built for HARD_SCHEME_MUSCL_HLLC", p);
+      return fail(HARD_ERR_UNSUPPORTED, "grid %d: the batched step is built for HARD_SCHEME_MUSCL_HLLC without radiation", p);
     }
     if (G.dtype != P->dtype || G.gamma != P->gamma) {
       delete P;

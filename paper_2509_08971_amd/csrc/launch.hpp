@@ -52,6 +52,29 @@ struct WenoArgs {
 
 hipError_t launch_weno_stage(int ndim, int dtype, const WenoArgs& a, int stage, hipStream_t s);
 
+// Radiation energy density (rad.hip): the E_r part of a Heun stage, and the
+// exchange with the fluid after stage 2 (with the fused next dt).
+struct RadArgs {
+  const void* src;
+  const void* un;
+  void* dst;          // stage output (rad_advect); the state after the step (rad_source)
+  const double* dt;
+  int n[3];
+  int bc[3][2];
+  double dx[3];
+  double inv_dx[3];
+  int dx_pow2;
+  double gamma;
+  double kappa, mu;
+  double cfl;
+  int fuse_cfl;
+  Control* ctl;
+  double* next_dt;
+};
+
+hipError_t launch_rad_advect(int ndim, int dtype, const RadArgs& a, int stage, hipStream_t s);
+hipError_t launch_rad_source(int ndim, int dtype, const RadArgs& a, hipStream_t s);
+
 // Standalone CFL dt (reads U once).
 hipError_t launch_cfl(int ndim, int dtype, const int* n, const double* dx, const double* inv_dx,
                       int dx_pow2, double gamma, const void* U, double cfl, double* dt,
@@ -64,7 +87,7 @@ hipError_t launch_time_control(Control* ctl, double t_end, long long max_steps, 
 hipError_t launch_control_clear(Control* ctl, hipStream_t s);
 
 // Compensated per-field sums: partials has room for nblocks_max * nvar * 2 doubles.
-hipError_t launch_sums(int ndim, int dtype, const int* n, const void* U, double* partials,
+hipError_t launch_sums(int nvar, int dtype, const int* n, const void* U, double* partials,
                        int nblocks_max, double* out, hipStream_t s);
 int sums_blocks(long long ncell);
 

@@ -179,12 +179,11 @@ int sums_blocks(long long N) {
   return (int)b;
 }
 
-hipError_t launch_sums(int ndim, int dtype, const int* n, const void* U, double* partials,
+hipError_t launch_sums(int nvar, int dtype, const int* n, const void* U, double* partials,
                        int nblocks_max, double* out, hipStream_t s) {
   long long N = (long long)n[0] * n[1] * n[2];
   int nb = sums_blocks(N);
   if (nb > nblocks_max) return hipErrorInvalidValue;
-  int nvar = ndim + 2;
   if (dtype == 0)
     hipLaunchKernelGGL(sums_kernel<double>, dim3(nb), dim3(RED_THREADS), 0, s,
                        static_cast<const double*>(U), N, nvar, partials);

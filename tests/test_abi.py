@@ -153,3 +153,27 @@ def test_scheme_checks():
     plan = ctypes.c_void_p()
     assert L.hard_batch_plan_create(arr, 1, None, ctypes.byref(plan)) == H.ERR_UNSUPPORTED
     assert not plan.value
+
+
+def test_radiation_checks():
+    """Radiation parameters are validated; the field is counted in the
+    workspace; stages, batched and adjoint calls reject it."""
+    L = H.lib()
+    assert call_step(grid(rad=2), work=None) == H.ERR_INVALID_ARG
+    g = H.make_grid((16, 16), rad=(-1.0, 0.6))
+    assert call_step(g, work=None) == H.ERR_INVALID_ARG
+    g = H.make_grid((16, 16), rad=(0.4, 0.0))
+    assert call_step(g, work=None) == H.ERR_INVALID_ARG
+    g = H.make_grid((16, 16), rad=(0.4, 0.6), scheme=H.WENO5Z_HLL)
+    assert call_step(g, work=None) == H.ERR_UNSUPPORTED
+    n = 64
+    g0 = H.make_grid((n, n, n))
+    g1 = H.make_grid((n, n, n), rad=(0.4, 0.6))
+    assert H.hard_workspace_bytes(g1) - H.hard_workspace_bytes(g0) >= n ** 3 * 8
+    assert L.hard_hydro_stage(ctypes.byref(g1), 1, FAKE, None, FAKE + 256, FAKE, 0.4, None, FAKE,
+                              1 << 40, None) == H.ERR_UNSUPPORTED
+    b = ctypes.c_size_t()
+    assert L.hard_adjoint_workspace_bytes(ctypes.byref(g1), ctypes.byref(b)) == H.ERR_UNSUPPORTED
+    arr = (H.hard_grid_t * 1)(H.make_grid((64,), rad=(0.4, 0.6)))
+    plan = ctypes.c_void_p()
+    assert L.hard_batch_plan_create(arr, 1, None, ctypes.byref(plan)) == H.ERR_UNSUPPORTED
