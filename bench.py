@@ -218,6 +218,37 @@ def bench_weno(args, n=256, steps=10):
             "achieved_hbm_gbs_pipeline": pipe_bytes * zus / 1e9, "status_flags": flags}
 
 
+def bench_rad(args, n=256, steps=20):
+    """The 256^3 FP64 blast carrying the radiation energy density (uniform
+    E_r = 1, kappa = 1e-9 cm^2/g, mu = 0.6): the hydro stage kernels, the
+    Rusanov advection of E_r in both stages and the heating/cooling exchange
+    with the fused next dt."""
+    import paper_2509_08971_amd as H
+    import workloads
+
+    log(f"bench: radiation blast {n}^3 fp64, {steps} steps")
+    rad = (1e-9, 0.6)
+    g = H.make_grid((n, n, n), bc=(H.REFLECT, H.REFLECT), rad=rad)
+    U = torch.ones((6, n, n, n), dtype=torch.float64, device="cuda")
+    U[:5] = torch.from_numpy(workloads.blast_3d(n)).to("cuda")
+    work = H.workspace(H.hard_workspace_bytes(g))
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    H.hard_cfl_dt(g, U, 0.4, dt, work)
+    for _ in range(2):
+        H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=dt)
+    ms = _time_steps(lambda: H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=dt), steps,
+                     stream)
+    flags = H.hard_status_read(work)
+    N = n ** 3
+    zus = N * steps / (ms * 1e-3)
+    log(f"  {ms / steps:.3f} ms/step, {zus / 1e9:.2f} G zu/s")
+    return {"value": zus, "unit": "zone-updates/s", "ms_per_step": ms / steps, "steps": steps,
+            "dtype": "f64", "workload": f"3D {n}^3 FP64 point-energy blast with the radiation "
+                                         f"energy density (E_r = 1, kappa = 1e-9, mu = 0.6)",
+            "status_flags": flags}
+
+
 def bench_adjoint(args, n=512, nsteps=200, every=20):
     """Config-4 gradient: 2D 512^2 FP64 periodic, 200 steps, checkpoints every
     20; gradient of J = dx^2/2 sum (rho_N - rho_T)^2 wrt the initial state."""
@@ -409,6 +440,10 @@ def main():
             extras["weno5z_hll_256"] = bench_weno(args)
         except Exception as e:
             extras["weno5z_hll_256"] = {"error": repr(e)}
+        try:
+            extras["radiation_256"] = bench_rad(args)
+        except Exception as e:
+            extras["radiation_256"] = {"error": repr(e)}
         out["beside_fp64_step"] = extras
 
     if not args.no_cpu_baseline:
