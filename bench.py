@@ -459,10 +459,16 @@ def main():
             d, _ = oracle.cfl_dt(og, Uc, 0.4)
             Uc, _ = oracle.step(og, Uc, d)
         el = time.perf_counter() - t0
+        cpu = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
         out["cpu_baseline"] = {"value": N * ksteps / el, "unit": "zone-updates/s",
                                "cores": oracle.threads(), "kind": "oracle",
                                "sample": f"{ksteps} steps (CFL dt + step) of the {n}^3 blast from "
-                                         f"its initial state, {el:.1f} s"}
+                                         f"its initial state, {el:.1f} s, on {cpu}"}
     print(json.dumps(out), flush=True)
 
 

@@ -625,7 +625,8 @@ static int step(const Grid& g, T* U, T dt) {
       for (int64_t c = 0; c < N; ++c) {
         const double rho = U[c];
         double q = U[N + c] * U[N + c];
-        for (int d = 1; d < nd; ++d) q = q + U[(size_t)(1 + d) * N + c] * U[(size_t)(1 + d) * N + c];
+        for (int d = 1; d < nd; ++d)
+          q = q + U[(size_t)(1 + d) * N + c] * U[(size_t)(1 + d) * N + c];
         const double ke = 0.5 * q / rho;
         exchange(rho, ke, U[(size_t)(nd + 1) * N + c], U[(size_t)(nd + 2) * N + c], value(dt), g);
       }
@@ -665,21 +666,24 @@ using namespace hard_oracle;
 extern "C" {
 
 // L(U) for one state; returns status bits.
-int oracle_rhs(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
+int oracle_rhs(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+               int scheme, const double* radp,
                const double* U, double* L) {
   Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   return rhs<double>(g, U, L);
 }
 
 // One SSP-RK2 step in place; returns status bits.
-int oracle_step(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
+int oracle_step(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+                int scheme, const double* radp,
                 double dt, double* U) {
   Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   return step<double>(g, U, dt);
 }
 
 // nsteps SSP-RK2 steps in place with the given dt list; returns OR of status.
-int oracle_steps_fixed(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
+int oracle_steps_fixed(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+                       int scheme, const double* radp,
                        int64_t nsteps, const double* dts, double* U) {
   Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   int st = 0;
@@ -688,7 +692,8 @@ int oracle_steps_fixed(int ndim, const int64_t* n, const double* dx, double gamm
 }
 
 // dt = cfl / max signal sum; writes the status bits of the state.
-double oracle_cfl_dt(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
+double oracle_cfl_dt(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+                     int scheme, const double* radp,
                      double cfl, const double* U, int* status) {
   Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   double smax = max_signal(g, U, status);
@@ -698,7 +703,8 @@ double oracle_cfl_dt(int ndim, const int64_t* n, const double* dx, double gamma,
 // CFL-driven run to t_end: dt <- min(cfl dt, t_end - t); stops when
 // t >= t_end (1 - 1e-14) or after max_steps.  Records each dt used if
 // dts_out is not null (capacity max_steps).  Returns OR of status bits.
-int oracle_run(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
+int oracle_run(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+               int scheme, const double* radp,
                double cfl, double t_end, int64_t max_steps, double* U, double* t_out,
                int64_t* nsteps_out, double* dts_out) {
   Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
@@ -723,8 +729,8 @@ int oracle_run(int ndim, const int64_t* n, const double* dx, double gamma, const
 // Forward-mode derivative of nsteps steps with a frozen dt list:
 // (U, dU) -> (U_n, dU_n) in place.  Returns OR of status bits.
 int oracle_steps_tangent(int ndim, const int64_t* n, const double* dx, double gamma,
-                         const int* bc, int scheme, const double* radp, int64_t nsteps, const double* dts, double* U,
-                         double* dU) {
+                         const int* bc, int scheme, const double* radp, int64_t nsteps,
+                         const double* dts, double* U, double* dU) {
   Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   const int64_t M = (int64_t)g.nvar * g.ncell;
   std::vector<Dual> X(M);
@@ -779,7 +785,8 @@ double oracle_weno5z(const double* v) { return weno5z<double>(v); }
 // Floating-point operations of one CFL dt plus one SSP-RK2 step of U (left
 // unchanged), tallied by kind: out[0..5] = add/sub, mul, div, sqrt, compare,
 // abs.  Runs on one thread.
-void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
+void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+                      int scheme, const double* radp,
                       double dt, const double* U, int64_t* out);
 
 #ifdef _OPENMP
@@ -791,7 +798,8 @@ static void omp_set_num_threads(int) {}
 static int omp_get_max_threads(void) { return 1; }
 #endif
 
-void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc, int scheme, const double* radp,
+void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
+                      int scheme, const double* radp,
                       double dt, const double* U, int64_t* out) {
   Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
   const int64_t M = (int64_t)g.nvar * g.ncell;
