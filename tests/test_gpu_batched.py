@@ -256,3 +256,25 @@ def test_batched_full_workload_sampled():
         ref, ref_dt = single_runs([((s[1],) * s[0], (O, O))], [states[i]], torch.float32, 3)
         assert torch.equal(outs[i].cpu(), ref[0]), i
         assert dts[i] == ref_dt[0], i
+
+
+def test_autotuner_writes_a_cache_the_plan_reads(tmp_path):
+    """tune_batched times every candidate setting on the caller's grids and
+    writes the winners; a plan built from that cache gives the same bits as
+    the default plan."""
+    from paper_2509_08971_amd import autotune
+
+    specs, states = mixed_batch()
+    grids = [H.make_grid(n, bc=bc, dtype=torch.float32) for n, bc in specs]
+    cache = tmp_path / "batched.tune"
+    best, times = autotune.tune_batched(grids, states, torch.float32, steps=2,
+                                        cache_path=str(cache))
+    text = cache.read_text()
+    for k, v in best.items():
+        assert f"{k} = {v}" in text
+    assert len(times) == sum(len(v) for v in autotune.default_candidates(torch.float32).values())
+    base, base_dt = batched_run(specs, states, torch.float32, 3)
+    got, got_dt = batched_run(specs, states, torch.float32, 3, tune=str(cache))
+    for p in range(len(specs)):
+        assert torch.equal(got[p], base[p])
+    assert got_dt == base_dt

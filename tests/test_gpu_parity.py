@@ -272,3 +272,43 @@ def test_turbulent_512_fp32_full_size_sampled():
     for v in range(5):
         rel = np.abs(got[:, v] - ref[:, v]).sum() / np.abs(ref[:, v]).sum()
         assert rel <= TOL32, (v, rel)
+
+
+def test_single_grid_step_graph_replay():
+    """hard_hydro_step (with the fused next dt) captured in a graph: every
+    replay equals the same steps run eagerly, bit for bit, with eager work
+    and synchronisations between the replays."""
+    n = (40, 36, 20)
+    bc = (P, P, R, R, O, O)
+    U0 = random_state(n, 12)
+    g = H.make_grid(n, bc=bc)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    dt0 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    U = torch.from_numpy(U0).to(DEV)
+    H.hard_cfl_dt(g, U, 0.4, dt0, work)
+    # eager reference: 4 steps from U0
+    Ue, dte = U.clone(), dt0.clone()
+    for _ in range(4):
+        H.hard_hydro_step(g, Ue, dte, work, cfl=0.4, next_dt_dev=dte)
+    torch.cuda.synchronize()
+    Ug, dtg = U.clone(), dt0.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            for _ in range(4):
+                H.hard_hydro_step(g, Ug, dtg, work, cfl=0.4, next_dt_dev=dtg)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        Ug.copy_(U)
+        dtg.copy_(dt0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Ug, Ue), rep
+        assert torch.equal(dtg, dte), rep
+        # eager work between replays
+        tmp = U.clone()
+        H.hard_hydro_step(g, tmp, dt0.clone(), work, cfl=0.4)
+        torch.cuda.synchronize()
