@@ -100,6 +100,8 @@ typedef int32_t hard_status_t;
 #define HARD_FLAG_DENSITY 1u   /* rho <= 0 or NaN in some cell */
 #define HARD_FLAG_PRESSURE 2u  /* p <= 0 or NaN in some cell */
 #define HARD_FLAG_NONFINITE 4u /* some conserved value is not finite */
+#define HARD_FLAG_RADIATION 8u /* radiation diffusion: E_r <= 0 or NaN, or a
+                                  diffusion coefficient that is not finite */
 
 typedef struct hard_grid_t {
   int32_t ndim;     /* 1, 2 or 3 */
@@ -243,6 +245,66 @@ hard_status_t hard_adjoint_workspace_bytes(const hard_grid_t* g, size_t* bytes);
  * device array shaped like U. */
 hard_status_t hard_hydro_step_adjoint(const hard_grid_t* g, const void* U_n, const double* dt_dev,
                                       void* lam, void* work, size_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Implicit radiation diffusion (rad = 1): one backward-Euler step of the
+ * diffusion term of the radiation energy equation (section 2.2.1, equation
+ * "radiation": d_t E_r = div(D grad E_r), D = c lambda / (kappa rho), lambda
+ * from the flux limiter), solved by geometric multigrid V-cycles with regular
+ * coarsening (section 2.2.2: the multigrid solver of A u = f, the residual
+ * equation on every coarser grid, the V-cycle).
+ *
+ * The operator-split diffusion part of a step: call it after hard_hydro_step
+ * with the same dt.  D is evaluated once from the state at the start of the
+ * call (so the system is linear), and E_r (field ndim + 2 of U) is replaced by
+ * the V-cycle iterate of
+ *     A E_new = E_old,   (A x)_c = x_c + sum_faces a_f (x_c - x_nb),
+ *     a_f = dt (D_c + D_nb)/2 / dx_d^2,
+ * with grad E_r by central differences and zero-flux walls on non-periodic
+ * sides.  The other fields are not modified.
+ *
+ * Solver: red-black Gauss-Seidel relaxation (cells with i + j + k even
+ * first), residual restriction by the mean over the children, prolongation by
+ * linear interpolation, coarse operators rediscretised from the mean of D
+ * over the children.  Every axis whose size is even is halved (a periodic
+ * axis only while the half is even or one); the coarsest level is relaxed
+ * `ncoarse` sweeps from zero.
+ * ------------------------------------------------------------------------ */
+#define HARD_FLD_EDDINGTON 0 /* lambda = 1/3 (optically thick limit) */
+#define HARD_FLD_LEVERMORE 1 /* lambda = (2 + R)/(6 + 3R + R^2),
+                                R = |grad E_r| / (rho kappa E_r) */
+
+typedef struct hard_gmg_opts_t {
+  int32_t limiter; /* HARD_FLD_EDDINGTON or HARD_FLD_LEVERMORE */
+  int32_t ncycles; /* V-cycles, 0..1000 (0: E_r unchanged) */
+  int32_t nu1;     /* red-black sweeps before the coarse correction, 0..64 */
+  int32_t nu2;     /* red-black sweeps after it, 0..64 */
+  int32_t ncoarse; /* sweeps on the coarsest level, 1..1024 */
+} hard_gmg_opts_t;
+
+/* Sizes of the multigrid levels of grid g, finest first: levels_n[3 l + d]
+ * for l < min(*nlevels, max_levels).  Host only.  The grid rules are those of
+ * hard_rad_diffuse. */
+hard_status_t hard_gmg_levels(const hard_grid_t* g, int32_t max_levels, int64_t* levels_n,
+                              int32_t* nlevels);
+
+/* Workspace bytes for hard_rad_diffuse (control block and the arrays of every
+ * level: about 3.4 doubles per finest cell in 3D). */
+hard_status_t hard_rad_diffuse_workspace_bytes(const hard_grid_t* g, size_t* bytes);
+
+/* One implicit diffusion step of E_r in U (in place) with the step *dt_dev
+ * (device double, dt >= 0), by opts->ncycles V(nu1, nu2) cycles starting from
+ * E_old.  resid_dev (device array of ncycles + 1 doubles, or NULL) receives
+ * the 2-norm of the finest-level residual E_old - A x before the first cycle
+ * and after each one (summed with atomics: not bitwise reproducible).
+ * Requirements: g->rad = 1, g->kappa > 0, HARD_F64 (HARD_F32 returns
+ * HARD_ERR_UNSUPPORTED), every periodic axis of even size (odd: UNSUPPORTED).
+ * rho <= 0 sets HARD_FLAG_DENSITY, E_r <= 0 or a non-finite D sets
+ * HARD_FLAG_RADIATION in the status word.  Stream-ordered, no host
+ * synchronisation, no allocation; graph-capturable. */
+hard_status_t hard_rad_diffuse(const hard_grid_t* g, void* U, const double* dt_dev,
+                               const hard_gmg_opts_t* opts, double* resid_dev, void* work,
+                               size_t work_bytes, void* stream);
 
 #ifdef __cplusplus
 }

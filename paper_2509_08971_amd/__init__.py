@@ -23,7 +23,8 @@ __all__ = [
     "hard_batch_workspace_bytes", "hard_cfl_dt_batched", "hard_hydro_step_batched",
     "hard_run_batched", "batch_pack", "batch_unpack",
     "hard_adjoint_workspace_bytes", "hard_hydro_step_adjoint", "workspace",
-    "PERIODIC", "OUTFLOW", "REFLECT", "F64", "F32",
+    "hard_gmg_opts_t", "hard_gmg_levels", "hard_rad_diffuse_workspace_bytes", "hard_rad_diffuse",
+    "PERIODIC", "OUTFLOW", "REFLECT", "F64", "F32", "FLD_EDDINGTON", "FLD_LEVERMORE",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -33,7 +34,8 @@ PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
 F64, F32 = 0, 1
 MUSCL_HLLC, WENO5Z_HLL = 0, 1  # face schemes (HARD_SCHEME_*)
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_NONPHYSICAL, ERR_HIP = range(6)
-FLAG_DENSITY, FLAG_PRESSURE, FLAG_NONFINITE = 1, 2, 4
+FLAG_DENSITY, FLAG_PRESSURE, FLAG_NONFINITE, FLAG_RADIATION = 1, 2, 4, 8
+FLD_EDDINGTON, FLD_LEVERMORE = 0, 1  # flux limiters of the radiation diffusion (HARD_FLD_*)
 
 
 class HardError(RuntimeError):
@@ -54,6 +56,16 @@ class hard_grid_t(ctypes.Structure):
         ("rad", ctypes.c_int32),
         ("kappa", ctypes.c_double),
         ("mu", ctypes.c_double),
+    ]
+
+
+class hard_gmg_opts_t(ctypes.Structure):
+    _fields_ = [
+        ("limiter", ctypes.c_int32),
+        ("ncycles", ctypes.c_int32),
+        ("nu1", ctypes.c_int32),
+        ("nu2", ctypes.c_int32),
+        ("ncoarse", ctypes.c_int32),
     ]
 
 
@@ -98,6 +110,11 @@ def lib():
                                  _vp, _sz, _vp],
             "hard_adjoint_workspace_bytes": [_gp, ctypes.POINTER(_sz)],
             "hard_hydro_step_adjoint": [_gp, _vp, _vp, _vp, _vp, _sz, _vp],
+            "hard_gmg_levels": [_gp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(ctypes.c_int32)],
+            "hard_rad_diffuse_workspace_bytes": [_gp, ctypes.POINTER(_sz)],
+            "hard_rad_diffuse": [_gp, _vp, _vp, ctypes.POINTER(hard_gmg_opts_t), _vp, _vp, _sz,
+                                 _vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -302,3 +319,27 @@ def hard_adjoint_workspace_bytes(g):
 def hard_hydro_step_adjoint(g, U_n, dt_dev, lam, work, stream=None):
     _check(lib().hard_hydro_step_adjoint(_grid(g), _ptr(U_n), _ptr(dt_dev), _ptr(lam), _ptr(work),
                                          work.numel(), _stream(stream)))
+
+
+def hard_gmg_levels(g):
+    """Multigrid level sizes [(nx, ny, nz), ...], finest first (host only)."""
+    out = (ctypes.c_int64 * (3 * 64))()
+    nl = ctypes.c_int32(0)
+    _check(lib().hard_gmg_levels(_grid(g), 64, out, ctypes.byref(nl)))
+    return [tuple(out[3 * l + d] for d in range(3)) for l in range(min(nl.value, 64))]
+
+
+def hard_rad_diffuse_workspace_bytes(g):
+    b = _sz(0)
+    _check(lib().hard_rad_diffuse_workspace_bytes(_grid(g), ctypes.byref(b)))
+    return b.value
+
+
+def hard_rad_diffuse(g, U, dt_dev, work, limiter=FLD_LEVERMORE, ncycles=4, nu1=2, nu2=2,
+                     ncoarse=8, resid_dev=None, stream=None):
+    """One implicit diffusion step of E_r in U (in place) by ncycles V(nu1, nu2)
+    cycles; resid_dev (float64 device tensor of ncycles + 1, or None) receives
+    the finest-level residual norms."""
+    o = hard_gmg_opts_t(int(limiter), int(ncycles), int(nu1), int(nu2), int(ncoarse))
+    _check(lib().hard_rad_diffuse(_grid(g), _ptr(U), _ptr(dt_dev), ctypes.byref(o),
+                                  _ptr(resid_dev), _ptr(work), work.numel(), _stream(stream)))

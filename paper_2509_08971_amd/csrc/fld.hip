@@ -1,0 +1,558 @@
+// Implicit flux-limited radiation diffusion solved by geometric multigrid
+// (section 2.2.1: the diffusion term of the radiation energy equation with
+// D = c lambda / (kappa rho) and the Levermore limiter; section 2.2.2: the
+// multigrid solver of A u = f, the residual equation on the coarse grids and
+// the V-cycle).
+//
+// One call advances E_r by one backward-Euler step of d_t E = div(D grad E)
+// with D frozen at the start of the step, so that
+//     A E_new = E_old,   (A x)_c = x_c + sum_faces a_f (x_c - x_nb),
+//     a_f = dt (D_c + D_nb)/2 / dx_d^2
+// (zero-flux walls on non-periodic sides), and solves it by `ncycles`
+// V-cycles from E_old:
+//
+//   fld_setup      per cell: grad E by central differences, R, lambda, D;
+//                  b = x = E_old; status bits
+//   fld_coarsen_D  per coarse cell: D = mean of its children's D
+//   fld_relax      one red-black half-sweep (Gauss-Seidel on one colour:
+//                  every cell of a colour depends only on the other colour,
+//                  so the half-sweep is one parallel pass in any order)
+//   fld_restrict   per coarse cell: the fine residual b - A x averaged over
+//                  the children -> coarse b; coarse x = 0
+//   fld_prolong    per fine cell: x += linear interpolation of the coarse x
+//                  (weights 3/4, 1/4 along each halved axis, the edge value
+//                  repeated beyond a wall)
+//   fld_store      the finest x back into the state's E_r field
+//   fld_resid_sq   per cell (b - A x)^2, one atomic add per block
+//
+// Every level keeps x, b and D colour-split (the red cells, then the black
+// ones, each colour packed two-to-one along x), so that a half-sweep reads
+// the other colour's x, its own b and both colours' D as contiguous streams
+// and writes its own x: 20 bytes per cell instead of the 32 that the natural
+// layout costs (every line of x, b and D is touched to update half of them).
+
+// Coarsening halves every axis whose size is even; a periodic axis only
+// while the half is even or one, so that the red-black colouring stays
+// consistent across the periodic seam.  The coarsest level is relaxed
+// `ncoarse` sweeps from zero (one cell: A = [1], exact in one sweep).
+//
+// Plain arithmetic throughout (IEEE division and square root, no
+// contraction), in the order the formulas above are written.  These kernels
+// stream a few arrays and do a handful of flops per cell: they are bound by
+// memory, not by arithmetic.
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/hard.h"
+#include "api_internal.hpp"
+#include "hydro_device.hpp"
+
+namespace hard {
+
+constexpr double FLD_C_LIGHT = 2.99792458e10;  // cm/s
+constexpr int FLD_MAX_LEVELS = 40;
+
+// One multigrid level.  Every array (x, b, D) is stored colour-split: the
+// red cells (i + j + k even) of all rows first, then the black ones; within
+// a colour, row (j, k) holds its cells i at slot i / 2 (hx = ceil(nx / 2)
+// slots per row; when nx is odd one colour leaves the last slot unused).
+// A red-black half-sweep then streams contiguous arrays: the cells it
+// updates, their right-hand sides, and the other colour's values.
+struct FldLevel {
+  int n[3];
+  int halved[3];   // axis halved from the next finer level
+  int hx;          // slots per row and colour
+  long long cs;    // elements per colour: n[1] n[2] hx
+  double dx[3];    // cell width
+  double dx2[3];   // dx_d * dx_d
+  double* x;
+  double* b;
+  double* D;
+};
+
+struct FldCommon {
+  int per[3];          // periodic axis
+  const double* dt;    // device dt
+};
+
+// Neighbour of p on an axis of n cells on side s (0 low, 1 high), or -1 when
+// the face carries no flux (a wall, or a periodic axis of one cell).
+__device__ __forceinline__ int fld_nb(int p, int n, int s, int periodic) {
+  if (s == 0) {
+    if (p > 0) return p - 1;
+    return periodic && n > 1 ? n - 1 : -1;
+  }
+  if (p < n - 1) return p + 1;
+  return periodic && n > 1 ? 0 : -1;
+}
+
+// Colour-split index of cell (i, j, k).
+__device__ __forceinline__ long long fld_at(const FldLevel& L, int i, int j, int k) {
+  return (((i + j + k) & 1) ? L.cs : 0) + ((long long)k * L.n[1] + j) * L.hx + (i >> 1);
+}
+
+__device__ __forceinline__ void fld_cell(const FldLevel& L, long long c, int* p) {
+  p[0] = (int)(c % L.n[0]);
+  p[1] = (int)((c / L.n[0]) % L.n[1]);
+  p[2] = (int)(c / ((long long)L.n[0] * L.n[1]));
+}
+
+// (A x) at cell p = (i, j, k) of level L
+template <int NDIM>
+__device__ __forceinline__ double fld_apply_row(const FldLevel& L, const FldCommon& cm, double dt,
+                                                const int* p) {
+#pragma clang fp contract(off)
+  const long long c = fld_at(L, p[0], p[1], p[2]);
+  const double xc = L.x[c], Dc = L.D[c];
+  double Ax = xc;
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int q = fld_nb(p[d], L.n[d], s, cm.per[d]);
+      if (q < 0) continue;
+      int o[3] = {p[0], p[1], p[2]};
+      o[d] = q;
+      const long long nb = fld_at(L, o[0], o[1], o[2]);
+      const double Dface = 0.5 * (Dc + L.D[nb]);
+      const double a = dt * Dface / L.dx2[d];
+      Ax += a * (xc - L.x[nb]);
+    }
+  return Ax;
+}
+
+// Finest level from the state: D, b = E, x = E (natural-order threads).
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_setup(FldLevel L, FldCommon cm, const double* rho,
+                                                 const double* E, double kappa, int limiter,
+                                                 Control* ctl) {
+#pragma clang fp contract(off)
+  const long long N = (long long)L.n[0] * L.n[1] * L.n[2];
+  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  unsigned flags = 0;
+  if (c < N) {
+    int p[3];
+    fld_cell(L, c, p);
+    const long long stride[3] = {1, L.n[0], (long long)L.n[0] * L.n[1]};
+    double g2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+      const int qlo = fld_nb(p[d], L.n[d], 0, cm.per[d]);
+      const int qhi = fld_nb(p[d], L.n[d], 1, cm.per[d]);
+      const long long lo = qlo < 0 ? c : c + (long long)(qlo - p[d]) * stride[d];
+      const long long hi = qhi < 0 ? c : c + (long long)(qhi - p[d]) * stride[d];
+      const double g = (E[hi] - E[lo]) / (2.0 * L.dx[d]);
+      g2 += g * g;
+    }
+    const double r = rho[c], e = E[c];
+    double lam = 1.0 / 3.0;
+    if (limiter) {
+      const double R = sqrt(g2) / (r * kappa * e);
+      lam = (2.0 + R) / (6.0 + 3.0 * R + R * R);
+    }
+    const double D = FLD_C_LIGHT * lam / (kappa * r);
+    const long long s = fld_at(L, p[0], p[1], p[2]);
+    L.D[s] = D;
+    L.b[s] = e;
+    L.x[s] = e;
+    if (!(r > 0.0)) flags |= FLAG_DENSITY;
+    if (!(e > 0.0) || !isfinite(D)) flags |= FLAG_RADIATION;
+  }
+  block_finish<256>(flags, 0.0, false, ctl, 0.0, nullptr);
+}
+
+// The finest x back into the state's E_r field.
+__global__ __launch_bounds__(256) void fld_store(FldLevel L, double* E) {
+  const long long N = (long long)L.n[0] * L.n[1] * L.n[2];
+  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (c >= N) return;
+  int p[3];
+  fld_cell(L, c, p);
+  E[c] = L.x[fld_at(L, p[0], p[1], p[2])];
+}
+
+// Children of a coarse cell: along a halved axis 2I and 2I+1, else I.
+__device__ __forceinline__ void fld_children(const FldLevel& C, const int* P, int* lo, int* cnt) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = C.halved[d] ? 2 * P[d] : P[d];
+    cnt[d] = C.halved[d] ? 2 : 1;
+  }
+}
+
+__global__ __launch_bounds__(256) void fld_coarsen_D(FldLevel F, FldLevel C, double inv) {
+#pragma clang fp contract(off)
+  const long long N = (long long)C.n[0] * C.n[1] * C.n[2];
+  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (c >= N) return;
+  int P[3], lo[3], cnt[3];
+  fld_cell(C, c, P);
+  fld_children(C, P, lo, cnt);
+  double s = 0.0;
+  for (int dz = 0; dz < cnt[2]; ++dz)
+    for (int dy = 0; dy < cnt[1]; ++dy)
+      for (int dx = 0; dx < cnt[0]; ++dx) s += F.D[fld_at(F, lo[0] + dx, lo[1] + dy, lo[2] + dz)];
+  C.D[fld_at(C, P[0], P[1], P[2])] = s * inv;
+}
+
+// One red-black half-sweep: every cell of colour `colour` (i + j + k = colour
+// mod 2) from the other colour's values.  Thread -> (slot h, row (j, k)).
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_relax(FldLevel L, FldCommon cm, int colour) {
+#pragma clang fp contract(off)
+  const int nx = L.n[0], ny = L.n[1];
+  const long long t = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (t >= L.cs) return;
+  const int h = (int)(t % L.hx);
+  const long long row = t / L.hx;
+  const int j = (int)(row % ny), k = (int)(row / ny);
+  const int i = 2 * h + ((j + k + colour) & 1);
+  if (i >= nx) return;
+  const double dt = *cm.dt;
+  const int p[3] = {i, j, k};
+  const long long c = (colour ? L.cs : 0) + t;
+  const double Dc = L.D[c];
+  double num = L.b[c];
+  double den = 1.0;
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int q = fld_nb(p[d], L.n[d], s, cm.per[d]);
+      if (q < 0) continue;
+      int o[3] = {i, j, k};
+      o[d] = q;
+      const long long nb = fld_at(L, o[0], o[1], o[2]);
+      const double Dface = 0.5 * (Dc + L.D[nb]);
+      const double a = dt * Dface / L.dx2[d];
+      num += a * L.x[nb];
+      den += a;
+    }
+  L.x[c] = num / den;
+}
+
+// Coarse right-hand side: the fine residual averaged over the children;
+// coarse x = 0.
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_restrict(FldLevel F, FldLevel C, FldCommon cm,
+                                                    double inv) {
+#pragma clang fp contract(off)
+  const long long N = (long long)C.n[0] * C.n[1] * C.n[2];
+  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (c >= N) return;
+  const double dt = *cm.dt;
+  int P[3], lo[3], cnt[3];
+  fld_cell(C, c, P);
+  fld_children(C, P, lo, cnt);
+  double s = 0.0;
+  for (int dz = 0; dz < cnt[2]; ++dz)
+    for (int dy = 0; dy < cnt[1]; ++dy)
+      for (int dx = 0; dx < cnt[0]; ++dx) {
+        const int p[3] = {lo[0] + dx, lo[1] + dy, lo[2] + dz};
+        const double r = F.b[fld_at(F, p[0], p[1], p[2])] - fld_apply_row<NDIM>(F, cm, dt, p);
+        s += r;
+      }
+  const long long cc = fld_at(C, P[0], P[1], P[2]);
+  C.b[cc] = s * inv;
+  C.x[cc] = 0.0;
+}
+
+// x_fine += linear interpolation of the coarse correction.
+__global__ __launch_bounds__(256) void fld_prolong(FldLevel F, FldLevel C, FldCommon cm) {
+#pragma clang fp contract(off)
+  const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
+  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (c >= N) return;
+  int f[3];
+  fld_cell(F, c, f);
+  int nr[3], fr[3], cnt[3];
+  double wn[3], wf[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!C.halved[d]) {
+      nr[d] = fr[d] = f[d];
+      wn[d] = 1.0;
+      wf[d] = 0.0;
+      cnt[d] = 1;
+      continue;
+    }
+    const int I = f[d] >> 1;
+    int q = fld_nb(I, C.n[d], f[d] & 1, cm.per[d]);
+    if (q < 0) q = I;
+    nr[d] = I;
+    fr[d] = q;
+    wn[d] = 0.75;
+    wf[d] = 0.25;
+    cnt[d] = 2;
+  }
+  double v = 0.0;
+  for (int cz = 0; cz < cnt[2]; ++cz)
+    for (int cy = 0; cy < cnt[1]; ++cy)
+      for (int cx = 0; cx < cnt[0]; ++cx) {
+        const double w = (cx ? wf[0] : wn[0]) * (cy ? wf[1] : wn[1]) * (cz ? wf[2] : wn[2]);
+        const double xc = C.x[fld_at(C, cx ? fr[0] : nr[0], cy ? fr[1] : nr[1], cz ? fr[2] : nr[2])];
+        v += w * xc;
+      }
+  F.x[fld_at(F, f[0], f[1], f[2])] += v;
+}
+
+__global__ void fld_zero(double* a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0;
+}
+
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_resid_sq(FldLevel L, FldCommon cm, double* acc) {
+#pragma clang fp contract(off)
+  __shared__ double part[4];
+  const long long N = (long long)L.n[0] * L.n[1] * L.n[2];
+  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+  double r2 = 0.0;
+  if (c < N) {
+    int p[3];
+    fld_cell(L, c, p);
+    const double r = L.b[fld_at(L, p[0], p[1], p[2])] - fld_apply_row<NDIM>(L, cm, *cm.dt, p);
+    r2 = r * r;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = r2;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(acc, (part[0] + part[1]) + (part[2] + part[3]));
+}
+
+__global__ void fld_sqrt(double* a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = sqrt(a[i]);
+}
+
+// ---------------------------------------------------------------- host side
+
+namespace {
+
+struct Hierarchy {
+  int nlev;
+  int n[FLD_MAX_LEVELS][3];
+  int halved[FLD_MAX_LEVELS][3];
+  double dx[FLD_MAX_LEVELS][3];
+};
+
+Hierarchy hierarchy_of(const Grid& G) {
+  Hierarchy H;
+  H.nlev = 1;
+  for (int d = 0; d < 3; ++d) {
+    H.n[0][d] = G.n[d];
+    H.halved[0][d] = 0;
+    H.dx[0][d] = G.dx[d];
+  }
+  while (H.nlev < FLD_MAX_LEVELS) {
+    const int l = H.nlev;
+    int any = 0;
+    for (int d = 0; d < 3; ++d) {
+      const int m = H.n[l - 1][d];
+      const int periodic = G.bc[d][0] == BC_PERIODIC;
+      int h = d < G.ndim && m % 2 == 0;
+      if (h && periodic) h = (m / 2) % 2 == 0 || m / 2 == 1;
+      H.halved[l][d] = h;
+      H.n[l][d] = h ? m / 2 : m;
+      H.dx[l][d] = h ? 2.0 * H.dx[l - 1][d] : H.dx[l - 1][d];
+      any |= h;
+    }
+    if (!any) break;
+    ++H.nlev;
+  }
+  return H;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+long long cells(const Hierarchy& H, int l) {
+  return (long long)H.n[l][0] * H.n[l][1] * H.n[l][2];
+}
+
+// Elements of one colour-split array of level l: 2 colours x rows x slots.
+long long split_elems(const Hierarchy& H, int l) {
+  return 2LL * H.n[l][1] * H.n[l][2] * ((H.n[l][0] + 1) / 2);
+}
+
+// Workspace: control block | per level: x, b, D (colour-split)
+size_t fld_workspace(const Hierarchy& H) {
+  size_t total = 256;
+  for (int l = 0; l < H.nlev; ++l) total += 3 * align256(split_elems(H, l) * sizeof(double));
+  return total;
+}
+
+hard_status_t check_fld_grid(const hard_grid_t* g, Grid* G) {
+  hard_status_t st = check_grid(g, G);
+  if (st) return st;
+  if (!G->rad) return fail(HARD_ERR_INVALID_ARG, "radiation diffusion needs rad = 1");
+  if (!(G->kappa > 0.0)) return fail(HARD_ERR_INVALID_ARG, "radiation diffusion needs kappa > 0");
+  if (G->dtype != HARD_F64) return fail(HARD_ERR_UNSUPPORTED, "radiation diffusion is built for HARD_F64");
+  for (int d = 0; d < G->ndim; ++d)
+    if (G->bc[d][0] == BC_PERIODIC && G->n[d] % 2)
+      return fail(HARD_ERR_UNSUPPORTED,
+                  "radiation diffusion: periodic axis %d has an odd size (%d); red-black "
+                  "relaxation needs an even one", d, G->n[d]);
+  return HARD_OK;
+}
+
+unsigned blocks_for(long long threads) { return (unsigned)((threads + 255) / 256); }
+
+struct Solver {
+  const Grid& G;
+  const Hierarchy& H;
+  FldLevel lv[FLD_MAX_LEVELS];
+  double inv_children[FLD_MAX_LEVELS];
+  FldCommon cm;
+  int nu1, nu2, ncoarse;
+  hipStream_t s;
+
+  template <int NDIM>
+  hipError_t relax(int l, int sweeps) {
+    const FldLevel& L = lv[l];
+    const long long t = L.cs;
+    for (int sw = 0; sw < sweeps; ++sw)
+      for (int colour = 0; colour < 2; ++colour) {
+        fld_relax<NDIM><<<blocks_for(t), 256, 0, s>>>(L, cm, colour);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+    return hipSuccess;
+  }
+
+  template <int NDIM>
+  hipError_t vcycle(int l) {
+    hipError_t e;
+    if (l + 1 == H.nlev) return relax<NDIM>(l, ncoarse);
+    if ((e = relax<NDIM>(l, nu1)) != hipSuccess) return e;
+    fld_restrict<NDIM><<<blocks_for(cells(H, l + 1)), 256, 0, s>>>(lv[l], lv[l + 1], cm,
+                                                                   inv_children[l + 1]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = vcycle<NDIM>(l + 1)) != hipSuccess) return e;
+    fld_prolong<<<blocks_for(cells(H, l)), 256, 0, s>>>(lv[l], lv[l + 1], cm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return relax<NDIM>(l, nu2);
+  }
+
+  template <int NDIM>
+  hipError_t run(double* U, int limiter, int ncycles, double* resid, Control* ctl) {
+    hipError_t e;
+    const long long N = cells(H, 0);
+    const double* rho = U;
+    double* E = U + (long long)(G.nvar - 1) * N;
+    fld_setup<NDIM><<<blocks_for(N), 256, 0, s>>>(lv[0], cm, rho, E, G.kappa, limiter, ctl);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int l = 1; l < H.nlev; ++l) {
+      fld_coarsen_D<<<blocks_for(cells(H, l)), 256, 0, s>>>(lv[l - 1], lv[l], inv_children[l]);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (resid) {
+      fld_zero<<<(ncycles + 1 + 255) / 256, 256, 0, s>>>(resid, ncycles + 1);
+      fld_resid_sq<NDIM><<<blocks_for(N), 256, 0, s>>>(lv[0], cm, resid);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    for (int c = 0; c < ncycles; ++c) {
+      if ((e = vcycle<NDIM>(0)) != hipSuccess) return e;
+      if (resid) {
+        fld_resid_sq<NDIM><<<blocks_for(N), 256, 0, s>>>(lv[0], cm, resid + c + 1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+    }
+    fld_store<<<blocks_for(N), 256, 0, s>>>(lv[0], E);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (resid) {
+      fld_sqrt<<<(ncycles + 1 + 255) / 256, 256, 0, s>>>(resid, ncycles + 1);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+};
+
+}  // namespace
+}  // namespace hard
+
+using namespace hard;
+
+extern "C" {
+
+hard_status_t hard_gmg_levels(const hard_grid_t* g, int32_t max_levels, int64_t* levels_n,
+                              int32_t* nlevels) {
+  Grid G;
+  hard_status_t st = check_fld_grid(g, &G);
+  if (st) return st;
+  if (!nlevels) return fail(HARD_ERR_INVALID_ARG, "nlevels is NULL");
+  if (max_levels > 0 && !levels_n) return fail(HARD_ERR_INVALID_ARG, "levels_n is NULL");
+  const Hierarchy H = hierarchy_of(G);
+  for (int l = 0; l < H.nlev && l < max_levels; ++l)
+    for (int d = 0; d < 3; ++d) levels_n[3 * l + d] = H.n[l][d];
+  *nlevels = H.nlev;
+  return ok();
+}
+
+hard_status_t hard_rad_diffuse_workspace_bytes(const hard_grid_t* g, size_t* bytes) {
+  Grid G;
+  hard_status_t st = check_fld_grid(g, &G);
+  if (st) return st;
+  if (!bytes) return fail(HARD_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = fld_workspace(hierarchy_of(G));
+  return ok();
+}
+
+hard_status_t hard_rad_diffuse(const hard_grid_t* g, void* U, const double* dt_dev,
+                               const hard_gmg_opts_t* opts, double* resid_dev, void* work,
+                               size_t work_bytes, void* stream) {
+  Grid G;
+  hard_status_t st = check_fld_grid(g, &G);
+  if (st) return st;
+  if ((st = check_ptr(U, 8, "U"))) return st;
+  if ((st = check_ptr(dt_dev, 8, "dt_dev"))) return st;
+  if (resid_dev && (st = check_ptr(resid_dev, 8, "resid_dev"))) return st;
+  if (!opts) return fail(HARD_ERR_INVALID_ARG, "opts is NULL");
+  if (opts->limiter != HARD_FLD_EDDINGTON && opts->limiter != HARD_FLD_LEVERMORE)
+    return fail(HARD_ERR_INVALID_ARG, "limiter must be HARD_FLD_EDDINGTON or HARD_FLD_LEVERMORE");
+  if (opts->ncycles < 0 || opts->ncycles > 1000)
+    return fail(HARD_ERR_INVALID_ARG, "ncycles must be in [0, 1000]");
+  if (opts->nu1 < 0 || opts->nu1 > 64 || opts->nu2 < 0 || opts->nu2 > 64)
+    return fail(HARD_ERR_INVALID_ARG, "nu1 and nu2 must be in [0, 64]");
+  if (opts->ncoarse < 1 || opts->ncoarse > 1024)
+    return fail(HARD_ERR_INVALID_ARG, "ncoarse must be in [1, 1024]");
+  const Hierarchy H = hierarchy_of(G);
+  if ((st = check_work(work, work_bytes, fld_workspace(H)))) return st;
+
+  char* wb = static_cast<char*>(work);
+  Solver S{G, H, {}, {}, {}, opts->nu1, opts->nu2, opts->ncoarse, (hipStream_t)stream};
+  size_t off = 256;
+  for (int l = 0; l < H.nlev; ++l) {
+    FldLevel& L = S.lv[l];
+    const size_t bytes = align256(split_elems(H, l) * sizeof(double));
+    for (int d = 0; d < 3; ++d) {
+      L.n[d] = H.n[l][d];
+      L.halved[d] = H.halved[l][d];
+      L.dx[d] = H.dx[l][d];
+      L.dx2[d] = H.dx[l][d] * H.dx[l][d];
+    }
+    L.hx = (H.n[l][0] + 1) / 2;
+    L.cs = (long long)H.n[l][1] * H.n[l][2] * L.hx;
+    L.x = reinterpret_cast<double*>(wb + off);
+    L.b = reinterpret_cast<double*>(wb + off + bytes);
+    L.D = reinterpret_cast<double*>(wb + off + 2 * bytes);
+    off += 3 * bytes;
+    const int nch = (H.halved[l][0] ? 2 : 1) * (H.halved[l][1] ? 2 : 1) * (H.halved[l][2] ? 2 : 1);
+    S.inv_children[l] = 1.0 / (double)nch;
+  }
+  for (int d = 0; d < 3; ++d) S.cm.per[d] = G.bc[d][0] == BC_PERIODIC;
+  S.cm.dt = dt_dev;
+  Control* ctl = reinterpret_cast<Control*>(wb);
+  double* Ud = static_cast<double*>(U);
+  hipError_t e;
+  switch (G.ndim) {
+    case 1: e = S.run<1>(Ud, opts->limiter, opts->ncycles, resid_dev, ctl); break;
+    case 2: e = S.run<2>(Ud, opts->limiter, opts->ncycles, resid_dev, ctl); break;
+    default: e = S.run<3>(Ud, opts->limiter, opts->ncycles, resid_dev, ctl); break;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hard_rad_diffuse launch");
+  return ok();
+}
+
+}  // extern "C"

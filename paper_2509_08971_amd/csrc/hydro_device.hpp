@@ -13,7 +13,7 @@
 namespace hard {
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
-enum : unsigned { FLAG_DENSITY = 1u, FLAG_PRESSURE = 2u, FLAG_NONFINITE = 4u };
+enum : unsigned { FLAG_DENSITY = 1u, FLAG_PRESSURE = 2u, FLAG_NONFINITE = 4u, FLAG_RADIATION = 8u };
 
 // Workspace control block (first 256 bytes of every workspace).
 struct Control {

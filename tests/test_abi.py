@@ -177,3 +177,50 @@ def test_radiation_checks():
     arr = (H.hard_grid_t * 1)(H.make_grid((64,), rad=(0.4, 0.6)))
     plan = ctypes.c_void_p()
     assert L.hard_batch_plan_create(arr, 1, None, ctypes.byref(plan)) == H.ERR_UNSUPPORTED
+
+
+def call_diffuse(g, U=FAKE, dt=FAKE, opts=None, resid=None, work=FAKE, nbytes=1 << 40):
+    L = H.lib()
+    if opts is None:
+        opts = H.hard_gmg_opts_t(H.FLD_LEVERMORE, 4, 2, 2, 8)
+    return L.hard_rad_diffuse(ctypes.byref(g), U, dt, ctypes.byref(opts) if opts != 0 else None,
+                              resid, work, nbytes, None)
+
+
+def test_diffusion_checks():
+    """The implicit diffusion call needs the radiation field, kappa > 0, FP64
+    and even periodic axes; its options and workspace are validated."""
+    rad = (0.4, 0.6)
+    assert call_diffuse(H.make_grid((16, 16))) == H.ERR_INVALID_ARG
+    assert call_diffuse(H.make_grid((16, 16), rad=(0.0, 0.6))) == H.ERR_INVALID_ARG
+    assert call_diffuse(H.make_grid((16, 16), rad=rad, dtype="f32")) == H.ERR_UNSUPPORTED
+    assert call_diffuse(H.make_grid((15, 16), bc=(0, 0, 1, 1), rad=rad)) == H.ERR_UNSUPPORTED
+    g = H.make_grid((15, 16), bc=(1, 2, 1, 1), rad=rad)  # odd walls are fine
+    assert H.hard_rad_diffuse_workspace_bytes(g) > 0
+    g = H.make_grid((16, 16), rad=rad)
+    assert call_diffuse(g, U=None) == H.ERR_INVALID_ARG
+    assert call_diffuse(g, dt=None) == H.ERR_INVALID_ARG
+    assert call_diffuse(g, opts=0) == H.ERR_INVALID_ARG
+    for o in [(2, 4, 2, 2, 8), (1, -1, 2, 2, 8), (1, 1001, 2, 2, 8), (1, 4, -1, 2, 8),
+              (1, 4, 2, 65, 8), (1, 4, 2, 2, 0), (1, 4, 2, 2, 1025)]:
+        assert call_diffuse(g, opts=H.hard_gmg_opts_t(*o)) == H.ERR_INVALID_ARG, o
+    need = H.hard_rad_diffuse_workspace_bytes(g)
+    assert call_diffuse(g, nbytes=need - 1) == H.ERR_WORKSPACE
+    assert call_diffuse(g, work=FAKE + 8) == H.ERR_INVALID_ARG  # not 256-byte aligned
+    # level arrays: b and D on the finest level, x, b and D on the coarser ones
+    g3 = H.make_grid((64, 64, 64), bc=(0, 0), rad=rad)
+    b3 = H.hard_rad_diffuse_workspace_bytes(g3)
+    assert 2 * 64 ** 3 * 8 + 3 * 32 ** 3 * 8 < b3 < 3.5 * 64 ** 3 * 8
+
+
+@pytest.mark.parametrize("n, bc", [
+    ((32, 32), (0, 0, 1, 1)), ((48, 40, 24), (0, 0, 1, 1, 2, 2)), ((6,), (0, 0)), ((6,), (1, 1)),
+    ((12, 4), (1, 1, 1, 1)), ((256, 256, 256), (2, 2)), ((100, 36), (0, 0, 0, 0)),
+    ((2, 2, 2), (0, 0)),
+])
+def test_multigrid_levels_match_the_oracle(n, bc):
+    import oracle
+    from oracle import fld
+    want = fld.gmg_levels(oracle.Grid(n, bc=bc, rad=(0.4, 0.6)))
+    got = H.hard_gmg_levels(H.make_grid(n, bc=bc, rad=(0.4, 0.6)))
+    assert got == want
