@@ -249,6 +249,71 @@ def bench_rad(args, n=256, steps=20):
             "status_flags": flags}
 
 
+def fld_cycle_bytes(levels):
+    """Algorithmic HBM bytes of one V(2,2) cycle over the given level sizes:
+    per level, 8 red-black half-sweeps of 20 B per cell (read the other
+    colour's x, the own colour's b, both colours' D; write the own x), the
+    residual restriction (read x, b, D: 24 B per fine cell) and the
+    prolongation (read and write x: 16 B per fine cell); the coarsest level
+    has no transfers."""
+    total = 0
+    for l, (a, b, c) in enumerate(levels):
+        cells = a * b * c
+        total += 8 * 20 * cells
+        if l + 1 < len(levels):
+            total += (24 + 16) * cells
+    return total
+
+
+def bench_fld(args, n=256, ncycles=4, reps=10):
+    """One implicit radiation diffusion step on the 256^3 grid: D from the
+    Levermore limiter on a hot Gaussian radiation spot in a uniform gas
+    (rho = 1 g/cm^3, kappa = 1 cm^2/g, reflecting walls), dt = 1e-12 s
+    (dt D / dx^2 of about 650 in the cold gas), four V(2,2) cycles."""
+    import paper_2509_08971_amd as H
+
+    log(f"bench: radiation diffusion {n}^3 fp64, {ncycles} V(2,2) cycles")
+    g = H.make_grid((n, n, n), bc=(H.REFLECT, H.REFLECT), rad=(1.0, 0.6))
+    c = (torch.arange(n, dtype=torch.float64, device="cuda") + 0.5) / n - 0.5
+    r2 = c[None, None, :] ** 2 + c[None, :, None] ** 2 + c[:, None, None] ** 2
+    U = torch.zeros((6, n, n, n), dtype=torch.float64, device="cuda")
+    U[0] = 1.0
+    U[4] = 1.0
+    a_rad = 4.0 * 5.670374419e-5 / 2.99792458e10
+    T = 1e4 + 1e6 * torch.exp(-r2 / 0.01)
+    U0 = U.clone()
+    U0[5] = a_rad * T ** 4
+    work = H.workspace(H.hard_rad_diffuse_workspace_bytes(g))
+    dt = torch.full((1,), 1e-12, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    levels = H.hard_gmg_levels(g)
+    res = torch.empty(ncycles + 1, dtype=torch.float64, device="cuda")
+    U.copy_(U0)
+    H.hard_rad_diffuse(g, U, dt, work, ncycles=ncycles, resid_dev=res)
+    torch.cuda.synchronize()
+    r = res.cpu().numpy()
+    times = []
+    for _ in range(reps):
+        U.copy_(U0)
+        times.append(_time_steps(lambda: H.hard_rad_diffuse(g, U, dt, work, ncycles=ncycles), 1,
+                                 stream))
+    flags = H.hard_status_read(work)
+    ms = sorted(times)[len(times) // 2]
+    N = n ** 3
+    cyc = fld_cycle_bytes(levels)
+    log(f"  {ms:.3f} ms per diffusion step ({ms / ncycles:.3f} ms per cycle), "
+        f"{N / ms / 1e6:.2f} G cells/s, residual {r[0]:.3e} -> {r[-1]:.3e}")
+    return {"value": N / (ms * 1e-3), "unit": "zone-updates/s",
+            "ms_per_step": ms, "ms_per_cycle": ms / ncycles, "dtype": "f64",
+            "workload": f"3D {n}^3 FP64 implicit flux-limited diffusion of E_r (Levermore), "
+                        f"hot Gaussian spot, {ncycles} V(2,2) cycles, {len(levels)} levels",
+            "residual_reduction": float(r[-1] / r[0]),
+            "cycle_algorithmic_bytes": cyc,
+            "achieved_gbs_cycles": cyc * ncycles / (ms * 1e-3) / 1e9,
+            "timing": f"median of {reps} calls, HIP events on the launch stream",
+            "status_flags": flags}
+
+
 def bench_adjoint(args, n=512, nsteps=200, every=20):
     """Config-4 gradient: 2D 512^2 FP64 periodic, 200 steps, checkpoints every
     20; gradient of J = dx^2/2 sum (rho_N - rho_T)^2 wrt the initial state."""
@@ -305,6 +370,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--only-main", action="store_true",
                     help="time only the FP64 blast (skip the FP32 and batched lines)")
+    ap.add_argument("--only-fld", action="store_true",
+                    help="only time the implicit radiation diffusion step (prints its object)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -320,6 +387,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
         sys.exit(2)
+    if args.only_fld:
+        print(json.dumps({"radiation_diffusion_256": bench_fld(args)}), flush=True)
+        return
 
     import paper_2509_08971_amd as H
     import workloads
@@ -444,6 +514,10 @@ def main():
             extras["radiation_256"] = bench_rad(args)
         except Exception as e:
             extras["radiation_256"] = {"error": repr(e)}
+        try:
+            extras["radiation_diffusion_256"] = bench_fld(args)
+        except Exception as e:
+            extras["radiation_diffusion_256"] = {"error": repr(e)}
         out["beside_fp64_step"] = extras
 
     if not args.no_cpu_baseline:

@@ -41,6 +41,7 @@
 // stream a few arrays and do a handful of flops per cell: they are bound by
 // memory, not by arithmetic.
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -59,11 +60,13 @@ constexpr int FLD_MAX_LEVELS = 40;
 // slots per row; when nx is odd one colour leaves the last slot unused).
 // A red-black half-sweep then streams contiguous arrays: the cells it
 // updates, their right-hand sides, and the other colour's values.
+// Indices are 32-bit: a level has fewer than 2^31 cells, so a colour-split
+// array has fewer than 2^32 elements.
 struct FldLevel {
   int n[3];
   int halved[3];   // axis halved from the next finer level
-  int hx;          // slots per row and colour
-  long long cs;    // elements per colour: n[1] n[2] hx
+  unsigned hx;     // slots per row and colour
+  unsigned cs;     // elements per colour: n[1] n[2] hx
   double dx[3];    // cell width
   double dx2[3];   // dx_d * dx_d
   double* x;
@@ -88,14 +91,22 @@ __device__ __forceinline__ int fld_nb(int p, int n, int s, int periodic) {
 }
 
 // Colour-split index of cell (i, j, k).
-__device__ __forceinline__ long long fld_at(const FldLevel& L, int i, int j, int k) {
-  return (((i + j + k) & 1) ? L.cs : 0) + ((long long)k * L.n[1] + j) * L.hx + (i >> 1);
+__device__ __forceinline__ unsigned fld_at(const FldLevel& L, int i, int j, int k) {
+  return (((i + j + k) & 1) ? L.cs : 0u) + ((unsigned)k * (unsigned)L.n[1] + (unsigned)j) * L.hx +
+         ((unsigned)i >> 1);
 }
 
-__device__ __forceinline__ void fld_cell(const FldLevel& L, long long c, int* p) {
-  p[0] = (int)(c % L.n[0]);
-  p[1] = (int)((c / L.n[0]) % L.n[1]);
-  p[2] = (int)(c / ((long long)L.n[0] * L.n[1]));
+// Natural-order cell index -> (i, j, k)
+__device__ __forceinline__ void fld_cell(const FldLevel& L, unsigned c, int* p) {
+  const unsigned nx = L.n[0], ny = L.n[1];
+  const unsigned row = c / nx;
+  p[0] = (int)(c - row * nx);
+  p[1] = (int)(row % ny);
+  p[2] = (int)(row / ny);
+}
+
+__device__ __forceinline__ unsigned fld_cells(const FldLevel& L) {
+  return (unsigned)L.n[0] * (unsigned)L.n[1] * (unsigned)L.n[2];
 }
 
 // (A x) at cell p = (i, j, k) of level L
@@ -103,7 +114,7 @@ template <int NDIM>
 __device__ __forceinline__ double fld_apply_row(const FldLevel& L, const FldCommon& cm, double dt,
                                                 const int* p) {
 #pragma clang fp contract(off)
-  const long long c = fld_at(L, p[0], p[1], p[2]);
+  const unsigned c = fld_at(L, p[0], p[1], p[2]);
   const double xc = L.x[c], Dc = L.D[c];
   double Ax = xc;
 #pragma unroll
@@ -114,7 +125,7 @@ __device__ __forceinline__ double fld_apply_row(const FldLevel& L, const FldComm
       if (q < 0) continue;
       int o[3] = {p[0], p[1], p[2]};
       o[d] = q;
-      const long long nb = fld_at(L, o[0], o[1], o[2]);
+      const unsigned nb = fld_at(L, o[0], o[1], o[2]);
       const double Dface = 0.5 * (Dc + L.D[nb]);
       const double a = dt * Dface / L.dx2[d];
       Ax += a * (xc - L.x[nb]);
@@ -122,96 +133,19 @@ __device__ __forceinline__ double fld_apply_row(const FldLevel& L, const FldComm
   return Ax;
 }
 
-// Finest level from the state: D, b = E, x = E (natural-order threads).
+// Gauss-Seidel update of the cell at slot t of colour `colour`:
+// x_c = (b_c + sum_faces a_f x_nb) / (1 + sum_faces a_f)
 template <int NDIM>
-__global__ __launch_bounds__(256) void fld_setup(FldLevel L, FldCommon cm, const double* rho,
-                                                 const double* E, double kappa, int limiter,
-                                                 Control* ctl) {
+__device__ __forceinline__ void fld_relax_slot(const FldLevel& L, const FldCommon& cm, double dt,
+                                               int colour, unsigned t) {
 #pragma clang fp contract(off)
-  const long long N = (long long)L.n[0] * L.n[1] * L.n[2];
-  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  unsigned flags = 0;
-  if (c < N) {
-    int p[3];
-    fld_cell(L, c, p);
-    const long long stride[3] = {1, L.n[0], (long long)L.n[0] * L.n[1]};
-    double g2 = 0.0;
-#pragma unroll
-    for (int d = 0; d < NDIM; ++d) {
-      const int qlo = fld_nb(p[d], L.n[d], 0, cm.per[d]);
-      const int qhi = fld_nb(p[d], L.n[d], 1, cm.per[d]);
-      const long long lo = qlo < 0 ? c : c + (long long)(qlo - p[d]) * stride[d];
-      const long long hi = qhi < 0 ? c : c + (long long)(qhi - p[d]) * stride[d];
-      const double g = (E[hi] - E[lo]) / (2.0 * L.dx[d]);
-      g2 += g * g;
-    }
-    const double r = rho[c], e = E[c];
-    double lam = 1.0 / 3.0;
-    if (limiter) {
-      const double R = sqrt(g2) / (r * kappa * e);
-      lam = (2.0 + R) / (6.0 + 3.0 * R + R * R);
-    }
-    const double D = FLD_C_LIGHT * lam / (kappa * r);
-    const long long s = fld_at(L, p[0], p[1], p[2]);
-    L.D[s] = D;
-    L.b[s] = e;
-    L.x[s] = e;
-    if (!(r > 0.0)) flags |= FLAG_DENSITY;
-    if (!(e > 0.0) || !isfinite(D)) flags |= FLAG_RADIATION;
-  }
-  block_finish<256>(flags, 0.0, false, ctl, 0.0, nullptr);
-}
-
-// The finest x back into the state's E_r field.
-__global__ __launch_bounds__(256) void fld_store(FldLevel L, double* E) {
-  const long long N = (long long)L.n[0] * L.n[1] * L.n[2];
-  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (c >= N) return;
-  int p[3];
-  fld_cell(L, c, p);
-  E[c] = L.x[fld_at(L, p[0], p[1], p[2])];
-}
-
-// Children of a coarse cell: along a halved axis 2I and 2I+1, else I.
-__device__ __forceinline__ void fld_children(const FldLevel& C, const int* P, int* lo, int* cnt) {
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    lo[d] = C.halved[d] ? 2 * P[d] : P[d];
-    cnt[d] = C.halved[d] ? 2 : 1;
-  }
-}
-
-__global__ __launch_bounds__(256) void fld_coarsen_D(FldLevel F, FldLevel C, double inv) {
-#pragma clang fp contract(off)
-  const long long N = (long long)C.n[0] * C.n[1] * C.n[2];
-  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (c >= N) return;
-  int P[3], lo[3], cnt[3];
-  fld_cell(C, c, P);
-  fld_children(C, P, lo, cnt);
-  double s = 0.0;
-  for (int dz = 0; dz < cnt[2]; ++dz)
-    for (int dy = 0; dy < cnt[1]; ++dy)
-      for (int dx = 0; dx < cnt[0]; ++dx) s += F.D[fld_at(F, lo[0] + dx, lo[1] + dy, lo[2] + dz)];
-  C.D[fld_at(C, P[0], P[1], P[2])] = s * inv;
-}
-
-// One red-black half-sweep: every cell of colour `colour` (i + j + k = colour
-// mod 2) from the other colour's values.  Thread -> (slot h, row (j, k)).
-template <int NDIM>
-__global__ __launch_bounds__(256) void fld_relax(FldLevel L, FldCommon cm, int colour) {
-#pragma clang fp contract(off)
-  const int nx = L.n[0], ny = L.n[1];
-  const long long t = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (t >= L.cs) return;
-  const int h = (int)(t % L.hx);
-  const long long row = t / L.hx;
-  const int j = (int)(row % ny), k = (int)(row / ny);
-  const int i = 2 * h + ((j + k + colour) & 1);
-  if (i >= nx) return;
-  const double dt = *cm.dt;
+  const unsigned h = t % L.hx;
+  const unsigned row = t / L.hx;
+  const int j = (int)(row % (unsigned)L.n[1]), k = (int)(row / (unsigned)L.n[1]);
+  const int i = 2 * (int)h + ((j + k + colour) & 1);
+  if (i >= L.n[0]) return;
   const int p[3] = {i, j, k};
-  const long long c = (colour ? L.cs : 0) + t;
+  const unsigned c = (colour ? L.cs : 0u) + t;
   const double Dc = L.D[c];
   double num = L.b[c];
   double den = 1.0;
@@ -223,7 +157,7 @@ __global__ __launch_bounds__(256) void fld_relax(FldLevel L, FldCommon cm, int c
       if (q < 0) continue;
       int o[3] = {i, j, k};
       o[d] = q;
-      const long long nb = fld_at(L, o[0], o[1], o[2]);
+      const unsigned nb = fld_at(L, o[0], o[1], o[2]);
       const double Dface = 0.5 * (Dc + L.D[nb]);
       const double a = dt * Dface / L.dx2[d];
       num += a * L.x[nb];
@@ -232,18 +166,22 @@ __global__ __launch_bounds__(256) void fld_relax(FldLevel L, FldCommon cm, int c
   L.x[c] = num / den;
 }
 
-// Coarse right-hand side: the fine residual averaged over the children;
-// coarse x = 0.
+// Children of a coarse cell: along a halved axis 2I and 2I+1, else I.
+__device__ __forceinline__ void fld_children(const FldLevel& C, const int* P, int* lo, int* cnt) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = C.halved[d] ? 2 * P[d] : P[d];
+    cnt[d] = C.halved[d] ? 2 : 1;
+  }
+}
+
+// Coarse cell P: b = mean over the children of the fine residual, x = 0.
 template <int NDIM>
-__global__ __launch_bounds__(256) void fld_restrict(FldLevel F, FldLevel C, FldCommon cm,
-                                                    double inv) {
+__device__ __forceinline__ void fld_restrict_cell(const FldLevel& F, const FldLevel& C,
+                                                  const FldCommon& cm, double dt, double inv,
+                                                  const int* P) {
 #pragma clang fp contract(off)
-  const long long N = (long long)C.n[0] * C.n[1] * C.n[2];
-  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (c >= N) return;
-  const double dt = *cm.dt;
-  int P[3], lo[3], cnt[3];
-  fld_cell(C, c, P);
+  int lo[3], cnt[3];
   fld_children(C, P, lo, cnt);
   double s = 0.0;
   for (int dz = 0; dz < cnt[2]; ++dz)
@@ -253,19 +191,15 @@ __global__ __launch_bounds__(256) void fld_restrict(FldLevel F, FldLevel C, FldC
         const double r = F.b[fld_at(F, p[0], p[1], p[2])] - fld_apply_row<NDIM>(F, cm, dt, p);
         s += r;
       }
-  const long long cc = fld_at(C, P[0], P[1], P[2]);
+  const unsigned cc = fld_at(C, P[0], P[1], P[2]);
   C.b[cc] = s * inv;
   C.x[cc] = 0.0;
 }
 
-// x_fine += linear interpolation of the coarse correction.
-__global__ __launch_bounds__(256) void fld_prolong(FldLevel F, FldLevel C, FldCommon cm) {
+// Fine cell f: x += linear interpolation of the coarse x.
+__device__ __forceinline__ void fld_prolong_cell(const FldLevel& F, const FldLevel& C,
+                                                 const FldCommon& cm, const int* f) {
 #pragma clang fp contract(off)
-  const long long N = (long long)F.n[0] * F.n[1] * F.n[2];
-  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (c >= N) return;
-  int f[3];
-  fld_cell(F, c, f);
   int nr[3], fr[3], cnt[3];
   double wn[3], wf[3];
 #pragma unroll
@@ -297,34 +231,240 @@ __global__ __launch_bounds__(256) void fld_prolong(FldLevel F, FldLevel C, FldCo
   F.x[fld_at(F, f[0], f[1], f[2])] += v;
 }
 
-__global__ void fld_zero(double* a, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = 0.0;
+// Block tile of the natural-order kernels: 256 cells, TX x TY x TZ.
+template <int NDIM> struct FldTile;
+template <> struct FldTile<1> { static constexpr int TX = 256, TY = 1, TZ = 1; };
+template <> struct FldTile<2> { static constexpr int TX = 64, TY = 4, TZ = 1; };
+template <> struct FldTile<3> { static constexpr int TX = 32, TY = 4, TZ = 2; };
+
+// Cell (i, j, k) of this thread in the tile grid of level L (tile ids dealt
+// XCD-contiguously); false if outside the level.
+template <int NDIM>
+__device__ __forceinline__ bool fld_tile_cell(const FldLevel& L, int* p) {
+  using T = FldTile<NDIM>;
+  const unsigned tx = (L.n[0] + T::TX - 1) / T::TX, ty = (L.n[1] + T::TY - 1) / T::TY;
+  const unsigned b = (unsigned)xcd_tile(blockIdx.x, gridDim.x);
+  const unsigned bx = b % tx, r = b / tx;
+  const unsigned by = r % ty, bz = r / ty;
+  const int t = threadIdx.x;
+  p[0] = (int)bx * T::TX + t % T::TX;
+  p[1] = (int)by * T::TY + (t / T::TX) % T::TY;
+  p[2] = (int)bz * T::TZ + t / (T::TX * T::TY);
+  return p[0] < L.n[0] && p[1] < L.n[1] && p[2] < L.n[2];
 }
 
 template <int NDIM>
-__global__ __launch_bounds__(256) void fld_resid_sq(FldLevel L, FldCommon cm, double* acc) {
+unsigned fld_tiles(const FldLevel& L) {
+  using T = FldTile<NDIM>;
+  return (unsigned)(((L.n[0] + T::TX - 1) / T::TX) * ((L.n[1] + T::TY - 1) / T::TY) *
+                    ((L.n[2] + T::TZ - 1) / T::TZ));
+}
+
+// Finest level from the state: D, b = E, x = E.
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_setup(FldLevel L, FldCommon cm, const double* rho,
+                                                 const double* E, double kappa, int limiter,
+                                                 Control* ctl) {
 #pragma clang fp contract(off)
-  __shared__ double part[4];
-  const long long N = (long long)L.n[0] * L.n[1] * L.n[2];
-  const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+  int p[3];
+  unsigned flags = 0;
+  if (fld_tile_cell<NDIM>(L, p)) {
+    const unsigned stride[3] = {1u, (unsigned)L.n[0], (unsigned)L.n[0] * (unsigned)L.n[1]};
+    const unsigned c = (unsigned)p[0] + (unsigned)p[1] * stride[1] + (unsigned)p[2] * stride[2];
+    double g2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+      const int qlo = fld_nb(p[d], L.n[d], 0, cm.per[d]);
+      const int qhi = fld_nb(p[d], L.n[d], 1, cm.per[d]);
+      const unsigned lo = qlo < 0 ? c : c + (unsigned)(qlo - p[d]) * stride[d];
+      const unsigned hi = qhi < 0 ? c : c + (unsigned)(qhi - p[d]) * stride[d];
+      const double g = (E[hi] - E[lo]) / (2.0 * L.dx[d]);
+      g2 += g * g;
+    }
+    const double r = rho[c], e = E[c];
+    double lam = 1.0 / 3.0;
+    if (limiter) {
+      const double R = sqrt(g2) / (r * kappa * e);
+      lam = (2.0 + R) / (6.0 + 3.0 * R + R * R);
+    }
+    const double D = FLD_C_LIGHT * lam / (kappa * r);
+    const unsigned s = fld_at(L, p[0], p[1], p[2]);
+    L.D[s] = D;
+    L.b[s] = e;
+    L.x[s] = e;
+    if (!(r > 0.0)) flags |= FLAG_DENSITY;
+    if (!(e > 0.0) || !isfinite(D)) flags |= FLAG_RADIATION;
+  }
+  block_finish<256>(flags, 0.0, false, ctl, 0.0, nullptr);
+}
+
+// The finest x back into the state's E_r field.
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_store(FldLevel L, double* E) {
+  int p[3];
+  if (!fld_tile_cell<NDIM>(L, p)) return;
+  const unsigned c = ((unsigned)p[2] * (unsigned)L.n[1] + (unsigned)p[1]) * (unsigned)L.n[0] +
+                     (unsigned)p[0];
+  E[c] = L.x[fld_at(L, p[0], p[1], p[2])];
+}
+
+__global__ __launch_bounds__(256) void fld_coarsen_D(FldLevel F, FldLevel C, double inv) {
+#pragma clang fp contract(off)
+  const unsigned c = (unsigned)blockIdx.x * 256u + threadIdx.x;
+  if (c >= fld_cells(C)) return;
+  int P[3], lo[3], cnt[3];
+  fld_cell(C, c, P);
+  fld_children(C, P, lo, cnt);
+  double s = 0.0;
+  for (int dz = 0; dz < cnt[2]; ++dz)
+    for (int dy = 0; dy < cnt[1]; ++dy)
+      for (int dx = 0; dx < cnt[0]; ++dx) s += F.D[fld_at(F, lo[0] + dx, lo[1] + dy, lo[2] + dz)];
+  C.D[fld_at(C, P[0], P[1], P[2])] = s * inv;
+}
+
+// One red-black half-sweep of level L: every cell of colour `colour`.
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_relax(FldLevel L, FldCommon cm, int colour) {
+  const unsigned t = (unsigned)xcd_tile(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+  if (t >= L.cs) return;
+  fld_relax_slot<NDIM>(L, cm, *cm.dt, colour, t);
+}
+
+// Restriction, one thread per coarse cell (any halving pattern).
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_restrict(FldLevel F, FldLevel C, FldCommon cm,
+                                                    double inv) {
+  const unsigned c = (unsigned)xcd_tile(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+  if (c >= fld_cells(C)) return;
+  int P[3];
+  fld_cell(C, c, P);
+  fld_restrict_cell<NDIM>(F, C, cm, *cm.dt, inv, P);
+}
+
+// Restriction when every active axis is halved: one thread per fine cell of
+// an even-aligned tile computes its residual; the tile's coarse cells then
+// sum their children from LDS in the same order as fld_restrict_cell.
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_restrict_tile(FldLevel F, FldLevel C, FldCommon cm,
+                                                         double inv) {
+#pragma clang fp contract(off)
+  using T = FldTile<NDIM>;
+  __shared__ double r[256];
+  int p[3];
+  const bool in = fld_tile_cell<NDIM>(F, p);
+  const double dt = *cm.dt;
+  double rv = 0.0;
+  if (in) rv = F.b[fld_at(F, p[0], p[1], p[2])] - fld_apply_row<NDIM>(F, cm, dt, p);
+  r[threadIdx.x] = rv;
+  __syncthreads();
+  constexpr int CX = T::TX / 2, CY = NDIM > 1 ? T::TY / 2 : 1, CZ = NDIM > 2 ? T::TZ / 2 : 1;
+  const int t = threadIdx.x;
+  if (t >= CX * CY * CZ) return;
+  const int cx = t % CX, cy = (t / CX) % CY, cz = t / (CX * CY);
+  // tile origin in fine cells, from this thread's own fine cell
+  const int fx0 = p[0] - t % T::TX, fy0 = p[1] - (t / T::TX) % T::TY, fz0 = p[2] - t / (T::TX * T::TY);
+  const int P[3] = {(fx0 >> 1) + cx, NDIM > 1 ? (fy0 >> 1) + cy : 0, NDIM > 2 ? (fz0 >> 1) + cz : 0};
+  if (P[0] >= C.n[0] || P[1] >= C.n[1] || P[2] >= C.n[2]) return;
+  double s = 0.0;
+  for (int dz = 0; dz < (NDIM > 2 ? 2 : 1); ++dz)
+    for (int dy = 0; dy < (NDIM > 1 ? 2 : 1); ++dy)
+      for (int dx = 0; dx < 2; ++dx)
+        s += r[(2 * cz + dz) * T::TX * T::TY + (2 * cy + dy) * T::TX + 2 * cx + dx];
+  const unsigned cc = fld_at(C, P[0], P[1], P[2]);
+  C.b[cc] = s * inv;
+  C.x[cc] = 0.0;
+}
+
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_prolong(FldLevel F, FldLevel C, FldCommon cm) {
+  int f[3];
+  if (!fld_tile_cell<NDIM>(F, f)) return;
+  fld_prolong_cell(F, C, cm, f);
+}
+
+// Residual norm, two deterministic passes: per-tile sums of r^2 in a fixed
+// order, then one workgroup adds the tile sums in a fixed order.
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_resid_sq(FldLevel L, FldCommon cm, double* part) {
+#pragma clang fp contract(off)
+  __shared__ double w[4];
+  int p[3];
   double r2 = 0.0;
-  if (c < N) {
-    int p[3];
-    fld_cell(L, c, p);
+  if (fld_tile_cell<NDIM>(L, p)) {
     const double r = L.b[fld_at(L, p[0], p[1], p[2])] - fld_apply_row<NDIM>(L, cm, *cm.dt, p);
     r2 = r * r;
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = r2;
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = r2;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(acc, (part[0] + part[1]) + (part[2] + part[3]));
+  if (threadIdx.x == 0) part[blockIdx.x] = (w[0] + w[1]) + (w[2] + w[3]);
 }
 
-__global__ void fld_sqrt(double* a, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = sqrt(a[i]);
+__global__ __launch_bounds__(1024) void fld_resid_final(const double* part, unsigned n, double* out) {
+#pragma clang fp contract(off)
+  __shared__ double w[16];
+  double s = 0.0;
+  for (unsigned i = threadIdx.x; i < n; i += 1024) s += part[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < 16; ++i) t += w[i];
+    *out = sqrt(t);
+  }
+}
+
+// The V-cycle below a level small enough for one workgroup: every phase
+// (half-sweep, restriction, prolongation) is a loop of the workgroup over the
+// level's cells, separated by barriers; the arrays stay in cache.  Same
+// per-cell arithmetic as the multi-workgroup kernels.
+constexpr int FLD_TAIL_LEVELS = 16;
+constexpr unsigned FLD_TAIL_CELLS = 4096;
+
+struct FldTail {
+  FldLevel lv[FLD_TAIL_LEVELS];
+  double inv[FLD_TAIL_LEVELS];  // 1 / children of level l (from level l - 1)
+  int nlev;
+  int nu1, nu2, ncoarse;
+};
+
+template <int NDIM>
+__device__ void fld_tail_relax(const FldLevel& L, const FldCommon& cm, double dt, int sweeps) {
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int colour = 0; colour < 2; ++colour) {
+      for (unsigned t = threadIdx.x; t < L.cs; t += 1024) fld_relax_slot<NDIM>(L, cm, dt, colour, t);
+      __syncthreads();
+    }
+}
+
+template <int NDIM>
+__global__ __launch_bounds__(1024) void fld_vcycle_tail(FldTail T, FldCommon cm) {
+  const double dt = *cm.dt;
+  const int last = T.nlev - 1;
+  for (int l = 0; l < last; ++l) {
+    fld_tail_relax<NDIM>(T.lv[l], cm, dt, T.nu1);
+    const FldLevel& C = T.lv[l + 1];
+    for (unsigned c = threadIdx.x; c < fld_cells(C); c += 1024) {
+      int P[3];
+      fld_cell(C, c, P);
+      fld_restrict_cell<NDIM>(T.lv[l], C, cm, dt, T.inv[l + 1], P);
+    }
+    __syncthreads();
+  }
+  fld_tail_relax<NDIM>(T.lv[last], cm, dt, T.ncoarse);
+  for (int l = last - 1; l >= 0; --l) {
+    const FldLevel& F = T.lv[l];
+    for (unsigned c = threadIdx.x; c < fld_cells(F); c += 1024) {
+      int f[3];
+      fld_cell(F, c, f);
+      fld_prolong_cell(F, T.lv[l + 1], cm, f);
+    }
+    __syncthreads();
+    fld_tail_relax<NDIM>(F, cm, dt, T.nu2);
+  }
 }
 
 // ---------------------------------------------------------------- host side
@@ -376,9 +516,20 @@ long long split_elems(const Hierarchy& H, int l) {
   return 2LL * H.n[l][1] * H.n[l][2] * ((H.n[l][0] + 1) / 2);
 }
 
-// Workspace: control block | per level: x, b, D (colour-split)
+// Tile-sum slots of the residual norm: one per 256-cell tile of the finest
+// level (the tile counts of the 1D, 2D and 3D tilings never exceed this).
+size_t resid_slots(const Hierarchy& H) {
+  const long long a = (H.n[0][0] + 31) / 32, b = (H.n[0][1] + 3) / 4, c = (H.n[0][2] + 1) / 2;
+  const long long t3 = a * b * c;
+  const long long t2 = ((H.n[0][0] + 63) / 64) * b * H.n[0][2];
+  const long long t1 = ((H.n[0][0] + 255) / 256) * H.n[0][1] * H.n[0][2];
+  return (size_t)std::max(t3, std::max(t2, t1));
+}
+
+// Workspace: control block | residual tile sums | per level: x, b, D
+// (colour-split)
 size_t fld_workspace(const Hierarchy& H) {
-  size_t total = 256;
+  size_t total = 256 + align256(resid_slots(H) * sizeof(double));
   for (int l = 0; l < H.nlev; ++l) total += 3 * align256(split_elems(H, l) * sizeof(double));
   return total;
 }
@@ -406,15 +557,22 @@ struct Solver {
   double inv_children[FLD_MAX_LEVELS];
   FldCommon cm;
   int nu1, nu2, ncoarse;
+  int tail;         // first level solved by the one-workgroup kernel
+  double* part;     // residual tile sums
   hipStream_t s;
+
+  bool all_halved(int l) const {  // every active axis halved from level l - 1
+    for (int d = 0; d < G.ndim; ++d)
+      if (!H.halved[l][d]) return false;
+    return true;
+  }
 
   template <int NDIM>
   hipError_t relax(int l, int sweeps) {
     const FldLevel& L = lv[l];
-    const long long t = L.cs;
     for (int sw = 0; sw < sweeps; ++sw)
       for (int colour = 0; colour < 2; ++colour) {
-        fld_relax<NDIM><<<blocks_for(t), 256, 0, s>>>(L, cm, colour);
+        fld_relax<NDIM><<<blocks_for(L.cs), 256, 0, s>>>(L, cm, colour);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
       }
@@ -424,15 +582,42 @@ struct Solver {
   template <int NDIM>
   hipError_t vcycle(int l) {
     hipError_t e;
-    if (l + 1 == H.nlev) return relax<NDIM>(l, ncoarse);
+    if (l < 0 || l >= H.nlev) return hipErrorInvalidValue;
+    if (l == tail) {
+      FldTail T;
+      T.nlev = H.nlev - l;
+      for (int m = 0; m < T.nlev; ++m) {
+        T.lv[m] = lv[l + m];
+        T.inv[m] = inv_children[l + m];
+      }
+      T.nu1 = nu1;
+      T.nu2 = nu2;
+      T.ncoarse = ncoarse;
+      fld_vcycle_tail<NDIM><<<1, 1024, 0, s>>>(T, cm);
+      return hipGetLastError();
+    }
+    if (l + 1 == H.nlev) return relax<NDIM>(l, ncoarse);  // coarsest level
+    if (l + 1 > H.nlev) return hipErrorInvalidValue;
     if ((e = relax<NDIM>(l, nu1)) != hipSuccess) return e;
-    fld_restrict<NDIM><<<blocks_for(cells(H, l + 1)), 256, 0, s>>>(lv[l], lv[l + 1], cm,
-                                                                   inv_children[l + 1]);
+    if (all_halved(l + 1))
+      fld_restrict_tile<NDIM><<<fld_tiles<NDIM>(lv[l]), 256, 0, s>>>(lv[l], lv[l + 1], cm,
+                                                                    inv_children[l + 1]);
+    else
+      fld_restrict<NDIM><<<blocks_for(cells(H, l + 1)), 256, 0, s>>>(lv[l], lv[l + 1], cm,
+                                                                     inv_children[l + 1]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = vcycle<NDIM>(l + 1)) != hipSuccess) return e;
-    fld_prolong<<<blocks_for(cells(H, l)), 256, 0, s>>>(lv[l], lv[l + 1], cm);
+    fld_prolong<NDIM><<<fld_tiles<NDIM>(lv[l]), 256, 0, s>>>(lv[l], lv[l + 1], cm);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return relax<NDIM>(l, nu2);
+  }
+
+  template <int NDIM>
+  hipError_t resid_norm(double* out) {
+    const unsigned nt = fld_tiles<NDIM>(lv[0]);
+    fld_resid_sq<NDIM><<<nt, 256, 0, s>>>(lv[0], cm, part);
+    fld_resid_final<<<1, 1024, 0, s>>>(part, nt, out);
+    return hipGetLastError();
   }
 
   template <int NDIM>
@@ -441,31 +626,19 @@ struct Solver {
     const long long N = cells(H, 0);
     const double* rho = U;
     double* E = U + (long long)(G.nvar - 1) * N;
-    fld_setup<NDIM><<<blocks_for(N), 256, 0, s>>>(lv[0], cm, rho, E, G.kappa, limiter, ctl);
+    fld_setup<NDIM><<<fld_tiles<NDIM>(lv[0]), 256, 0, s>>>(lv[0], cm, rho, E, G.kappa, limiter, ctl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int l = 1; l < H.nlev; ++l) {
       fld_coarsen_D<<<blocks_for(cells(H, l)), 256, 0, s>>>(lv[l - 1], lv[l], inv_children[l]);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (resid) {
-      fld_zero<<<(ncycles + 1 + 255) / 256, 256, 0, s>>>(resid, ncycles + 1);
-      fld_resid_sq<NDIM><<<blocks_for(N), 256, 0, s>>>(lv[0], cm, resid);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    if (resid && (e = resid_norm<NDIM>(resid)) != hipSuccess) return e;
     for (int c = 0; c < ncycles; ++c) {
       if ((e = vcycle<NDIM>(0)) != hipSuccess) return e;
-      if (resid) {
-        fld_resid_sq<NDIM><<<blocks_for(N), 256, 0, s>>>(lv[0], cm, resid + c + 1);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-      }
+      if (resid && (e = resid_norm<NDIM>(resid + c + 1)) != hipSuccess) return e;
     }
-    fld_store<<<blocks_for(N), 256, 0, s>>>(lv[0], E);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (resid) {
-      fld_sqrt<<<(ncycles + 1 + 255) / 256, 256, 0, s>>>(resid, ncycles + 1);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    fld_store<NDIM><<<fld_tiles<NDIM>(lv[0]), 256, 0, s>>>(lv[0], E);
+    return hipGetLastError();
   }
 };
 
@@ -521,8 +694,17 @@ hard_status_t hard_rad_diffuse(const hard_grid_t* g, void* U, const double* dt_d
   if ((st = check_work(work, work_bytes, fld_workspace(H)))) return st;
 
   char* wb = static_cast<char*>(work);
-  Solver S{G, H, {}, {}, {}, opts->nu1, opts->nu2, opts->ncoarse, (hipStream_t)stream};
-  size_t off = 256;
+  Solver S{G, H, {}, {}, {}, opts->nu1, opts->nu2, opts->ncoarse, 0, nullptr, (hipStream_t)stream};
+  // the one-workgroup tail starts at the first level of at most
+  // FLD_TAIL_CELLS cells, if the levels from there fit its table
+  S.tail = H.nlev;
+  for (int l = 0; l < H.nlev; ++l)
+    if (cells(H, l) <= (long long)FLD_TAIL_CELLS && H.nlev - l <= FLD_TAIL_LEVELS) {
+      S.tail = l;
+      break;
+    }
+  S.part = reinterpret_cast<double*>(wb + 256);
+  size_t off = 256 + align256(resid_slots(H) * sizeof(double));
   for (int l = 0; l < H.nlev; ++l) {
     FldLevel& L = S.lv[l];
     const size_t bytes = align256(split_elems(H, l) * sizeof(double));
@@ -532,8 +714,8 @@ hard_status_t hard_rad_diffuse(const hard_grid_t* g, void* U, const double* dt_d
       L.dx[d] = H.dx[l][d];
       L.dx2[d] = H.dx[l][d] * H.dx[l][d];
     }
-    L.hx = (H.n[l][0] + 1) / 2;
-    L.cs = (long long)H.n[l][1] * H.n[l][2] * L.hx;
+    L.hx = (unsigned)((H.n[l][0] + 1) / 2);
+    L.cs = (unsigned)H.n[l][1] * (unsigned)H.n[l][2] * L.hx;
     L.x = reinterpret_cast<double*>(wb + off);
     L.b = reinterpret_cast<double*>(wb + off + bytes);
     L.D = reinterpret_cast<double*>(wb + off + 2 * bytes);
