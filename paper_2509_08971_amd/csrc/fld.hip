@@ -69,6 +69,7 @@ struct FldLevel {
   unsigned cs;     // elements per colour: n[1] n[2] hx
   double dx[3];    // cell width
   double dx2[3];   // dx_d * dx_d
+  const double* K; // device: K_d = (dt/2) / dx_d^2 of this level (3 doubles)
   double* x;
   double* b;
   double* D;
@@ -109,61 +110,119 @@ __device__ __forceinline__ unsigned fld_cells(const FldLevel& L) {
   return (unsigned)L.n[0] * (unsigned)L.n[1] * (unsigned)L.n[2];
 }
 
-// (A x) at cell p = (i, j, k) of level L
+// The 2 NDIM face neighbours of cell (i, j, k) (row = k n1 + j), all of the
+// other colour: their colour-split indices, read straight from the layout
+// (x: slot (i -+ 1)/2 of the same row; y, z: slot i/2 of the rows +-1 and
+// +-n1), and whether each face is open.  A closed face (wall, or a periodic
+// axis of one cell) still gets an in-range index, so every load is
+// unconditional and a cell's loads are all in flight together; the
+// coefficient of a closed face is zeroed by a select.
 template <int NDIM>
-__device__ __forceinline__ double fld_apply_row(const FldLevel& L, const FldCommon& cm, double dt,
+__device__ __forceinline__ void fld_faces(const FldLevel& L, const FldCommon& cm, int i, int j,
+                                          int k, unsigned row, unsigned* nb, bool* open) {
+  const unsigned hx = L.hx;
+  const unsigned ob = (((i + j + k) & 1) ? 0u : L.cs) + row * hx;  // other colour, this row
+  const unsigned o = ob + ((unsigned)i >> 1);
+  const int nx = L.n[0];
+  {
+    const bool lo = i > 0, hi = i < nx - 1, wrap = cm.per[0] && nx > 1;
+    nb[0] = ob + (lo ? (unsigned)(i - 1) >> 1 : (unsigned)(nx - 1) >> 1);
+    nb[1] = ob + (hi ? (unsigned)(i + 1) >> 1 : 0u);
+    open[0] = lo || wrap;
+    open[1] = hi || wrap;
+  }
+  if (NDIM > 1) {
+    const int ny = L.n[1];
+    const bool lo = j > 0, hi = j < ny - 1, wrap = cm.per[1] && ny > 1;
+    const unsigned span = (unsigned)(ny - 1) * hx;
+    nb[2] = lo ? o - hx : o + span;
+    nb[3] = hi ? o + hx : o - span;
+    open[2] = lo || wrap;
+    open[3] = hi || wrap;
+  }
+  if (NDIM > 2) {
+    const int nz = L.n[2];
+    const unsigned ps = (unsigned)L.n[1] * hx;
+    const bool lo = k > 0, hi = k < nz - 1, wrap = cm.per[2] && nz > 1;
+    const unsigned span = (unsigned)(nz - 1) * ps;
+    nb[4] = lo ? o - ps : o + span;
+    nb[5] = hi ? o + ps : o - span;
+    open[4] = lo || wrap;
+    open[5] = hi || wrap;
+  }
+}
+
+// (A x) at cell p = (i, j, k) of level L: x_c + sum over open faces, in the
+// order x low, x high, y low, ..., of a_f (x_c - x_nb), a_f = (D_c + D_nb) K_d.
+// A closed face adds exactly zero.
+template <int NDIM>
+__device__ __forceinline__ double fld_apply_row(const FldLevel& L, const FldCommon& cm,
                                                 const int* p) {
 #pragma clang fp contract(off)
-  const unsigned c = fld_at(L, p[0], p[1], p[2]);
+  constexpr int NF = 2 * NDIM;
+  const unsigned row = (unsigned)p[2] * (unsigned)L.n[1] + (unsigned)p[1];
+  const unsigned c = (((p[0] + p[1] + p[2]) & 1) ? L.cs : 0u) + row * L.hx + ((unsigned)p[0] >> 1);
+  unsigned nb[NF];
+  bool open[NF];
+  fld_faces<NDIM>(L, cm, p[0], p[1], p[2], row, nb, open);
   const double xc = L.x[c], Dc = L.D[c];
+  double Dn[NF], xn[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    Dn[f] = L.D[nb[f]];
+    xn[f] = L.x[nb[f]];
+  }
   double Ax = xc;
 #pragma unroll
-  for (int d = 0; d < NDIM; ++d)
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int q = fld_nb(p[d], L.n[d], s, cm.per[d]);
-      if (q < 0) continue;
-      int o[3] = {p[0], p[1], p[2]};
-      o[d] = q;
-      const unsigned nb = fld_at(L, o[0], o[1], o[2]);
-      const double Dface = 0.5 * (Dc + L.D[nb]);
-      const double a = dt * Dface / L.dx2[d];
-      Ax += a * (xc - L.x[nb]);
-    }
+  for (int f = 0; f < NF; ++f) {
+    const double a = open[f] ? (Dc + Dn[f]) * L.K[f >> 1] : 0.0;
+    Ax += a * (open[f] ? xc - xn[f] : 0.0);
+  }
   return Ax;
 }
 
-// Gauss-Seidel update of the cell at slot t of colour `colour`:
-// x_c = (b_c + sum_faces a_f x_nb) / (1 + sum_faces a_f)
+// Gauss-Seidel update of cell (i, j, k) of colour `colour` (row = k n1 + j,
+// slot h = i / 2): x_c = (b_c + sum_faces a_f x_nb) / (1 + sum_faces a_f),
+// open faces in the order x low, x high, y low, ...; a closed face adds
+// exactly zero.
 template <int NDIM>
-__device__ __forceinline__ void fld_relax_slot(const FldLevel& L, const FldCommon& cm, double dt,
-                                               int colour, unsigned t) {
+__device__ __forceinline__ void fld_relax_cell(const FldLevel& L, const FldCommon& cm, int colour,
+                                               int i, int j, int k, unsigned row) {
 #pragma clang fp contract(off)
+  constexpr int NF = 2 * NDIM;
+  const unsigned c = (colour ? L.cs : 0u) + row * L.hx + ((unsigned)i >> 1);
+  unsigned nb[NF];
+  bool open[NF];
+  fld_faces<NDIM>(L, cm, i, j, k, row, nb, open);
+  const double Dc = L.D[c];
+  const double bc = L.b[c];
+  double Dn[NF], xn[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    Dn[f] = L.D[nb[f]];
+    xn[f] = L.x[nb[f]];
+  }
+  double num = bc;
+  double den = 1.0;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const double a = open[f] ? (Dc + Dn[f]) * L.K[f >> 1] : 0.0;
+    num += a * (open[f] ? xn[f] : 0.0);
+    den += a;
+  }
+  L.x[c] = num / den;
+}
+
+// The cell at slot t of colour `colour` (t = row hx + h).
+template <int NDIM>
+__device__ __forceinline__ void fld_relax_slot(const FldLevel& L, const FldCommon& cm, int colour,
+                                               unsigned t) {
   const unsigned h = t % L.hx;
   const unsigned row = t / L.hx;
   const int j = (int)(row % (unsigned)L.n[1]), k = (int)(row / (unsigned)L.n[1]);
   const int i = 2 * (int)h + ((j + k + colour) & 1);
   if (i >= L.n[0]) return;
-  const int p[3] = {i, j, k};
-  const unsigned c = (colour ? L.cs : 0u) + t;
-  const double Dc = L.D[c];
-  double num = L.b[c];
-  double den = 1.0;
-#pragma unroll
-  for (int d = 0; d < NDIM; ++d)
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int q = fld_nb(p[d], L.n[d], s, cm.per[d]);
-      if (q < 0) continue;
-      int o[3] = {i, j, k};
-      o[d] = q;
-      const unsigned nb = fld_at(L, o[0], o[1], o[2]);
-      const double Dface = 0.5 * (Dc + L.D[nb]);
-      const double a = dt * Dface / L.dx2[d];
-      num += a * L.x[nb];
-      den += a;
-    }
-  L.x[c] = num / den;
+  fld_relax_cell<NDIM>(L, cm, colour, i, j, k, row);
 }
 
 // Children of a coarse cell: along a halved axis 2I and 2I+1, else I.
@@ -178,8 +237,7 @@ __device__ __forceinline__ void fld_children(const FldLevel& C, const int* P, in
 // Coarse cell P: b = mean over the children of the fine residual, x = 0.
 template <int NDIM>
 __device__ __forceinline__ void fld_restrict_cell(const FldLevel& F, const FldLevel& C,
-                                                  const FldCommon& cm, double dt, double inv,
-                                                  const int* P) {
+                                                  const FldCommon& cm, double inv, const int* P) {
 #pragma clang fp contract(off)
   int lo[3], cnt[3];
   fld_children(C, P, lo, cnt);
@@ -188,7 +246,7 @@ __device__ __forceinline__ void fld_restrict_cell(const FldLevel& F, const FldLe
     for (int dy = 0; dy < cnt[1]; ++dy)
       for (int dx = 0; dx < cnt[0]; ++dx) {
         const int p[3] = {lo[0] + dx, lo[1] + dy, lo[2] + dz};
-        const double r = F.b[fld_at(F, p[0], p[1], p[2])] - fld_apply_row<NDIM>(F, cm, dt, p);
+        const double r = F.b[fld_at(F, p[0], p[1], p[2])] - fld_apply_row<NDIM>(F, cm, p);
         s += r;
       }
   const unsigned cc = fld_at(C, P[0], P[1], P[2]);
@@ -229,6 +287,37 @@ __device__ __forceinline__ void fld_prolong_cell(const FldLevel& F, const FldLev
         v += w * xc;
       }
   F.x[fld_at(F, f[0], f[1], f[2])] += v;
+}
+
+// fld_prolong_cell when every active axis is halved: the 2^NDIM coarse
+// values are loaded together, then summed in the same order and with the
+// same weights.
+template <int NDIM>
+__device__ __forceinline__ void fld_prolong_cell_all(const FldLevel& F, const FldLevel& C,
+                                                     const FldCommon& cm, const int* f) {
+#pragma clang fp contract(off)
+  constexpr int NC = 1 << NDIM;
+  int nr[3] = {0, 0, 0}, fr[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) {
+    const int I = f[d] >> 1;
+    const int q = fld_nb(I, C.n[d], f[d] & 1, cm.per[d]);
+    nr[d] = I;
+    fr[d] = q < 0 ? I : q;
+  }
+  double xc[NC];
+#pragma unroll
+  for (int m = 0; m < NC; ++m)
+    xc[m] = C.x[fld_at(C, (m & 1) ? fr[0] : nr[0], (m & 2) ? fr[1] : nr[1], (m & 4) ? fr[2] : nr[2])];
+  double v = 0.0;
+#pragma unroll
+  for (int m = 0; m < NC; ++m) {
+    const double w = ((m & 1) ? 0.25 : 0.75) * (NDIM > 1 ? ((m & 2) ? 0.25 : 0.75) : 1.0) *
+                     (NDIM > 2 ? ((m & 4) ? 0.25 : 0.75) : 1.0);
+    v += w * xc[m];
+  }
+  const unsigned c = fld_at(F, f[0], f[1], f[2]);
+  F.x[c] += v;
 }
 
 // Block tile of the natural-order kernels: 256 cells, TX x TY x TZ.
@@ -322,12 +411,22 @@ __global__ __launch_bounds__(256) void fld_coarsen_D(FldLevel F, FldLevel C, dou
   C.D[fld_at(C, P[0], P[1], P[2])] = s * inv;
 }
 
-// One red-black half-sweep of level L: every cell of colour `colour`.
+// One red-black half-sweep of level L: every cell of colour `colour`.  A
+// workgroup takes 64 consecutive slots of 4 rows (one row per wave), tiles
+// dealt XCD-contiguously.
 template <int NDIM>
 __global__ __launch_bounds__(256) void fld_relax(FldLevel L, FldCommon cm, int colour) {
-  const unsigned t = (unsigned)xcd_tile(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
-  if (t >= L.cs) return;
-  fld_relax_slot<NDIM>(L, cm, *cm.dt, colour, t);
+  const unsigned tiles_h = (L.hx + 63) / 64;
+  const unsigned b = (unsigned)xcd_tile(blockIdx.x, gridDim.x);
+  const unsigned rg = b / tiles_h;
+  const unsigned h = (b - rg * tiles_h) * 64 + (threadIdx.x & 63);
+  const unsigned row = rg * 4 + (threadIdx.x >> 6);
+  const unsigned rows = (unsigned)L.n[1] * (unsigned)L.n[2];
+  if (h >= L.hx || row >= rows) return;
+  const int j = (int)(row % (unsigned)L.n[1]), k = (int)(row / (unsigned)L.n[1]);
+  const int i = 2 * (int)h + ((j + k + colour) & 1);
+  if (i >= L.n[0]) return;
+  fld_relax_cell<NDIM>(L, cm, colour, i, j, k, row);
 }
 
 // Restriction, one thread per coarse cell (any halving pattern).
@@ -338,7 +437,7 @@ __global__ __launch_bounds__(256) void fld_restrict(FldLevel F, FldLevel C, FldC
   if (c >= fld_cells(C)) return;
   int P[3];
   fld_cell(C, c, P);
-  fld_restrict_cell<NDIM>(F, C, cm, *cm.dt, inv, P);
+  fld_restrict_cell<NDIM>(F, C, cm, inv, P);
 }
 
 // Restriction when every active axis is halved: one thread per fine cell of
@@ -352,9 +451,8 @@ __global__ __launch_bounds__(256) void fld_restrict_tile(FldLevel F, FldLevel C,
   __shared__ double r[256];
   int p[3];
   const bool in = fld_tile_cell<NDIM>(F, p);
-  const double dt = *cm.dt;
   double rv = 0.0;
-  if (in) rv = F.b[fld_at(F, p[0], p[1], p[2])] - fld_apply_row<NDIM>(F, cm, dt, p);
+  if (in) rv = F.b[fld_at(F, p[0], p[1], p[2])] - fld_apply_row<NDIM>(F, cm, p);
   r[threadIdx.x] = rv;
   __syncthreads();
   constexpr int CX = T::TX / 2, CY = NDIM > 1 ? T::TY / 2 : 1, CZ = NDIM > 2 ? T::TZ / 2 : 1;
@@ -382,6 +480,13 @@ __global__ __launch_bounds__(256) void fld_prolong(FldLevel F, FldLevel C, FldCo
   fld_prolong_cell(F, C, cm, f);
 }
 
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_prolong_all(FldLevel F, FldLevel C, FldCommon cm) {
+  int f[3];
+  if (!fld_tile_cell<NDIM>(F, f)) return;
+  fld_prolong_cell_all<NDIM>(F, C, cm, f);
+}
+
 // Residual norm, two deterministic passes: per-tile sums of r^2 in a fixed
 // order, then one workgroup adds the tile sums in a fixed order.
 template <int NDIM>
@@ -391,7 +496,7 @@ __global__ __launch_bounds__(256) void fld_resid_sq(FldLevel L, FldCommon cm, do
   int p[3];
   double r2 = 0.0;
   if (fld_tile_cell<NDIM>(L, p)) {
-    const double r = L.b[fld_at(L, p[0], p[1], p[2])] - fld_apply_row<NDIM>(L, cm, *cm.dt, p);
+    const double r = L.b[fld_at(L, p[0], p[1], p[2])] - fld_apply_row<NDIM>(L, cm, p);
     r2 = r * r;
   }
 #pragma unroll
@@ -399,6 +504,16 @@ __global__ __launch_bounds__(256) void fld_resid_sq(FldLevel L, FldCommon cm, do
   if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = r2;
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = (w[0] + w[1]) + (w[2] + w[3]);
+}
+
+// K_d = (dt/2) / dx_d^2 of every level (dx2 from the host, dt on the device).
+struct FldDx2 {
+  double v[FLD_MAX_LEVELS][3];
+};
+__global__ void fld_coeffs(FldDx2 dx2, int nlev, const double* dt, double* K) {
+#pragma clang fp contract(off)
+  const int t = threadIdx.x;
+  if (t < 3 * nlev) K[t] = (0.5 * *dt) / dx2.v[t / 3][t % 3];
 }
 
 __global__ __launch_bounds__(1024) void fld_resid_final(const double* part, unsigned n, double* out) {
@@ -432,29 +547,28 @@ struct FldTail {
 };
 
 template <int NDIM>
-__device__ void fld_tail_relax(const FldLevel& L, const FldCommon& cm, double dt, int sweeps) {
+__device__ void fld_tail_relax(const FldLevel& L, const FldCommon& cm, int sweeps) {
   for (int sw = 0; sw < sweeps; ++sw)
     for (int colour = 0; colour < 2; ++colour) {
-      for (unsigned t = threadIdx.x; t < L.cs; t += 1024) fld_relax_slot<NDIM>(L, cm, dt, colour, t);
+      for (unsigned t = threadIdx.x; t < L.cs; t += 1024) fld_relax_slot<NDIM>(L, cm, colour, t);
       __syncthreads();
     }
 }
 
 template <int NDIM>
 __global__ __launch_bounds__(1024) void fld_vcycle_tail(FldTail T, FldCommon cm) {
-  const double dt = *cm.dt;
   const int last = T.nlev - 1;
   for (int l = 0; l < last; ++l) {
-    fld_tail_relax<NDIM>(T.lv[l], cm, dt, T.nu1);
+    fld_tail_relax<NDIM>(T.lv[l], cm, T.nu1);
     const FldLevel& C = T.lv[l + 1];
     for (unsigned c = threadIdx.x; c < fld_cells(C); c += 1024) {
       int P[3];
       fld_cell(C, c, P);
-      fld_restrict_cell<NDIM>(T.lv[l], C, cm, dt, T.inv[l + 1], P);
+      fld_restrict_cell<NDIM>(T.lv[l], C, cm, T.inv[l + 1], P);
     }
     __syncthreads();
   }
-  fld_tail_relax<NDIM>(T.lv[last], cm, dt, T.ncoarse);
+  fld_tail_relax<NDIM>(T.lv[last], cm, T.ncoarse);
   for (int l = last - 1; l >= 0; --l) {
     const FldLevel& F = T.lv[l];
     for (unsigned c = threadIdx.x; c < fld_cells(F); c += 1024) {
@@ -463,7 +577,7 @@ __global__ __launch_bounds__(1024) void fld_vcycle_tail(FldTail T, FldCommon cm)
       fld_prolong_cell(F, T.lv[l + 1], cm, f);
     }
     __syncthreads();
-    fld_tail_relax<NDIM>(F, cm, dt, T.nu2);
+    fld_tail_relax<NDIM>(F, cm, T.nu2);
   }
 }
 
@@ -526,10 +640,13 @@ size_t resid_slots(const Hierarchy& H) {
   return (size_t)std::max(t3, std::max(t2, t1));
 }
 
-// Workspace: control block | residual tile sums | per level: x, b, D
-// (colour-split)
+// Workspace: control block | K of every level | residual tile sums | per
+// level: x, b, D (colour-split)
+constexpr size_t FLD_K_BYTES = 1024;  // FLD_MAX_LEVELS x 3 doubles, rounded up
+static_assert(FLD_MAX_LEVELS * 3 * sizeof(double) <= FLD_K_BYTES, "K slots");
+
 size_t fld_workspace(const Hierarchy& H) {
-  size_t total = 256 + align256(resid_slots(H) * sizeof(double));
+  size_t total = 256 + FLD_K_BYTES + align256(resid_slots(H) * sizeof(double));
   for (int l = 0; l < H.nlev; ++l) total += 3 * align256(split_elems(H, l) * sizeof(double));
   return total;
 }
@@ -559,6 +676,7 @@ struct Solver {
   int nu1, nu2, ncoarse;
   int tail;         // first level solved by the one-workgroup kernel
   double* part;     // residual tile sums
+  double* Kbuf;     // K_d of every level
   hipStream_t s;
 
   bool all_halved(int l) const {  // every active axis halved from level l - 1
@@ -570,9 +688,10 @@ struct Solver {
   template <int NDIM>
   hipError_t relax(int l, int sweeps) {
     const FldLevel& L = lv[l];
+    const unsigned tiles = ((L.hx + 63) / 64) * (((unsigned)L.n[1] * L.n[2] + 3) / 4);
     for (int sw = 0; sw < sweeps; ++sw)
       for (int colour = 0; colour < 2; ++colour) {
-        fld_relax<NDIM><<<blocks_for(L.cs), 256, 0, s>>>(L, cm, colour);
+        fld_relax<NDIM><<<tiles, 256, 0, s>>>(L, cm, colour);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
       }
@@ -607,7 +726,10 @@ struct Solver {
                                                                      inv_children[l + 1]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = vcycle<NDIM>(l + 1)) != hipSuccess) return e;
-    fld_prolong<NDIM><<<fld_tiles<NDIM>(lv[l]), 256, 0, s>>>(lv[l], lv[l + 1], cm);
+    if (all_halved(l + 1))
+      fld_prolong_all<NDIM><<<fld_tiles<NDIM>(lv[l]), 256, 0, s>>>(lv[l], lv[l + 1], cm);
+    else
+      fld_prolong<NDIM><<<fld_tiles<NDIM>(lv[l]), 256, 0, s>>>(lv[l], lv[l + 1], cm);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return relax<NDIM>(l, nu2);
   }
@@ -627,6 +749,11 @@ struct Solver {
     const double* rho = U;
     double* E = U + (long long)(G.nvar - 1) * N;
     fld_setup<NDIM><<<fld_tiles<NDIM>(lv[0]), 256, 0, s>>>(lv[0], cm, rho, E, G.kappa, limiter, ctl);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    FldDx2 dx2;
+    for (int l = 0; l < H.nlev; ++l)
+      for (int d = 0; d < 3; ++d) dx2.v[l][d] = lv[l].dx2[d];
+    fld_coeffs<<<1, 3 * FLD_MAX_LEVELS, 0, s>>>(dx2, H.nlev, cm.dt, Kbuf);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int l = 1; l < H.nlev; ++l) {
       fld_coarsen_D<<<blocks_for(cells(H, l)), 256, 0, s>>>(lv[l - 1], lv[l], inv_children[l]);
@@ -694,7 +821,8 @@ hard_status_t hard_rad_diffuse(const hard_grid_t* g, void* U, const double* dt_d
   if ((st = check_work(work, work_bytes, fld_workspace(H)))) return st;
 
   char* wb = static_cast<char*>(work);
-  Solver S{G, H, {}, {}, {}, opts->nu1, opts->nu2, opts->ncoarse, 0, nullptr, (hipStream_t)stream};
+  Solver S{G, H, {}, {}, {}, opts->nu1, opts->nu2, opts->ncoarse, 0, nullptr, nullptr,
+           (hipStream_t)stream};
   // the one-workgroup tail starts at the first level of at most
   // FLD_TAIL_CELLS cells, if the levels from there fit its table
   S.tail = H.nlev;
@@ -703,8 +831,9 @@ hard_status_t hard_rad_diffuse(const hard_grid_t* g, void* U, const double* dt_d
       S.tail = l;
       break;
     }
-  S.part = reinterpret_cast<double*>(wb + 256);
-  size_t off = 256 + align256(resid_slots(H) * sizeof(double));
+  S.Kbuf = reinterpret_cast<double*>(wb + 256);
+  S.part = reinterpret_cast<double*>(wb + 256 + FLD_K_BYTES);
+  size_t off = 256 + FLD_K_BYTES + align256(resid_slots(H) * sizeof(double));
   for (int l = 0; l < H.nlev; ++l) {
     FldLevel& L = S.lv[l];
     const size_t bytes = align256(split_elems(H, l) * sizeof(double));
@@ -714,6 +843,7 @@ hard_status_t hard_rad_diffuse(const hard_grid_t* g, void* U, const double* dt_d
       L.dx[d] = H.dx[l][d];
       L.dx2[d] = H.dx[l][d] * H.dx[l][d];
     }
+    L.K = S.Kbuf + 3 * l;
     L.hx = (unsigned)((H.n[l][0] + 1) / 2);
     L.cs = (unsigned)H.n[l][1] * (unsigned)H.n[l][2] * L.hx;
     L.x = reinterpret_cast<double*>(wb + off);
