@@ -532,19 +532,33 @@ __global__ __launch_bounds__(1024) void fld_resid_final(const double* part, unsi
   }
 }
 
-// The V-cycle below a level small enough for one workgroup: every phase
-// (half-sweep, restriction, prolongation) is a loop of the workgroup over the
-// level's cells, separated by barriers; the arrays stay in cache.  Same
-// per-cell arithmetic as the multi-workgroup kernels.
+// The V-cycle below a level small enough for one workgroup: the arrays of
+// those levels are copied into LDS (x, b and D of the first one, D of the
+// rest; the coarse x and b are written by the restriction before they are
+// read), every phase (half-sweep, restriction, prolongation) is a loop of
+// the workgroup over the level's cells separated by barriers, and x of the
+// first level is copied back at the end.  Same per-cell arithmetic as the
+// multi-workgroup kernels; LDS latency instead of L2 latency for the ~50
+// short phases of a cycle.
 constexpr int FLD_TAIL_LEVELS = 16;
-constexpr unsigned FLD_TAIL_CELLS = 4096;
 
 struct FldTail {
-  FldLevel lv[FLD_TAIL_LEVELS];
-  double inv[FLD_TAIL_LEVELS];  // 1 / children of level l (from level l - 1)
+  FldLevel lv[FLD_TAIL_LEVELS];       // global arrays
+  double inv[FLD_TAIL_LEVELS];        // 1 / children of level m (from level m - 1)
+  unsigned lds_off[FLD_TAIL_LEVELS];  // element offset of level m's arrays in LDS
   int nlev;
   int nu1, nu2, ncoarse;
 };
+
+// Level m of the tail with x, b, D in LDS (each 2 cs elements, in that order).
+__device__ __forceinline__ FldLevel fld_lds_level(const FldTail& T, int m, double* lds) {
+  FldLevel L = T.lv[m];
+  const unsigned e = 2u * L.cs;
+  L.x = lds + T.lds_off[m];
+  L.b = L.x + e;
+  L.D = L.b + e;
+  return L;
+}
 
 template <int NDIM>
 __device__ void fld_tail_relax(const FldLevel& L, const FldCommon& cm, int sweeps) {
@@ -557,28 +571,47 @@ __device__ void fld_tail_relax(const FldLevel& L, const FldCommon& cm, int sweep
 
 template <int NDIM>
 __global__ __launch_bounds__(1024) void fld_vcycle_tail(FldTail T, FldCommon cm) {
+  extern __shared__ double lds[];
+  for (int m = 0; m < T.nlev; ++m) {
+    const FldLevel& G = T.lv[m];
+    const FldLevel L = fld_lds_level(T, m, lds);
+    const unsigned e = 2u * G.cs;
+    for (unsigned t = threadIdx.x; t < e; t += 1024) {
+      L.D[t] = G.D[t];
+      if (m == 0) {
+        L.x[t] = G.x[t];
+        L.b[t] = G.b[t];
+      }
+    }
+  }
+  __syncthreads();
   const int last = T.nlev - 1;
   for (int l = 0; l < last; ++l) {
-    fld_tail_relax<NDIM>(T.lv[l], cm, T.nu1);
-    const FldLevel& C = T.lv[l + 1];
+    const FldLevel F = fld_lds_level(T, l, lds);
+    fld_tail_relax<NDIM>(F, cm, T.nu1);
+    const FldLevel C = fld_lds_level(T, l + 1, lds);
     for (unsigned c = threadIdx.x; c < fld_cells(C); c += 1024) {
       int P[3];
       fld_cell(C, c, P);
-      fld_restrict_cell<NDIM>(T.lv[l], C, cm, T.inv[l + 1], P);
+      fld_restrict_cell<NDIM>(F, C, cm, T.inv[l + 1], P);
     }
     __syncthreads();
   }
-  fld_tail_relax<NDIM>(T.lv[last], cm, T.ncoarse);
+  fld_tail_relax<NDIM>(fld_lds_level(T, last, lds), cm, T.ncoarse);
   for (int l = last - 1; l >= 0; --l) {
-    const FldLevel& F = T.lv[l];
+    const FldLevel F = fld_lds_level(T, l, lds);
+    const FldLevel C = fld_lds_level(T, l + 1, lds);
     for (unsigned c = threadIdx.x; c < fld_cells(F); c += 1024) {
       int f[3];
       fld_cell(F, c, f);
-      fld_prolong_cell(F, T.lv[l + 1], cm, f);
+      fld_prolong_cell(F, C, cm, f);
     }
     __syncthreads();
     fld_tail_relax<NDIM>(F, cm, T.nu2);
   }
+  const FldLevel& G = T.lv[0];
+  const FldLevel L = fld_lds_level(T, 0, lds);
+  for (unsigned t = threadIdx.x; t < 2u * G.cs; t += 1024) G.x[t] = L.x[t];
 }
 
 // ---------------------------------------------------------------- host side
@@ -712,7 +745,16 @@ struct Solver {
       T.nu1 = nu1;
       T.nu2 = nu2;
       T.ncoarse = ncoarse;
-      fld_vcycle_tail<NDIM><<<1, 1024, 0, s>>>(T, cm);
+      unsigned off = 0;
+      for (int m = 0; m < T.nlev; ++m) {
+        T.lds_off[m] = off;
+        off += 6u * lv[l + m].cs;
+      }
+      const size_t bytes = (size_t)off * sizeof(double);
+      hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&fld_vcycle_tail<NDIM>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      if (e2 != hipSuccess) return e2;
+      fld_vcycle_tail<NDIM><<<1, 1024, bytes, s>>>(T, cm);
       return hipGetLastError();
     }
     if (l + 1 == H.nlev) return relax<NDIM>(l, ncoarse);  // coarsest level
@@ -823,14 +865,26 @@ hard_status_t hard_rad_diffuse(const hard_grid_t* g, void* U, const double* dt_d
   char* wb = static_cast<char*>(work);
   Solver S{G, H, {}, {}, {}, opts->nu1, opts->nu2, opts->ncoarse, 0, nullptr, nullptr,
            (hipStream_t)stream};
-  // the one-workgroup tail starts at the first level of at most
-  // FLD_TAIL_CELLS cells, if the levels from there fit its table
+  // the one-workgroup tail starts at the first level from which all the
+  // coarser levels' arrays (x, b, D: 48 bytes per colour slot) fit in the
+  // workgroup's LDS and in the tail's table
+  int dev = 0, lds_max = 0;
+  hipError_t he;
+  if ((he = hipGetDevice(&dev)) != hipSuccess ||
+      (he = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) !=
+          hipSuccess)
+    return hip_fail(he, "hard_rad_diffuse: device LDS size");
   S.tail = H.nlev;
-  for (int l = 0; l < H.nlev; ++l)
-    if (cells(H, l) <= (long long)FLD_TAIL_CELLS && H.nlev - l <= FLD_TAIL_LEVELS) {
+  for (int l = 0; l < H.nlev; ++l) {
+    long long need = 0;
+    for (int m = l; m < H.nlev; ++m) need += 48LL * (split_elems(H, m) / 2);
+    if (need <= (long long)lds_max && H.nlev - l <= FLD_TAIL_LEVELS) {
       S.tail = l;
       break;
     }
+  }
+  // (no level fits: every level, the coarsest included, runs in the
+  // multi-workgroup kernels)
   S.Kbuf = reinterpret_cast<double*>(wb + 256);
   S.part = reinterpret_cast<double*>(wb + 256 + FLD_K_BYTES);
   size_t off = 256 + FLD_K_BYTES + align256(resid_slots(H) * sizeof(double));

@@ -8,7 +8,7 @@
 //               c_R) taken from the hydro face states.  The hydro fields of
 //               the same stage are updated by the fused stage kernel; E_r
 //               does not act on them, so the two kernels are independent.
-//   rad_source  after stage 2, one thread per cell: the exchange between
+//   rad_source  after stage 2, grid-stride over the cells: the exchange between
 //               fluid internal energy and radiation by the heating rate
 //               qdot = c kappa rho (E_r - a T^4) (equation "heating-cooling"),
 //               backward Euler solved for the new temperature by Newton
@@ -118,6 +118,188 @@ __global__ __launch_bounds__(256) void rad_advect(RadArgs a) {
   if ((threadIdx.x & 63) == 0 && flags) atomicOr(&a.ctl->flags, flags);
 }
 
+// The E_r part of a Heun stage on a 3D grid, as a walk: a workgroup takes a
+// 32 x 8 tile of cells in x-y and walks it along z over a chunk of planes.
+// For each plane the primitives (rho, u_x, u_y, p, E_r) of the tile and its
+// two-cell halo in x and y (ghosts by index remap, the normal velocity
+// negated beyond a reflecting wall) go to LDS once, and every cell's x and y
+// faces read them from there; the z faces come from a window of five planes
+// of (rho, u_z, p, E_r) that each thread keeps for its own column.  Each
+// primitive is thus recovered about twice per plane instead of fifteen times
+// per cell.  Face states, fluxes and the stage combine are those of
+// rad_advect, term for term and in the same order.
+constexpr int RW_TX = 32, RW_TY = 8, RW_CZ = 32;
+constexpr int RW_LX = RW_TX + 4, RW_LY = RW_TY + 4;
+
+// Primitives of cell q of src: rho, u_x, u_y, u_z, p, E_r; the momentum of
+// axis `flip_axis` (or none, -1) negated first.
+template <typename R>
+__device__ __forceinline__ void rad_prims(const R* src, long long N, long long q, double gamma,
+                                          int flip_axis, double* w) {
+#pragma clang fp contract(off)
+  const double r = (double)src[q];
+  double m[3];
+  double m2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    m[k] = (double)src[(1 + k) * N + q];
+    m2 = k == 0 ? m[k] * m[k] : m2 + m[k] * m[k];
+  }
+  const double ke = 0.5 * m2 / r;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) w[1 + k] = (k == flip_axis ? -m[k] : m[k]) / r;
+  w[0] = r;
+  w[4] = (gamma - 1.0) * ((double)src[4 * N + q] - ke);
+  w[5] = (double)src[5 * N + q];
+}
+
+// Rusanov flux of E_r at the face between cells 1 and 2 of four cells
+// (rho, u_n, p, E_r per cell), from MUSCL-minmod face states.
+__device__ __forceinline__ double rad_face(const double* rho, const double* un, const double* p,
+                                           const double* er, double gamma) {
+#pragma clang fp contract(off)
+  auto face = [](const double* w, double& wl, double& wr) {
+    const double sl = minmod_rule(w[1] - w[0], w[2] - w[1]);
+    const double sr = minmod_rule(w[2] - w[1], w[3] - w[2]);
+    wl = w[1] + 0.5 * sl;
+    wr = w[2] - 0.5 * sr;
+  };
+  double rL, rR, uL, uR, pL, pR, eL, eR;
+  face(rho, rL, rR);
+  face(un, uL, uR);
+  face(p, pL, pR);
+  face(er, eL, eR);
+  const double cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+  const double sL = fabs(uL) + cL, sR = fabs(uR) + cR;
+  const double sm = sL >= sR ? sL : sR;
+  return 0.5 * (eL * uL + eR * uR) - 0.5 * sm * (eR - eL);
+}
+
+template <typename R, int STAGE>
+__global__ __launch_bounds__(256) void rad_advect_walk(RadArgs a) {
+#pragma clang fp contract(off)
+  __shared__ double P[5][RW_LY][RW_LX];  // rho, u_x, u_y, p, E_r of one plane
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const long long N = (long long)nx * ny * nz;
+  const R* src = static_cast<const R*>(a.src);
+  const unsigned tx = (nx + RW_TX - 1) / RW_TX, ty = (ny + RW_TY - 1) / RW_TY;
+  const unsigned b = (unsigned)xcd_tile(blockIdx.x, gridDim.x);
+  const unsigned bx = b % tx, rest = b / tx;
+  const unsigned by = rest % ty, bz = rest / ty;
+  const int x0 = (int)bx * RW_TX, y0 = (int)by * RW_TY;
+  const int lx = threadIdx.x % RW_TX, ly = threadIdx.x / RW_TX;
+  const int i = x0 + lx, j = y0 + ly;
+  const bool own = i < nx && j < ny;
+  const int z0 = (int)bz * RW_CZ, z1 = min(nz, z0 + RW_CZ);
+  // z window of the own column: planes k-2 .. k+2
+  double wr_[5], wu[5], wp[5], we[5];
+  auto load_z = [&](int s, int kk) {
+    if (!own) return;
+    bool flip;
+    const int kq = remap(kk, nz, a.bc[2][0], a.bc[2][1], flip);
+    double w[6];
+    rad_prims<R>(src, N, ((long long)kq * ny + j) * nx + i, a.gamma, flip ? 2 : -1, w);
+    wr_[s] = w[0];
+    wu[s] = w[3];
+    wp[s] = w[4];
+    we[s] = w[5];
+  };
+#pragma unroll
+  for (int s = 0; s < 4; ++s) load_z(s, z0 - 2 + s);
+  unsigned flags = 0;
+  for (int k = z0; k < z1; ++k) {
+    load_z(4, k + 2);
+    // the plane's tile and halo (corners are not needed)
+    for (int t = threadIdx.x; t < RW_LX * RW_LY; t += 256) {
+      const int px = t % RW_LX, py = t / RW_LX;
+      const int gi = x0 - 2 + px, gj = y0 - 2 + py;
+      const bool xin = gi >= 0 && gi < nx, yin = gj >= 0 && gj < ny;
+      if (!xin && !yin) continue;
+      bool fx = false, fy = false;
+      const int qi = xin ? gi : remap(gi, nx, a.bc[0][0], a.bc[0][1], fx);
+      const int qj = yin ? gj : remap(gj, ny, a.bc[1][0], a.bc[1][1], fy);
+      double w[6];
+      rad_prims<R>(src, N, ((long long)k * ny + qj) * nx + qi, a.gamma, fx ? 0 : (fy ? 1 : -1), w);
+      P[0][py][px] = w[0];
+      P[1][py][px] = w[1];
+      P[2][py][px] = w[2];
+      P[3][py][px] = w[4];
+      P[4][py][px] = w[5];
+    }
+    __syncthreads();
+    if (own) {
+      double l = 0.0;
+      // x faces: cells i-2 .. i+2 of the LDS row
+      {
+        const int cx = lx + 2, cy = ly + 2;
+        double F[2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          double rho[4], un[4], p[4], er[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            rho[s] = P[0][cy][cx - 2 + f + s];
+            un[s] = P[1][cy][cx - 2 + f + s];
+            p[s] = P[3][cy][cx - 2 + f + s];
+            er[s] = P[4][cy][cx - 2 + f + s];
+          }
+          F[f] = rad_face(rho, un, p, er, a.gamma);
+        }
+        const double df = F[1] - F[0];
+        l = l - (a.dx_pow2 ? df * a.inv_dx[0] : df / a.dx[0]);
+      }
+      // y faces
+      {
+        const int cx = lx + 2, cy = ly + 2;
+        double F[2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          double rho[4], un[4], p[4], er[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            rho[s] = P[0][cy - 2 + f + s][cx];
+            un[s] = P[2][cy - 2 + f + s][cx];
+            p[s] = P[3][cy - 2 + f + s][cx];
+            er[s] = P[4][cy - 2 + f + s][cx];
+          }
+          F[f] = rad_face(rho, un, p, er, a.gamma);
+        }
+        const double df = F[1] - F[0];
+        l = l - (a.dx_pow2 ? df * a.inv_dx[1] : df / a.dx[1]);
+      }
+      // z faces from the window
+      {
+        const double F0 = rad_face(wr_, wu, wp, we, a.gamma);
+        const double F1 = rad_face(wr_ + 1, wu + 1, wp + 1, we + 1, a.gamma);
+        const double df = F1 - F0;
+        l = l - (a.dx_pow2 ? df * a.inv_dx[2] : df / a.dx[2]);
+      }
+      const long long c = ((long long)k * ny + j) * nx + i;
+      R* dst = static_cast<R*>(a.dst);
+      const R* un_ = static_cast<const R*>(a.un);
+      const R ec = src[5 * N + c];
+      const R dt = R(*a.dt);
+      R out;
+      if (STAGE == 1)
+        out = ec + dt * R(l);
+      else
+        out = R(0.5) * (un_[5 * N + c] + (ec + dt * R(l)));
+      dst[5 * N + c] = out;
+      if (!isfinite(out)) flags = FLAG_NONFINITE;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      wr_[s] = wr_[s + 1];
+      wu[s] = wu[s + 1];
+      wp[s] = wp[s + 1];
+      we[s] = we[s + 1];
+    }
+  }
+  flags = wave_or(flags);
+  if ((threadIdx.x & 63) == 0 && flags) atomicOr(&a.ctl->flags, flags);
+}
+
 // Backward-Euler exchange of one cell (see the file comment); returns the
 // new (E_fluid, E_r).  e + E_r is conserved; the kinetic energy is untouched.
 __device__ __forceinline__ void exchange(double rho, double ke, double& Ef, double& Er, double dt,
@@ -145,16 +327,21 @@ __device__ __forceinline__ void exchange(double rho, double ke, double& Ef, doub
   Er = W - e_new;
 }
 
+// Grid-stride over the cells with a bounded grid: the fused CFL step ends
+// with one pair of atomics per workgroup, and a few thousand workgroups keep
+// those from queueing on the control block.
+constexpr unsigned RAD_SOURCE_BLOCKS = 2048;
+
 template <typename R, int NDIM>
 __global__ __launch_bounds__(256) void rad_source(RadArgs a) {
 #pragma clang fp contract(off)
   constexpr int NH = NDIM + 2;
   const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   double smax = 0.0;
   unsigned flags = 0;
-  if (c < N) {
-    R* U = static_cast<R*>(a.dst);
+  R* U = static_cast<R*>(a.dst);
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+       c += (long long)gridDim.x * blockDim.x) {
     const double rho = (double)U[c];
     double m2 = 0.0;
 #pragma unroll
@@ -168,12 +355,12 @@ __global__ __launch_bounds__(256) void rad_source(RadArgs a) {
     exchange(rho, ke, Ef, Er, *a.dt, a.gamma, a.kappa, a.mu);
     if (Ef != Ef0) U[(NDIM + 1) * N + c] = R(Ef);
     if (Er != Er0) U[NH * N + c] = R(Er);
-    if (!isfinite(Er) || !isfinite(Ef)) flags = FLAG_NONFINITE;
+    if (!isfinite(Er) || !isfinite(Ef)) flags |= FLAG_NONFINITE;
     if (a.fuse_cfl) {
       double Ud[NH];
 #pragma unroll
       for (int v = 0; v < NH; ++v) Ud[v] = (double)U[v * N + c];
-      smax = signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma);
+      smax = fmax(smax, signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
     }
   }
   block_finish<256>(flags, smax, a.fuse_cfl != 0, a.ctl, a.cfl, a.next_dt);
@@ -187,7 +374,22 @@ static void rad_advect_t(const RadArgs& a, int stage, dim3 grid, hipStream_t s) 
     hipLaunchKernelGGL((rad_advect<R, NDIM, 2>), grid, dim3(256), 0, s, a);
 }
 
+template <typename R>
+static void rad_advect_walk_t(const RadArgs& a, int stage, hipStream_t s) {
+  const unsigned tiles = (unsigned)(((a.n[0] + RW_TX - 1) / RW_TX) * ((a.n[1] + RW_TY - 1) / RW_TY) *
+                                    ((a.n[2] + RW_CZ - 1) / RW_CZ));
+  if (stage == 1)
+    hipLaunchKernelGGL((rad_advect_walk<R, 1>), dim3(tiles), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((rad_advect_walk<R, 2>), dim3(tiles), dim3(256), 0, s, a);
+}
+
 hipError_t launch_rad_advect(int ndim, int dtype, const RadArgs& a, int stage, hipStream_t s) {
+  if (ndim == 3) {
+    if (dtype == 0) rad_advect_walk_t<double>(a, stage, s);
+    else rad_advect_walk_t<float>(a, stage, s);
+    return hipGetLastError();
+  }
   const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
   const dim3 grid((unsigned)((N + 255) / 256));
   if (dtype == 0) {
@@ -204,7 +406,8 @@ hipError_t launch_rad_advect(int ndim, int dtype, const RadArgs& a, int stage, h
 
 hipError_t launch_rad_source(int ndim, int dtype, const RadArgs& a, hipStream_t s) {
   const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
-  const dim3 grid((unsigned)((N + 255) / 256)), block(256);
+  const long long nb = (N + 255) / 256;
+  const dim3 grid((unsigned)(nb < RAD_SOURCE_BLOCKS ? nb : RAD_SOURCE_BLOCKS)), block(256);
   if (dtype == 0) {
     if (ndim == 1) hipLaunchKernelGGL((rad_source<double, 1>), grid, block, 0, s, a);
     else if (ndim == 2) hipLaunchKernelGGL((rad_source<double, 2>), grid, block, 0, s, a);

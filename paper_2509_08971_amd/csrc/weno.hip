@@ -9,7 +9,7 @@
 //   weno_face    one thread per face, one launch per axis: six W cells along
 //                the axis (ghosts by index remap), WENO5-Z left and right
 //                states, HLL flux into a per-axis face array;
-//   weno_update  one thread per cell: L(U) = -sum_d (F+ - F-)/dx_d in the order
+//   weno_update  grid-stride over the cells: L(U) = -sum_d (F+ - F-)/dx_d in the order
 //                x, y, z, the stage combine, and in stage 2 the fused CFL step.
 // Bytes per cell and stage: the fused MUSCL kernel moves 2-3 nvar words; this
 // pipeline about 6 + 4 ndim nvar words (W and the face arrays round-trip
@@ -228,10 +228,11 @@ __global__ __launch_bounds__(256) void weno_update(WenoArgs a) {
   constexpr int NV = NDIM + 2;
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const long long N = (long long)nx * ny * nz;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool fuse = STAGE == 2 && a.fuse_cfl;
   double smax = 0.0;
-  if (c < N) {
+  // grid-stride with a bounded grid: one pair of CFL atomics per workgroup
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+       c += (long long)gridDim.x * blockDim.x) {
     const int i = (int)(c % nx);
     const long long r = c / nx;
     const int j = (int)(r % ny), k = (int)(r / ny);
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(256) void weno_update(WenoArgs a) {
       double Ud[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) Ud[v] = (double)Out[v];
-      smax = signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma);
+      smax = fmax(smax, signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
     }
   }
   block_finish<256>(0u, smax, fuse, a.ctl, a.cfl, a.next_dt);
@@ -286,10 +287,11 @@ static hipError_t weno_stage_t(const WenoArgs& a, int stage, hipStream_t s) {
   hipLaunchKernelGGL((weno_face<R, NDIM, 0>), dim3(faces(0)), dim3(256), 0, s, a);
   if constexpr (NDIM >= 2) hipLaunchKernelGGL((weno_face<R, NDIM, 1>), dim3(faces(1)), dim3(256), 0, s, a);
   if constexpr (NDIM >= 3) hipLaunchKernelGGL((weno_face<R, NDIM, 2>), dim3(faces(2)), dim3(256), 0, s, a);
+  const unsigned nbu = nb < 2048u ? nb : 2048u;
   if (stage == 1)
-    hipLaunchKernelGGL((weno_update<R, NDIM, 1>), dim3(nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((weno_update<R, NDIM, 1>), dim3(nbu), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((weno_update<R, NDIM, 2>), dim3(nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((weno_update<R, NDIM, 2>), dim3(nbu), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
