@@ -215,7 +215,10 @@ def bench_weno(args, n=256, steps=10):
             "dtype": "f64", "workload": f"3D {n}^3 FP64 point-energy blast, reflecting, CFL 0.4, "
                                          f"WENO5-Z + HLL (the paper's scheme) + SSP-RK2",
             "pipeline_bytes_per_zone_update": pipe_bytes,
-            "achieved_hbm_gbs_pipeline": pipe_bytes * zus / 1e9, "status_flags": flags}
+            "roofline": {"bound": "hbm", "kernel": "whole WENO5-Z + HLL step (pipeline bytes)",
+                         "achieved": pipe_bytes * zus / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": pipe_bytes * zus / 1e9 / 8000.0, "traffic": None},
+            "status_flags": flags}
 
 
 def bench_rad(args, n=256, steps=20):
@@ -242,10 +245,20 @@ def bench_rad(args, n=256, steps=20):
     flags = H.hard_status_read(work)
     N = n ** 3
     zus = N * steps / (ms * 1e-3)
+    # algorithmic bytes per zone-update: hydro stage 1 (read U^n, write U^1:
+    # 2 x 5 words) and stage 2 (read U^1, U^n, write: 3 x 5); E_r advection
+    # stage 1 (read 6 fields, write E_r) and stage 2 (also read E_r of U^n);
+    # exchange + next dt (read 6 fields, write E and E_r)
+    step_bytes = 8 * ((10 + 15) + (6 + 1) + (6 + 2) + (6 + 2))
     log(f"  {ms / steps:.3f} ms/step, {zus / 1e9:.2f} G zu/s")
     return {"value": zus, "unit": "zone-updates/s", "ms_per_step": ms / steps, "steps": steps,
             "dtype": "f64", "workload": f"3D {n}^3 FP64 point-energy blast with the radiation "
                                          f"energy density (E_r = 1, kappa = 1e-9, mu = 0.6)",
+            "step_bytes_per_zone_update": step_bytes,
+            "roofline": {"bound": "hbm", "kernel": "whole radiation step (stage kernels, E_r "
+                                                  "advection, exchange)",
+                         "achieved": step_bytes * zus / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": step_bytes * zus / 1e9 / 8000.0, "traffic": None},
             "status_flags": flags}
 
 

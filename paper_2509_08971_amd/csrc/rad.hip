@@ -122,11 +122,12 @@ __global__ __launch_bounds__(256) void rad_advect(RadArgs a) {
 // 32 x 8 tile of cells in x-y and walks it along z over a chunk of planes.
 // For each plane the primitives (rho, u_x, u_y, p, E_r) of the tile and its
 // two-cell halo in x and y (ghosts by index remap, the normal velocity
-// negated beyond a reflecting wall) go to LDS once, and every cell's x and y
-// faces read them from there; the z faces come from a window of five planes
-// of (rho, u_z, p, E_r) that each thread keeps for its own column.  Each
-// primitive is thus recovered about twice per plane instead of fifteen times
-// per cell.  Face states, fluxes and the stage combine are those of
+// negated beyond a reflecting wall) go to LDS once, every x and y face of the
+// plane is computed once into LDS, and the z faces come from a window of five
+// planes of (rho, u_z, p, E_r) that each thread keeps for its own column (the
+// face above a cell is the face below it on the next plane).  Each primitive
+// is thus recovered about twice per plane instead of fifteen times per cell,
+// and each face once instead of twice.  Face states, fluxes and the stage combine are those of
 // rad_advect, term for term and in the same order.
 constexpr int RW_TX = 32, RW_TY = 8, RW_CZ = 32;
 constexpr int RW_LX = RW_TX + 4, RW_LY = RW_TY + 4;
@@ -178,7 +179,9 @@ __device__ __forceinline__ double rad_face(const double* rho, const double* un, 
 template <typename R, int STAGE>
 __global__ __launch_bounds__(256) void rad_advect_walk(RadArgs a) {
 #pragma clang fp contract(off)
-  __shared__ double P[5][RW_LY][RW_LX];  // rho, u_x, u_y, p, E_r of one plane
+  __shared__ double P[5][RW_LY][RW_LX];        // rho, u_x, u_y, p, E_r of one plane
+  __shared__ double FX[RW_TY][RW_TX + 1];      // x faces of the plane's rows
+  __shared__ double FY[RW_TY + 1][RW_TX];      // y faces of the plane's columns
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const long long N = (long long)nx * ny * nz;
   const R* src = static_cast<const R*>(a.src);
@@ -207,6 +210,7 @@ __global__ __launch_bounds__(256) void rad_advect_walk(RadArgs a) {
 #pragma unroll
   for (int s = 0; s < 4; ++s) load_z(s, z0 - 2 + s);
   unsigned flags = 0;
+  double fz_lo = 0.0;  // z face below the current plane, carried from the plane before
   for (int k = z0; k < z1; ++k) {
     load_z(4, k + 2);
     // the plane's tile and halo (corners are not needed)
@@ -227,53 +231,51 @@ __global__ __launch_bounds__(256) void rad_advect_walk(RadArgs a) {
       P[4][py][px] = w[5];
     }
     __syncthreads();
-    if (own) {
-      double l = 0.0;
-      // x faces: cells i-2 .. i+2 of the LDS row
-      {
-        const int cx = lx + 2, cy = ly + 2;
-        double F[2];
+    // every x and y face of the plane once: x face f of row r lies between
+    // tile cells f-1 and f (LDS cells f .. f+3), y face f of column c likewise
+    for (int t = threadIdx.x; t < RW_TY * (RW_TX + 1) + (RW_TY + 1) * RW_TX; t += 256) {
+      double rho[4], un[4], p[4], er[4];
+      if (t < RW_TY * (RW_TX + 1)) {
+        const int r = t / (RW_TX + 1), f = t % (RW_TX + 1);
 #pragma unroll
-        for (int f = 0; f < 2; ++f) {
-          double rho[4], un[4], p[4], er[4];
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            rho[s] = P[0][cy][cx - 2 + f + s];
-            un[s] = P[1][cy][cx - 2 + f + s];
-            p[s] = P[3][cy][cx - 2 + f + s];
-            er[s] = P[4][cy][cx - 2 + f + s];
-          }
-          F[f] = rad_face(rho, un, p, er, a.gamma);
+        for (int s = 0; s < 4; ++s) {
+          rho[s] = P[0][r + 2][f + s];
+          un[s] = P[1][r + 2][f + s];
+          p[s] = P[3][r + 2][f + s];
+          er[s] = P[4][r + 2][f + s];
         }
-        const double df = F[1] - F[0];
+        FX[r][f] = rad_face(rho, un, p, er, a.gamma);
+      } else {
+        const int u = t - RW_TY * (RW_TX + 1);
+        const int f = u / RW_TX, cc = u % RW_TX;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          rho[s] = P[0][f + s][cc + 2];
+          un[s] = P[2][f + s][cc + 2];
+          p[s] = P[3][f + s][cc + 2];
+          er[s] = P[4][f + s][cc + 2];
+        }
+        FY[f][cc] = rad_face(rho, un, p, er, a.gamma);
+      }
+    }
+    __syncthreads();
+    if (own) {
+      if (k == z0) fz_lo = rad_face(wr_, wu, wp, we, a.gamma);
+      const double fz_hi = rad_face(wr_ + 1, wu + 1, wp + 1, we + 1, a.gamma);
+      double l = 0.0;
+      {
+        const double df = FX[ly][lx + 1] - FX[ly][lx];
         l = l - (a.dx_pow2 ? df * a.inv_dx[0] : df / a.dx[0]);
       }
-      // y faces
       {
-        const int cx = lx + 2, cy = ly + 2;
-        double F[2];
-#pragma unroll
-        for (int f = 0; f < 2; ++f) {
-          double rho[4], un[4], p[4], er[4];
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            rho[s] = P[0][cy - 2 + f + s][cx];
-            un[s] = P[2][cy - 2 + f + s][cx];
-            p[s] = P[3][cy - 2 + f + s][cx];
-            er[s] = P[4][cy - 2 + f + s][cx];
-          }
-          F[f] = rad_face(rho, un, p, er, a.gamma);
-        }
-        const double df = F[1] - F[0];
+        const double df = FY[ly + 1][lx] - FY[ly][lx];
         l = l - (a.dx_pow2 ? df * a.inv_dx[1] : df / a.dx[1]);
       }
-      // z faces from the window
       {
-        const double F0 = rad_face(wr_, wu, wp, we, a.gamma);
-        const double F1 = rad_face(wr_ + 1, wu + 1, wp + 1, we + 1, a.gamma);
-        const double df = F1 - F0;
+        const double df = fz_hi - fz_lo;
         l = l - (a.dx_pow2 ? df * a.inv_dx[2] : df / a.dx[2]);
       }
+      fz_lo = fz_hi;
       const long long c = ((long long)k * ny + j) * nx + i;
       R* dst = static_cast<R*>(a.dst);
       const R* un_ = static_cast<const R*>(a.un);
