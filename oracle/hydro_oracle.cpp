@@ -342,9 +342,10 @@ static void hll_flux(const Prim<T>& L, const Prim<T>& R, int nt, double gamma, T
 // (i+2, i+1, i, i-1, i-2).
 template <class T>
 static T weno5z(const T* v) {
-  T q0 = (T(2.0) * v[0] - T(7.0) * v[1] + T(11.0) * v[2]) / T(6.0);
-  T q1 = (-v[1] + T(5.0) * v[2] + T(2.0) * v[3]) / T(6.0);
-  T q2 = (T(2.0) * v[2] + T(5.0) * v[3] - v[4]) / T(6.0);
+  // 6 x the three third-order candidates
+  T q0 = T(2.0) * v[0] - T(7.0) * v[1] + T(11.0) * v[2];
+  T q1 = -v[1] + T(5.0) * v[2] + T(2.0) * v[3];
+  T q2 = T(2.0) * v[2] + T(5.0) * v[3] - v[4];
   T s0 = v[0] - T(2.0) * v[1] + v[2];
   T t0 = v[0] - T(4.0) * v[1] + T(3.0) * v[2];
   T s1 = v[1] - T(2.0) * v[2] + v[3];
@@ -356,10 +357,14 @@ static T weno5z(const T* v) {
   T b1 = c1 * s1 * s1 + c2 * t1 * t1;
   T b2 = c1 * s2 * s2 + c2 * t2 * t2;
   T tau = fabs(b0 - b2);
-  T a0 = T(0.1) * (T(1.0) + tau / (b0 + eps));
-  T a1 = T(0.6) * (T(1.0) + tau / (b1 + eps));
-  T a2 = T(0.3) * (T(1.0) + tau / (b2 + eps));
-  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+  // the weights d_k (1 + tau/(b_k + eps)) over the common denominator
+  // (b_0 + eps)(b_1 + eps)(b_2 + eps), the 1/6 of the candidates folded into
+  // the normalisation: one division instead of seven
+  T e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
+  T a0 = T(0.1) * (e0 + tau) * (e1 * e2);
+  T a1 = T(0.6) * (e1 + tau) * (e0 * e2);
+  T a2 = T(0.3) * (e2 + tau) * (e0 * e1);
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (T(6.0) * (a0 + a1 + a2));
 }
 
 // Primitive variables of one conserved state: rho, u_0..u_{ndim-1}, p.

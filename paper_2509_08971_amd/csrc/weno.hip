@@ -29,15 +29,17 @@ namespace hard {
 // WENO5-Z value at the right face of the middle cell of v0..v4 (cells
 // i-2..i+2): third-order candidates on the three sub-stencils, Jiang-Shu
 // smoothness indicators, tau5 = |beta0 - beta2|, weights
-// d_k (1 + tau5 / (beta_k + eps)) with d = (1/10, 6/10, 3/10), eps = 1e-40.
+// d_k (1 + tau5 / (beta_k + eps)) with d = (1/10, 6/10, 3/10), eps = 1e-40,
+// evaluated over their common denominator with a single division.
 // Evaluated in double for both storage types: at a jump the weight ratios
 // reach 1e40 and beyond, out of float range (and the FP64 vector rate of
 // gfx950 equals its unpacked FP32 rate).
 __device__ __forceinline__ double weno5z_d(double v0, double v1, double v2, double v3, double v4) {
 #pragma clang fp contract(off)
-  double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) / 6.0;
-  double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) / 6.0;
-  double q2 = (2.0 * v2 + 5.0 * v3 - v4) / 6.0;
+  // 6 x the three third-order candidates
+  double q0 = 2.0 * v0 - 7.0 * v1 + 11.0 * v2;
+  double q1 = -v1 + 5.0 * v2 + 2.0 * v3;
+  double q2 = 2.0 * v2 + 5.0 * v3 - v4;
   double s0 = v0 - 2.0 * v1 + v2, t0 = v0 - 4.0 * v1 + 3.0 * v2;
   double s1 = v1 - 2.0 * v2 + v3, t1 = v1 - v3;
   double s2 = v2 - 2.0 * v3 + v4, t2 = 3.0 * v2 - 4.0 * v3 + v4;
@@ -46,10 +48,13 @@ __device__ __forceinline__ double weno5z_d(double v0, double v1, double v2, doub
   double b1 = c1 * s1 * s1 + c2 * t1 * t1;
   double b2 = c1 * s2 * s2 + c2 * t2 * t2;
   double tau = fabs(b0 - b2);
-  double a0 = 0.1 * (1.0 + tau / (b0 + eps));
-  double a1 = 0.6 * (1.0 + tau / (b1 + eps));
-  double a2 = 0.3 * (1.0 + tau / (b2 + eps));
-  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+  // the weights over the common denominator (b0 + eps)(b1 + eps)(b2 + eps),
+  // the 1/6 of the candidates folded into the normalisation: one division
+  const double e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
+  double a0 = 0.1 * (e0 + tau) * (e1 * e2);
+  double a1 = 0.6 * (e1 + tau) * (e0 * e2);
+  double a2 = 0.3 * (e2 + tau) * (e0 * e1);
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (6.0 * (a0 + a1 + a2));
 }
 template <typename R>
 __device__ __forceinline__ R weno5z(R v0, R v1, R v2, R v3, R v4) {
@@ -136,7 +141,7 @@ template <typename R, int NDIM>
 __global__ __launch_bounds__(256) void weno_prim(WenoArgs a) {
   constexpr int NV = NDIM + 2;
   const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   unsigned flags = 0;
   if (c < N) {
     const R* U = static_cast<const R*>(a.src);
@@ -162,7 +167,7 @@ __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const long long N = (long long)nx * ny * nz;
   const long long nface = N / a.n[AX] * (a.n[AX] + 1);
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long idx = (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (idx >= nface) return;
   int i, j, k, f;
   if constexpr (AX == 0) {
