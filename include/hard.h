@@ -297,8 +297,9 @@ hard_status_t hard_rad_diffuse_workspace_bytes(const hard_grid_t* g, size_t* byt
  * E_old.  resid_dev (device array of ncycles + 1 doubles, or NULL) receives
  * the 2-norm of the finest-level residual E_old - A x before the first cycle
  * and after each one (summed with atomics: not bitwise reproducible).
- * Requirements: g->rad = 1, g->kappa > 0, HARD_F64 (HARD_F32 returns
- * HARD_ERR_UNSUPPORTED), every periodic axis of even size (odd: UNSUPPORTED).
+ * Requirements: g->rad = 1, g->kappa > 0, every periodic axis of even size
+ * (odd: HARD_ERR_UNSUPPORTED).  HARD_F32 states are read into and solved in
+ * double; E_r is rounded to float when it is stored back.
  * rho <= 0 sets HARD_FLAG_DENSITY, E_r <= 0 or a non-finite D sets
  * HARD_FLAG_RADIATION in the status word.  Stream-ordered, no host
  * synchronisation, no allocation; graph-capturable. */

@@ -349,10 +349,11 @@ unsigned fld_tiles(const FldLevel& L) {
                     ((L.n[2] + T::TZ - 1) / T::TZ));
 }
 
-// Finest level from the state: D, b = E, x = E.
-template <int NDIM>
-__global__ __launch_bounds__(256) void fld_setup(FldLevel L, FldCommon cm, const double* rho,
-                                                 const double* E, double kappa, int limiter,
+// Finest level from the state: D, b = E, x = E (a float state is widened:
+// the solve itself is in double for both storage types).
+template <int NDIM, typename T>
+__global__ __launch_bounds__(256) void fld_setup(FldLevel L, FldCommon cm, const T* rho,
+                                                 const T* E, double kappa, int limiter,
                                                  Control* ctl) {
 #pragma clang fp contract(off)
   int p[3];
@@ -367,10 +368,10 @@ __global__ __launch_bounds__(256) void fld_setup(FldLevel L, FldCommon cm, const
       const int qhi = fld_nb(p[d], L.n[d], 1, cm.per[d]);
       const unsigned lo = qlo < 0 ? c : c + (unsigned)(qlo - p[d]) * stride[d];
       const unsigned hi = qhi < 0 ? c : c + (unsigned)(qhi - p[d]) * stride[d];
-      const double g = (E[hi] - E[lo]) / (2.0 * L.dx[d]);
+      const double g = ((double)E[hi] - (double)E[lo]) / (2.0 * L.dx[d]);
       g2 += g * g;
     }
-    const double r = rho[c], e = E[c];
+    const double r = (double)rho[c], e = (double)E[c];
     double lam = 1.0 / 3.0;
     if (limiter) {
       const double R = sqrt(g2) / (r * kappa * e);
@@ -387,14 +388,15 @@ __global__ __launch_bounds__(256) void fld_setup(FldLevel L, FldCommon cm, const
   block_finish<256>(flags, 0.0, false, ctl, 0.0, nullptr);
 }
 
-// The finest x back into the state's E_r field.
-template <int NDIM>
-__global__ __launch_bounds__(256) void fld_store(FldLevel L, double* E) {
+// The finest x back into the state's E_r field (rounded to float for a
+// float state).
+template <int NDIM, typename R>
+__global__ __launch_bounds__(256) void fld_store(FldLevel L, R* E) {
   int p[3];
   if (!fld_tile_cell<NDIM>(L, p)) return;
   const unsigned c = ((unsigned)p[2] * (unsigned)L.n[1] + (unsigned)p[1]) * (unsigned)L.n[0] +
                      (unsigned)p[0];
-  E[c] = L.x[fld_at(L, p[0], p[1], p[2])];
+  E[c] = R(L.x[fld_at(L, p[0], p[1], p[2])]);
 }
 
 __global__ __launch_bounds__(256) void fld_coarsen_D(FldLevel F, FldLevel C, double inv) {
@@ -689,7 +691,6 @@ hard_status_t check_fld_grid(const hard_grid_t* g, Grid* G) {
   if (st) return st;
   if (!G->rad) return fail(HARD_ERR_INVALID_ARG, "radiation diffusion needs rad = 1");
   if (!(G->kappa > 0.0)) return fail(HARD_ERR_INVALID_ARG, "radiation diffusion needs kappa > 0");
-  if (G->dtype != HARD_F64) return fail(HARD_ERR_UNSUPPORTED, "radiation diffusion is built for HARD_F64");
   for (int d = 0; d < G->ndim; ++d)
     if (G->bc[d][0] == BC_PERIODIC && G->n[d] % 2)
       return fail(HARD_ERR_UNSUPPORTED,
@@ -784,13 +785,13 @@ struct Solver {
     return hipGetLastError();
   }
 
-  template <int NDIM>
-  hipError_t run(double* U, int limiter, int ncycles, double* resid, Control* ctl) {
+  template <int NDIM, typename R>
+  hipError_t run(R* U, int limiter, int ncycles, double* resid, Control* ctl) {
     hipError_t e;
     const long long N = cells(H, 0);
-    const double* rho = U;
-    double* E = U + (long long)(G.nvar - 1) * N;
-    fld_setup<NDIM><<<fld_tiles<NDIM>(lv[0]), 256, 0, s>>>(lv[0], cm, rho, E, G.kappa, limiter, ctl);
+    const R* rho = U;
+    R* E = U + (long long)(G.nvar - 1) * N;
+    fld_setup<NDIM, R><<<fld_tiles<NDIM>(lv[0]), 256, 0, s>>>(lv[0], cm, rho, E, G.kappa, limiter, ctl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     FldDx2 dx2;
     for (int l = 0; l < H.nlev; ++l)
@@ -806,7 +807,7 @@ struct Solver {
       if ((e = vcycle<NDIM>(0)) != hipSuccess) return e;
       if (resid && (e = resid_norm<NDIM>(resid + c + 1)) != hipSuccess) return e;
     }
-    fld_store<NDIM><<<fld_tiles<NDIM>(lv[0]), 256, 0, s>>>(lv[0], E);
+    fld_store<NDIM, R><<<fld_tiles<NDIM>(lv[0]), 256, 0, s>>>(lv[0], E);
     return hipGetLastError();
   }
 };
@@ -847,7 +848,7 @@ hard_status_t hard_rad_diffuse(const hard_grid_t* g, void* U, const double* dt_d
   Grid G;
   hard_status_t st = check_fld_grid(g, &G);
   if (st) return st;
-  if ((st = check_ptr(U, 8, "U"))) return st;
+  if ((st = check_ptr(U, G.wsize, "U"))) return st;
   if ((st = check_ptr(dt_dev, 8, "dt_dev"))) return st;
   if (resid_dev && (st = check_ptr(resid_dev, 8, "resid_dev"))) return st;
   if (!opts) return fail(HARD_ERR_INVALID_ARG, "opts is NULL");
@@ -910,12 +911,21 @@ hard_status_t hard_rad_diffuse(const hard_grid_t* g, void* U, const double* dt_d
   for (int d = 0; d < 3; ++d) S.cm.per[d] = G.bc[d][0] == BC_PERIODIC;
   S.cm.dt = dt_dev;
   Control* ctl = reinterpret_cast<Control*>(wb);
-  double* Ud = static_cast<double*>(U);
   hipError_t e;
-  switch (G.ndim) {
-    case 1: e = S.run<1>(Ud, opts->limiter, opts->ncycles, resid_dev, ctl); break;
-    case 2: e = S.run<2>(Ud, opts->limiter, opts->ncycles, resid_dev, ctl); break;
-    default: e = S.run<3>(Ud, opts->limiter, opts->ncycles, resid_dev, ctl); break;
+  if (G.dtype == HARD_F64) {
+    double* Ud = static_cast<double*>(U);
+    switch (G.ndim) {
+      case 1: e = S.run<1>(Ud, opts->limiter, opts->ncycles, resid_dev, ctl); break;
+      case 2: e = S.run<2>(Ud, opts->limiter, opts->ncycles, resid_dev, ctl); break;
+      default: e = S.run<3>(Ud, opts->limiter, opts->ncycles, resid_dev, ctl); break;
+    }
+  } else {
+    float* Uf = static_cast<float*>(U);
+    switch (G.ndim) {
+      case 1: e = S.run<1>(Uf, opts->limiter, opts->ncycles, resid_dev, ctl); break;
+      case 2: e = S.run<2>(Uf, opts->limiter, opts->ncycles, resid_dev, ctl); break;
+      default: e = S.run<3>(Uf, opts->limiter, opts->ncycles, resid_dev, ctl); break;
+    }
   }
   if (e != hipSuccess) return hip_fail(e, "hard_rad_diffuse launch");
   return ok();

@@ -188,12 +188,14 @@ def call_diffuse(g, U=FAKE, dt=FAKE, opts=None, resid=None, work=FAKE, nbytes=1 
 
 
 def test_diffusion_checks():
-    """The implicit diffusion call needs the radiation field, kappa > 0, FP64
-    and even periodic axes; its options and workspace are validated."""
+    """The implicit diffusion call needs the radiation field, kappa > 0 and
+    even periodic axes; its options and workspace are validated."""
     rad = (0.4, 0.6)
     assert call_diffuse(H.make_grid((16, 16))) == H.ERR_INVALID_ARG
     assert call_diffuse(H.make_grid((16, 16), rad=(0.0, 0.6))) == H.ERR_INVALID_ARG
-    assert call_diffuse(H.make_grid((16, 16), rad=rad, dtype="f32")) == H.ERR_UNSUPPORTED
+    gf = H.make_grid((16, 16), rad=rad, dtype="f32")
+    assert call_diffuse(gf, U=FAKE + 4, nbytes=H.hard_rad_diffuse_workspace_bytes(gf) - 1) == \
+        H.ERR_WORKSPACE  # float states are accepted (4-byte aligned U)
     assert call_diffuse(H.make_grid((15, 16), bc=(0, 0, 1, 1), rad=rad)) == H.ERR_UNSUPPORTED
     g = H.make_grid((15, 16), bc=(1, 2, 1, 1), rad=rad)  # odd walls are fine
     assert H.hard_rad_diffuse_workspace_bytes(g) > 0

@@ -85,6 +85,8 @@ CASES = [
     ((48, 40), (P, P, O, O)), ((33, 20), (O, R, P, P)), ((64, 64), (R, R, R, R)),
     ((32, 24, 16), (P, P, R, R, O, O)), ((21, 17, 19), (O, O, R, R, O, R)),
     ((32, 32, 32), (P, P, P, P, P, P)),
+    # the smallest grids: two cells per axis (one coarse cell below), odd walls
+    ((2,), (P, P)), ((2, 2, 2), (P, P, P, P, P, P)), ((3, 2), (O, O, P, P)), ((2, 3, 2), (R, R, O, R, P, P)),
 ]
 
 
@@ -239,3 +241,81 @@ def test_diffusion_graph_replay():
         H.hard_rad_diffuse(g, tmp, dtd, work, ncycles=1)
         torch.cuda.synchronize()
     assert H.hard_status_read(work) == 0
+
+
+def test_operator_split_radiation_hydro_step_parity():
+    """The paper's operator split on the GPU: each step is hard_hydro_step
+    with the radiation field (Heun advection of the hydro fields and E_r,
+    then the heating/cooling exchange) followed by hard_rad_diffuse with the
+    same dt; three such steps equal the oracle's step + diffusion to 1e-12
+    in every field.  CGS state of a hot, radiation-dominated gas (rho ~ 1e-7
+    g/cm^3, T ~ 1e6 K, kappa = 0.4 cm^2/g as in the paper's heating and
+    cooling test) on a 1e10 cm box, where dt D / dx^2 is about 3."""
+    KB, MU_, A_RAD = 1.380649e-16, 1.66053906660e-24, 4.0 * 5.670374419e-5 / C_LIGHT
+    n, bc = (32, 24, 16), (P, P, O, O, R, R)
+    gamma, kappa, mu = 5.0 / 3.0, 0.4, 0.6
+    dx = (1e10 / 32,) * 3
+    rng = np.random.default_rng(19)
+    shape = tuple(reversed(n))
+    rho = rng.uniform(0.5, 1.5, shape) * 1e-7
+    e = rho * KB / (mu * MU_ * (gamma - 1.0)) * rng.uniform(1.0, 2.0, shape) * 1e6
+    cs = np.sqrt(gamma * (gamma - 1.0) * e / rho)
+    U0 = np.zeros((6,) + shape)
+    U0[0] = rho
+    for d in range(3):
+        U0[1 + d] = rho * 0.3 * cs * rng.uniform(-1.0, 1.0, shape)
+    U0[4] = e + 0.5 * (U0[1] ** 2 + U0[2] ** 2 + U0[3] ** 2) / rho
+    U0[5] = A_RAD * (rng.uniform(1.0, 2.0, shape) * 1e6) ** 4
+    og = oracle.Grid(n, bc=bc, dx=dx, gamma=gamma, rad=(kappa, mu))
+    dt, _ = oracle.cfl_dt(og, U0, 0.3)
+    ref = U0.copy()
+    for _ in range(3):
+        ref, st = oracle.steps(og, ref, [dt])
+        assert st == 0
+        ref, st, _ = fld.rad_diffuse(og, ref, dt, ncycles=3)
+        assert st == 0
+    g = H.make_grid(n, bc=bc, dx=dx, gamma=gamma, rad=(kappa, mu))
+    U = torch.from_numpy(U0).to(DEV)
+    hwork = H.workspace(H.hard_workspace_bytes(g))
+    fwork = H.workspace(H.hard_rad_diffuse_workspace_bytes(g))
+    dtd = torch.full((1,), dt, dtype=torch.float64, device=DEV)
+    for _ in range(3):
+        H.hard_hydro_step(g, U, dtd, hwork)
+        H.hard_rad_diffuse(g, U, dtd, fwork, ncycles=3)
+    torch.cuda.synchronize()
+    assert H.hard_status_read(hwork) == 0 and H.hard_status_read(fwork) == 0
+    out = U.cpu().numpy()
+    for v in range(6):
+        err = np.abs(out[v] - ref[v]).max() / np.abs(ref[v]).max()
+        assert err <= 1e-12, (v, err)
+    # the diffusion moved E_r: it differs from the same steps without it
+    alone = U0.copy()
+    for _ in range(3):
+        alone, _ = oracle.steps(og, alone, [dt])
+    assert np.abs(alone[5] - ref[5]).max() > 0.1 * np.abs(ref[5]).max()
+
+
+@pytest.mark.parametrize("n,bc", [((40, 24, 12), (P, P, O, O, R, R)), ((100,), (O, R)),
+                                  ((48, 40), (P, P, O, O))])
+def test_diffusion_parity_fp32_state(n, bc):
+    """A float state: rho and E_r are widened, the solve runs in double, and
+    E_r is rounded to float on the way back, so the result is the oracle's
+    (run on the float-rounded input) to within the float rounding."""
+    log("fld fp32", n, bc)
+    U0 = rad_state(n, 20, smooth=True).astype(np.float32).astype(np.float64)
+    dx = 1.0 / max(n)
+    dt = 50.0 * dx * dx * KAPPA / C_LIGHT
+    og = oracle.Grid(n, bc=bc, rad=(KAPPA, 0.6))
+    ref, st, _ = fld.rad_diffuse(og, U0, dt, ncycles=3)
+    assert st == 0
+    g = H.make_grid(n, bc=bc, rad=(KAPPA, 0.6), dtype=torch.float32)
+    U = torch.from_numpy(U0.astype(np.float32)).to(DEV)
+    work = H.workspace(H.hard_rad_diffuse_workspace_bytes(g))
+    dtd = torch.full((1,), float(dt), dtype=torch.float64, device=DEV)
+    H.hard_rad_diffuse(g, U, dtd, work, ncycles=3)
+    torch.cuda.synchronize()
+    assert H.hard_status_read(work) == 0
+    out = U.cpu().numpy()
+    np.testing.assert_array_equal(out[:-1], U0[:-1].astype(np.float32))
+    # within the float rounding of the double solve (half an ulp, 6e-8)
+    np.testing.assert_allclose(out[-1], ref[-1], rtol=1.2e-7, atol=0)
