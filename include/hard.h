@@ -307,6 +307,22 @@ hard_status_t hard_rad_diffuse(const hard_grid_t* g, void* U, const double* dt_d
                                const hard_gmg_opts_t* opts, double* resid_dev, void* work,
                                size_t work_bytes, void* stream);
 
+/* hard_run for a state with the radiation field, with the implicit
+ * diffusion in every step: the operator split of section 2.2.2 under the
+ * control model of section 2.1.  Each step takes dt = min(CFL dt, t_end - t)
+ * as hard_run does, then hard_hydro_step (hydro fields and E_r advected,
+ * heating/cooling exchange) and hard_rad_diffuse with the same dt and
+ * `opts`.  work: a hard_workspace_bytes workspace; fld_work: a
+ * hard_rad_diffuse_workspace_bytes workspace (its control block's dt slot
+ * holds the step size).  Both must be cleared before first use.  The host
+ * synchronises once per 64 steps; steps after the end are exact no-ops.
+ * Writes the final t and the number of steps; returns HARD_ERR_NONPHYSICAL
+ * if either status word has bits set.  Requires g->rad = 1, g->kappa > 0. */
+hard_status_t hard_run_rhd(const hard_grid_t* g, void* U, double cfl, double t_end,
+                           int64_t max_steps, const hard_gmg_opts_t* opts, double* t_out,
+                           int64_t* steps_out, void* work, size_t work_bytes, void* fld_work,
+                           size_t fld_work_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

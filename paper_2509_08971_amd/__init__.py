@@ -24,6 +24,7 @@ __all__ = [
     "hard_run_batched", "batch_pack", "batch_unpack",
     "hard_adjoint_workspace_bytes", "hard_hydro_step_adjoint", "workspace",
     "hard_gmg_opts_t", "hard_gmg_levels", "hard_rad_diffuse_workspace_bytes", "hard_rad_diffuse",
+    "hard_run_rhd",
     "PERIODIC", "OUTFLOW", "REFLECT", "F64", "F32", "FLD_EDDINGTON", "FLD_LEVERMORE",
 ]
 
@@ -115,6 +116,9 @@ def lib():
             "hard_rad_diffuse_workspace_bytes": [_gp, ctypes.POINTER(_sz)],
             "hard_rad_diffuse": [_gp, _vp, _vp, ctypes.POINTER(hard_gmg_opts_t), _vp, _vp, _sz,
                                  _vp],
+            "hard_run_rhd": [_gp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                             ctypes.POINTER(hard_gmg_opts_t), ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_int64), _vp, _sz, _vp, _sz, _vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -343,3 +347,15 @@ def hard_rad_diffuse(g, U, dt_dev, work, limiter=FLD_LEVERMORE, ncycles=4, nu1=2
     o = hard_gmg_opts_t(int(limiter), int(ncycles), int(nu1), int(nu2), int(ncoarse))
     _check(lib().hard_rad_diffuse(_grid(g), _ptr(U), _ptr(dt_dev), ctypes.byref(o),
                                   _ptr(resid_dev), _ptr(work), work.numel(), _stream(stream)))
+
+
+def hard_run_rhd(g, U, cfl, t_end, work, fld_work, limiter=FLD_LEVERMORE, ncycles=4, nu1=2, nu2=2,
+                 ncoarse=8, max_steps=10_000_000, stream=None):
+    """Run to t_end in place with the diffusion in every step; returns (t, steps)."""
+    o = hard_gmg_opts_t(int(limiter), int(ncycles), int(nu1), int(nu2), int(ncoarse))
+    t = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().hard_run_rhd(_grid(g), _ptr(U), float(cfl), float(t_end), int(max_steps),
+                              ctypes.byref(o), ctypes.byref(t), ctypes.byref(n), _ptr(work),
+                              work.numel(), _ptr(fld_work), fld_work.numel(), _stream(stream)))
+    return t.value, n.value

@@ -411,6 +411,64 @@ hard_status_t hard_run(const hard_grid_t* g, void* U, double cfl, double t_end,
   return ok();
 }
 
+hard_status_t hard_run_rhd(const hard_grid_t* g, void* U, double cfl, double t_end,
+                           int64_t max_steps, const hard_gmg_opts_t* opts, double* t_out,
+                           int64_t* steps_out, void* work, size_t work_bytes, void* fld_work,
+                           size_t fld_work_bytes, void* stream) {
+  Grid G;
+  hard_status_t st = check_grid(g, &G);
+  if (st) return st;
+  if (!G.rad) return fail(HARD_ERR_INVALID_ARG, "hard_run_rhd needs rad = 1");
+  if ((st = check_ptr(U, G.wsize, "U"))) return st;
+  if ((st = check_cfl(cfl))) return st;
+  if (!(std::isfinite(t_end) && t_end > 0.0)) return fail(HARD_ERR_INVALID_ARG, "t_end must be finite and > 0");
+  if (max_steps < 1) return fail(HARD_ERR_INVALID_ARG, "max_steps must be >= 1");
+  if (!t_out || !steps_out) return fail(HARD_ERR_INVALID_ARG, "t_out and steps_out must not be NULL");
+  WorkLayout L = layout_of(G);
+  if ((st = check_work(work, work_bytes, L.total))) return st;
+  size_t fld_need = 0;
+  if ((st = hard_rad_diffuse_workspace_bytes(g, &fld_need))) return st;
+  if ((st = check_work(fld_work, fld_work_bytes, fld_need))) return st;
+  if (!opts) return fail(HARD_ERR_INVALID_ARG, "opts is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  Control* ctl = reinterpret_cast<Control*>(static_cast<char*>(work) + L.ctl);
+  // the diffusion reads the step size from its own control block's dt slot
+  Control* fctl = static_cast<Control*>(fld_work);
+  double* dt = &ctl->dt;
+  double* dt_step = &fctl->dt;
+  hipError_t e = launch_control_clear(ctl, s);
+  if (e != hipSuccess) return hip_fail(e, "hard_run_rhd clear");
+  if ((e = launch_cfl(G.ndim, G.dtype, G.n, G.dx, G.inv_dx, G.dx_pow2, G.gamma, U, cfl, dt,
+                      ctl, s)) != hipSuccess)
+    return hip_fail(e, "hard_run_rhd cfl");
+  const int batch = 64;
+  int done = 0;
+  while (!done) {
+    for (int i = 0; i < batch; ++i) {
+      if ((e = launch_time_control(ctl, t_end, max_steps, s)) != hipSuccess ||
+          (e = launch_fld_copy_dt(dt, dt_step, s)) != hipSuccess)
+        return hip_fail(e, "hard_run_rhd time control");
+      if ((st = hard_hydro_step(g, U, dt, cfl, dt, work, work_bytes, stream))) return st;
+      if ((st = hard_rad_diffuse(g, U, dt_step, opts, nullptr, fld_work, fld_work_bytes, stream)))
+        return st;
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hard_run_rhd sync");
+    if ((e = hipMemcpy(&done, &ctl->done, sizeof done, hipMemcpyDeviceToHost)) != hipSuccess)
+      return hip_fail(e, "hard_run_rhd read");
+  }
+  long long steps = 0;
+  unsigned flags = 0, fflags = 0;
+  if ((e = hipMemcpy(t_out, &ctl->t, sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess ||
+      (e = hipMemcpy(&steps, &ctl->steps, sizeof steps, hipMemcpyDeviceToHost)) != hipSuccess ||
+      (e = hipMemcpy(&flags, &ctl->flags, sizeof flags, hipMemcpyDeviceToHost)) != hipSuccess ||
+      (e = hipMemcpy(&fflags, &fctl->flags, sizeof fflags, hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "hard_run_rhd read");
+  *steps_out = steps;
+  if (flags | fflags)
+    return fail(HARD_ERR_NONPHYSICAL, "non-physical state (flags 0x%x)", flags | fflags);
+  return ok();
+}
+
 hard_status_t hard_status_read(void* work, size_t work_bytes, uint32_t* flags, void* stream) {
   hard_status_t st = check_work(work, work_bytes, sizeof(Control));
   if (st) return st;

@@ -49,6 +49,9 @@ RadArgs rad_args(const Grid& G, const StageArgs& a);
 hipError_t launch_scheme_stage(const Grid& G, const WorkLayout& L, char* wb, const StageArgs& a,
                                int stage, hipStream_t s);
 
+// *to = *from on the stream (fld.hip).
+hipError_t launch_fld_copy_dt(const double* from, double* to, hipStream_t s);
+
 // z planes per workgroup for the 3D stage kernel: HARD_STAGE_CZ in the
 // environment overrides the default (read once; 0 = default).
 int stage_cz_override();

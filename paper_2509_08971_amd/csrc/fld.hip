@@ -616,6 +616,18 @@ __global__ __launch_bounds__(1024) void fld_vcycle_tail(FldTail T, FldCommon cm)
   for (unsigned t = threadIdx.x; t < 2u * G.cs; t += 1024) G.x[t] = L.x[t];
 }
 
+// One double from device slot to device slot (the step size of a time loop
+// handed to the diffusion before the hydro step overwrites its slot with the
+// next CFL step).
+__global__ void fld_copy_dt(const double* from, double* to) {
+  if (threadIdx.x == 0) *to = *from;
+}
+
+hipError_t launch_fld_copy_dt(const double* from, double* to, hipStream_t s) {
+  fld_copy_dt<<<1, 64, 0, s>>>(from, to);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- host side
 
 namespace {

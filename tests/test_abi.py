@@ -226,3 +226,25 @@ def test_multigrid_levels_match_the_oracle(n, bc):
     want = fld.gmg_levels(oracle.Grid(n, bc=bc, rad=(0.4, 0.6)))
     got = H.hard_gmg_levels(H.make_grid(n, bc=bc, rad=(0.4, 0.6)))
     assert got == want
+
+
+def test_run_rhd_checks():
+    """hard_run_rhd validates the grid (radiation field needed), both
+    workspaces and the multigrid options before anything is enqueued."""
+    L = H.lib()
+    t = ctypes.c_double()
+    n = ctypes.c_int64()
+    opts = H.hard_gmg_opts_t(H.FLD_LEVERMORE, 2, 2, 2, 8)
+
+    def call(g, o=opts, work_bytes=1 << 40, fld_bytes=1 << 40, fld=FAKE):
+        return L.hard_run_rhd(ctypes.byref(g), FAKE, 0.4, 1.0, 10, ctypes.byref(o) if o else None,
+                              ctypes.byref(t), ctypes.byref(n), FAKE, work_bytes, fld, fld_bytes,
+                              None)
+
+    assert call(H.make_grid((16, 16))) == H.ERR_INVALID_ARG  # no radiation field
+    g = H.make_grid((16, 16), rad=(0.4, 0.6))
+    assert call(g, o=None) == H.ERR_INVALID_ARG
+    assert call(g, fld_bytes=H.hard_rad_diffuse_workspace_bytes(g) - 1) == H.ERR_WORKSPACE
+    assert call(g, work_bytes=H.hard_workspace_bytes(g) - 1) == H.ERR_WORKSPACE
+    assert call(g, fld=None) == H.ERR_INVALID_ARG
+    assert call(H.make_grid((15, 16), bc=(0, 0, 1, 1), rad=(0.4, 0.6))) == H.ERR_UNSUPPORTED

@@ -319,3 +319,46 @@ def test_diffusion_parity_fp32_state(n, bc):
     np.testing.assert_array_equal(out[:-1], U0[:-1].astype(np.float32))
     # within the float rounding of the double solve (half an ulp, 6e-8)
     np.testing.assert_allclose(out[-1], ref[-1], rtol=1.2e-7, atol=0)
+
+
+def test_run_rhd_matches_the_oracle_loop():
+    """hard_run_rhd: the time loop of hard_run (CFL step clipped to t_end)
+    with the implicit diffusion in every step, against the same loop of the
+    oracle's step and diffusion; same step count, every field to 1e-12."""
+    KB, MU_, A_RAD = 1.380649e-16, 1.66053906660e-24, 4.0 * 5.670374419e-5 / C_LIGHT
+    n, bc = (24, 16, 8), (P, P, R, R, O, O)
+    gamma, kappa, mu = 5.0 / 3.0, 0.4, 0.6
+    dx = (1e10 / 24,) * 3
+    rng = np.random.default_rng(21)
+    shape = tuple(reversed(n))
+    rho = rng.uniform(0.5, 1.5, shape) * 1e-7
+    e = rho * KB / (mu * MU_ * (gamma - 1.0)) * rng.uniform(1.0, 2.0, shape) * 1e6
+    U0 = np.zeros((6,) + shape)
+    U0[0] = rho
+    U0[4] = e
+    U0[5] = A_RAD * (rng.uniform(1.0, 2.0, shape) * 1e6) ** 4
+    og = oracle.Grid(n, bc=bc, dx=dx, gamma=gamma, rad=(kappa, mu))
+    cfl = 0.4
+    dt0, _ = oracle.cfl_dt(og, U0, cfl)
+    t_end = 2.5 * dt0
+    ref, t, steps = U0.copy(), 0.0, 0
+    dt = dt0
+    while t < t_end * (1.0 - 1e-14):
+        d = min(dt, t_end - t)
+        ref, st = oracle.steps(og, ref, [d])
+        assert st == 0
+        ref, st, _ = fld.rad_diffuse(og, ref, d, ncycles=2)
+        assert st == 0
+        t, steps = t + d, steps + 1
+        dt, _ = oracle.cfl_dt(og, ref, cfl)
+    g = H.make_grid(n, bc=bc, dx=dx, gamma=gamma, rad=(kappa, mu))
+    U = torch.from_numpy(U0).to(DEV)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    fwork = H.workspace(H.hard_rad_diffuse_workspace_bytes(g))
+    tg, sg = H.hard_run_rhd(g, U, cfl, t_end, work, fwork, ncycles=2)
+    assert sg == steps == 3
+    assert tg == pytest.approx(t, rel=1e-14)
+    out = U.cpu().numpy()
+    for v in range(6):
+        err = np.abs(out[v] - ref[v]).max() / np.abs(ref[v]).max()
+        assert err <= 1e-12, (v, err)
