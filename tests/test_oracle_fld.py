@@ -327,3 +327,30 @@ def test_zero_cycles_return_the_old_field_and_its_residual():
     np.testing.assert_array_equal(X, U)
     y, _ = fld.fld_apply(g, U, 1e-10, U[-1])
     assert res[0] == pytest.approx(np.linalg.norm(U[-1] - y), rel=1e-12)
+
+
+def test_gaussian_pulse_converges_at_first_order_in_dt():
+    # Eddington limit, uniform rho: the diffusion step solves the heat
+    # equation d_t E = D d_xx E, whose Gaussian pulse spreads with variance
+    # s0^2 + 2 D t; backward Euler approaches it at first order in dt
+    n = 512
+    g = grid((n,), (P, P), dx=(1.0 / n,))
+    x = (np.arange(n) + 0.5) / n - 0.5
+    D = C_LIGHT / (3.0 * KAPPA * 1.0)
+    s0 = 0.03
+    t_final = 0.5 * s0 ** 2 / D
+
+    def exact(t):
+        s2 = s0 ** 2 + 2.0 * D * t
+        return 1.0 + np.sqrt(s0 ** 2 / s2) * np.exp(-x ** 2 / (2.0 * s2))
+
+    errs = []
+    for k in (4, 8, 16, 32):
+        U = state(g, 1.0, exact(0.0))
+        for _ in range(k):
+            U, st, _ = fld.rad_diffuse(g, U, t_final / k, ncycles=30, limiter=fld.EDDINGTON)
+            assert st == 0
+        errs.append(np.abs(U[-1] - exact(t_final)).max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all((orders > 0.85) & (orders < 1.15)), orders
+    assert errs[-1] < 3e-3
