@@ -35,6 +35,9 @@ OPS_PER_ZU_3D = 1145
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_08971_amd", "csrc", f)
                   for f in ("hydro_device.hpp", "stage_tile.hpp", "stage.hip", "launch.hpp")]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "stage_kernel_blast256_fp64_hbm_counters.md")
+FLD_SOURCES = [os.path.join(ROOT, "paper_2509_08971_amd", "csrc", f)
+               for f in ("fld.hip", "hydro_device.hpp")]
+FLD_COUNTERS_FILE = os.path.join(ROOT, "profiles", "fld_relax_diffusion256_fp64_hbm_counters.md")
 
 
 def kernel_source_hash():
@@ -45,6 +48,31 @@ def kernel_source_hash():
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def fld_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in FLD_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def fld_measured_cycle_bytes():
+    """HBM bytes per V(2,2) cycle of the 256^3 diffusion from the committed
+    FETCH_SIZE/WRITE_SIZE runs, if the diffusion sources are unchanged since."""
+    try:
+        lines = dict(l.split(": ", 1) for l in open(FLD_COUNTERS_FILE).read().splitlines()
+                     if ": " in l and not l.startswith(("|", " ", "#")))
+    except OSError:
+        return None
+    if lines.get("fld-source-sha256", "").strip() != fld_source_hash():
+        return None
+    try:
+        return int(lines["cycle-bytes-measured"])
+    except (KeyError, ValueError):
+        return None
 
 
 def _counter_lines():
@@ -349,7 +377,7 @@ def bench_fld(args, n=256, ncycles=4, reps=10):
             "residual_reduction": float(r[-1] / r[0]),
             "roofline": {"bound": "hbm", "kernel": "one V(2,2) cycle (all levels)",
                          "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                         "frac": achieved / 8000.0, "traffic": None,
+                         "frac": achieved / 8000.0, "traffic": fld_measured_cycle_bytes(),
                          "algorithmic_bytes": cyc},
             "timing": f"median of {reps} calls each of {ncycles} and {2 * ncycles} cycles, HIP "
                       f"events on the launch stream; a cycle is the difference / {ncycles}",
