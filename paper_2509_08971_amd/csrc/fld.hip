@@ -326,15 +326,26 @@ template <> struct FldTile<1> { static constexpr int TX = 256, TY = 1, TZ = 1; }
 template <> struct FldTile<2> { static constexpr int TX = 64, TY = 4, TZ = 1; };
 template <> struct FldTile<3> { static constexpr int TX = 32, TY = 4, TZ = 2; };
 
+// Tile rows (along y) of one panel: tile ids run x fastest, then y inside the
+// panel, then z, then panel.  The z neighbours of a tile were then touched one
+// panel slab earlier (TX*tx x TY*FLD_PANEL x TZ cells, about 0.4 MB of x, b
+// and D at 256 cells in x), well inside one XCD's 4 MB L2; in plain x-y-z
+// order they were a full x-y slab earlier and came from HBM again.
+constexpr unsigned FLD_PANEL = 8;
+
 // Cell (i, j, k) of this thread in the tile grid of level L (tile ids dealt
-// XCD-contiguously); false if outside the level.
+// XCD-contiguously, in y panels); false if outside the level.
 template <int NDIM>
 __device__ __forceinline__ bool fld_tile_cell(const FldLevel& L, int* p) {
   using T = FldTile<NDIM>;
   const unsigned tx = (L.n[0] + T::TX - 1) / T::TX, ty = (L.n[1] + T::TY - 1) / T::TY;
+  const unsigned tz = (L.n[2] + T::TZ - 1) / T::TZ;
   const unsigned b = (unsigned)xcd_tile(blockIdx.x, gridDim.x);
-  const unsigned bx = b % tx, r = b / tx;
-  const unsigned by = r % ty, bz = r / ty;
+  // panel pn holds tile rows [pn*FLD_PANEL, pn*FLD_PANEL + py); the last may be short
+  const unsigned pn = b / (tx * FLD_PANEL * tz), rem = b - pn * (tx * FLD_PANEL * tz);
+  const unsigned py = min(FLD_PANEL, ty - pn * FLD_PANEL);
+  const unsigned bx = rem % tx, r = rem / tx;
+  const unsigned by = pn * FLD_PANEL + r % py, bz = r / py;
   const int t = threadIdx.x;
   p[0] = (int)bx * T::TX + t % T::TX;
   p[1] = (int)by * T::TY + (t / T::TX) % T::TY;
