@@ -311,18 +311,21 @@ def bench_rad(args, n=256, steps=20):
 
 
 def fld_cycle_bytes(levels):
-    """Algorithmic HBM bytes of one V(2,2) cycle over the given level sizes:
-    per level, 8 red-black half-sweeps of 20 B per cell (read the other
-    colour's x, the own colour's b, both colours' D; write the own x), the
-    residual restriction (read x, b, D: 24 B per fine cell) and the
-    prolongation (read and write x: 16 B per fine cell); the coarsest level
-    has no transfers."""
+    """Algorithmic HBM bytes of one V(2,2) cycle over the given level sizes,
+    per cell of a level: 8 red-black half-sweeps of 20 B (read the other
+    colour's x, the own colour's b, both colours' D; write the own x); the
+    restriction of the red residuals (the black ones are zero after the
+    black half-sweep): read b, x and D of the red cells and x and D of the
+    black ones, 20 B, and write the coarse b and x, 2 B; the prolongation into
+    the black cells only (the red half-sweep that follows overwrites the red
+    ones): read and write the black x, 8 B, and read the coarse x, 1 B.  The
+    coarsest level has no transfers."""
     total = 0
     for l, (a, b, c) in enumerate(levels):
         cells = a * b * c
         total += 8 * 20 * cells
         if l + 1 < len(levels):
-            total += (24 + 16) * cells
+            total += (20 + 2 + 8 + 1) * cells
     return total
 
 

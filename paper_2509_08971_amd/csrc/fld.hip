@@ -328,16 +328,23 @@ template <> struct FldTile<3> { static constexpr int TX = 32, TY = 4, TZ = 2; };
 
 // Tile rows (along y) of one panel: tile ids run x fastest, then y inside the
 // panel, then z, then panel.  The z neighbours of a tile were then touched one
-// panel slab earlier (TX*tx x TY*FLD_PANEL x TZ cells, about 0.4 MB of x, b
+// panel slab earlier (TX*tx x TY*FLD_PANEL x TZ cells, about 0.2 MB of x, b
 // and D at 256 cells in x), well inside one XCD's 4 MB L2; in plain x-y-z
 // order they were a full x-y slab earlier and came from HBM again.
-constexpr unsigned FLD_PANEL = 8;
+constexpr unsigned FLD_PANEL = 4;
 
-// Cell (i, j, k) of this thread in the tile grid of level L (tile ids dealt
-// XCD-contiguously, in y panels); false if outside the level.
-template <int NDIM>
-__device__ __forceinline__ bool fld_tile_cell(const FldLevel& L, int* p) {
-  using T = FldTile<NDIM>;
+// Tiles of 512 cells for the kernels that work on one colour (half-sweep,
+// red residuals, prolongation into the black cells): one thread per cell of
+// that colour, so a wave covers 32 slots of two rows.
+template <int NDIM> struct FldColourTile;
+template <> struct FldColourTile<1> { static constexpr int TX = 512, TY = 1, TZ = 1; };
+template <> struct FldColourTile<2> { static constexpr int TX = 64, TY = 8, TZ = 1; };
+template <> struct FldColourTile<3> { static constexpr int TX = 64, TY = 4, TZ = 2; };
+
+// Origin (in cells) of this workgroup's TX x TY x TZ tile of level L: tile ids
+// dealt XCD-contiguously, in y panels.
+template <class T>
+__device__ __forceinline__ void fld_tile_origin(const FldLevel& L, int* o) {
   const unsigned tx = (L.n[0] + T::TX - 1) / T::TX, ty = (L.n[1] + T::TY - 1) / T::TY;
   const unsigned tz = (L.n[2] + T::TZ - 1) / T::TZ;
   const unsigned b = (unsigned)xcd_tile(blockIdx.x, gridDim.x);
@@ -346,18 +353,48 @@ __device__ __forceinline__ bool fld_tile_cell(const FldLevel& L, int* p) {
   const unsigned py = min(FLD_PANEL, ty - pn * FLD_PANEL);
   const unsigned bx = rem % tx, r = rem / tx;
   const unsigned by = pn * FLD_PANEL + r % py, bz = r / py;
+  o[0] = (int)bx * T::TX;
+  o[1] = (int)by * T::TY;
+  o[2] = (int)bz * T::TZ;
+}
+
+template <class T>
+unsigned fld_tiles_of(const FldLevel& L) {
+  return (unsigned)(((L.n[0] + T::TX - 1) / T::TX) * ((L.n[1] + T::TY - 1) / T::TY) *
+                    ((L.n[2] + T::TZ - 1) / T::TZ));
+}
+
+// Cell (i, j, k) of this thread in the tile grid of level L; false if
+// outside the level.
+template <int NDIM>
+__device__ __forceinline__ bool fld_tile_cell(const FldLevel& L, int* p) {
+  using T = FldTile<NDIM>;
+  fld_tile_origin<T>(L, p);
   const int t = threadIdx.x;
-  p[0] = (int)bx * T::TX + t % T::TX;
-  p[1] = (int)by * T::TY + (t / T::TX) % T::TY;
-  p[2] = (int)bz * T::TZ + t / (T::TX * T::TY);
+  p[0] += t % T::TX;
+  p[1] += (t / T::TX) % T::TY;
+  p[2] += t / (T::TX * T::TY);
   return p[0] < L.n[0] && p[1] < L.n[1] && p[2] < L.n[2];
 }
 
 template <int NDIM>
 unsigned fld_tiles(const FldLevel& L) {
-  using T = FldTile<NDIM>;
-  return (unsigned)(((L.n[0] + T::TX - 1) / T::TX) * ((L.n[1] + T::TY - 1) / T::TY) *
-                    ((L.n[2] + T::TZ - 1) / T::TZ));
+  return fld_tiles_of<FldTile<NDIM>>(L);
+}
+
+// Cell (i, j, k) of colour `colour` of this thread in the colour tile grid of
+// level L (the tile origin is even along x, so the colour fixes i's parity);
+// false if outside the level.
+template <int NDIM>
+__device__ __forceinline__ bool fld_colour_cell(const FldLevel& L, int colour, int* p) {
+  using T = FldColourTile<NDIM>;
+  fld_tile_origin<T>(L, p);
+  const int t = threadIdx.x;
+  constexpr int SX = T::TX / 2;
+  p[1] += (t / SX) % T::TY;
+  p[2] += t / (SX * T::TY);
+  p[0] += 2 * (t % SX) + ((p[1] + p[2] + colour) & 1);
+  return p[0] < L.n[0] && p[1] < L.n[1] && p[2] < L.n[2];
 }
 
 // Finest level from the state: D, b = E, x = E (a float state is widened:
@@ -424,22 +461,14 @@ __global__ __launch_bounds__(256) void fld_coarsen_D(FldLevel F, FldLevel C, dou
   C.D[fld_at(C, P[0], P[1], P[2])] = s * inv;
 }
 
-// One red-black half-sweep of level L: every cell of colour `colour`.  A
-// workgroup takes 64 consecutive slots of 4 rows (one row per wave), tiles
-// dealt XCD-contiguously.
+// One red-black half-sweep of level L: every cell of colour `colour`, one
+// thread per cell of a colour tile.
 template <int NDIM>
 __global__ __launch_bounds__(256) void fld_relax(FldLevel L, FldCommon cm, int colour) {
-  const unsigned tiles_h = (L.hx + 63) / 64;
-  const unsigned b = (unsigned)xcd_tile(blockIdx.x, gridDim.x);
-  const unsigned rg = b / tiles_h;
-  const unsigned h = (b - rg * tiles_h) * 64 + (threadIdx.x & 63);
-  const unsigned row = rg * 4 + (threadIdx.x >> 6);
-  const unsigned rows = (unsigned)L.n[1] * (unsigned)L.n[2];
-  if (h >= L.hx || row >= rows) return;
-  const int j = (int)(row % (unsigned)L.n[1]), k = (int)(row / (unsigned)L.n[1]);
-  const int i = 2 * (int)h + ((j + k + colour) & 1);
-  if (i >= L.n[0]) return;
-  fld_relax_cell<NDIM>(L, cm, colour, i, j, k, row);
+  int p[3];
+  if (!fld_colour_cell<NDIM>(L, colour, p)) return;
+  fld_relax_cell<NDIM>(L, cm, colour, p[0], p[1], p[2],
+                       (unsigned)p[2] * (unsigned)L.n[1] + (unsigned)p[1]);
 }
 
 // Restriction, one thread per coarse cell (any halving pattern).
@@ -486,6 +515,51 @@ __global__ __launch_bounds__(256) void fld_restrict_tile(FldLevel F, FldLevel C,
   C.x[cc] = 0.0;
 }
 
+// Restriction after a pre-smoothing that ended with a black half-sweep.  A
+// black cell's neighbours are all red and have not changed since that
+// half-sweep set the cell so that its equation holds, so its residual is zero
+// in exact arithmetic (what the fine arithmetic would leave is rounding of
+// order eps |b|).  Only the red cells' residuals are computed, one thread per
+// red cell of a colour tile (even-aligned on every axis); the black ones enter
+// the child sums as zeros, in the same order as fld_restrict_cell.
+template <int NDIM>
+__global__ __launch_bounds__(256) void fld_restrict_red(FldLevel F, FldLevel C, FldCommon cm,
+                                                        double inv) {
+#pragma clang fp contract(off)
+  using T = FldColourTile<NDIM>;
+  static_assert(T::TX * T::TY * T::TZ == 512, "two fine cells per thread");
+  __shared__ double r[512];
+  int o[3];
+  fld_tile_origin<T>(F, o);
+  const int t = threadIdx.x;
+  constexpr int SX = T::TX / 2;
+  const int ly = (t / SX) % T::TY, lz = t / (SX * T::TY);
+  const int j = o[1] + ly, k = o[2] + lz;
+  // red: i + j + k even (o[0] is even)
+  const int li = 2 * (t % SX) + ((j + k) & 1);
+  const int p[3] = {o[0] + li, j, k};
+  double rv = 0.0;
+  if (p[0] < F.n[0] && p[1] < F.n[1] && p[2] < F.n[2])
+    rv = F.b[fld_at(F, p[0], p[1], p[2])] - fld_apply_row<NDIM>(F, cm, p);
+  const int row = (lz * T::TY + ly) * T::TX;
+  r[row + li] = rv;
+  r[row + (li ^ 1)] = 0.0;
+  __syncthreads();
+  constexpr int CX = T::TX / 2, CY = NDIM > 1 ? T::TY / 2 : 1, CZ = NDIM > 2 ? T::TZ / 2 : 1;
+  if (t >= CX * CY * CZ) return;
+  const int cx = t % CX, cy = (t / CX) % CY, cz = t / (CX * CY);
+  const int P[3] = {(o[0] >> 1) + cx, NDIM > 1 ? (o[1] >> 1) + cy : 0, NDIM > 2 ? (o[2] >> 1) + cz : 0};
+  if (P[0] >= C.n[0] || P[1] >= C.n[1] || P[2] >= C.n[2]) return;
+  double sum = 0.0;
+  for (int dz = 0; dz < (NDIM > 2 ? 2 : 1); ++dz)
+    for (int dy = 0; dy < (NDIM > 1 ? 2 : 1); ++dy)
+      for (int dx = 0; dx < 2; ++dx)
+        sum += r[(2 * cz + dz) * T::TX * T::TY + (2 * cy + dy) * T::TX + 2 * cx + dx];
+  const unsigned cc = fld_at(C, P[0], P[1], P[2]);
+  C.b[cc] = sum * inv;
+  C.x[cc] = 0.0;
+}
+
 template <int NDIM>
 __global__ __launch_bounds__(256) void fld_prolong(FldLevel F, FldLevel C, FldCommon cm) {
   int f[3];
@@ -498,6 +572,22 @@ __global__ __launch_bounds__(256) void fld_prolong_all(FldLevel F, FldLevel C, F
   int f[3];
   if (!fld_tile_cell<NDIM>(F, f)) return;
   fld_prolong_cell_all<NDIM>(F, C, cm, f);
+}
+
+// Prolongation into the cells of one colour only, one thread per cell of a
+// colour tile.  When post-smoothing follows, its first half-sweep (red) recomputes
+// every red cell from b and the black neighbours alone, so the correction of
+// the red cells is never read and only the black ones (colour 1) need it; the
+// result is the same, bit for bit, as correcting every cell.
+template <int NDIM, bool ALL>
+__global__ __launch_bounds__(256) void fld_prolong_colour(FldLevel F, FldLevel C, FldCommon cm,
+                                                          int colour) {
+  int f[3];
+  if (!fld_colour_cell<NDIM>(F, colour, f)) return;
+  if (ALL)
+    fld_prolong_cell_all<NDIM>(F, C, cm, f);
+  else
+    fld_prolong_cell(F, C, cm, f);
 }
 
 // Residual norm, two deterministic passes: per-tile sums of r^2 in a fixed
@@ -745,7 +835,7 @@ struct Solver {
   template <int NDIM>
   hipError_t relax(int l, int sweeps) {
     const FldLevel& L = lv[l];
-    const unsigned tiles = ((L.hx + 63) / 64) * (((unsigned)L.n[1] * L.n[2] + 3) / 4);
+    const unsigned tiles = fld_tiles_of<FldColourTile<NDIM>>(L);
     for (int sw = 0; sw < sweeps; ++sw)
       for (int colour = 0; colour < 2; ++colour) {
         fld_relax<NDIM><<<tiles, 256, 0, s>>>(L, cm, colour);
@@ -784,7 +874,10 @@ struct Solver {
     if (l + 1 == H.nlev) return relax<NDIM>(l, ncoarse);  // coarsest level
     if (l + 1 > H.nlev) return hipErrorInvalidValue;
     if ((e = relax<NDIM>(l, nu1)) != hipSuccess) return e;
-    if (all_halved(l + 1))
+    if (all_halved(l + 1) && nu1 > 0)
+      fld_restrict_red<NDIM><<<fld_tiles_of<FldColourTile<NDIM>>(lv[l]), 256, 0, s>>>(
+          lv[l], lv[l + 1], cm, inv_children[l + 1]);
+    else if (all_halved(l + 1))
       fld_restrict_tile<NDIM><<<fld_tiles<NDIM>(lv[l]), 256, 0, s>>>(lv[l], lv[l + 1], cm,
                                                                     inv_children[l + 1]);
     else
@@ -792,10 +885,17 @@ struct Solver {
                                                                      inv_children[l + 1]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = vcycle<NDIM>(l + 1)) != hipSuccess) return e;
-    if (all_halved(l + 1))
+    if (nu2 > 0) {
+      const unsigned tiles = fld_tiles_of<FldColourTile<NDIM>>(lv[l]);
+      if (all_halved(l + 1))
+        fld_prolong_colour<NDIM, true><<<tiles, 256, 0, s>>>(lv[l], lv[l + 1], cm, 1);
+      else
+        fld_prolong_colour<NDIM, false><<<tiles, 256, 0, s>>>(lv[l], lv[l + 1], cm, 1);
+    } else if (all_halved(l + 1)) {
       fld_prolong_all<NDIM><<<fld_tiles<NDIM>(lv[l]), 256, 0, s>>>(lv[l], lv[l + 1], cm);
-    else
+    } else {
       fld_prolong<NDIM><<<fld_tiles<NDIM>(lv[l]), 256, 0, s>>>(lv[l], lv[l + 1], cm);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return relax<NDIM>(l, nu2);
   }
