@@ -40,23 +40,30 @@ FLD_SOURCES = [os.path.join(ROOT, "paper_2509_08971_amd", "csrc", f)
 FLD_COUNTERS_FILE = os.path.join(ROOT, "profiles", "fld_relax_diffusion256_fp64_hbm_counters.md")
 
 
-def kernel_source_hash():
+def code_hash(files):
+    """sha256 of the code of the given C++/HIP sources: comments, trailing
+    blanks and empty lines removed, so that an edit of a comment keeps the
+    counters taken on the same code."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+    for f in files:
+        with open(f) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            line = line.split("//", 1)[0].rstrip()
+            if line:
+                h.update(line.encode() + b"\n")
     return h.hexdigest()
+
+
+def kernel_source_hash():
+    return code_hash(KERNEL_SOURCES)
 
 
 def fld_source_hash():
-    import hashlib
-    h = hashlib.sha256()
-    for f in FLD_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    return code_hash(FLD_SOURCES)
 
 
 def fld_measured_cycle_bytes():

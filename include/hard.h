@@ -268,7 +268,9 @@ hard_status_t hard_hydro_step_adjoint(const hard_grid_t* g, const void* U_n, con
  * linear interpolation, coarse operators rediscretised from the mean of D
  * over the children.  Every axis whose size is even is halved (a periodic
  * axis only while the half is even or one); the coarsest level is relaxed
- * `ncoarse` sweeps from zero.
+ * `ncoarse` sweeps from zero.  After pre-smoothing (nu1 > 0) the residuals
+ * of the black cells, zero in exact arithmetic after a black half-sweep, are
+ * taken as zero, so results agree with a plain evaluation to rounding only.
  * ------------------------------------------------------------------------ */
 #define HARD_FLD_EDDINGTON 0 /* lambda = 1/3 (optically thick limit) */
 #define HARD_FLD_LEVERMORE 1 /* lambda = (2 + R)/(6 + 3R + R^2),
@@ -296,7 +298,8 @@ hard_status_t hard_rad_diffuse_workspace_bytes(const hard_grid_t* g, size_t* byt
  * (device double, dt >= 0), by opts->ncycles V(nu1, nu2) cycles starting from
  * E_old.  resid_dev (device array of ncycles + 1 doubles, or NULL) receives
  * the 2-norm of the finest-level residual E_old - A x before the first cycle
- * and after each one (summed with atomics: not bitwise reproducible).
+ * and after each one (per-tile sums added in a fixed order: bitwise
+ * reproducible).
  * Requirements: g->rad = 1, g->kappa > 0, every periodic axis of even size
  * (odd: HARD_ERR_UNSUPPORTED).  HARD_F32 states are read into and solved in
  * double; E_r is rounded to float when it is stored back.

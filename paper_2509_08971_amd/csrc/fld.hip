@@ -18,12 +18,19 @@
 //                  every cell of a colour depends only on the other colour,
 //                  so the half-sweep is one parallel pass in any order)
 //   fld_restrict   per coarse cell: the fine residual b - A x averaged over
-//                  the children -> coarse b; coarse x = 0
+//                  the children -> coarse b; coarse x = 0 (fld_restrict_tile
+//                  and fld_restrict_red: the same from an LDS tile of fine
+//                  residuals; the latter computes only the red ones, the black
+//                  residuals being zero after a black half-sweep)
 //   fld_prolong    per fine cell: x += linear interpolation of the coarse x
 //                  (weights 3/4, 1/4 along each halved axis, the edge value
-//                  repeated beyond a wall)
+//                  repeated beyond a wall); fld_prolong_colour: the black
+//                  cells only, when a red half-sweep follows
+//   fld_vcycle_tail  the V-cycle below the first level that fits in one
+//                  workgroup's LDS, in one launch
 //   fld_store      the finest x back into the state's E_r field
-//   fld_resid_sq   per cell (b - A x)^2, one atomic add per block
+//   fld_resid_sq   per tile the sum of (b - A x)^2; fld_resid_final adds the
+//                  tile sums in a fixed order (deterministic)
 //
 // Every level keeps x, b and D colour-split (the red cells, then the black
 // ones, each colour packed two-to-one along x), so that a half-sweep reads
@@ -37,7 +44,9 @@
 // `ncoarse` sweeps from zero (one cell: A = [1], exact in one sweep).
 //
 // Plain arithmetic throughout (IEEE division and square root, no
-// contraction), in the order the formulas above are written.  These kernels
+// contraction), in the order the formulas above are written; the zero black
+// residuals of fld_restrict_red are the one departure from evaluating each
+// formula as written.  These kernels
 // stream a few arrays and do a handful of flops per cell: they are bound by
 // memory, not by arithmetic.
 
