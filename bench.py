@@ -35,9 +35,16 @@ OPS_PER_ZU_3D = 1145
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_08971_amd", "csrc", f)
                   for f in ("hydro_device.hpp", "stage_tile.hpp", "stage.hip", "launch.hpp")]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "stage_kernel_blast256_fp64_hbm_counters.md")
-FLD_SOURCES = [os.path.join(ROOT, "paper_2509_08971_amd", "csrc", f)
-               for f in ("fld.hip", "hydro_device.hpp")]
+def _csrc(*names):
+    return [os.path.join(ROOT, "paper_2509_08971_amd", "csrc", f) for f in names]
+
+
+FLD_SOURCES = _csrc("fld.hip", "hydro_device.hpp")
 FLD_COUNTERS_FILE = os.path.join(ROOT, "profiles", "fld_relax_diffusion256_fp64_hbm_counters.md")
+WENO_SOURCES = _csrc("weno.hip", "hydro_device.hpp", "launch.hpp")
+WENO_COUNTERS_FILE = os.path.join(ROOT, "profiles", "weno_pipeline_blast256_fp64_hbm_counters.md")
+RAD_SOURCES = _csrc("rad.hip", "stage.hip", "stage_tile.hpp", "hydro_device.hpp", "launch.hpp")
+RAD_COUNTERS_FILE = os.path.join(ROOT, "profiles", "rad_step_radiation256_fp64_hbm_counters.md")
 
 
 def code_hash(files):
@@ -66,20 +73,28 @@ def fld_source_hash():
     return code_hash(FLD_SOURCES)
 
 
-def fld_measured_cycle_bytes():
-    """HBM bytes per V(2,2) cycle of the 256^3 diffusion from the committed
-    FETCH_SIZE/WRITE_SIZE runs, if the diffusion sources are unchanged since."""
+def measured_bytes(path, key, sources):
+    """HBM bytes (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel factors)
+    per unit of a bench leg from the committed counter summary `path`: its
+    lines `<key>-source-sha256` and `<key>-bytes-measured`, or None if the code
+    of `sources` changed since the counters were taken."""
     try:
-        lines = dict(l.split(": ", 1) for l in open(FLD_COUNTERS_FILE).read().splitlines()
-                     if ": " in l and not l.startswith(("|", " ", "#")))
+        with open(path) as f:
+            lines = dict(l.split(": ", 1) for l in f.read().splitlines()
+                         if l.startswith(key + "-") and ": " in l)
     except OSError:
         return None
-    if lines.get("fld-source-sha256", "").strip() != fld_source_hash():
+    if lines.get(f"{key}-source-sha256", "").strip() != code_hash(sources):
         return None
     try:
-        return int(lines["cycle-bytes-measured"])
+        return int(lines[f"{key}-bytes-measured"])
     except (KeyError, ValueError):
         return None
+
+
+def fld_measured_cycle_bytes():
+    """HBM bytes per V(2,2) cycle of the 256^3 diffusion."""
+    return measured_bytes(FLD_COUNTERS_FILE, "fld", FLD_SOURCES)
 
 
 def _counter_lines():
@@ -272,7 +287,9 @@ def bench_weno(args, n=256, steps=10):
             "pipeline_bytes_per_zone_update": pipe_bytes,
             "roofline": {"bound": "hbm", "kernel": "whole WENO5-Z + HLL step (pipeline bytes)",
                          "achieved": pipe_bytes * zus / 1e9, "peak": 8000.0, "unit": "GB/s",
-                         "frac": pipe_bytes * zus / 1e9 / 8000.0, "traffic": None},
+                         "frac": pipe_bytes * zus / 1e9 / 8000.0,
+                         "traffic": measured_bytes(WENO_COUNTERS_FILE, "weno", WENO_SOURCES),
+                         "algorithmic_bytes": pipe_bytes * N, "per": "step"},
             "status_flags": flags}
 
 
@@ -313,7 +330,9 @@ def bench_rad(args, n=256, steps=20):
             "roofline": {"bound": "hbm", "kernel": "whole radiation step (stage kernels, E_r "
                                                   "advection, exchange)",
                          "achieved": step_bytes * zus / 1e9, "peak": 8000.0, "unit": "GB/s",
-                         "frac": step_bytes * zus / 1e9 / 8000.0, "traffic": None},
+                         "frac": step_bytes * zus / 1e9 / 8000.0,
+                         "traffic": measured_bytes(RAD_COUNTERS_FILE, "rad", RAD_SOURCES),
+                         "algorithmic_bytes": step_bytes * N, "per": "step"},
             "status_flags": flags}
 
 
@@ -388,7 +407,7 @@ def bench_fld(args, n=256, ncycles=4, reps=10):
             "roofline": {"bound": "hbm", "kernel": "one V(2,2) cycle (all levels)",
                          "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                          "frac": achieved / 8000.0, "traffic": fld_measured_cycle_bytes(),
-                         "algorithmic_bytes": cyc},
+                         "algorithmic_bytes": cyc, "per": "V(2,2) cycle"},
             "timing": f"median of {reps} calls each of {ncycles} and {2 * ncycles} cycles, HIP "
                       f"events on the launch stream; a cycle is the difference / {ncycles}",
             "status_flags": flags}

@@ -159,17 +159,40 @@ __global__ __launch_bounds__(256) void weno_prim(WenoArgs a) {
 }
 
 // Faces along axis AX: face f (0..n_AX) lies between cells f-1 and f.
-// Linear face index, x fastest: AX = 0: (f, j, k); AX = 1: (i, f, k);
-// AX = 2: (i, j, f).
+// Linear face index (the layout of the face array), x fastest: AX = 0:
+// (f, j, k); AX = 1: (i, f, k); AX = 2: (i, j, f).
+//
+// Along x and y a block takes 256 consecutive faces of that layout: the six
+// cells of a face lie in its own row or plane, which the L2 holds.  Along z
+// they lie in six planes, and in layout order a W plane is needed again
+// about six planes of work later (16 MB at 256^2 cells a plane, beyond one
+// XCD's 4 MB L2), so the z faces go by tile columns instead: a block takes
+// a 64 x 4 (i, j) tile of one face plane, and the blocks of one tile column
+// follow each other plane by plane.
+constexpr int WENO_ZTX = 64, WENO_ZTY = 4;
+
 template <typename R, int NDIM, int AX>
 __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
   constexpr int NV = NDIM + 2;
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const long long N = (long long)nx * ny * nz;
   const long long nface = N / a.n[AX] * (a.n[AX] + 1);
-  const long long idx = (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (idx >= nface) return;
+  long long idx;
   int i, j, k, f;
+  if constexpr (AX == 2) {
+    const long long b = xcd_tile(blockIdx.x, gridDim.x);
+    const int tx = (nx + WENO_ZTX - 1) / WENO_ZTX;
+    f = (int)(b % (nz + 1));
+    const long long r = b / (nz + 1);
+    i = (int)(r % tx) * WENO_ZTX + (int)(threadIdx.x % WENO_ZTX);
+    j = (int)(r / tx) * WENO_ZTY + (int)(threadIdx.x / WENO_ZTX);
+    k = 0;
+    if (i >= nx || j >= ny) return;
+    idx = ((long long)f * ny + j) * nx + i;
+  } else {
+    idx = (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nface) return;
+  }
   if constexpr (AX == 0) {
     f = (int)(idx % (nx + 1));
     long long r = idx / (nx + 1);
@@ -182,12 +205,6 @@ __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
     f = (int)(r % (ny + 1));
     k = (int)(r / (ny + 1));
     j = 0;
-  } else {
-    i = (int)(idx % nx);
-    long long r = idx / nx;
-    j = (int)(r % ny);
-    f = (int)(r / ny);
-    k = 0;
   }
   const R* W = static_cast<const R*>(a.W);
   // six cells f-3 .. f+2 along AX, primitives with the wall flip applied
@@ -291,7 +308,11 @@ static hipError_t weno_stage_t(const WenoArgs& a, int stage, hipStream_t s) {
   auto faces = [&](int d) { return (unsigned)((N / a.n[d] * (a.n[d] + 1) + 255) / 256); };
   hipLaunchKernelGGL((weno_face<R, NDIM, 0>), dim3(faces(0)), dim3(256), 0, s, a);
   if constexpr (NDIM >= 2) hipLaunchKernelGGL((weno_face<R, NDIM, 1>), dim3(faces(1)), dim3(256), 0, s, a);
-  if constexpr (NDIM >= 3) hipLaunchKernelGGL((weno_face<R, NDIM, 2>), dim3(faces(2)), dim3(256), 0, s, a);
+  if constexpr (NDIM >= 3) {
+    const unsigned zt = (unsigned)((a.n[0] + WENO_ZTX - 1) / WENO_ZTX) *
+                        (unsigned)((a.n[1] + WENO_ZTY - 1) / WENO_ZTY) * (unsigned)(a.n[2] + 1);
+    hipLaunchKernelGGL((weno_face<R, NDIM, 2>), dim3(zt), dim3(256), 0, s, a);
+  }
   const unsigned nbu = nb < 2048u ? nb : 2048u;
   if (stage == 1)
     hipLaunchKernelGGL((weno_update<R, NDIM, 1>), dim3(nbu), dim3(256), 0, s, a);
