@@ -125,10 +125,12 @@ __global__ __launch_bounds__(256) void rad_advect(RadArgs a) {
 // negated beyond a reflecting wall) go to LDS once, every x and y face of the
 // plane is computed once into LDS, and the z faces come from a window of five
 // planes of (rho, u_z, p, E_r) that each thread keeps for its own column (the
-// face above a cell is the face below it on the next plane).  Each primitive
-// is thus recovered about twice per plane instead of fifteen times per cell,
-// and each face once instead of twice.  Face states, fluxes and the stage combine are those of
-// rad_advect, term for term and in the same order.
+// face above a cell is the face below it on the next plane).  The window is
+// fed from the LDS plane, so each cell of a plane is read and its primitives
+// recovered once (its halo copies aside): a thread finishes plane q-2 when
+// plane q arrives, carrying the x and y part of L of the planes in between.
+// Face states, fluxes and the stage combine are those of rad_advect, term for
+// term and in the same order.
 constexpr int RW_TX = 32, RW_TY = 8, RW_CZ = 32;
 constexpr int RW_LX = RW_TX + 4, RW_LY = RW_TY + 4;
 
@@ -180,6 +182,7 @@ template <typename R, int STAGE>
 __global__ __launch_bounds__(256) void rad_advect_walk(RadArgs a) {
 #pragma clang fp contract(off)
   __shared__ double P[5][RW_LY][RW_LX];        // rho, u_x, u_y, p, E_r of one plane
+  __shared__ double UZ[RW_TY][RW_TX];          // u_z of the plane's tile cells
   __shared__ double FX[RW_TY][RW_TX + 1];      // x faces of the plane's rows
   __shared__ double FY[RW_TY + 1][RW_TX];      // y faces of the plane's columns
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
@@ -194,8 +197,10 @@ __global__ __launch_bounds__(256) void rad_advect_walk(RadArgs a) {
   const int i = x0 + lx, j = y0 + ly;
   const bool own = i < nx && j < ny;
   const int z0 = (int)bz * RW_CZ, z1 = min(nz, z0 + RW_CZ);
-  // z window of the own column: planes k-2 .. k+2
+  // z window of the own column: planes q-4 .. q when plane q has been loaded
   double wr_[5], wu[5], wp[5], we[5];
+  // x and y part of L for the own cell of planes q-2, q-1, q
+  double lxy[3] = {0.0, 0.0, 0.0};
   auto load_z = [&](int s, int kk) {
     if (!own) return;
     bool flip;
@@ -207,70 +212,95 @@ __global__ __launch_bounds__(256) void rad_advect_walk(RadArgs a) {
     wp[s] = w[4];
     we[s] = w[5];
   };
+  // planes z0-4 .. z0-1 of the window (slots 0..3; z0-4 and z0-3 are never
+  // read by a face of this chunk, but keep the slot arithmetic uniform)
 #pragma unroll
-  for (int s = 0; s < 4; ++s) load_z(s, z0 - 2 + s);
+  for (int s = 2; s < 4; ++s) load_z(s, z0 - 4 + s);
   unsigned flags = 0;
-  double fz_lo = 0.0;  // z face below the current plane, carried from the plane before
-  for (int k = z0; k < z1; ++k) {
-    load_z(4, k + 2);
-    // the plane's tile and halo (corners are not needed)
-    for (int t = threadIdx.x; t < RW_LX * RW_LY; t += 256) {
-      const int px = t % RW_LX, py = t / RW_LX;
-      const int gi = x0 - 2 + px, gj = y0 - 2 + py;
-      const bool xin = gi >= 0 && gi < nx, yin = gj >= 0 && gj < ny;
-      if (!xin && !yin) continue;
-      bool fx = false, fy = false;
-      const int qi = xin ? gi : remap(gi, nx, a.bc[0][0], a.bc[0][1], fx);
-      const int qj = yin ? gj : remap(gj, ny, a.bc[1][0], a.bc[1][1], fy);
-      double w[6];
-      rad_prims<R>(src, N, ((long long)k * ny + qj) * nx + qi, a.gamma, fx ? 0 : (fy ? 1 : -1), w);
-      P[0][py][px] = w[0];
-      P[1][py][px] = w[1];
-      P[2][py][px] = w[2];
-      P[3][py][px] = w[4];
-      P[4][py][px] = w[5];
-    }
-    __syncthreads();
-    // every x and y face of the plane once: x face f of row r lies between
-    // tile cells f-1 and f (LDS cells f .. f+3), y face f of column c likewise
-    for (int t = threadIdx.x; t < RW_TY * (RW_TX + 1) + (RW_TY + 1) * RW_TX; t += 256) {
-      double rho[4], un[4], p[4], er[4];
-      if (t < RW_TY * (RW_TX + 1)) {
-        const int r = t / (RW_TX + 1), f = t % (RW_TX + 1);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          rho[s] = P[0][r + 2][f + s];
-          un[s] = P[1][r + 2][f + s];
-          p[s] = P[3][r + 2][f + s];
-          er[s] = P[4][r + 2][f + s];
-        }
-        FX[r][f] = rad_face(rho, un, p, er, a.gamma);
-      } else {
-        const int u = t - RW_TY * (RW_TX + 1);
-        const int f = u / RW_TX, cc = u % RW_TX;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          rho[s] = P[0][f + s][cc + 2];
-          un[s] = P[2][f + s][cc + 2];
-          p[s] = P[3][f + s][cc + 2];
-          er[s] = P[4][f + s][cc + 2];
-        }
-        FY[f][cc] = rad_face(rho, un, p, er, a.gamma);
+  double fz_lo = 0.0;  // z face below plane q-2, carried from the plane before
+  for (int q = z0; q < z1 + 2; ++q) {
+    if (q < z1) {
+      // plane q: the tile and its halo (corners are not needed) into LDS, the
+      // own column's (rho, u_z, p, E_r) into the window from there
+      for (int t = threadIdx.x; t < RW_LX * RW_LY; t += 256) {
+        const int px = t % RW_LX, py = t / RW_LX;
+        const int gi = x0 - 2 + px, gj = y0 - 2 + py;
+        const bool xin = gi >= 0 && gi < nx, yin = gj >= 0 && gj < ny;
+        if (!xin && !yin) continue;
+        bool fx = false, fy = false;
+        const int qi = xin ? gi : remap(gi, nx, a.bc[0][0], a.bc[0][1], fx);
+        const int qj = yin ? gj : remap(gj, ny, a.bc[1][0], a.bc[1][1], fy);
+        double w[6];
+        rad_prims<R>(src, N, ((long long)q * ny + qj) * nx + qi, a.gamma, fx ? 0 : (fy ? 1 : -1), w);
+        P[0][py][px] = w[0];
+        P[1][py][px] = w[1];
+        P[2][py][px] = w[2];
+        P[3][py][px] = w[4];
+        P[4][py][px] = w[5];
+        const int cx = px - 2, cy = py - 2;
+        if (cx >= 0 && cx < RW_TX && cy >= 0 && cy < RW_TY) UZ[cy][cx] = w[3];
       }
+      __syncthreads();
+      if (own) {
+        wr_[4] = P[0][ly + 2][lx + 2];
+        wu[4] = UZ[ly][lx];
+        wp[4] = P[3][ly + 2][lx + 2];
+        we[4] = P[4][ly + 2][lx + 2];
+      }
+      // every x and y face of the plane once: x face f of row r lies between
+      // tile cells f-1 and f (LDS cells f .. f+3), y face f of column c likewise
+      for (int t = threadIdx.x; t < RW_TY * (RW_TX + 1) + (RW_TY + 1) * RW_TX; t += 256) {
+        double rho[4], un[4], p[4], er[4];
+        if (t < RW_TY * (RW_TX + 1)) {
+          const int r = t / (RW_TX + 1), f = t % (RW_TX + 1);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            rho[s] = P[0][r + 2][f + s];
+            un[s] = P[1][r + 2][f + s];
+            p[s] = P[3][r + 2][f + s];
+            er[s] = P[4][r + 2][f + s];
+          }
+          FX[r][f] = rad_face(rho, un, p, er, a.gamma);
+        } else {
+          const int u = t - RW_TY * (RW_TX + 1);
+          const int f = u / RW_TX, cc = u % RW_TX;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            rho[s] = P[0][f + s][cc + 2];
+            un[s] = P[2][f + s][cc + 2];
+            p[s] = P[3][f + s][cc + 2];
+            er[s] = P[4][f + s][cc + 2];
+          }
+          FY[f][cc] = rad_face(rho, un, p, er, a.gamma);
+        }
+      }
+      __syncthreads();
+      if (own) {
+        double l = 0.0;
+        {
+          const double df = FX[ly][lx + 1] - FX[ly][lx];
+          l = l - (a.dx_pow2 ? df * a.inv_dx[0] : df / a.dx[0]);
+        }
+        {
+          const double df = FY[ly + 1][lx] - FY[ly][lx];
+          l = l - (a.dx_pow2 ? df * a.inv_dx[1] : df / a.dx[1]);
+        }
+        lxy[2] = l;
+      }
+      // no barrier here: the next plane's loader writes only P and UZ, whose
+      // last reads came before the barrier above, and FX and FY are written
+      // again only after the loader's barrier, which every reader reaches
+      // after its reads
+    } else {
+      // planes z1 and z1+1 close the window (the next chunk's, or ghosts)
+      load_z(4, q);
     }
-    __syncthreads();
-    if (own) {
+    // plane k = q-2 is complete: its z faces from planes k-2 .. k+2
+    const int k = q - 2;
+    if (own && k >= z0) {
       if (k == z0) fz_lo = rad_face(wr_, wu, wp, we, a.gamma);
       const double fz_hi = rad_face(wr_ + 1, wu + 1, wp + 1, we + 1, a.gamma);
-      double l = 0.0;
-      {
-        const double df = FX[ly][lx + 1] - FX[ly][lx];
-        l = l - (a.dx_pow2 ? df * a.inv_dx[0] : df / a.dx[0]);
-      }
-      {
-        const double df = FY[ly + 1][lx] - FY[ly][lx];
-        l = l - (a.dx_pow2 ? df * a.inv_dx[1] : df / a.dx[1]);
-      }
+      double l = lxy[0];
       {
         const double df = fz_hi - fz_lo;
         l = l - (a.dx_pow2 ? df * a.inv_dx[2] : df / a.dx[2]);
@@ -289,7 +319,6 @@ __global__ __launch_bounds__(256) void rad_advect_walk(RadArgs a) {
       dst[5 * N + c] = out;
       if (!isfinite(out)) flags = FLAG_NONFINITE;
     }
-    __syncthreads();
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       wr_[s] = wr_[s + 1];
@@ -297,6 +326,8 @@ __global__ __launch_bounds__(256) void rad_advect_walk(RadArgs a) {
       wp[s] = wp[s + 1];
       we[s] = we[s + 1];
     }
+    lxy[0] = lxy[1];
+    lxy[1] = lxy[2];
   }
   flags = wave_or(flags);
   if ((threadIdx.x & 63) == 0 && flags) atomicOr(&a.ctl->flags, flags);

@@ -58,7 +58,11 @@ def run_gpu(n, bc, U0, dts, rad, gamma=1.4, dtype=torch.float64, dx=None):
 
 
 CASES = [((200,), (O, O)), ((64,), (R, R)), ((40, 33), (P, P, R, R)),
-         ((21, 17, 19), (P, P, O, O, R, R)), ((16, 16, 16), (P, P))]
+         ((21, 17, 19), (P, P, O, O, R, R)), ((16, 16, 16), (P, P)),
+         # 3D walks over several 32-plane z chunks (the last one short), ragged
+         # x-y tiles, with walls, outflow and periodic seams along z
+         ((24, 12, 70), (O, O, P, P, R, R)), ((40, 9, 66), (R, R, O, O, P, P)),
+         ((33, 10, 40), (P, P, R, R, O, O))]
 
 
 @pytest.mark.parametrize("n,bc", CASES)
