@@ -480,6 +480,88 @@ __global__ __launch_bounds__(256) void fld_relax(FldLevel L, FldCommon cm, int c
                        (unsigned)p[2] * (unsigned)L.n[1] + (unsigned)p[1]);
 }
 
+// The 3D half-sweep with two cells of the colour per thread (slots h and
+// h + 1 of a row, h even) and 16-byte loads.  The half-sweep's loads all hit
+// the L1 in the end, but a 64-lane load of 8-byte words costs the L1's
+// address and data path about as many cycles as it has 4-lane groups, so
+// with six neighbour rows of x and D per cell that path, not HBM, set the
+// time.  Here one 16-byte load brings a neighbour row's values for both
+// cells: 14 loads and stores per two cells instead of 30.  Needs hx even (the
+// pairs and both colour halves 16-byte aligned), hence nx a multiple of 4.
+// Faces, order and arithmetic are those of fld_relax_cell.
+struct FldPairTile {
+  static constexpr int TX = 128, TY = 4, TZ = 2;  // cells; 32 threads take a row
+};
+
+__device__ __forceinline__ double2 fld_ld2(const double* p) {
+  return *reinterpret_cast<const double2*>(p);
+}
+
+__global__ __launch_bounds__(256) void fld_relax_pair(FldLevel L, FldCommon cm, int colour) {
+#pragma clang fp contract(off)
+  int o[3];
+  fld_tile_origin<FldPairTile>(L, o);
+  const int t = threadIdx.x;
+  const int j = o[1] + (t / 32) % FldPairTile::TY, k = o[2] + t / (32 * FldPairTile::TY);
+  const int h = (o[0] >> 1) + 2 * (t % 32);
+  const int n0 = L.n[0], n1 = L.n[1], n2 = L.n[2], hx = (int)L.hx;
+  if (j >= n1 || k >= n2 || h >= hx) return;
+  const int par = (j + k + colour) & 1;
+  const int i0 = 2 * h + par;  // the second cell is i0 + 2 (< nx: nx = 2 hx)
+  const unsigned row = (unsigned)k * (unsigned)n1 + (unsigned)j;
+  const unsigned ob = colour ? 0u : L.cs;  // other colour
+  const unsigned own = (colour ? L.cs : 0u) + row * L.hx + (unsigned)h;
+  const unsigned oth = ob + row * L.hx + (unsigned)h;
+  // the in-row slot beyond the pair: h - 1 below the first cell (par 0) or
+  // h + 2 above the second (par 1), wrapped on a periodic axis, clamped on a
+  // wall (where the face is closed and the value unused)
+  int he = par ? h + 2 : h - 1;
+  if (he < 0) he = cm.per[0] ? hx - 1 : 0;
+  if (he >= hx) he = cm.per[0] ? 0 : hx - 1;
+  const int jm = j > 0 ? j - 1 : (cm.per[1] ? n1 - 1 : j);
+  const int jp = j < n1 - 1 ? j + 1 : (cm.per[1] ? 0 : j);
+  const int km = k > 0 ? k - 1 : (cm.per[2] ? n2 - 1 : k);
+  const int kp = k < n2 - 1 ? k + 1 : (cm.per[2] ? 0 : k);
+  auto at = [&](int jj, int kk) {
+    return ob + ((unsigned)kk * (unsigned)n1 + (unsigned)jj) * L.hx + (unsigned)h;
+  };
+  const double2 Dc = fld_ld2(L.D + own), bc = fld_ld2(L.b + own);
+  const double2 xr = fld_ld2(L.x + oth), Dr = fld_ld2(L.D + oth);
+  const double xe = L.x[oth - (unsigned)h + (unsigned)he], De = L.D[oth - (unsigned)h + (unsigned)he];
+  const double2 xym = fld_ld2(L.x + at(jm, k)), Dym = fld_ld2(L.D + at(jm, k));
+  const double2 xyp = fld_ld2(L.x + at(jp, k)), Dyp = fld_ld2(L.D + at(jp, k));
+  const double2 xzm = fld_ld2(L.x + at(j, km)), Dzm = fld_ld2(L.D + at(j, km));
+  const double2 xzp = fld_ld2(L.x + at(j, kp)), Dzp = fld_ld2(L.D + at(j, kp));
+  const bool wx = cm.per[0] && n0 > 1, wy = cm.per[1] && n1 > 1, wz = cm.per[2] && n2 > 1;
+  const bool oy[2] = {j > 0 || wy, j < n1 - 1 || wy};
+  const bool oz[2] = {k > 0 || wz, k < n2 - 1 || wz};
+  double res[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int i = i0 + 2 * c;
+    const double xn[6] = {c == 0 ? (par ? xr.x : xe) : (par ? xr.y : xr.x),
+                          c == 0 ? (par ? xr.y : xr.x) : (par ? xe : xr.y),
+                          c ? xym.y : xym.x, c ? xyp.y : xyp.x,
+                          c ? xzm.y : xzm.x, c ? xzp.y : xzp.x};
+    const double Dn[6] = {c == 0 ? (par ? Dr.x : De) : (par ? Dr.y : Dr.x),
+                          c == 0 ? (par ? Dr.y : Dr.x) : (par ? De : Dr.y),
+                          c ? Dym.y : Dym.x, c ? Dyp.y : Dyp.x,
+                          c ? Dzm.y : Dzm.x, c ? Dzp.y : Dzp.x};
+    const bool open[6] = {i > 0 || wx, i < n0 - 1 || wx, oy[0], oy[1], oz[0], oz[1]};
+    const double D0 = c ? Dc.y : Dc.x;
+    double num = c ? bc.y : bc.x;
+    double den = 1.0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const double a = open[f] ? (D0 + Dn[f]) * L.K[f >> 1] : 0.0;
+      num += a * (open[f] ? xn[f] : 0.0);
+      den += a;
+    }
+    res[c] = num / den;
+  }
+  *reinterpret_cast<double2*>(L.x + own) = make_double2(res[0], res[1]);
+}
+
 // Restriction, one thread per coarse cell (any halving pattern).
 template <int NDIM>
 __global__ __launch_bounds__(256) void fld_restrict(FldLevel F, FldLevel C, FldCommon cm,
@@ -845,9 +927,14 @@ struct Solver {
   hipError_t relax(int l, int sweeps) {
     const FldLevel& L = lv[l];
     const unsigned tiles = fld_tiles_of<FldColourTile<NDIM>>(L);
+    const bool pair = NDIM == 3 && L.hx % 2 == 0;
+    const unsigned ptiles = fld_tiles_of<FldPairTile>(L);
     for (int sw = 0; sw < sweeps; ++sw)
       for (int colour = 0; colour < 2; ++colour) {
-        fld_relax<NDIM><<<tiles, 256, 0, s>>>(L, cm, colour);
+        if (pair)
+          fld_relax_pair<<<ptiles, 256, 0, s>>>(L, cm, colour);
+        else
+          fld_relax<NDIM><<<tiles, 256, 0, s>>>(L, cm, colour);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
       }
