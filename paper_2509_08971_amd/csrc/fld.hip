@@ -497,20 +497,26 @@ __device__ __forceinline__ double2 fld_ld2(const double* p) {
   return *reinterpret_cast<const double2*>(p);
 }
 
-__global__ __launch_bounds__(256) void fld_relax_pair(FldLevel L, FldCommon cm, int colour) {
-#pragma clang fp contract(off)
-  int o[3];
-  fld_tile_origin<FldPairTile>(L, o);
-  const int t = threadIdx.x;
-  const int j = o[1] + (t / 32) % FldPairTile::TY, k = o[2] + t / (32 * FldPairTile::TY);
-  const int h = (o[0] >> 1) + 2 * (t % 32);
+// The neighbourhood of the pair of cells of colour `colour` at slots h, h+1 of
+// row (j, k): both cells' own D and b (and x when want_x), and for each cell
+// the other colour's x and D across its six faces (x low, x high, y low, y
+// high, z low, z high) with the faces' open flags, as fld_faces names them.
+struct FldPair {
+  unsigned own;          // index of slot h of the own colour
+  int i0;                // x of the first cell; the second is i0 + 2
+  double D[2], b[2], x[2];
+  double xn[2][6], Dn[2][6];
+  bool open[2][6];
+};
+
+__device__ __forceinline__ void fld_pair_load(const FldLevel& L, const FldCommon& cm, int colour,
+                                              int h, int j, int k, bool want_x, FldPair& q) {
   const int n0 = L.n[0], n1 = L.n[1], n2 = L.n[2], hx = (int)L.hx;
-  if (j >= n1 || k >= n2 || h >= hx) return;
   const int par = (j + k + colour) & 1;
-  const int i0 = 2 * h + par;  // the second cell is i0 + 2 (< nx: nx = 2 hx)
+  q.i0 = 2 * h + par;
   const unsigned row = (unsigned)k * (unsigned)n1 + (unsigned)j;
   const unsigned ob = colour ? 0u : L.cs;  // other colour
-  const unsigned own = (colour ? L.cs : 0u) + row * L.hx + (unsigned)h;
+  q.own = (colour ? L.cs : 0u) + row * L.hx + (unsigned)h;
   const unsigned oth = ob + row * L.hx + (unsigned)h;
   // the in-row slot beyond the pair: h - 1 below the first cell (par 0) or
   // h + 2 above the second (par 1), wrapped on a periodic axis, clamped on a
@@ -525,7 +531,8 @@ __global__ __launch_bounds__(256) void fld_relax_pair(FldLevel L, FldCommon cm, 
   auto at = [&](int jj, int kk) {
     return ob + ((unsigned)kk * (unsigned)n1 + (unsigned)jj) * L.hx + (unsigned)h;
   };
-  const double2 Dc = fld_ld2(L.D + own), bc = fld_ld2(L.b + own);
+  const double2 Dc = fld_ld2(L.D + q.own), bc = fld_ld2(L.b + q.own);
+  const double2 xc = want_x ? fld_ld2(L.x + q.own) : make_double2(0.0, 0.0);
   const double2 xr = fld_ld2(L.x + oth), Dr = fld_ld2(L.D + oth);
   const double xe = L.x[oth - (unsigned)h + (unsigned)he], De = L.D[oth - (unsigned)h + (unsigned)he];
   const double2 xym = fld_ld2(L.x + at(jm, k)), Dym = fld_ld2(L.D + at(jm, k));
@@ -533,33 +540,106 @@ __global__ __launch_bounds__(256) void fld_relax_pair(FldLevel L, FldCommon cm, 
   const double2 xzm = fld_ld2(L.x + at(j, km)), Dzm = fld_ld2(L.D + at(j, km));
   const double2 xzp = fld_ld2(L.x + at(j, kp)), Dzp = fld_ld2(L.D + at(j, kp));
   const bool wx = cm.per[0] && n0 > 1, wy = cm.per[1] && n1 > 1, wz = cm.per[2] && n2 > 1;
-  const bool oy[2] = {j > 0 || wy, j < n1 - 1 || wy};
-  const bool oz[2] = {k > 0 || wz, k < n2 - 1 || wz};
+  q.D[0] = Dc.x; q.D[1] = Dc.y;
+  q.b[0] = bc.x; q.b[1] = bc.y;
+  q.x[0] = xc.x; q.x[1] = xc.y;
+  // first cell: x low is xe (par 0) or slot h (par 1), x high slot h (par 0)
+  // or h + 1 (par 1); second cell: x low slot h or h + 1, x high h + 1 or xe
+  q.xn[0][0] = par ? xr.x : xe;   q.Dn[0][0] = par ? Dr.x : De;
+  q.xn[0][1] = par ? xr.y : xr.x; q.Dn[0][1] = par ? Dr.y : Dr.x;
+  q.xn[1][0] = par ? xr.y : xr.x; q.Dn[1][0] = par ? Dr.y : Dr.x;
+  q.xn[1][1] = par ? xe : xr.y;   q.Dn[1][1] = par ? De : Dr.y;
+  q.xn[0][2] = xym.x; q.xn[1][2] = xym.y; q.Dn[0][2] = Dym.x; q.Dn[1][2] = Dym.y;
+  q.xn[0][3] = xyp.x; q.xn[1][3] = xyp.y; q.Dn[0][3] = Dyp.x; q.Dn[1][3] = Dyp.y;
+  q.xn[0][4] = xzm.x; q.xn[1][4] = xzm.y; q.Dn[0][4] = Dzm.x; q.Dn[1][4] = Dzm.y;
+  q.xn[0][5] = xzp.x; q.xn[1][5] = xzp.y; q.Dn[0][5] = Dzp.x; q.Dn[1][5] = Dzp.y;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int i = q.i0 + 2 * c;
+    q.open[c][0] = i > 0 || wx;
+    q.open[c][1] = i < n0 - 1 || wx;
+    q.open[c][2] = j > 0 || wy;
+    q.open[c][3] = j < n1 - 1 || wy;
+    q.open[c][4] = k > 0 || wz;
+    q.open[c][5] = k < n2 - 1 || wz;
+  }
+}
+
+__global__ __launch_bounds__(256) void fld_relax_pair(FldLevel L, FldCommon cm, int colour) {
+#pragma clang fp contract(off)
+  int o[3];
+  fld_tile_origin<FldPairTile>(L, o);
+  const int t = threadIdx.x;
+  const int j = o[1] + (t / 32) % FldPairTile::TY, k = o[2] + t / (32 * FldPairTile::TY);
+  const int h = (o[0] >> 1) + 2 * (t % 32);
+  if (j >= L.n[1] || k >= L.n[2] || h >= (int)L.hx) return;
+  FldPair q;
+  fld_pair_load(L, cm, colour, h, j, k, false, q);
   double res[2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
-    const int i = i0 + 2 * c;
-    const double xn[6] = {c == 0 ? (par ? xr.x : xe) : (par ? xr.y : xr.x),
-                          c == 0 ? (par ? xr.y : xr.x) : (par ? xe : xr.y),
-                          c ? xym.y : xym.x, c ? xyp.y : xyp.x,
-                          c ? xzm.y : xzm.x, c ? xzp.y : xzp.x};
-    const double Dn[6] = {c == 0 ? (par ? Dr.x : De) : (par ? Dr.y : Dr.x),
-                          c == 0 ? (par ? Dr.y : Dr.x) : (par ? De : Dr.y),
-                          c ? Dym.y : Dym.x, c ? Dyp.y : Dyp.x,
-                          c ? Dzm.y : Dzm.x, c ? Dzp.y : Dzp.x};
-    const bool open[6] = {i > 0 || wx, i < n0 - 1 || wx, oy[0], oy[1], oz[0], oz[1]};
-    const double D0 = c ? Dc.y : Dc.x;
-    double num = c ? bc.y : bc.x;
+    double num = q.b[c];
     double den = 1.0;
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-      const double a = open[f] ? (D0 + Dn[f]) * L.K[f >> 1] : 0.0;
-      num += a * (open[f] ? xn[f] : 0.0);
+      const double a = q.open[c][f] ? (q.D[c] + q.Dn[c][f]) * L.K[f >> 1] : 0.0;
+      num += a * (q.open[c][f] ? q.xn[c][f] : 0.0);
       den += a;
     }
     res[c] = num / den;
   }
-  *reinterpret_cast<double2*>(L.x + own) = make_double2(res[0], res[1]);
+  *reinterpret_cast<double2*>(L.x + q.own) = make_double2(res[0], res[1]);
+}
+
+// fld_restrict_red with two red cells per thread and 16-byte loads (3D, hx
+// even, every axis halved): the residuals b - A x of the pair in the order of
+// fld_apply_row, the black cells' entries zero, then the tile's 128 coarse
+// cells add their children from LDS in the order of fld_restrict_cell.
+__global__ __launch_bounds__(256) void fld_restrict_red_pair(FldLevel F, FldLevel C, FldCommon cm,
+                                                             double inv) {
+#pragma clang fp contract(off)
+  using T = FldPairTile;
+  __shared__ double r[T::TZ][T::TY][T::TX];
+  int o[3];
+  fld_tile_origin<T>(F, o);
+  const int t = threadIdx.x;
+  const int dy = (t / 32) % T::TY, dz = t / (32 * T::TY), sx = t % 32;
+  const int j = o[1] + dy, k = o[2] + dz;
+  const int h = (o[0] >> 1) + 2 * sx;
+  const int par = (j + k) & 1;  // red: i + j + k even
+  double rv[2] = {0.0, 0.0};
+  if (j < F.n[1] && k < F.n[2] && h < (int)F.hx) {
+    FldPair q;
+    fld_pair_load(F, cm, 0, h, j, k, true, q);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      double Ax = q.x[c];
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        const double a = q.open[c][f] ? (q.D[c] + q.Dn[c][f]) * F.K[f >> 1] : 0.0;
+        Ax += a * (q.open[c][f] ? q.x[c] - q.xn[c][f] : 0.0);
+      }
+      rv[c] = q.b[c] - Ax;
+    }
+  }
+  // this thread's four cells of the row: 4 sx + par and 4 sx + 2 + par are red
+  r[dz][dy][4 * sx + par] = rv[0];
+  r[dz][dy][4 * sx + 2 + par] = rv[1];
+  r[dz][dy][4 * sx + 1 - par] = 0.0;
+  r[dz][dy][4 * sx + 3 - par] = 0.0;
+  __syncthreads();
+  constexpr int CX = T::TX / 2, CY = T::TY / 2, CZ = T::TZ / 2;
+  if (t >= CX * CY * CZ) return;
+  const int cx = t % CX, cy = (t / CX) % CY, cz = t / (CX * CY);
+  const int P[3] = {(o[0] >> 1) + cx, (o[1] >> 1) + cy, (o[2] >> 1) + cz};
+  if (P[0] >= C.n[0] || P[1] >= C.n[1] || P[2] >= C.n[2]) return;
+  double sum = 0.0;
+  for (int ez = 0; ez < 2; ++ez)
+    for (int ey = 0; ey < 2; ++ey)
+      for (int ex = 0; ex < 2; ++ex) sum += r[2 * cz + ez][2 * cy + ey][2 * cx + ex];
+  const unsigned cc = fld_at(C, P[0], P[1], P[2]);
+  C.b[cc] = sum * inv;
+  C.x[cc] = 0.0;
 }
 
 // Restriction, one thread per coarse cell (any halving pattern).
@@ -970,7 +1050,10 @@ struct Solver {
     if (l + 1 == H.nlev) return relax<NDIM>(l, ncoarse);  // coarsest level
     if (l + 1 > H.nlev) return hipErrorInvalidValue;
     if ((e = relax<NDIM>(l, nu1)) != hipSuccess) return e;
-    if (all_halved(l + 1) && nu1 > 0)
+    if (NDIM == 3 && all_halved(l + 1) && nu1 > 0 && lv[l].hx % 2 == 0)
+      fld_restrict_red_pair<<<fld_tiles_of<FldPairTile>(lv[l]), 256, 0, s>>>(
+          lv[l], lv[l + 1], cm, inv_children[l + 1]);
+    else if (all_halved(l + 1) && nu1 > 0)
       fld_restrict_red<NDIM><<<fld_tiles_of<FldColourTile<NDIM>>(lv[l]), 256, 0, s>>>(
           lv[l], lv[l + 1], cm, inv_children[l + 1]);
     else if (all_halved(l + 1))
