@@ -21,6 +21,8 @@
 // bound by memory traffic loses nothing by it, so over a run of hundreds of
 // steps the GPU stays within rounding of a plain evaluation.
 
+#include <type_traits>
+
 #include "hydro_device.hpp"
 #include "launch.hpp"
 
@@ -300,6 +302,77 @@ __global__ __launch_bounds__(256) void weno_update(WenoArgs a) {
   block_finish<256>(0u, smax, fuse, a.ctl, a.cfl, a.next_dt);
 }
 
+// weno_update for FP64 3D grids with nx even: two cells of a row per thread
+// (x = i, i + 1 with i even) and 16-byte loads of the cell-centred arrays and
+// of the y and z face arrays (a pair of x faces rows of nx + 1 is not always
+// 16-byte aligned, so the three x faces come as 8-byte loads).  The update
+// loads every word once and the L1 data path, not HBM, bounded the one-cell
+// form: 18 accesses per field and two cells there, 10 here.  Per cell the
+// arithmetic is weno_update's, in the same order.
+template <int STAGE>
+__global__ __launch_bounds__(256) void weno_update_pair(WenoArgs a) {
+#pragma clang fp contract(off)
+  constexpr int NDIM = 3, NV = 5;
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const long long N = (long long)nx * ny * nz;
+  const bool fuse = STAGE == 2 && a.fuse_cfl;
+  const double* src = static_cast<const double*>(a.src);
+  const double* un = static_cast<const double*>(a.un);
+  double* dst = static_cast<double*>(a.dst);
+  const double dt = *a.dt;
+  const long long nf0 = (long long)(nx + 1) * ny * nz, nf1 = (long long)nx * (ny + 1) * nz;
+  const long long nf2 = (long long)nx * ny * (nz + 1);
+  double smax = 0.0;
+  for (long long c = 2 * ((long long)blockIdx.x * blockDim.x + threadIdx.x); c < N;
+       c += 2 * (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(c % nx);
+    const long long r = c / nx;
+    const int j = (int)(r % ny), k = (int)(r / ny);
+    const long long fx = ((long long)k * ny + j) * (nx + 1) + i;
+    const long long fy = ((long long)k * (ny + 1) + j) * nx + i;
+    const long long fz = c;
+    double Out[2][NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double* Fx = static_cast<const double*>(a.F[0]) + v * nf0;
+      const double* Fy = static_cast<const double*>(a.F[1]) + v * nf1;
+      const double* Fz = static_cast<const double*>(a.F[2]) + v * nf2;
+      const double x0 = Fx[fx], x1 = Fx[fx + 1], x2 = Fx[fx + 2];
+      const double2 y0 = *reinterpret_cast<const double2*>(Fy + fy);
+      const double2 y1 = *reinterpret_cast<const double2*>(Fy + fy + nx);
+      const double2 z0 = *reinterpret_cast<const double2*>(Fz + fz);
+      const double2 z1 = *reinterpret_cast<const double2*>(Fz + fz + (long long)nx * ny);
+      const double2 u = *reinterpret_cast<const double2*>(src + v * N + c);
+      double2 uo = make_double2(0.0, 0.0);
+      if (STAGE == 2) uo = *reinterpret_cast<const double2*>(un + v * N + c);
+      const double dfs[2][3] = {{x1 - x0, y1.x - y0.x, z1.x - z0.x}, {x2 - x1, y1.y - y0.y, z1.y - z0.y}};
+      const double us[2] = {u.x, u.y}, uos[2] = {uo.x, uo.y};
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        double l = 0.0;
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) {
+          const double df = dfs[e][d];
+          l = l - (a.dx_pow2 ? df * a.inv_dx[d] : df / a.dx[d]);
+        }
+        if (STAGE == 1)
+          Out[e][v] = us[e] + dt * l;
+        else
+          Out[e][v] = 0.5 * (uos[e] + (us[e] + dt * l));
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      *reinterpret_cast<double2*>(dst + v * N + c) = make_double2(Out[0][v], Out[1][v]);
+    if (fuse) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        smax = fmax(smax, signal_sum<NDIM>(Out[e], a.dx, a.inv_dx, a.dx_pow2, a.gamma));
+    }
+  }
+  block_finish<256>(0u, smax, fuse, a.ctl, a.cfl, a.next_dt);
+}
+
 template <typename R, int NDIM>
 static hipError_t weno_stage_t(const WenoArgs& a, int stage, hipStream_t s) {
   const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
@@ -314,10 +387,19 @@ static hipError_t weno_stage_t(const WenoArgs& a, int stage, hipStream_t s) {
     hipLaunchKernelGGL((weno_face<R, NDIM, 2>), dim3(zt), dim3(256), 0, s, a);
   }
   const unsigned nbu = nb < 2048u ? nb : 2048u;
-  if (stage == 1)
+  const bool pair = std::is_same<R, double>::value && NDIM == 3 && a.n[0] % 2 == 0 &&
+                    ((uintptr_t)a.src | (uintptr_t)a.un | (uintptr_t)a.dst) % 16 == 0;
+  if (pair) {
+    const unsigned np = (unsigned)((N / 2 + 255) / 256), nbp = np < 2048u ? np : 2048u;
+    if (stage == 1)
+      hipLaunchKernelGGL((weno_update_pair<1>), dim3(nbp), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((weno_update_pair<2>), dim3(nbp), dim3(256), 0, s, a);
+  } else if (stage == 1) {
     hipLaunchKernelGGL((weno_update<R, NDIM, 1>), dim3(nbu), dim3(256), 0, s, a);
-  else
+  } else {
     hipLaunchKernelGGL((weno_update<R, NDIM, 2>), dim3(nbu), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -67,6 +67,8 @@ CASES = [
     ((37, 21, 19), (P, P, R, R, O, O)),
     ((16, 16, 16), (R, R)),
     ((5, 6, 7), (O, R, P, P, R, O)),
+    # even nx in 3D FP64: the two-cells-per-thread update
+    ((24, 13, 11), (O, R, P, P, R, O)), ((4, 5, 6), (R, O, O, R, P, P)),
 ]
 
 
