@@ -375,11 +375,14 @@ __global__ __launch_bounds__(256) void rad_source(RadArgs a) {
   R* U = static_cast<R*>(a.dst);
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
        c += (long long)gridDim.x * blockDim.x) {
+    double Ud[NH];  // the cell's hydro state after the exchange, as stored
     const double rho = (double)U[c];
+    Ud[0] = rho;
     double m2 = 0.0;
 #pragma unroll
     for (int k = 0; k < NDIM; ++k) {
       const double m = (double)U[(1 + k) * N + c];
+      Ud[1 + k] = m;
       m2 = k == 0 ? m * m : m2 + m * m;
     }
     const double ke = 0.5 * m2 / rho;
@@ -390,9 +393,9 @@ __global__ __launch_bounds__(256) void rad_source(RadArgs a) {
     if (Er != Er0) U[NH * N + c] = R(Er);
     if (!isfinite(Er) || !isfinite(Ef)) flags |= FLAG_NONFINITE;
     if (a.fuse_cfl) {
-      double Ud[NH];
-#pragma unroll
-      for (int v = 0; v < NH; ++v) Ud[v] = (double)U[v * N + c];
+      // an unchanged value came from R, so R(value) is the stored word either
+      // way; E_r is not part of the signal sum
+      Ud[NDIM + 1] = (double)R(Ef);
       smax = fmax(smax, signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
     }
   }
