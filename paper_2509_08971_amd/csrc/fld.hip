@@ -761,6 +761,70 @@ __global__ __launch_bounds__(256) void fld_prolong_colour(FldLevel F, FldLevel C
     fld_prolong_cell(F, C, cm, f);
 }
 
+// fld_prolong_colour for the black cells of a 3D level with every axis halved
+// and hx even: two black cells of a row per thread (slots h, h + 1).  Their
+// parents along x are three consecutive coarse cells (h - 1, h, h + 1 when the
+// row's black cells are even, h, h + 1, h + 2 when odd, the outer one wrapped
+// or clamped as fld_nb says), so each of the four coarse rows gives its three
+// values once; the fine pair is one 16-byte load and store.  Per cell the
+// weights, the order of the eight terms and the sum are those of
+// fld_prolong_cell_all.
+__global__ __launch_bounds__(256) void fld_prolong_pair(FldLevel F, FldLevel C, FldCommon cm) {
+#pragma clang fp contract(off)
+  int o[3];
+  fld_tile_origin<FldPairTile>(F, o);
+  const int t = threadIdx.x;
+  const int j = o[1] + (t / 32) % FldPairTile::TY, k = o[2] + t / (32 * FldPairTile::TY);
+  const int h = (o[0] >> 1) + 2 * (t % 32);
+  if (j >= F.n[1] || k >= F.n[2] || h >= (int)F.hx) return;
+  const int par = (j + k + 1) & 1;  // black: i + j + k odd
+  // the three coarse x positions; the first cell takes (near, far) = (1, 0)
+  // of them for even black cells and (0, 1) for odd, the second (2, 1) and
+  // (1, 2)
+  int xs[3];
+  if (par == 0) {
+    const int a = fld_nb(h, C.n[0], 0, cm.per[0]);
+    xs[0] = a < 0 ? h : a; xs[1] = h; xs[2] = h + 1;
+  } else {
+    const int c = fld_nb(h + 1, C.n[0], 1, cm.per[0]);
+    xs[0] = h; xs[1] = h + 1; xs[2] = c < 0 ? h + 1 : c;
+  }
+  const int J = j >> 1, K = k >> 1;
+  const int jq = fld_nb(J, C.n[1], j & 1, cm.per[1]), kq = fld_nb(K, C.n[2], k & 1, cm.per[2]);
+  const int Jf = jq < 0 ? J : jq, Kf = kq < 0 ? K : kq;
+  // coarse values: row r = (y far) | (z far) << 1, three x positions each
+  double xc[4][3];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int jj = (r & 1) ? Jf : J, kk = (r & 2) ? Kf : K;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) xc[r][q] = C.x[fld_at(C, xs[q], jj, kk)];
+  }
+  // selects on the parity keep xc in registers (a run-time index would not)
+  double cn[2][4], cf[2][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    cn[0][r] = par ? xc[r][0] : xc[r][1];
+    cf[0][r] = par ? xc[r][1] : xc[r][0];
+    cn[1][r] = par ? xc[r][1] : xc[r][2];
+    cf[1][r] = par ? xc[r][2] : xc[r][1];
+  }
+  double v[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const double w = ((m & 1) ? 0.25 : 0.75) * ((m & 2) ? 0.25 : 0.75) * ((m & 4) ? 0.25 : 0.75);
+      s += w * ((m & 1) ? cf[c][m >> 1] : cn[c][m >> 1]);
+    }
+    v[c] = s;
+  }
+  double* xf = F.x + F.cs + ((unsigned)k * (unsigned)F.n[1] + (unsigned)j) * F.hx + (unsigned)h;
+  const double2 x = fld_ld2(xf);
+  *reinterpret_cast<double2*>(xf) = make_double2(x.x + v[0], x.y + v[1]);
+}
+
 // Residual norm, two deterministic passes: per-tile sums of r^2 in a fixed
 // order, then one workgroup adds the tile sums in a fixed order.
 template <int NDIM>
@@ -1064,7 +1128,9 @@ struct Solver {
                                                                      inv_children[l + 1]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = vcycle<NDIM>(l + 1)) != hipSuccess) return e;
-    if (nu2 > 0) {
+    if (NDIM == 3 && nu2 > 0 && all_halved(l + 1) && lv[l].hx % 2 == 0) {
+      fld_prolong_pair<<<fld_tiles_of<FldPairTile>(lv[l]), 256, 0, s>>>(lv[l], lv[l + 1], cm);
+    } else if (nu2 > 0) {
       const unsigned tiles = fld_tiles_of<FldColourTile<NDIM>>(lv[l]);
       if (all_halved(l + 1))
         fld_prolong_colour<NDIM, true><<<tiles, 256, 0, s>>>(lv[l], lv[l + 1], cm, 1);

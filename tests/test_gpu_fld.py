@@ -91,6 +91,8 @@ CASES = [
     ((2,), (P, P)), ((2, 2, 2), (P, P, P, P, P, P)), ((3, 2), (O, O, P, P)), ((2, 3, 2), (R, R, O, R, P, P)),
     # nx a multiple of 4 with walls along x (the two-cells-per-thread half-sweep), odd y and z
     ((36, 10, 12), (R, O, P, P, O, R)), ((44, 7, 9), (O, R, R, O, R, O)),
+    # every axis even but nx = 2 mod 4: the one-cell 3D half-sweep and red restriction
+    ((30, 20, 16), (R, R, P, P, O, O)),
 ]
 
 
