@@ -53,6 +53,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "../../include/hard.h"
 #include "api_internal.hpp"
@@ -350,6 +351,16 @@ template <> struct FldColourTile<1> { static constexpr int TX = 512, TY = 1, TZ 
 template <> struct FldColourTile<2> { static constexpr int TX = 64, TY = 8, TZ = 1; };
 template <> struct FldColourTile<3> { static constexpr int TX = 64, TY = 4, TZ = 2; };
 
+// Tiles of the kernels that take two cells of a colour (or four cells of a
+// row) per thread with 16-byte accesses: 32 threads take a row of 128 cells.
+struct FldPairTile {
+  static constexpr int TX = 128, TY = 4, TZ = 2;
+};
+
+__device__ __forceinline__ double2 fld_ld2(const double* p) {
+  return *reinterpret_cast<const double2*>(p);
+}
+
 // Origin (in cells) of this workgroup's TX x TY x TZ tile of level L: tile ids
 // dealt XCD-contiguously, in y panels.
 template <class T>
@@ -447,6 +458,86 @@ __global__ __launch_bounds__(256) void fld_setup(FldLevel L, FldCommon cm, const
 
 // The finest x back into the state's E_r field (rounded to float for a
 // float state).
+// fld_setup for FP64 3D states with nx a multiple of 4: four cells of a row
+// per thread (x = i0 .. i0 + 3, i0 a multiple of 4).  E and rho come as
+// 16-byte pairs, the six neighbour values per cell from the row itself, one
+// value beyond each end and the pairs of the rows above and below: 14 loads
+// per four cells instead of 32.  Cells i0 and i0 + 2 share a colour, as do
+// i0 + 1 and i0 + 3, each pair at two consecutive slots: x, b and D go out as
+// six 16-byte stores instead of twelve.  Per cell the arithmetic is
+// fld_setup's, in the same order.
+__global__ __launch_bounds__(256) void fld_setup_quad(FldLevel L, FldCommon cm, const double* rho,
+                                                      const double* E, double kappa, int limiter,
+                                                      Control* ctl) {
+#pragma clang fp contract(off)
+  int o[3];
+  fld_tile_origin<FldPairTile>(L, o);
+  const int t = threadIdx.x;
+  const int j = o[1] + (t / 32) % FldPairTile::TY, k = o[2] + t / (32 * FldPairTile::TY);
+  const int i0 = o[0] + 4 * (t % 32);
+  const int n0 = L.n[0], n1 = L.n[1], n2 = L.n[2];
+  unsigned flags = 0;
+  if (i0 < n0 && j < n1 && k < n2) {
+    const unsigned sy = (unsigned)n0, sz = (unsigned)n0 * (unsigned)n1;
+    const unsigned c = (unsigned)i0 + (unsigned)j * sy + (unsigned)k * sz;
+    // a wall side uses the cell itself, as fld_nb's -1 does in fld_setup
+    const int xl = fld_nb(i0, n0, 0, cm.per[0]), xh = fld_nb(i0 + 3, n0, 1, cm.per[0]);
+    const int jl = fld_nb(j, n1, 0, cm.per[1]), jh = fld_nb(j, n1, 1, cm.per[1]);
+    const int kl = fld_nb(k, n2, 0, cm.per[2]), kh = fld_nb(k, n2, 1, cm.per[2]);
+    const unsigned cxl = xl < 0 ? c : c - (unsigned)i0 + (unsigned)xl;
+    const unsigned cxh = xh < 0 ? c + 3u : c - (unsigned)i0 + (unsigned)xh;
+    const unsigned cyl = jl < 0 ? c : c + (unsigned)(jl - j) * sy;
+    const unsigned cyh = jh < 0 ? c : c + (unsigned)(jh - j) * sy;
+    const unsigned czl = kl < 0 ? c : c + (unsigned)(kl - k) * sz;
+    const unsigned czh = kh < 0 ? c : c + (unsigned)(kh - k) * sz;
+    const double2 e01 = fld_ld2(E + c), e23 = fld_ld2(E + c + 2);
+    const double2 r01 = fld_ld2(rho + c), r23 = fld_ld2(rho + c + 2);
+    const double exl = E[cxl], exh = E[cxh];
+    const double2 yl01 = fld_ld2(E + cyl), yl23 = fld_ld2(E + cyl + 2);
+    const double2 yh01 = fld_ld2(E + cyh), yh23 = fld_ld2(E + cyh + 2);
+    const double2 zl01 = fld_ld2(E + czl), zl23 = fld_ld2(E + czl + 2);
+    const double2 zh01 = fld_ld2(E + czh), zh23 = fld_ld2(E + czh + 2);
+    const double ev[4] = {e01.x, e01.y, e23.x, e23.y};
+    const double rv[4] = {r01.x, r01.y, r23.x, r23.y};
+    const double ylv[4] = {yl01.x, yl01.y, yl23.x, yl23.y}, yhv[4] = {yh01.x, yh01.y, yh23.x, yh23.y};
+    const double zlv[4] = {zl01.x, zl01.y, zl23.x, zl23.y}, zhv[4] = {zh01.x, zh01.y, zh23.x, zh23.y};
+    double Dv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double lo[3] = {q == 0 ? exl : ev[q - 1], ylv[q], zlv[q]};
+      const double hi[3] = {q == 3 ? exh : ev[q + 1], yhv[q], zhv[q]};
+      double g2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double g = (hi[d] - lo[d]) / (2.0 * L.dx[d]);
+        g2 += g * g;
+      }
+      const double r = rv[q], e = ev[q];
+      double lam = 1.0 / 3.0;
+      if (limiter) {
+        const double R = sqrt(g2) / (r * kappa * e);
+        lam = (2.0 + R) / (6.0 + 3.0 * R + R * R);
+      }
+      Dv[q] = FLD_C_LIGHT * lam / (kappa * r);
+      if (!(r > 0.0)) flags |= FLAG_DENSITY;
+      if (!(e > 0.0) || !isfinite(Dv[q])) flags |= FLAG_RADIATION;
+    }
+    // colour of cell i0 and its partner i0 + 2 at slots i0/2, i0/2 + 1; the
+    // other colour holds i0 + 1 and i0 + 3 at the same slots
+    const unsigned row = (unsigned)k * (unsigned)n1 + (unsigned)j;
+    const unsigned base = row * L.hx + (unsigned)(i0 >> 1);
+    const int c0 = (i0 + j + k) & 1;
+    const unsigned s0 = (c0 ? L.cs : 0u) + base, s1 = (c0 ? 0u : L.cs) + base;
+    *reinterpret_cast<double2*>(L.D + s0) = make_double2(Dv[0], Dv[2]);
+    *reinterpret_cast<double2*>(L.b + s0) = make_double2(ev[0], ev[2]);
+    *reinterpret_cast<double2*>(L.x + s0) = make_double2(ev[0], ev[2]);
+    *reinterpret_cast<double2*>(L.D + s1) = make_double2(Dv[1], Dv[3]);
+    *reinterpret_cast<double2*>(L.b + s1) = make_double2(ev[1], ev[3]);
+    *reinterpret_cast<double2*>(L.x + s1) = make_double2(ev[1], ev[3]);
+  }
+  block_finish<256>(flags, 0.0, false, ctl, 0.0, nullptr);
+}
+
 template <int NDIM, typename R>
 __global__ __launch_bounds__(256) void fld_store(FldLevel L, R* E) {
   int p[3];
@@ -489,13 +580,6 @@ __global__ __launch_bounds__(256) void fld_relax(FldLevel L, FldCommon cm, int c
 // cells: 14 loads and stores per two cells instead of 30.  Needs hx even (the
 // pairs and both colour halves 16-byte aligned), hence nx a multiple of 4.
 // Faces, order and arithmetic are those of fld_relax_cell.
-struct FldPairTile {
-  static constexpr int TX = 128, TY = 4, TZ = 2;  // cells; 32 threads take a row
-};
-
-__device__ __forceinline__ double2 fld_ld2(const double* p) {
-  return *reinterpret_cast<const double2*>(p);
-}
 
 // The neighbourhood of the pair of cells of colour `colour` at slots h, h+1 of
 // row (j, k): both cells' own D and b (and x when want_x), and for each cell
@@ -1159,7 +1243,14 @@ struct Solver {
     const long long N = cells(H, 0);
     const R* rho = U;
     R* E = U + (long long)(G.nvar - 1) * N;
-    fld_setup<NDIM, R><<<fld_tiles<NDIM>(lv[0]), 256, 0, s>>>(lv[0], cm, rho, E, G.kappa, limiter, ctl);
+    if (NDIM == 3 && std::is_same<R, double>::value && G.n[0] % 4 == 0 &&
+        ((uintptr_t)rho | (uintptr_t)E) % 16 == 0)
+      fld_setup_quad<<<fld_tiles_of<FldPairTile>(lv[0]), 256, 0, s>>>(
+          lv[0], cm, reinterpret_cast<const double*>(rho), reinterpret_cast<const double*>(E),
+          G.kappa, limiter, ctl);
+    else
+      fld_setup<NDIM, R><<<fld_tiles<NDIM>(lv[0]), 256, 0, s>>>(lv[0], cm, rho, E, G.kappa, limiter,
+                                                               ctl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     FldDx2 dx2;
     for (int l = 0; l < H.nlev; ++l)
