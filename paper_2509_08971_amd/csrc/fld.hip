@@ -984,6 +984,15 @@ __device__ __forceinline__ FldLevel fld_lds_level(const FldTail& T, int m, doubl
 
 template <int NDIM>
 __device__ void fld_tail_relax(const FldLevel& L, const FldCommon& cm, int sweeps) {
+  // A level of one cell has every face closed: one sweep sets x = b / 1 = b,
+  // and every further sweep computes the same bits again, over a black colour
+  // with no cell.  Its phases (each ending in a barrier of the workgroup) are
+  // skipped; the result is that of `sweeps` sweeps.
+  if (fld_cells(L) == 1) {
+    if (sweeps > 0 && threadIdx.x == 0) fld_relax_slot<NDIM>(L, cm, 0, 0);
+    __syncthreads();
+    return;
+  }
   for (int sw = 0; sw < sweeps; ++sw)
     for (int colour = 0; colour < 2; ++colour) {
       for (unsigned t = threadIdx.x; t < L.cs; t += 1024) fld_relax_slot<NDIM>(L, cm, colour, t);
