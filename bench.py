@@ -484,7 +484,7 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 8, "launches": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "the kernels run on one GPU; --gpus must be 1"}), flush=True)
         sys.exit(2)
     if args.only_leg:
         legs = {"fp32": ("fp32_512_turbulent", bench_fp32_turbulent),
