@@ -248,3 +248,13 @@ def test_run_rhd_checks():
     assert call(g, work_bytes=H.hard_workspace_bytes(g) - 1) == H.ERR_WORKSPACE
     assert call(g, fld=None) == H.ERR_INVALID_ARG
     assert call(H.make_grid((15, 16), bc=(0, 0, 1, 1), rad=(0.4, 0.6))) == H.ERR_UNSUPPORTED
+
+
+def test_cell_count_limit():
+    """Grids of 2^31 cells or more are refused before any work: the kernels
+    index cells and level arrays with 32-bit arithmetic below that bound."""
+    for call in (H.hard_workspace_bytes, H.hard_rad_diffuse_workspace_bytes):
+        with pytest.raises(H.HardError) as e:
+            call(H.make_grid((2048, 1024, 1024), rad=(0.4, 0.6)))
+        assert e.value.code == H.ERR_INVALID_ARG
+    assert H.hard_workspace_bytes(H.make_grid((2048, 1024, 1023))) > 0
