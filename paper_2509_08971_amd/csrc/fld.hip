@@ -572,14 +572,15 @@ __global__ __launch_bounds__(256) void fld_relax(FldLevel L, FldCommon cm, int c
 }
 
 // The 3D half-sweep with two cells of the colour per thread (slots h and
-// h + 1 of a row, h even) and 16-byte loads.  The half-sweep's loads all hit
-// the L1 in the end, but a 64-lane load of 8-byte words costs the L1's
-// address and data path about as many cycles as it has 4-lane groups, so
-// with six neighbour rows of x and D per cell that path, not HBM, set the
-// time.  Here one 16-byte load brings a neighbour row's values for both
-// cells: 14 loads and stores per two cells instead of 30.  Needs hx even (the
-// pairs and both colour halves 16-byte aligned), hence nx a multiple of 4.
-// Faces, order and arithmetic are those of fld_relax_cell.
+// h + 1 of a row, h even) and 16-byte loads.  The half-sweep's neighbour
+// loads hit the L1, but each 64-lane load instruction still occupies the L1's
+// address and data units for tens of cycles (about 26 measured for 8-byte
+// words), so with six neighbour rows of x and D per cell that path, not HBM,
+// set the time.  Here one 16-byte load brings a neighbour row's values for
+// both cells: 14 loads and one store per two cells instead of 28 loads and
+// two stores.  Needs hx even (the pairs and both colour halves 16-byte
+// aligned), hence nx a multiple of 4.  Faces, order and arithmetic are those
+// of fld_relax_cell.
 
 // The neighbourhood of the pair of cells of colour `colour` at slots h, h+1 of
 // row (j, k): both cells' own D and b (and x when want_x), and for each cell
