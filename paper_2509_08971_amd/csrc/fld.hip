@@ -547,6 +547,26 @@ __global__ __launch_bounds__(256) void fld_store(FldLevel L, R* E) {
   E[c] = R(L.x[fld_at(L, p[0], p[1], p[2])]);
 }
 
+// fld_store for FP64 3D states with nx a multiple of 4: four cells of a row
+// per thread, the two colour pairs (slots i0/2, i0/2 + 1 of each colour) and
+// E as 16-byte accesses, the same words as fld_store writes.
+__global__ __launch_bounds__(256) void fld_store_quad(FldLevel L, double* E) {
+  int o[3];
+  fld_tile_origin<FldPairTile>(L, o);
+  const int t = threadIdx.x;
+  const int j = o[1] + (t / 32) % FldPairTile::TY, k = o[2] + t / (32 * FldPairTile::TY);
+  const int i0 = o[0] + 4 * (t % 32);
+  if (i0 >= L.n[0] || j >= L.n[1] || k >= L.n[2]) return;
+  const unsigned row = (unsigned)k * (unsigned)L.n[1] + (unsigned)j;
+  const unsigned base = row * L.hx + (unsigned)(i0 >> 1);
+  const int c0 = (i0 + j + k) & 1;  // colour of cells i0 and i0 + 2
+  const double2 a = fld_ld2(L.x + (c0 ? L.cs : 0u) + base);
+  const double2 b = fld_ld2(L.x + (c0 ? 0u : L.cs) + base);
+  double* e = E + row * (unsigned)L.n[0] + (unsigned)i0;
+  *reinterpret_cast<double2*>(e) = make_double2(a.x, b.x);
+  *reinterpret_cast<double2*>(e + 2) = make_double2(a.y, b.y);
+}
+
 __global__ __launch_bounds__(256) void fld_coarsen_D(FldLevel F, FldLevel C, double inv) {
 #pragma clang fp contract(off)
   const unsigned c = (unsigned)blockIdx.x * 256u + threadIdx.x;
@@ -1276,7 +1296,11 @@ struct Solver {
       if ((e = vcycle<NDIM>(0)) != hipSuccess) return e;
       if (resid && (e = resid_norm<NDIM>(resid + c + 1)) != hipSuccess) return e;
     }
-    fld_store<NDIM, R><<<fld_tiles<NDIM>(lv[0]), 256, 0, s>>>(lv[0], E);
+    if (NDIM == 3 && std::is_same<R, double>::value && G.n[0] % 4 == 0 && (uintptr_t)E % 16 == 0)
+      fld_store_quad<<<fld_tiles_of<FldPairTile>(lv[0]), 256, 0, s>>>(
+          lv[0], reinterpret_cast<double*>(E));
+    else
+      fld_store<NDIM, R><<<fld_tiles<NDIM>(lv[0]), 256, 0, s>>>(lv[0], E);
     return hipGetLastError();
   }
 };
