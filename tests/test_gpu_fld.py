@@ -368,3 +368,34 @@ def test_run_rhd_matches_the_oracle_loop():
     for v in range(6):
         err = np.abs(out[v] - ref[v]).max() / np.abs(ref[v]).max()
         assert err <= 1e-12, (v, err)
+
+
+def _state_at(U0, off):
+    """U0 on the GPU at `off` doubles into a fresh buffer (off = 1: 8-byte
+    but not 16-byte aligned)."""
+    buf = torch.zeros(U0.size + 2, dtype=torch.float64, device=DEV)
+    U = buf[off:off + U0.size].view(U0.shape)
+    U.copy_(torch.from_numpy(np.ascontiguousarray(U0)))
+    assert (U.data_ptr() % 16 == 0) == (off == 0)
+    return U
+
+
+def test_aligned_and_unaligned_states_give_the_same_bits():
+    """Setup and store take four cells of a row per thread with 16-byte
+    accesses when the state is 16-byte aligned, one cell per thread
+    otherwise; the diffusion result is the same bit for bit."""
+    n, bc = (32, 24, 16), (P, P, R, R, O, O)
+    log("fld aligned vs unaligned state", n, bc)
+    U0 = rad_state(n, 21)
+    dx = 1.0 / max(n)
+    dtd = torch.full((1,), 50.0 * dx * dx * KAPPA / C_LIGHT, dtype=torch.float64, device=DEV)
+    g = H.make_grid(n, bc=bc, rad=(KAPPA, 0.6))
+    out = []
+    for off in (0, 1):
+        U = _state_at(U0, off)
+        work = H.workspace(H.hard_rad_diffuse_workspace_bytes(g))
+        H.hard_rad_diffuse(g, U, dtd, work, ncycles=3)
+        torch.cuda.synchronize()
+        assert H.hard_status_read(work) == 0
+        out.append(U.cpu().numpy())
+    np.testing.assert_array_equal(out[0], out[1])

@@ -146,3 +146,32 @@ def test_turbulent_64_periodic_one_step():
     out, nxt = run_gpu((n, n, n), (P, P), U0, [dt])
     for v in range(5):
         assert field_rel_linf(out[v], ref[v]) <= TOL64, v
+
+
+def test_aligned_and_unaligned_states_give_the_same_bits():
+    """The FP64 3D update takes two cells per thread with 16-byte accesses
+    when the states are 16-byte aligned, one cell otherwise: the same step,
+    bit for bit, and the same fused dt."""
+    n, bc = (24, 13, 11), (O, R, P, P, R, O)
+    log("weno aligned vs unaligned state", n, bc)
+    U0 = random_state(n, 8)
+    og = oracle.Grid(n, bc=bc, scheme=W5)
+    dt0, _ = oracle.cfl_dt(og, U0, 0.3)
+    g = H.make_grid(n, bc=bc, scheme=W5)
+    out, nxt = [], []
+    for off in (0, 1):
+        buf = torch.zeros(U0.size + 2, dtype=torch.float64, device=DEV)
+        U = buf[off:off + U0.size].view(U0.shape)
+        U.copy_(torch.from_numpy(np.ascontiguousarray(U0)))
+        assert (U.data_ptr() % 16 == 0) == (off == 0)
+        work = H.workspace(H.hard_workspace_bytes(g))
+        dt = torch.full((1,), dt0, dtype=torch.float64, device=DEV)
+        nd = torch.zeros(1, dtype=torch.float64, device=DEV)
+        for _ in range(2):
+            H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=nd)
+        torch.cuda.synchronize()
+        assert H.hard_status_read(work) == 0
+        out.append(U.cpu().numpy())
+        nxt.append(nd.item())
+    np.testing.assert_array_equal(out[0], out[1])
+    assert nxt[0] == nxt[1]
