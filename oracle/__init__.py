@@ -70,6 +70,8 @@ def lib(path=None):
         L.oracle_hll.restype = None
         L.oracle_weno5z.argtypes = [dp]
         L.oracle_weno5z.restype = ctypes.c_double
+        L.oracle_weno5z_indicators.argtypes = [dp, dp]
+        L.oracle_weno5z_indicators.restype = None
         L.oracle_threads.argtypes = []
         L.oracle_threads.restype = ctypes.c_int
         L.oracle_count_ops.argtypes = common + [ctypes.c_double, dp, i64p]
@@ -256,6 +258,15 @@ def weno5z(v):
     v = np.ascontiguousarray(v, dtype=np.float64)
     assert v.size == 5
     return lib().oracle_weno5z(_dptr(v))
+
+
+def weno5z_indicators(v):
+    """The three smoothness indicators beta_k of five cell values."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert v.size == 5
+    b = np.empty(3)
+    lib().oracle_weno5z_indicators(_dptr(v), _dptr(b))
+    return b
 
 
 def primitives(U, gamma=1.4):

@@ -25,8 +25,7 @@
 //   * grad E at a cell centre by central differences; a non-periodic side
 //     takes the edge cell itself as its neighbour (zero normal gradient);
 //   * the face coefficient is dt * (D_i + D_j)/2 / dx^2 (arithmetic mean of
-//     the two cells), rounded as (D_i + D_j) * ((dt/2)/dx^2); non-periodic
-//     domain faces carry no flux (zero-flux
+//     the two cells); non-periodic domain faces carry no flux (zero-flux
 //     walls), and a periodic axis of one cell carries none either (the face
 //     joins the cell to itself);
 //   * the smoother is red-black Gauss-Seidel (cells with i+j+k even first);
@@ -95,11 +94,10 @@ inline int64_t face_neighbour(const Level& L, const Problem& P, int64_t i, int64
   return L.at(c[0], c[1], c[2]);
 }
 
-// a_f = dt (D_a + D_b)/2 / dx_d^2, evaluated as (D_a + D_b) K_d with
-// K_d = (dt/2) / dx_d^2 (one rounding order of the same coefficient).
+// a_f = dt D_f / dx_d^2 with the face value D_f = (D_a + D_b)/2.
 inline double face_coeff(const Level& L, const Problem& P, int d, int64_t a, int64_t b) {
-  const double K = (0.5 * P.dt) / (L.dx[d] * L.dx[d]);
-  return (L.D[a] + L.D[b]) * K;
+  const double Dface = 0.5 * (L.D[a] + L.D[b]);
+  return P.dt * Dface / (L.dx[d] * L.dx[d]);
 }
 
 // (A x)_c = x_c + sum over faces a_f (x_c - x_nb)

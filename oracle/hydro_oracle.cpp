@@ -332,6 +332,25 @@ static void hll_flux(const Prim<T>& L, const Prim<T>& R, int nt, double gamma, T
   }
 }
 
+// Jiang-Shu smoothness indicators of the three candidate stencils of
+// v[0..4]: beta_k = sum over l = 1, 2 of the integral over the middle cell of
+// dx^(2l-1) (d^l p_k/dx^l)^2, p_k the quadratic with the stencil's three cell
+// averages; in closed form 13/12 (second difference)^2 + 1/4 (first-order
+// combination)^2.
+template <class T>
+static void weno5z_indicators(const T* v, T* beta) {
+  T s0 = v[0] - T(2.0) * v[1] + v[2];
+  T t0 = v[0] - T(4.0) * v[1] + T(3.0) * v[2];
+  T s1 = v[1] - T(2.0) * v[2] + v[3];
+  T t1 = v[1] - v[3];
+  T s2 = v[2] - T(2.0) * v[3] + v[4];
+  T t2 = T(3.0) * v[2] - T(4.0) * v[3] + v[4];
+  const T c1(13.0 / 12.0), c2(0.25);
+  beta[0] = c1 * s0 * s0 + c2 * t0 * t0;
+  beta[1] = c1 * s1 * s1 + c2 * t1 * t1;
+  beta[2] = c1 * s2 * s2 + c2 * t2 * t2;
+}
+
 // WENO5-Z value at the right face of the middle cell of v[0..4] (cells
 // i-2 .. i+2), Borges et al. 2008: the three third-order candidate values on
 // the stencils {i-2,i-1,i}, {i-1,i,i+1}, {i,i+1,i+2}; the Jiang-Shu
@@ -342,29 +361,20 @@ static void hll_flux(const Prim<T>& L, const Prim<T>& R, int nt, double gamma, T
 // (i+2, i+1, i, i-1, i-2).
 template <class T>
 static T weno5z(const T* v) {
-  // 6 x the three third-order candidates
-  T q0 = T(2.0) * v[0] - T(7.0) * v[1] + T(11.0) * v[2];
-  T q1 = -v[1] + T(5.0) * v[2] + T(2.0) * v[3];
-  T q2 = T(2.0) * v[2] + T(5.0) * v[3] - v[4];
-  T s0 = v[0] - T(2.0) * v[1] + v[2];
-  T t0 = v[0] - T(4.0) * v[1] + T(3.0) * v[2];
-  T s1 = v[1] - T(2.0) * v[2] + v[3];
-  T t1 = v[1] - v[3];
-  T s2 = v[2] - T(2.0) * v[3] + v[4];
-  T t2 = T(3.0) * v[2] - T(4.0) * v[3] + v[4];
-  const T c1(13.0 / 12.0), c2(0.25), eps(1e-40);
-  T b0 = c1 * s0 * s0 + c2 * t0 * t0;
-  T b1 = c1 * s1 * s1 + c2 * t1 * t1;
-  T b2 = c1 * s2 * s2 + c2 * t2 * t2;
+  // the three third-order candidate values
+  T q0 = (T(2.0) * v[0] - T(7.0) * v[1] + T(11.0) * v[2]) / T(6.0);
+  T q1 = (-v[1] + T(5.0) * v[2] + T(2.0) * v[3]) / T(6.0);
+  T q2 = (T(2.0) * v[2] + T(5.0) * v[3] - v[4]) / T(6.0);
+  T beta[3];
+  weno5z_indicators(v, beta);
+  T b0 = beta[0], b1 = beta[1], b2 = beta[2];
+  const T eps(1e-40);
+  // global smoothness measure and the unnormalised Z weights
   T tau = fabs(b0 - b2);
-  // the weights d_k (1 + tau/(b_k + eps)) over the common denominator
-  // (b_0 + eps)(b_1 + eps)(b_2 + eps), the 1/6 of the candidates folded into
-  // the normalisation: one division instead of seven
-  T e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
-  T a0 = T(0.1) * (e0 + tau) * (e1 * e2);
-  T a1 = T(0.6) * (e1 + tau) * (e0 * e2);
-  T a2 = T(0.3) * (e2 + tau) * (e0 * e1);
-  return (a0 * q0 + a1 * q1 + a2 * q2) / (T(6.0) * (a0 + a1 + a2));
+  T a0 = T(0.1) * (T(1.0) + tau / (b0 + eps));
+  T a1 = T(0.6) * (T(1.0) + tau / (b1 + eps));
+  T a2 = T(0.3) * (T(1.0) + tau / (b2 + eps));
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 
 // Primitive variables of one conserved state: rho, u_0..u_{ndim-1}, p.
@@ -786,6 +796,9 @@ void oracle_hll(int nt, double gamma, const double* WL, const double* WR, double
 
 // WENO5-Z value at the right face of the middle cell of v[0..4].
 double oracle_weno5z(const double* v) { return weno5z<double>(v); }
+
+// The three smoothness indicators beta_k of v[0..4].
+void oracle_weno5z_indicators(const double* v, double* beta) { weno5z_indicators<double>(v, beta); }
 
 // Floating-point operations of one CFL dt plus one SSP-RK2 step of U (left
 // unchanged), tallied by kind: out[0..5] = add/sub, mul, div, sqrt, compare,

@@ -123,9 +123,9 @@ def quick_pins():
 
 
 MUTATIONS = {
-    "face coefficient without the mean": ("(0.5 * P.dt) / (L.dx[d] * L.dx[d])",
-                                          "P.dt / (L.dx[d] * L.dx[d])"),
-    "face coefficient over dx": ("(0.5 * P.dt) / (L.dx[d] * L.dx[d])", "(0.5 * P.dt) / L.dx[d]"),
+    "face coefficient without the mean": ("const double Dface = 0.5 * (L.D[a] + L.D[b]);",
+                                          "const double Dface = L.D[a] + L.D[b];"),
+    "face coefficient over dx": ("P.dt * Dface / (L.dx[d] * L.dx[d])", "P.dt * Dface / L.dx[d]"),
     "operator sign": ("Ax += a * (x[c] - x[nb]);", "Ax -= a * (x[c] - x[nb]);"),
     "relaxation diagonal": ("den += a;", "den += 2.0 * a;"),
     "relaxation neighbour sign": ("num += a * L.x[nb];", "num -= a * L.x[nb];"),

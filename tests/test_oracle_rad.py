@@ -156,6 +156,66 @@ def test_rusanov_flux_of_equal_states_is_the_physical_flux():
         assert np.array_equal(out, X)
 
 
+def jump_state(n, rho, u, p, Er, gamma=1.4):
+    """1D state with rho, u, p and E_r each constant on the two halves
+    (cells 0 .. n/2-1 and n/2 .. n-1), as (rho, m, E, E_r)."""
+    half = lambda a, b: np.where(np.arange(n) < n // 2, a, b)
+    r, vel, pr = half(*rho), half(*u), half(*p)
+    U = workloads.conserved_from_primitive(r, [vel], pr, gamma)
+    return np.concatenate([U, half(*Er)[None]])
+
+
+def test_rusanov_jump_on_a_stationary_contact():
+    """Fluid at rest at uniform pressure with a density jump (a stationary
+    contact, so every hydro flux difference vanishes) and an E_r jump at the
+    same face.  Every field is piecewise constant, so each minmod slope is 0
+    and the face states are the cell values.  Only the jump face carries an
+    E_r flux, pure dissipation: F = -s (E_R - E_L)/2 with the larger signal
+    speed s = max(c_L, c_R), c = sqrt(gamma p/rho).  L(E_r) is -F/dx in the
+    cell left of the face, +F/dx right of it, and 0 elsewhere."""
+    n, g = 16, 1.4
+    rho, p, Er = (1.0, 0.25), 0.7, (2.0, 0.5)
+    X = jump_state(n, rho, (0.0, 0.0), (p, p), Er, g)
+    grid = oracle.Grid((n,), gamma=g, bc=(O, O), rad=(0.0, 0.6))
+    L, st = oracle.rhs(grid, X)
+    assert st == 0
+    assert np.all(L[:3] == 0.0)
+    # pressure as the oracle recovers it from E (identical on both sides)
+    pr = (g - 1.0) * X[2, 0]
+    s = max(np.sqrt(g * pr / rho[0]), np.sqrt(g * pr / rho[1]))
+    F = -0.5 * s * (Er[1] - Er[0])
+    expect = np.zeros(n)
+    expect[n // 2 - 1] = -F * n
+    expect[n // 2] = F * n
+    assert np.allclose(L[3], expect, rtol=1e-14, atol=0.0), (L[3], expect)
+
+
+def test_rusanov_flux_at_a_velocity_jump():
+    """Uniform rho and p, the velocity and E_r jumping at the same face (the
+    right side moving left, faster): the slopes are 0, so the jump face sees
+    the cell values and its E_r flux is the mean of the two advective fluxes,
+    (E_L u_L + E_R u_R)/2, minus the dissipation s (E_R - E_L)/2 with
+    s = max(|u_L| + c, |u_R| + c).  Every other face carries E u of its
+    (equal) neighbours, so L(E_r) is -(F - E_L u_L)/dx and -(E_R u_R - F)/dx
+    in the two cells at the jump and 0 elsewhere."""
+    n, g = 16, 1.4
+    rho, p, u, Er = 0.5, 0.625, (0.25, -0.75), (1.5, 0.4)
+    X = jump_state(n, (rho, rho), u, (p, p), Er, g)
+    grid = oracle.Grid((n,), gamma=g, bc=(O, O), rad=(0.0, 0.6))
+    L, st = oracle.rhs(grid, X)
+    assert st == 0
+    vel = X[1] / X[0]
+    pr = (g - 1.0) * (X[2] - 0.5 * X[1] * X[1] / X[0])
+    c = np.sqrt(g * pr / X[0])
+    uL, uR, cL, cR = vel[0], vel[-1], c[0], c[-1]
+    s = max(abs(uL) + cL, abs(uR) + cR)
+    F = 0.5 * (Er[0] * uL + Er[1] * uR) - 0.5 * s * (Er[1] - Er[0])
+    expect = np.zeros(n)
+    expect[n // 2 - 1] = -(F - Er[0] * uL) * n
+    expect[n // 2] = -(Er[1] * uR - F) * n
+    assert np.allclose(L[3], expect, rtol=1e-13, atol=1e-13 * np.abs(expect).max())
+
+
 @pytest.mark.parametrize("bc", [P, R])
 def test_mirror_symmetry_with_radiation(bc):
     n = 20

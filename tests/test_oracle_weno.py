@@ -116,6 +116,51 @@ def test_weno5z_step_is_non_oscillatory():
         assert abs(oracle.weno5z([lo, hi, hi, hi, hi]) - hi) <= 1e-12 * max(abs(lo), abs(hi))
 
 
+def test_weno5z_indicators_match_their_integral_definition():
+    """Each smoothness indicator is, by its definition (Jiang and Shu 1996, the
+    indicators WENO5-Z uses), the integral over the middle cell of
+    dx (p_k')^2 + dx^3 (p_k'')^2 for the quadratic p_k whose averages over the
+    stencil's three cells are the data.  Here p_k comes from solving that
+    3 x 3 system and the integral from Gauss-Legendre quadrature (exact for
+    these polynomials), with dx = 1 and the middle cell on [-1/2, 1/2]; this
+    fixes both closed-form coefficients (13/12 and 1/4)."""
+    rng = np.random.default_rng(17)
+    xg, wg = np.polynomial.legendre.leggauss(4)
+    xg, wg = 0.5 * xg, 0.5 * wg  # nodes and weights on [-1/2, 1/2]
+    for _ in range(40):
+        v = rng.uniform(-2, 2, 5)
+        beta = oracle.weno5z_indicators(v)
+        for k in range(3):
+            centres = np.arange(k, k + 3) - 2.0
+            # average of 1, x, x^2 over [c - 1/2, c + 1/2]
+            A = np.stack([np.ones(3), centres, centres ** 2 + 1.0 / 12.0], axis=1)
+            a, b, c = np.linalg.solve(A, v[k:k + 3])
+            d1 = b + 2.0 * c * xg
+            d2 = 2.0 * c
+            expect = np.sum(wg * (d1 * d1 + d2 * d2))
+            assert beta[k] == pytest.approx(expect, rel=1e-12, abs=1e-13)
+
+
+def test_weno5z_tends_to_the_linear_scheme_at_eighth_order():
+    """On smooth data with f' != 0, a Taylor expansion gives beta_k = f'^2 dx^2
+    + O(dx^3) for every k and tau5 = |beta_0 - beta_2| = O(dx^5), so with the
+    ratio tau5/(beta_k + eps) taken to the first power the face value differs
+    from the fifth-order linear reconstruction (2, -13, 47, 27, -3)/60 (the
+    limit of the optimal weights d = (1, 6, 3)/10) by O(dx^8); the square of
+    the ratio would give O(dx^11).  Fitted order over dx = 1/4 .. 1/32."""
+    # f = sin(2.1 x + 0.4) + exp(0.7 x) through its antiderivative
+    F = lambda x: -np.cos(2.1 * x + 0.4) / 2.1 + np.exp(0.7 * x) / 0.7
+    hs = [2.0 ** -k for k in range(2, 6)]
+    diffs = []
+    for h in hs:
+        x = 0.3 + (np.arange(6) - 3) * h
+        v = (F(x[1:]) - F(x[:-1])) / h
+        lin = (2 * v[0] - 13 * v[1] + 47 * v[2] + 27 * v[3] - 3 * v[4]) / 60
+        diffs.append(abs(oracle.weno5z(v) - lin))
+    order = fitted_order([1 / h for h in hs], diffs)
+    assert 7.0 <= order <= 9.0, (order, diffs)
+
+
 def test_weno5z_affine_equivariance():
     """Shifting and scaling the data by a > 0 shifts and scales the face value
     (the smoothness ratios are scale-free; eps = 1e-40 is negligible here)."""
