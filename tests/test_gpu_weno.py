@@ -5,7 +5,9 @@ Tolerances as for the MUSCL-HLLC path: FP64 per field max|g - o| / max|o|
 <= 1e-12; FP32 bulk per field sum|g - o| / sum|o| <= 1e-5 against the FP64
 oracle on the float-rounded input.  The fused CFL step equals the oracle's
 bit for bit.  The paper's Sod figure (L1(rho) < 5e-4 at t = 0.0669, dx =
-2^-10, Courant 0.3) is also checked on the GPU run.
+2^-10, Courant 0.3) is also checked on the GPU run, whose every step is held
+to the 1e-12 bar against the oracle's step from the same state (the run as a
+whole: see SOD_RUN_TOL).
 """
 import json
 import os
@@ -111,10 +113,21 @@ def test_uniform_state_preserved_bitwise(ndim):
     assert np.array_equal(out, U0)
 
 
+# End-to-end bound for the paper's Sod run (503 steps).  Two IEEE-double
+# evaluations of the same WENO5-Z weights -- the plain alpha_k = d_k (1 +
+# tau5/(beta_k + eps)) and the one-division common-denominator form the GPU
+# uses -- both run on the CPU by the oracle's code, end 2.14e-11 apart (in m,
+# normwise) after this run: at the rarefaction head the indicators beta_k are
+# near rounding level next to eps = 1e-40, so the weights amplify last-bit
+# differences.  The end-to-end gate is 1e-10; every single step is gated at
+# 1e-12 by test_sod_paper_run_stepwise_on_gpu.
+SOD_RUN_TOL = 1e-10
+
+
 def test_sod_paper_figure_on_gpu():
     """The paper's Sod run on the GPU with the device time loop: the same
-    number of steps as the oracle, fields within 1e-12, and L1(rho) below
-    the paper's 5e-4."""
+    number of steps and final time as the oracle, fields within SOD_RUN_TOL
+    (see above), and L1(rho) below the paper's 5e-4."""
     with open(os.path.join(GOLD, "sod_paper.json")) as f:
         s = json.load(f)
     n = int(round(1.0 / s["dx"]))
@@ -128,12 +141,48 @@ def test_sod_paper_figure_on_gpu():
     out = U.cpu().numpy()
     assert steps == steps_ref and t == pytest.approx(t_ref, rel=1e-15, abs=0)
     for v in range(3):
-        assert field_rel_linf(out[v], ref[v]) <= 1e-11, (v, field_rel_linf(out[v], ref[v]))
+        err = field_rel_linf(out[v], ref[v])
+        log(f"Sod run field {v}: {err:.3e} (rel L1 {field_rel_l1(out[v], ref[v]):.3e})")
+        assert err <= SOD_RUN_TOL, (v, err)
     ex = RiemannSolution(1.0, 0.0, 1.0, 0.125, 0.0, 0.1)
     r, _, _ = ex.cell_averages(n, t)
     err = l1_error(out[0], r, s["dx"])
     log(f"GPU WENO5-Z + HLL Sod L1(rho) = {err:.3e}")
     assert err < s["paper_L1_rho_bound"]
+
+
+def test_sod_paper_run_stepwise_on_gpu():
+    """Every step of the paper's Sod run at the 1e-12 bar: the GPU takes the
+    oracle's dt sequence, and after each step its state is compared with the
+    oracle's step from the GPU's own previous state (so rounding differences
+    of earlier steps are not amplified into the comparison)."""
+    with open(os.path.join(GOLD, "sod_paper.json")) as f:
+        s = json.load(f)
+    n = int(round(1.0 / s["dx"]))
+    U0 = workloads.sod(n)
+    og = oracle.Grid((n,), bc=(O, O), scheme=W5)
+    _, _, nsteps, st, dts = oracle.run(og, U0, s["courant"], s["t_final"], max_steps=100_000,
+                                       record_dts=True)
+    assert st == 0 and nsteps == len(dts) > 400
+    g = H.make_grid((n,), bc=(O, O), scheme=W5)
+    U = torch.from_numpy(U0).to(DEV)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    dt = torch.zeros(1, dtype=torch.float64, device=DEV)
+    prev = U0.copy()
+    worst = 0.0
+    for k, d in enumerate(dts):
+        dt.fill_(d)
+        H.hard_hydro_step(g, U, dt, work)
+        out = U.cpu().numpy()
+        ref, st = oracle.step(og, prev, d)
+        assert st == 0
+        for v in range(3):
+            err = field_rel_linf(out[v], ref[v])
+            worst = max(worst, err)
+            assert err <= TOL64, (k, v, err)
+        prev = out
+    assert H.hard_status_read(work) == 0
+    log(f"Sod stepwise: {len(dts)} steps, worst per-step field error {worst:.3e}")
 
 
 def test_turbulent_64_periodic_one_step():
