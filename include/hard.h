@@ -152,6 +152,25 @@ hard_status_t hard_cfl_dt(const hard_grid_t* g, const void* U, double cfl, doubl
 hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_dev, double cfl,
                               double* next_dt_dev, void* work, size_t work_bytes, void* stream);
 
+/* hard_hydro_step for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same step through the same kernels, with the workspace
+ * taken from a static device array of HARD_NOALLOC_SCRATCH_BYTES bytes that
+ * the library holds on every GPU it runs on until the process ends.  The
+ * call allocates nothing.  Grids whose hard_workspace_bytes exceeds that size
+ * return HARD_ERR_WORKSPACE before anything is enqueued.  Each call first
+ * clears the array's control block with a fill kernel; if flags_dev (device
+ * uint32, may be NULL) is given it receives the status bits (HARD_FLAG_*)
+ * of this call's step when the enqueued work completes.  All calls on one
+ * GPU share that GPU's array: calls that may overlap in time (different
+ * streams, threads or processes' own libraries aside) race and must be
+ * stream-ordered by the caller.  The array's contents after a call are
+ * those of its last step. */
+#define HARD_NOALLOC_SCRATCH_BYTES (64u << 20)
+hard_status_t hard_hydro_step_noalloc(const hard_grid_t* g, void* U, const double* dt_dev,
+                                      double cfl, double* next_dt_dev, uint32_t* flags_dev,
+                                      void* stream);
+
 /* One stage of hard_hydro_step (stage = 1 or 2), for callers that schedule
  * the two stages themselves (hard_hydro_step is exactly stage 1 then 2):
  *   stage 1: dst = src + dt L(src)                      (src = U^n, dst = U^1)

@@ -18,7 +18,7 @@ import torch  # loads the HIP runtime that libhard.so then shares
 __all__ = [
     "HardError", "hard_grid_t", "make_grid", "lib",
     "hard_last_error", "hard_workspace_bytes", "hard_workspace_init", "hard_cfl_dt",
-    "hard_hydro_step", "hard_hydro_stage", "hard_run", "hard_status_read", "hard_conservation_sums",
+    "hard_hydro_step", "hard_hydro_step_noalloc", "hard_hydro_stage", "hard_run", "hard_status_read", "hard_conservation_sums",
     "hard_batch_plan_create", "hard_batch_plan_destroy", "hard_batch_offsets",
     "hard_batch_workspace_bytes", "hard_cfl_dt_batched", "hard_hydro_step_batched",
     "hard_run_batched", "batch_pack", "batch_unpack",
@@ -36,6 +36,7 @@ F64, F32 = 0, 1
 MUSCL_HLLC, WENO5Z_HLL = 0, 1  # face schemes (HARD_SCHEME_*)
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_NONPHYSICAL, ERR_HIP = range(6)
 FLAG_DENSITY, FLAG_PRESSURE, FLAG_NONFINITE, FLAG_RADIATION = 1, 2, 4, 8
+NOALLOC_SCRATCH_BYTES = 64 << 20  # HARD_NOALLOC_SCRATCH_BYTES
 FLD_EDDINGTON, FLD_LEVERMORE = 0, 1  # flux limiters of the radiation diffusion (HARD_FLD_*)
 
 
@@ -92,6 +93,7 @@ def lib():
             "hard_cfl_dt": [_gp, _vp, ctypes.c_double, _vp, ctypes.POINTER(ctypes.c_double), _vp,
                             _sz, _vp],
             "hard_hydro_step": [_gp, _vp, _vp, ctypes.c_double, _vp, _vp, _sz, _vp],
+            "hard_hydro_step_noalloc": [_gp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp],
             "hard_hydro_stage": [_gp, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_double, _vp,
                                  _vp, _sz, _vp],
             "hard_run": [_gp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
@@ -212,6 +214,14 @@ def hard_cfl_dt(g, U, cfl, dt_dev, work, want_host=False, stream=None):
 def hard_hydro_step(g, U, dt_dev, work, cfl=0.4, next_dt_dev=None, stream=None):
     _check(lib().hard_hydro_step(_grid(g), _ptr(U), _ptr(dt_dev), float(cfl), _ptr(next_dt_dev),
                                  _ptr(work), work.numel(), _stream(stream)))
+
+
+def hard_hydro_step_noalloc(g, U, dt_dev, cfl=0.4, next_dt_dev=None, flags_dev=None,
+                            stream=None):
+    """hard_hydro_step without a workspace argument (the library's static
+    device scratch; grids up to NOALLOC_SCRATCH_BYTES of workspace)."""
+    _check(lib().hard_hydro_step_noalloc(_grid(g), _ptr(U), _ptr(dt_dev), float(cfl),
+                                         _ptr(next_dt_dev), _ptr(flags_dev), _stream(stream)))
 
 
 def hard_hydro_stage(g, stage, src, un, dst, dt_dev, work, cfl=0.4, next_dt_dev=None,

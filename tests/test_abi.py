@@ -258,3 +258,18 @@ def test_cell_count_limit():
             call(H.make_grid((2048, 1024, 1024), rad=(0.4, 0.6)))
         assert e.value.code == H.ERR_INVALID_ARG
     assert H.hard_workspace_bytes(H.make_grid((2048, 1024, 1023))) > 0
+
+
+def test_noalloc_refuses_grids_beyond_its_scratch():
+    """hard_hydro_step_noalloc checks the grid and the size of the workspace
+    it would need against its static scratch before touching the device."""
+    L = H.lib()
+    g = H.make_grid((256, 256, 256), bc=(H.PERIODIC, H.PERIODIC))
+    assert L.hard_hydro_step_noalloc(ctypes.byref(g), FAKE, FAKE, 0.4, None, None, None) \
+        == H.ERR_WORKSPACE
+    assert "scratch" in H.hard_last_error()
+    assert H.hard_workspace_bytes(g) > H.NOALLOC_SCRATCH_BYTES
+    assert L.hard_hydro_step_noalloc(ctypes.byref(grid(ndim=0)), FAKE, FAKE, 0.4, None, None,
+                                     None) == H.ERR_INVALID_ARG
+    assert L.hard_hydro_step_noalloc(ctypes.byref(H.make_grid((16, 16))), FAKE, FAKE, 0.4, None,
+                                     FAKE + 2, None) == H.ERR_INVALID_ARG  # misaligned flags_dev
