@@ -177,9 +177,10 @@ hard_status_t hard_hydro_step_noalloc(const hard_grid_t* g, void* U, const doubl
  *   stage 2: dst = (un + (src + dt L(src))) / 2         (src = U^1, un = U^n)
  * dst may alias un in stage 2, never src.  next_dt_dev (stage 2 only, may be
  * NULL) receives the CFL step of dst.  Same layouts and rules as
- * hard_hydro_step; for HARD_SCHEME_MUSCL_HLLC the workspace needs only the
- * control block (256 bytes), for HARD_SCHEME_WENO5Z_HLL the full
- * hard_workspace_bytes. */
+ * hard_hydro_step; for HARD_SCHEME_MUSCL_HLLC without next_dt_dev the
+ * workspace needs only the control block (256 bytes), otherwise the full
+ * hard_workspace_bytes (which holds the per-workgroup slots of the CFL
+ * reduction and, for HARD_SCHEME_WENO5Z_HLL, the pipeline arrays). */
 hard_status_t hard_hydro_stage(const hard_grid_t* g, int32_t stage, const void* src,
                                const void* un, void* dst, const double* dt_dev, double cfl,
                                double* next_dt_dev, void* work, size_t work_bytes, void* stream);

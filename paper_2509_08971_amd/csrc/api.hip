@@ -113,7 +113,11 @@ WorkLayout layout_of(const Grid& g) {
   w.stage_bytes = align256((size_t)g.nvar * g.ncell * g.wsize);
   w.partials = w.stage + w.stage_bytes;
   w.partials_blocks = sums_blocks(g.ncell);
-  w.total = w.partials + align256((size_t)w.partials_blocks * g.nvar * 2 * sizeof(double));
+  w.slots = w.partials + align256((size_t)w.partials_blocks * g.nvar * 2 * sizeof(double));
+  long long ns = stage_launch_blocks(g.ndim, g.dtype, g.n);
+  if (ns < GRID_STRIDE_MAX_BLOCKS) ns = GRID_STRIDE_MAX_BLOCKS;
+  w.nslots = (int)ns;
+  w.total = w.slots + align256((size_t)ns * sizeof(double));
   w.weno_w = 0;
   w.weno_f[0] = w.weno_f[1] = w.weno_f[2] = 0;
   if (g.scheme == HARD_SCHEME_WENO5Z_HLL) {
@@ -165,6 +169,8 @@ hipError_t launch_scheme_stage(const Grid& G, const WorkLayout& L, char* wb, con
   w.fuse_cfl = a.fuse_cfl;
   w.ctl = a.ctl;
   w.next_dt = a.next_dt;
+  w.slots = a.slots;
+  w.nslots = a.nslots;
   w.W = wb + L.weno_w;
   return launch_weno_stage(G.ndim, G.dtype, w, stage, s);
 }
@@ -191,6 +197,8 @@ RadArgs rad_args(const Grid& G, const StageArgs& a) {
   r.cfl = a.cfl;
   r.ctl = a.ctl;
   r.next_dt = a.next_dt;
+  r.slots = a.slots;
+  r.nslots = a.nslots;
   return r;
 }
 
@@ -247,7 +255,8 @@ hard_status_t hard_cfl_dt(const hard_grid_t* g, const void* U, double cfl, doubl
   hipStream_t s = (hipStream_t)stream;
   Control* ctl = reinterpret_cast<Control*>(static_cast<char*>(work) + L.ctl);
   hipError_t e = launch_cfl(G.ndim, G.dtype, G.n, G.dx, G.inv_dx, G.dx_pow2, G.gamma, U, cfl, dt_dev,
-                                ctl, s);
+                            ctl, reinterpret_cast<double*>(static_cast<char*>(work) + L.slots),
+                            L.nslots, s);
   if (e != hipSuccess) return hip_fail(e, "hard_cfl_dt launch");
   if (dt_host) {
     unsigned flags = 0;
@@ -290,6 +299,8 @@ hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_de
   a.cfl = cfl;
   a.dt = dt_dev;
   a.ctl = reinterpret_cast<Control*>(wb + L.ctl);
+  a.slots = reinterpret_cast<double*>(wb + L.slots);
+  a.nslots = L.nslots;
   a.cz = stage_cz_override();
   void* U1 = wb + L.stage;
   // stage 1: U1 = U + dt L(U)
@@ -340,7 +351,8 @@ hard_status_t hard_hydro_stage(const hard_grid_t* g, int32_t stage, const void* 
     if ((st = check_cfl(cfl))) return st;
   }
   WorkLayout L = layout_of(G);
-  const size_t need = G.scheme == HARD_SCHEME_MUSCL_HLLC ? sizeof(Control) : L.total;
+  const bool fused = stage == 2 && next_dt_dev;
+  const size_t need = G.scheme == HARD_SCHEME_MUSCL_HLLC && !fused ? sizeof(Control) : L.total;
   if ((st = check_work(work, work_bytes, need))) return st;
   StageArgs a;
   std::memset(&a, 0, sizeof a);
@@ -356,6 +368,8 @@ hard_status_t hard_hydro_stage(const hard_grid_t* g, int32_t stage, const void* 
   a.cfl = cfl;
   a.dt = dt_dev;
   a.ctl = static_cast<Control*>(work);
+  a.slots = fused ? reinterpret_cast<double*>(static_cast<char*>(work) + L.slots) : nullptr;
+  a.nslots = fused ? L.nslots : 0;
   a.cz = stage_cz_override();
   a.src = src;
   a.un = stage == 2 ? un : src;
@@ -386,7 +400,8 @@ hard_status_t hard_run(const hard_grid_t* g, void* U, double cfl, double t_end,
   if (e != hipSuccess) return hip_fail(e, "hard_run clear");
   double* dt = &ctl->dt;
   if ((e = launch_cfl(G.ndim, G.dtype, G.n, G.dx, G.inv_dx, G.dx_pow2, G.gamma, U, cfl, dt,
-                      ctl, s)) != hipSuccess)
+                      ctl, reinterpret_cast<double*>(static_cast<char*>(work) + L.slots), L.nslots,
+                      s)) != hipSuccess)
     return hip_fail(e, "hard_run cfl");
   const int batch = 64;
   int done = 0;
@@ -439,7 +454,8 @@ hard_status_t hard_run_rhd(const hard_grid_t* g, void* U, double cfl, double t_e
   hipError_t e = launch_control_clear(ctl, s);
   if (e != hipSuccess) return hip_fail(e, "hard_run_rhd clear");
   if ((e = launch_cfl(G.ndim, G.dtype, G.n, G.dx, G.inv_dx, G.dx_pow2, G.gamma, U, cfl, dt,
-                      ctl, s)) != hipSuccess)
+                      ctl, reinterpret_cast<double*>(static_cast<char*>(work) + L.slots), L.nslots,
+                      s)) != hipSuccess)
     return hip_fail(e, "hard_run_rhd cfl");
   const int batch = 64;
   int done = 0;

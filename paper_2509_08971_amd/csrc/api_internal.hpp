@@ -30,6 +30,8 @@ struct WorkLayout {
   size_t stage_bytes;
   size_t partials;       // compensated-sum partials
   int partials_blocks;
+  size_t slots;          // CFL reductions: one signal-sum max per workgroup
+  int nslots;
   size_t weno_w;         // WENO5-Z pipeline: primitives (0 if unused)
   size_t weno_f[3];      // WENO5-Z pipeline: face fluxes per axis
   size_t total;

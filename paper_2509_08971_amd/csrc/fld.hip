@@ -453,7 +453,7 @@ __global__ __launch_bounds__(256) void fld_setup(FldLevel L, FldCommon cm, const
     if (!(r > 0.0)) flags |= FLAG_DENSITY;
     if (!(e > 0.0) || !isfinite(D)) flags |= FLAG_RADIATION;
   }
-  block_finish<256>(flags, 0.0, false, ctl, 0.0, nullptr);
+  block_finish<256>(flags, 0.0, false, ctl, nullptr);
 }
 
 // The finest x back into the state's E_r field (rounded to float for a
@@ -535,7 +535,7 @@ __global__ __launch_bounds__(256) void fld_setup_quad(FldLevel L, FldCommon cm, 
     *reinterpret_cast<double2*>(L.b + s1) = make_double2(ev[1], ev[3]);
     *reinterpret_cast<double2*>(L.x + s1) = make_double2(ev[1], ev[3]);
   }
-  block_finish<256>(flags, 0.0, false, ctl, 0.0, nullptr);
+  block_finish<256>(flags, 0.0, false, ctl, nullptr);
 }
 
 template <int NDIM, typename R>

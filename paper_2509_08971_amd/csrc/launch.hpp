@@ -25,9 +25,23 @@ struct StageArgs {
   int cz;                // walk positions per workgroup (z in 3D, y in 2D), 0 = default
   Control* ctl;          // workspace control block
   double* next_dt;       // fused CFL output (stage 2)
+  double* slots;         // fused CFL: one signal-sum max per workgroup
+  int nslots;            // room in slots (checked against the launch size)
 };
 
 hipError_t launch_stage(int ndim, int dtype, const StageArgs& a, int stage, hipStream_t s);
+
+// Workgroups of the stage-2 launch of launch_stage for this grid (the CFL
+// slots it needs).
+long long stage_launch_blocks(int ndim, int dtype, const int* n);
+
+// dt = cfl / max(slots[0 .. n)) by one workgroup (the second half of every
+// fused or standalone CFL reduction).
+hipError_t launch_cfl_final(const double* slots, int n, double cfl, double* dt, hipStream_t s);
+
+// Upper bound on the workgroups of the grid-stride kernels that end in a
+// CFL reduction (standalone CFL, WENO5-Z update, radiation exchange).
+constexpr int GRID_STRIDE_MAX_BLOCKS = 4096;
 
 // WENO5-Z + HLL stage (weno.hip): same stage semantics as StageArgs, with the
 // workspace arrays of the pipeline.
@@ -46,6 +60,8 @@ struct WenoArgs {
   int fuse_cfl;
   Control* ctl;
   double* next_dt;
+  double* slots;
+  int nslots;
   void* W;      // primitives of the stage source, [nvar][N]
   void* F[3];   // face fluxes per axis, [nvar][faces along that axis]
 };
@@ -70,6 +86,8 @@ struct RadArgs {
   int fuse_cfl;
   Control* ctl;
   double* next_dt;
+  double* slots;
+  int nslots;
 };
 
 hipError_t launch_rad_advect(int ndim, int dtype, const RadArgs& a, int stage, hipStream_t s);
@@ -78,7 +96,7 @@ hipError_t launch_rad_source(int ndim, int dtype, const RadArgs& a, hipStream_t 
 // Standalone CFL dt (reads U once).
 hipError_t launch_cfl(int ndim, int dtype, const int* n, const double* dx, const double* inv_dx,
                       int dx_pow2, double gamma, const void* U, double cfl, double* dt,
-                      Control* ctl, hipStream_t s);
+                      Control* ctl, double* slots, int nslots, hipStream_t s);
 
 // hard_run time control (one thread).
 hipError_t launch_time_control(Control* ctl, double t_end, long long max_steps, hipStream_t s);

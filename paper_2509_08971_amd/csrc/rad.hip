@@ -399,7 +399,7 @@ __global__ __launch_bounds__(256) void rad_source(RadArgs a) {
       smax = fmax(smax, signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
     }
   }
-  block_finish<256>(flags, smax, a.fuse_cfl != 0, a.ctl, a.cfl, a.next_dt);
+  block_finish<256>(flags, smax, a.fuse_cfl != 0, a.ctl, a.slots + blockIdx.x);
 }
 
 template <typename R, int NDIM>
@@ -443,7 +443,9 @@ hipError_t launch_rad_advect(int ndim, int dtype, const RadArgs& a, int stage, h
 hipError_t launch_rad_source(int ndim, int dtype, const RadArgs& a, hipStream_t s) {
   const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
   const long long nb = (N + 255) / 256;
-  const dim3 grid((unsigned)(nb < RAD_SOURCE_BLOCKS ? nb : RAD_SOURCE_BLOCKS)), block(256);
+  const unsigned nbs = (unsigned)(nb < RAD_SOURCE_BLOCKS ? nb : RAD_SOURCE_BLOCKS);
+  if (a.fuse_cfl && (int)nbs > a.nslots) return hipErrorInvalidValue;
+  const dim3 grid(nbs), block(256);
   if (dtype == 0) {
     if (ndim == 1) hipLaunchKernelGGL((rad_source<double, 1>), grid, block, 0, s, a);
     else if (ndim == 2) hipLaunchKernelGGL((rad_source<double, 2>), grid, block, 0, s, a);
@@ -453,7 +455,9 @@ hipError_t launch_rad_source(int ndim, int dtype, const RadArgs& a, hipStream_t 
     else if (ndim == 2) hipLaunchKernelGGL((rad_source<float, 2>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((rad_source<float, 3>), grid, block, 0, s, a);
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !a.fuse_cfl) return e;
+  return launch_cfl_final(a.slots, (int)nbs, a.cfl, a.next_dt, s);
 }
 
 }  // namespace hard

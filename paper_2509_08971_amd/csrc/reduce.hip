@@ -19,8 +19,8 @@ struct CflGeo {
 
 template <int NDIM, typename R>
 __global__ __launch_bounds__(RED_THREADS) void cfl_kernel(const R* __restrict__ U, CflGeo g,
-                                                          double gamma, double cfl, double* dt,
-                                                          Control* ctl) {
+                                                          double gamma, Control* ctl,
+                                                          double* slots) {
   constexpr int NV = NDIM + 2;
   const long long N = (long long)g.n[0] * g.n[1] * g.n[2];
   double smax = 0.0;
@@ -39,21 +39,45 @@ __global__ __launch_bounds__(RED_THREADS) void cfl_kernel(const R* __restrict__ 
     flags |= cell_flags<R, NV>(Ur, W[NV - 1]);
     smax = fmax(smax, signal_sum<NDIM>(Ud, g.dx, g.inv_dx, g.dx_pow2, gamma));
   }
-  block_finish<RED_THREADS>(flags, smax, true, ctl, cfl, dt);
+  block_finish<RED_THREADS>(flags, smax, true, ctl, slots + blockIdx.x);
+}
+
+// dt = cfl / (max of the per-workgroup signal-sum maxima), one workgroup.
+constexpr int FINAL_THREADS = 1024;
+__global__ __launch_bounds__(FINAL_THREADS) void cfl_final_kernel(const double* __restrict__ slots,
+                                                                  int n, double cfl, double* dt) {
+  __shared__ double red[FINAL_THREADS / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += FINAL_THREADS) s = fmax(s, slots[i]);
+  s = wave_max(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int i = 0; i < FINAL_THREADS / 64; ++i) m = fmax(m, red[i]);
+    *dt = cfl / m;
+  }
+}
+
+hipError_t launch_cfl_final(const double* slots, int n, double cfl, double* dt, hipStream_t s) {
+  hipLaunchKernelGGL(cfl_final_kernel, dim3(1), dim3(FINAL_THREADS), 0, s, slots, n, cfl, dt);
+  return hipGetLastError();
 }
 
 static int cfl_blocks(long long N) {
   long long b = (N + RED_THREADS * 4 - 1) / (RED_THREADS * 4);
-  if (b > 4096) b = 4096;
+  if (b > GRID_STRIDE_MAX_BLOCKS) b = GRID_STRIDE_MAX_BLOCKS;
   if (b < 1) b = 1;
   return (int)b;
 }
 
 hipError_t launch_cfl(int ndim, int dtype, const int* n, const double* dx, const double* inv_dx,
                       int dx_pow2, double gamma, const void* U, double cfl, double* dt,
-                      Control* ctl, hipStream_t s) {
+                      Control* ctl, double* slots, int nslots, hipStream_t s) {
   long long N = (long long)n[0] * n[1] * n[2];
-  dim3 grid(cfl_blocks(N)), block(RED_THREADS);
+  const int nb = cfl_blocks(N);
+  if (nb > nslots) return hipErrorInvalidValue;
+  dim3 grid(nb), block(RED_THREADS);
   CflGeo g;
   for (int d = 0; d < 3; ++d) {
     g.n[d] = n[d];
@@ -63,7 +87,7 @@ hipError_t launch_cfl(int ndim, int dtype, const int* n, const double* dx, const
   g.dx_pow2 = dx_pow2;
 #define HARD_CFL(D, T)                                                                      \
   hipLaunchKernelGGL((cfl_kernel<D, T>), grid, block, 0, s, static_cast<const T*>(U), g, gamma, \
-                     cfl, dt, ctl)
+                     ctl, slots)
   if (dtype == 0) {
     if (ndim == 1) HARD_CFL(1, double);
     else if (ndim == 2) HARD_CFL(2, double);
@@ -74,7 +98,9 @@ hipError_t launch_cfl(int ndim, int dtype, const int* n, const double* dx, const
     else HARD_CFL(3, float);
   }
 #undef HARD_CFL
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_cfl_final(slots, nb, cfl, dt, s);
 }
 
 __global__ void control_clear_kernel(Control* ctl) {

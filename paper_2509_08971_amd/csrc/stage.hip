@@ -4,9 +4,10 @@
 // 2); halo re-reads hit the L2 of the XCD that owns the neighbouring tiles.
 //
 // Stage 2 optionally folds the CFL signal-speed max of the new state into
-// the same pass (wave64 shuffle max -> LDS -> one atomicMax per workgroup;
-// the last workgroup turns the max into dt and re-arms the slot).
+// the same pass (wave64 shuffle max -> LDS -> one slot per workgroup); a
+// one-workgroup kernel after it turns the slots into dt.
 
+#include "api_internal.hpp"
 #include "hydro_device.hpp"
 #include "launch.hpp"
 #include "stage_tile.hpp"
@@ -52,33 +53,46 @@ void stage_kernel(StageArgs a) {
   unsigned flags = 0;
   double smax = 0.0;
   run_tile<NDIM, R, STAGE, TX, TY, NTHR, NDIM == 3>(t, lds, flags, smax);
-  block_finish<NTHR>(flags, smax, STAGE == 2 && a.fuse_cfl, a.ctl, a.cfl, a.next_dt);
+  block_finish<NTHR>(flags, smax, STAGE == 2 && a.fuse_cfl, a.ctl, a.slots + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// TX x TY cells per tile (3D), or a row of TX cells (1D, 2D); NTHR threads;
-// a.cz positions per walk chunk (0 = default).
+// Launch shape of a stage: workgroups (tiles x walk chunks) and the chunk
+// length.  TX x TY cells per tile (3D), or a row of TX cells (1D, 2D); cz_in
+// walk positions per chunk (0 = cz_default).
+template <int NDIM, int TX, int TY>
+static long long stage_shape(const int* n, int cz_in, int cz_default, int& tiles_x, int& tiles_y,
+                             int& cz) {
+  tiles_x = (n[0] + TX - 1) / TX;
+  tiles_y = NDIM == 3 ? (n[1] + TY - 1) / TY : 1;
+  long long nchunk = 1;
+  cz = 1;
+  if (NDIM >= 2) {
+    const int nwalk = NDIM == 3 ? n[2] : n[1];
+    cz = cz_in > 0 ? cz_in : cz_default;
+    nchunk = (nwalk + cz - 1) / cz;
+  }
+  return (long long)tiles_x * tiles_y * nchunk;
+}
+
+// NTHR threads per workgroup; stage 2 with a fused CFL step ends with the
+// one-workgroup reduction of the slots.
 template <int NDIM, typename R, int TX, int TY, int NTHR>
 static hipError_t launch_stage_t(const StageArgs& a0, int stage, int cz_default, hipStream_t s) {
   StageArgs a = a0;
-  a.tiles_x = (int)((a.n[0] + TX - 1) / TX);
-  a.tiles_y = NDIM == 3 ? (int)((a.n[1] + TY - 1) / TY) : 1;
-  int nchunk = 1;
-  if (NDIM >= 2) {
-    const int nwalk = NDIM == 3 ? a.n[2] : a.n[1];
-    if (a.cz <= 0) a.cz = cz_default;
-    nchunk = (nwalk + a.cz - 1) / a.cz;
-  } else {
-    a.cz = 1;
-  }
-  dim3 grid((unsigned)(a.tiles_x * a.tiles_y * nchunk)), block(NTHR);
+  const long long nb = stage_shape<NDIM, TX, TY>(a.n, a.cz, cz_default, a.tiles_x, a.tiles_y, a.cz);
+  const bool fuse = stage == 2 && a.fuse_cfl;
+  if (nb >= (1LL << 31) || (fuse && nb > a.nslots)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)nb), block(NTHR);
   if (stage == 1)
     hipLaunchKernelGGL((stage_kernel<NDIM, R, 1, TX, TY, NTHR>), grid, block, 0, s, a);
   else
     hipLaunchKernelGGL((stage_kernel<NDIM, R, 2, TX, TY, NTHR>), grid, block, 0, s, a);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !fuse) return e;
+  return launch_cfl_final(a.slots, (int)nb, a.cfl, a.next_dt, s);
 }
 
 // tile shapes (x by y) of the 3D kernels.  32 x 8 also for FP64: its x halo
@@ -90,21 +104,42 @@ static hipError_t launch_stage_t(const StageArgs& a0, int stage, int cz_default,
 #ifndef HARD_TILE32
 #define HARD_TILE32 32, 8
 #endif
+// z planes per workgroup of the 3D kernels
+#ifndef HARD_STAGE_CZ_3D
+#define HARD_STAGE_CZ_3D 32
+#endif
+constexpr int STAGE_CZ_3D = HARD_STAGE_CZ_3D;
 
 // 2D grids: rows of 255, 127 or 63 cells (one face per thread per row) and
 // enough walk chunks to give the machine a few thousand workgroups.
+static int chunk_2d(int nx, int ny, int tx) {
+  long long tiles = (nx + tx - 1) / tx;
+  long long want = 4096;
+  long long c = (tiles * ny + want - 1) / want;
+  return (int)(c < 4 ? 4 : (c > 64 ? 64 : c));
+}
+
 template <typename R>
 static hipError_t launch_stage_2d(const StageArgs& a, int stage, hipStream_t s) {
   const int nx = a.n[0], ny = a.n[1];
-  auto chunk_for = [&](int tx) {
-    long long tiles = (nx + tx - 1) / tx;
-    long long want = 4096;
-    long long c = (tiles * ny + want - 1) / want;
-    return (int)(c < 4 ? 4 : (c > 64 ? 64 : c));
-  };
-  if (nx >= 1024) return launch_stage_t<2, R, 255, 1, 256>(a, stage, chunk_for(255), s);
-  if (nx >= 256) return launch_stage_t<2, R, 127, 1, 128>(a, stage, chunk_for(127), s);
-  return launch_stage_t<2, R, 63, 1, 64>(a, stage, chunk_for(63), s);
+  if (nx >= 1024) return launch_stage_t<2, R, 255, 1, 256>(a, stage, chunk_2d(nx, ny, 255), s);
+  if (nx >= 256) return launch_stage_t<2, R, 127, 1, 128>(a, stage, chunk_2d(nx, ny, 127), s);
+  return launch_stage_t<2, R, 63, 1, 64>(a, stage, chunk_2d(nx, ny, 63), s);
+}
+
+long long stage_launch_blocks(int ndim, int dtype, const int* n) {
+  const int cz = stage_cz_override();
+  int tx, ty, c;
+  switch (ndim) {
+    case 1: return stage_shape<1, 255, 1>(n, cz, 1, tx, ty, c);
+    case 2:
+      if (n[0] >= 1024) return stage_shape<2, 255, 1>(n, cz, chunk_2d(n[0], n[1], 255), tx, ty, c);
+      if (n[0] >= 256) return stage_shape<2, 127, 1>(n, cz, chunk_2d(n[0], n[1], 127), tx, ty, c);
+      return stage_shape<2, 63, 1>(n, cz, chunk_2d(n[0], n[1], 63), tx, ty, c);
+    default:
+      return dtype == 0 ? stage_shape<3, HARD_TILE64>(n, cz, STAGE_CZ_3D, tx, ty, c)
+                        : stage_shape<3, HARD_TILE32>(n, cz, STAGE_CZ_3D, tx, ty, c);
+  }
 }
 
 hipError_t launch_stage(int ndim, int dtype, const StageArgs& a, int stage, hipStream_t s) {
@@ -112,13 +147,13 @@ hipError_t launch_stage(int ndim, int dtype, const StageArgs& a, int stage, hipS
     switch (ndim) {
       case 1: return launch_stage_t<1, double, 255, 1, 256>(a, stage, 1, s);
       case 2: return launch_stage_2d<double>(a, stage, s);
-      case 3: return launch_stage_t<3, double, HARD_TILE64, 256>(a, stage, 32, s);
+      case 3: return launch_stage_t<3, double, HARD_TILE64, 256>(a, stage, STAGE_CZ_3D, s);
     }
   } else {
     switch (ndim) {
       case 1: return launch_stage_t<1, float, 255, 1, 256>(a, stage, 1, s);
       case 2: return launch_stage_2d<float>(a, stage, s);
-      case 3: return launch_stage_t<3, float, HARD_TILE32, 256>(a, stage, 32, s);
+      case 3: return launch_stage_t<3, float, HARD_TILE32, 256>(a, stage, STAGE_CZ_3D, s);
     }
   }
   return hipErrorInvalidValue;

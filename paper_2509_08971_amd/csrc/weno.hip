@@ -299,7 +299,7 @@ __global__ __launch_bounds__(256) void weno_update(WenoArgs a) {
       smax = fmax(smax, signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
     }
   }
-  block_finish<256>(0u, smax, fuse, a.ctl, a.cfl, a.next_dt);
+  block_finish<256>(0u, smax, fuse, a.ctl, a.slots + blockIdx.x);
 }
 
 // weno_update for FP64 3D grids with nx even: two cells of a row per thread
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(256) void weno_update_pair(WenoArgs a) {
         smax = fmax(smax, signal_sum<NDIM>(Out[e], a.dx, a.inv_dx, a.dx_pow2, a.gamma));
     }
   }
-  block_finish<256>(0u, smax, fuse, a.ctl, a.cfl, a.next_dt);
+  block_finish<256>(0u, smax, fuse, a.ctl, a.slots + blockIdx.x);
 }
 
 template <typename R, int NDIM>
@@ -389,8 +389,12 @@ static hipError_t weno_stage_t(const WenoArgs& a, int stage, hipStream_t s) {
   const unsigned nbu = nb < 2048u ? nb : 2048u;
   const bool pair = std::is_same<R, double>::value && NDIM == 3 && a.n[0] % 2 == 0 &&
                     ((uintptr_t)a.src | (uintptr_t)a.un | (uintptr_t)a.dst) % 16 == 0;
+  const bool fuse = stage == 2 && a.fuse_cfl;
+  unsigned nbx = nbu;
   if (pair) {
     const unsigned np = (unsigned)((N / 2 + 255) / 256), nbp = np < 2048u ? np : 2048u;
+    nbx = nbp;
+    if (fuse && (int)nbx > a.nslots) return hipErrorInvalidValue;
     if (stage == 1)
       hipLaunchKernelGGL((weno_update_pair<1>), dim3(nbp), dim3(256), 0, s, a);
     else
@@ -398,9 +402,12 @@ static hipError_t weno_stage_t(const WenoArgs& a, int stage, hipStream_t s) {
   } else if (stage == 1) {
     hipLaunchKernelGGL((weno_update<R, NDIM, 1>), dim3(nbu), dim3(256), 0, s, a);
   } else {
+    if (fuse && (int)nbx > a.nslots) return hipErrorInvalidValue;
     hipLaunchKernelGGL((weno_update<R, NDIM, 2>), dim3(nbu), dim3(256), 0, s, a);
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !fuse) return e;
+  return launch_cfl_final(a.slots, (int)nbx, a.cfl, a.next_dt, s);
 }
 
 hipError_t launch_weno_stage(int ndim, int dtype, const WenoArgs& a, int stage, hipStream_t s) {
