@@ -41,7 +41,7 @@ def lib(path=None):
     global _lib
     if _lib is None:
         if path is None:
-            path = _build.LIB
+            path = os.environ.get("HARD_ORACLE_LIB") or _build.LIB
             if not os.path.exists(path):
                 _build.build()
         L = ctypes.CDLL(path)
@@ -74,6 +74,8 @@ def lib(path=None):
         L.oracle_weno5z_indicators.restype = None
         L.oracle_threads.argtypes = []
         L.oracle_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
         L.oracle_count_ops.argtypes = common + [ctypes.c_double, dp, i64p]
         L.oracle_count_ops.restype = None
         _lib = L
@@ -237,6 +239,11 @@ def ops_per_zone_update(ndim, U_of_n, n_small, n_large, bc=None, dt=1e-4):
 def threads():
     """OpenMP threads the oracle's loops use."""
     return lib().oracle_threads()
+
+
+def set_threads(n):
+    """Use n OpenMP threads from now on (the results are the same for any n)."""
+    lib().oracle_set_threads(int(n))
 
 
 def minmod(a, b):

@@ -16,9 +16,15 @@ FLD_LIB = os.path.join(HERE, "libfld_oracle.so")
 FLD_SRC = [os.path.join(HERE, "fld_oracle.cpp")]
 
 
-def _compile(srcs, out, verbose):
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+             "-fno-omit-frame-pointer", "-g"]
+ASAN_LIB = os.path.join(HERE, "liboracle_asan.so")
+ASAN_FLD_LIB = os.path.join(HERE, "libfld_oracle_asan.so")
+
+
+def _compile(srcs, out, verbose, extra=()):
     cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", out + ".tmp"] + srcs
+           "-fPIC", "-shared", "-Wall", "-Wextra", *extra, "-o", out + ".tmp"] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -32,6 +38,17 @@ def build(verbose: bool = False, src=None, out=None) -> str:
     if src is None:
         _compile(FLD_SRC, FLD_LIB, verbose)
     return _compile([src] if src else SRC, out or LIB, verbose)
+
+
+def build_sanitized(verbose: bool = False):
+    """AddressSanitizer + UndefinedBehaviorSanitizer builds of both oracle
+    libraries (liboracle_asan.so, libfld_oracle_asan.so).  A process that
+    loads them needs gcc's libasan (first) and libubsan in LD_PRELOAD; the
+    oracle modules load them instead of the plain builds when the environment
+    names them in HARD_ORACLE_LIB and HARD_FLD_ORACLE_LIB."""
+    _compile(SRC, ASAN_LIB, verbose, SAN_FLAGS)
+    _compile(FLD_SRC, ASAN_FLD_LIB, verbose, SAN_FLAGS)
+    return ASAN_LIB, ASAN_FLD_LIB
 
 
 def build_fld(verbose: bool = False, src=None, out=None) -> str:

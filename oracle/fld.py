@@ -34,7 +34,7 @@ def lib(path=None):
     global _lib
     if _lib is None:
         if path is None:
-            path = _build.FLD_LIB
+            path = os.environ.get("HARD_FLD_ORACLE_LIB") or _build.FLD_LIB
             if not os.path.exists(path):
                 _build.build_fld()
         L = ctypes.CDLL(path)

@@ -815,6 +815,8 @@ int oracle_threads(void) { return 1; }
 static void omp_set_num_threads(int) {}
 static int omp_get_max_threads(void) { return 1; }
 #endif
+// Threads of the OpenMP loops from now on (results do not depend on it).
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
                       int scheme, const double* radp,
