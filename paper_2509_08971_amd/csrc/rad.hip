@@ -396,7 +396,7 @@ __global__ __launch_bounds__(256) void rad_source(RadArgs a) {
       // an unchanged value came from R, so R(value) is the stored word either
       // way; E_r is not part of the signal sum
       Ud[NDIM + 1] = (double)R(Ef);
-      smax = fmax(smax, signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
+      smax = fmax(smax, cfl_signal<R, NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
     }
   }
   block_finish<256>(flags, smax, a.fuse_cfl != 0, a.ctl, a.slots + blockIdx.x);

@@ -70,7 +70,10 @@ struct TileShape {
   static constexpr int NFY = PD == 2 ? TX * (TY + 1) : 0;  // y faces per plane (3D)
   static constexpr int NF = NFX + NFY;
   static constexpr int NHALO = PD == 2 ? 4 * (TX + TY) : 4;
-  static constexpr int lds_elems = NV * (LXY + NF);
+  // FP64 3D: the flux through the face below each cell along the walk axis
+  // lives in LDS instead of registers (10 VGPRs fewer at the peak)
+  static constexpr bool FZ_LDS = PD == 2 && sizeof(R) == 8;
+  static constexpr int lds_elems = NV * (LXY + NF) + (FZ_LDS ? NV * TX * TY : 0);
   static_assert(PD == 2 || TY == 1, "1D and 2D planes are one row");
 };
 
@@ -93,6 +96,10 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
 
   R* Ws = lds;             // NV * LXY: primitives of the plane (tile + halo)
   R* Fs = lds + NV * LXY;  // NV * NF: in-plane face fluxes, x faces then y faces
+  // (FZ_LDS) the walk-axis flux below each owner cell; each thread reads and
+  // writes only its own slots, so no barrier guards them
+  R* Fz = lds + NV * (LXY + NF);
+  constexpr bool FZ_LDS = S::FZ_LDS;
 
   const int tid = threadIdx.x;
   const bool owner = NT == TX * TY || tid < TX * TY;  // this thread owns a cell column of the tile
@@ -152,7 +159,18 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
 
   // walk-axis register window: P0 = position w, P1 = w+1, S0 = slope at w,
   // Fm = flux through the face w-1/2; conserved values Ucur (w) and Uc1 (w+1)
-  R P0[NV], P1[NV], S0[NV], Fm[NV];
+  R P0[NV], P1[NV], S0[NV], Fm[FZ_LDS ? 1 : NV];
+  auto fz_get = [&](int v) -> R {
+    if constexpr (FZ_LDS) return Fz[v * (TX * TY) + tid];
+    else return Fm[v];
+  };
+  auto fz_set = [&](int v, R x) {
+    if constexpr (FZ_LDS) {
+      if (owner) Fz[v * (TX * TY) + tid] = x;
+    } else {
+      Fm[v] = x;
+    }
+  };
   R Ucur[NV], Uc1[NV];
   if constexpr (!WALK) load_cons(col, Ucur);
   if constexpr (WALK) {
@@ -175,7 +193,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
     }
     hllc_ordered<R, NV>(A, B, gam, inv_gm1, Fn);
 #pragma unroll
-    for (int k = 0; k < NV; ++k) Fm[wperm[k]] = Fn[k];
+    for (int k = 0; k < NV; ++k) fz_set(wperm[k], Fn[k]);
   }
 
   // Halo slot of this thread: NHALO <= NT, so each thread owns at most one
@@ -286,28 +304,54 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
         // far faces the spare threads did not cover
         constexpr int RX = NSPARE < TY ? TY - NSPARE : 0;
         constexpr int RY = NSPARE < TX ? TX - NSPARE : 0;
-        // the x far faces on wave 0, the y far faces on wave 1: no wave computes
-        // two faces in this round (the others would wait for it at the
-        // barrier), and only two waves spend the round's instructions.
-        // Measured: 2.8% faster than all far faces on wave 0 (two divergent
-        // face computations there) and than one face on every wave.
-        constexpr int NW = NT / 64;
-        static_assert(NW >= 2, "far-face split needs two waves");
-        constexpr int FW = 2;  // waves that take far faces
-        constexpr int PX = (RX + FW / 2 - 1) / (FW / 2), PY = (RY + FW / 2 - 1) / (FW / 2);
-        static_assert(PX <= 64 && PY <= 64, "one far face per lane");
         const int wv = tid >> 6, ln = tid & 63;
-        if (wv < FW / 2) {
-          const int r = wv * PX + ln;
-          if (ln < PX && r < RX) {
-            const int j = NSPARE + r;
-            face((j + OY) * LX + TX, j * (TX + 1) + TX, XF{});
+        if constexpr (RX + RY <= 64 && sizeof(R) == 8) {
+          // FP64: all far faces on wave 0 in one pass, the axis chosen per
+          // lane (x faces on the first RX lanes): one wave computes one extra
+          // face (measured 2% faster per step than one wave per axis)
+          if (wv == 0 && ln < RX + RY) {
+            const bool yf = ln >= RX;
+            const int j = NSPARE + (yf ? ln - RX : ln);
+            const int base = yf ? TY * LX + j + 2 : (j + OY) * LX + TX;
+            const int fidx = yf ? NFX + TY * TX + j : j * (TX + 1) + TX;
+            const int stride = yf ? LX : 1;
+            R WL[NV], WR[NV], Fn[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              const int sv = (PD == 2 && yf && (v == 1 || v == 2)) ? 3 - v : v;
+              const R* wp = Ws + sv * LXY + base;
+              muscl_pair(wp[0], wp[stride], wp[2 * stride], wp[3 * stride], WL[v], WR[v]);
+            }
+            hllc_ordered<R, NV>(WL, WR, gam, inv_gm1, Fn);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              const int sv = (PD == 2 && yf && (v == 1 || v == 2)) ? 3 - v : v;
+              Fs[sv * NF + fidx] = Fn[v];
+            }
           }
-        } else if (wv < FW) {
-          const int r = (wv - FW / 2) * PY + ln;
-          if (ln < PY && r < RY) {
-            const int j = NSPARE + r;
-            face(TY * LX + j + 2, NFX + TY * TX + j, YF{});
+        } else {
+          // the x far faces on wave 0, the y far faces on wave 1: no wave
+          // computes two faces in this round (the others would wait for it at
+          // the barrier), and only two waves spend the round's instructions.
+          // FP32 keeps this form: the per-lane axis choice costs it registers
+          // (128 instead of 96, one wave per SIMD fewer).
+          constexpr int NW = NT / 64;
+          static_assert(NW >= 2, "far-face split needs two waves");
+          constexpr int FW = 2;  // waves that take far faces
+          constexpr int PX = (RX + FW / 2 - 1) / (FW / 2), PY = (RY + FW / 2 - 1) / (FW / 2);
+          static_assert(PX <= 64 && PY <= 64, "one far face per lane");
+          if (wv < FW / 2) {
+            const int r = wv * PX + ln;
+            if (ln < PX && r < RX) {
+              const int j = NSPARE + r;
+              face((j + OY) * LX + TX, j * (TX + 1) + TX, XF{});
+            }
+          } else if (wv < FW) {
+            const int r = (wv - FW / 2) * PY + ln;
+            if (ln < PY && r < RY) {
+              const int j = NSPARE + r;
+              face(TY * LX + j + 2, NFX + TY * TX + j, YF{});
+            }
           }
         }
       }
@@ -344,7 +388,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
       for (int v = 0; v < NV; ++v) {
         R l = R(0) - (Fs[v * NF + fxl + 1] - Fs[v * NF + fxl]) * idx0;
         if (PD == 2) l = l - (Fs[v * NF + fyl + TX] - Fs[v * NF + fyl]) * idx1;
-        if (WALK) l = l - (Fp[v] - Fm[v]) * idxw;
+        if (WALK) l = l - (Fp[v] - fz_get(v)) * idxw;
         if (STAGE == 1) {
           Out[v] = Ucur[v] + dt * l;
         } else {
@@ -357,7 +401,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
         double Ud[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) Ud[v] = (double)Out[v];
-        smax = fmax(smax, signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
+        smax = fmax(smax, cfl_signal<R, NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
       }
     }
 
@@ -365,7 +409,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
     if constexpr (WALK) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        Fm[v] = Fp[v];
+        fz_set(v, Fp[v]);
         P0[v] = P1[v];
         P1[v] = P2[v];
         Ucur[v] = Uc1[v];

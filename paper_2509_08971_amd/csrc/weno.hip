@@ -296,7 +296,7 @@ __global__ __launch_bounds__(256) void weno_update(WenoArgs a) {
       double Ud[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) Ud[v] = (double)Out[v];
-      smax = fmax(smax, signal_sum<NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
+      smax = fmax(smax, cfl_signal<R, NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
     }
   }
   block_finish<256>(0u, smax, fuse, a.ctl, a.slots + blockIdx.x);
