@@ -74,6 +74,11 @@ def lib(path=None):
         L.oracle_weno5z_indicators.restype = None
         L.oracle_threads.argtypes = []
         L.oracle_threads.restype = ctypes.c_int
+        L.oracle_steps_tangent_multi.argtypes = common + [ctypes.c_int64, dp, ctypes.c_int,
+                                                               dp, dp]
+        L.oracle_steps_tangent_multi.restype = ctypes.c_int
+        L.oracle_branch_signature.argtypes = common + [ctypes.c_int64, dp, dp]
+        L.oracle_branch_signature.restype = ctypes.c_uint64
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_set_threads.restype = None
         L.oracle_count_ops.argtypes = common + [ctypes.c_double, dp, i64p]
@@ -195,6 +200,34 @@ def steps_tangent(g: Grid, U, dU, dts):
     d = np.ascontiguousarray(dts, dtype=np.float64)
     st = lib().oracle_steps_tangent(*g._args(), len(d), _dptr(d), _dptr(X), _dptr(D))
     return X, D, st
+
+
+def steps_tangent_multi(g: Grid, U, dUs, dts):
+    """Forward-mode derivatives of len(dts) steps with frozen dts along
+    len(dUs) directions at once (1, 2, 4 or 8), by one evaluation with
+    dual numbers of that many components.
+
+    Returns (U_n, [dU_n per direction], status).
+    """
+    X = _as_state(g, U).copy()
+    K = len(dUs)
+    D = np.ascontiguousarray(np.stack([_as_state(g, d) for d in dUs]))
+    d = np.ascontiguousarray(dts, dtype=np.float64)
+    st = lib().oracle_steps_tangent_multi(*g._args(), len(d), _dptr(d), K, _dptr(X),
+                                          _dptr(D))
+    if st < 0:
+        raise ValueError("1, 2, 4 or 8 directions")
+    return X, [D[k] for k in range(K)], st
+
+
+def branch_signature(g: Grid, U, dts):
+    """64-bit hash of the outcome of every comparison that len(dts) steps
+    from U with the step sizes dts make (minmod picks, wave-speed min/max,
+    HLLC regions, |x|), in evaluation order: two inputs with the same
+    signature take the same branches everywhere."""
+    X = np.ascontiguousarray(_as_state(g, U), dtype=np.float64)
+    d = np.ascontiguousarray(dts, dtype=np.float64)
+    return int(lib().oracle_branch_signature(*g._args(), len(d), _dptr(d), _dptr(X)))
 
 
 def hllc(WL, WR, gamma=1.4):

@@ -81,8 +81,102 @@ inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
 inline double value(double a) { return a; }
 inline double value(Dual a) { return a.v; }
 
+// K directional derivatives carried at once: the rules of Dual applied to
+// each derivative component (one evaluation of the values for K directions).
+template <int K>
+struct DualN {
+  double v;
+  double d[K];
+  DualN() : v(0.0) {
+    for (int k = 0; k < K; ++k) d[k] = 0.0;
+  }
+  DualN(double a) : v(a) {  // NOLINT: constants promote implicitly
+    for (int k = 0; k < K; ++k) d[k] = 0.0;
+  }
+};
+template <int K>
+inline DualN<K> operator+(const DualN<K>& a, const DualN<K>& b) {
+  DualN<K> r(a.v + b.v);
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+template <int K>
+inline DualN<K> operator-(const DualN<K>& a, const DualN<K>& b) {
+  DualN<K> r(a.v - b.v);
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+template <int K>
+inline DualN<K> operator-(const DualN<K>& a) {
+  DualN<K> r(-a.v);
+  for (int k = 0; k < K; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+template <int K>
+inline DualN<K> operator*(const DualN<K>& a, const DualN<K>& b) {
+  DualN<K> r(a.v * b.v);
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+template <int K>
+inline DualN<K> operator/(const DualN<K>& a, const DualN<K>& b) {
+  const double q = a.v / b.v;
+  DualN<K> r(q);
+  for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] - q * b.d[k]) / b.v;
+  return r;
+}
+template <int K>
+inline DualN<K> sqrt(const DualN<K>& a) {
+  const double s = std::sqrt(a.v);
+  DualN<K> r(s);
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] / (2.0 * s);
+  return r;
+}
+template <int K>
+inline DualN<K> fabs(const DualN<K>& a) { return a.v >= 0.0 ? a : -a; }
+template <int K>
+inline bool operator<(const DualN<K>& a, const DualN<K>& b) { return a.v < b.v; }
+template <int K>
+inline bool operator<=(const DualN<K>& a, const DualN<K>& b) { return a.v <= b.v; }
+template <int K>
+inline bool operator>(const DualN<K>& a, const DualN<K>& b) { return a.v > b.v; }
+template <int K>
+inline bool operator>=(const DualN<K>& a, const DualN<K>& b) { return a.v >= b.v; }
+template <int K>
+inline double value(const DualN<K>& a) { return a.v; }
+
 using std::fabs;
 using std::sqrt;
+
+// ----------------------------------------------------------------------------
+// Branch-recording scalar: a double whose comparisons (every branch of the
+// method: minmod picks, wave-speed min/max, the HLLC region, |x|) fold their
+// outcomes into a running hash, so two inputs that take the same branches
+// everywhere give the same signature.  The hash is a plain global, so
+// recording runs use one thread.
+// ----------------------------------------------------------------------------
+static uint64_t g_sig;
+inline bool sig_note(bool b) {
+  g_sig = (g_sig ^ (b ? 0x9e3779b97f4a7c15ull : 0x7f4a7c159e3779b9ull)) * 0x100000001b3ull;
+  return b;
+}
+struct Sig {
+  double v;
+  Sig() : v(0.0) {}
+  Sig(double a) : v(a) {}  // NOLINT: constants promote implicitly
+};
+inline Sig operator+(Sig a, Sig b) { return Sig(a.v + b.v); }
+inline Sig operator-(Sig a, Sig b) { return Sig(a.v - b.v); }
+inline Sig operator-(Sig a) { return Sig(-a.v); }
+inline Sig operator*(Sig a, Sig b) { return Sig(a.v * b.v); }
+inline Sig operator/(Sig a, Sig b) { return Sig(a.v / b.v); }
+inline Sig sqrt(Sig a) { return Sig(std::sqrt(a.v)); }
+inline Sig fabs(Sig a) { return sig_note(a.v >= 0.0) ? a : -a; }
+inline bool operator<(Sig a, Sig b) { return sig_note(a.v < b.v); }
+inline bool operator<=(Sig a, Sig b) { return sig_note(a.v <= b.v); }
+inline bool operator>(Sig a, Sig b) { return sig_note(a.v > b.v); }
+inline bool operator>=(Sig a, Sig b) { return sig_note(a.v >= b.v); }
+inline double value(Sig a) { return a.v; }
 
 // ----------------------------------------------------------------------------
 // Operation-counting scalar: a double that tallies the floating-point
@@ -678,6 +772,25 @@ static double max_signal(const Grid& g, const T* U, int* status) {
 // ----------------------------------------------------------------------------
 using namespace hard_oracle;
 
+// The K-direction tangent of nsteps steps (oracle_steps_tangent_multi).
+template <int K>
+static int steps_tangent_multi(const Grid& g, int64_t nsteps, const double* dts, double* U,
+                               double* dU) {
+  const int64_t M = (int64_t)g.nvar * g.ncell;
+  std::vector<DualN<K>> X(M);
+  for (int64_t x = 0; x < M; ++x) {
+    X[x].v = U[x];
+    for (int k = 0; k < K; ++k) X[x].d[k] = dU[k * M + x];
+  }
+  int st = 0;
+  for (int64_t s = 0; s < nsteps; ++s) st |= step<DualN<K>>(g, X.data(), DualN<K>(dts[s]));
+  for (int64_t x = 0; x < M; ++x) {
+    U[x] = X[x].v;
+    for (int k = 0; k < K; ++k) dU[k * M + x] = X[x].d[k];
+  }
+  return st;
+}
+
 extern "C" {
 
 // L(U) for one state; returns status bits.
@@ -759,6 +872,22 @@ int oracle_steps_tangent(int ndim, const int64_t* n, const double* dx, double ga
   return st;
 }
 
+// K directional derivatives of nsteps steps at once (K = 1, 2, 4 or 8): dU
+// holds K state-shaped directions one after another and receives the
+// derivatives.
+int oracle_steps_tangent_multi(int ndim, const int64_t* n, const double* dx, double gamma,
+                               const int* bc, int scheme, const double* radp, int64_t nsteps,
+                               const double* dts, int ndir, double* U, double* dU) {
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
+  switch (ndir) {
+    case 1: return steps_tangent_multi<1>(g, nsteps, dts, U, dU);
+    case 2: return steps_tangent_multi<2>(g, nsteps, dts, U, dU);
+    case 4: return steps_tangent_multi<4>(g, nsteps, dts, U, dU);
+    case 8: return steps_tangent_multi<8>(g, nsteps, dts, U, dU);
+    default: return -1;
+  }
+}
+
 // HLLC flux for one face: WL, WR = (rho, un, ut[0..nt-1], p); F gets
 // (mass, normal momentum, transverse momenta, energy).
 void oracle_hllc(int nt, double gamma, const double* WL, const double* WR, double* F) {
@@ -817,6 +946,24 @@ static int omp_get_max_threads(void) { return 1; }
 #endif
 // Threads of the OpenMP loops from now on (results do not depend on it).
 void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
+// Branch signature of nsteps steps from U with the step sizes dts: a hash of
+// the outcome of every comparison the method makes, in evaluation order (one
+// thread).  U is left unchanged.
+uint64_t oracle_branch_signature(int ndim, const int64_t* n, const double* dx, double gamma,
+                                 const int* bc, int scheme, const double* radp, int64_t nsteps,
+                                 const double* dts, const double* U) {
+  Grid g = make_grid(ndim, n, dx, gamma, bc, scheme, radp);
+  const int64_t M = (int64_t)g.nvar * g.ncell;
+  std::vector<Sig> X(M);
+  for (int64_t x = 0; x < M; ++x) X[x] = Sig(U[x]);
+  const int threads = omp_get_max_threads();
+  omp_set_num_threads(1);
+  g_sig = 0xcbf29ce484222325ull;
+  for (int64_t s = 0; s < nsteps; ++s) (void)step<Sig>(g, X.data(), Sig(dts[s]));
+  omp_set_num_threads(threads);
+  return g_sig;
+}
 
 void oracle_count_ops(int ndim, const int64_t* n, const double* dx, double gamma, const int* bc,
                       int scheme, const double* radp,

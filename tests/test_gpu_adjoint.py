@@ -8,7 +8,9 @@
   loss J = dx^2/2 sum (rho_N - rho_T)^2, target from rho (1 + 0.01 g')):
   <grad J, v> against the oracle's dual directional derivative (each side
   with its own CFL step list), and against central differences of the GPU
-  forward map (remainders shrink with h; minmod kinks make them O(h)).
+  forward map (remainders shrink with h; minmod kinks make them O(h)), and
+  on samples that the oracle's branch signature shows to cross no kink,
+  where the remainder is O(h^2).
 """
 import numpy as np
 import pytest
@@ -115,6 +117,30 @@ def test_rollout_gradient_vs_oracle_dual_64():
         assert abs(got - ref[k]) <= 1e-10 * scale + 1e-14 * abs(ref[k]), (k, got, ref[k])
 
 
+def test_rollout_gradient_vs_oracle_dual_512_full():
+    """The config-4 workload at full size: 512x512, 200 steps, checkpoints
+    every 20, eight random directions, each against the oracle's dual-number
+    directional derivative (one evaluation carrying the eight derivative
+    components) with the oracle's own CFL step list."""
+    n, nsteps = 512, 200
+    J, grad, g, _ = gpu_grad(n, nsteps, 20)
+    rng = np.random.default_rng(12)
+    U0 = c4_state(n)
+    V = [rng.standard_normal(U0.shape) * np.abs(U0).mean(axis=(1, 2), keepdims=True)
+         for _ in range(8)]
+    og = oracle.Grid((n, n), bc=(P, P))
+    _, _, _, _, dts = oracle.run(og, U0, 0.4, 1e9, max_steps=nsteps, record_dts=True)
+    rhoT = oracle.steps(og, c4_target_state(n), dts)[0][0]
+    UN, dUN, st = oracle.steps_tangent_multi(og, U0, V, dts)
+    assert st == 0
+    for k, v in enumerate(V):
+        ref = (1.0 / n) ** 2 * float(((UN[0] - rhoT) * dUN[k][0]).sum())
+        got = float((grad * v).sum())
+        scale = float(np.abs(grad * v).sum())
+        log(f"  dir {k}: gpu {got:.12e} oracle {ref:.12e}")
+        assert abs(got - ref) <= 1e-10 * scale, (k, got, ref)
+
+
 def test_rollout_gradient_vs_oracle_dual_512_short():
     """The 512x512 config-4 grid at full size, 20 steps (checkpoints every 5),
     one direction."""
@@ -165,3 +191,70 @@ def test_rollout_gradient_vs_finite_differences_64():
         log(f"  direction {k}: relative FD remainders {errs}")
         assert errs[-1] < 1e-5
         assert errs[-1] < 0.2 * errs[0]
+
+
+def test_rollout_gradient_fd_kink_free_samples_64():
+    """Central differences of J on the GPU forward map against the GPU
+    gradient, on samples that cross no branch point of the method.
+
+    Smooth 64x64 periodic state with non-uniform pressure, 20 steps
+    (checkpoints every 5), loss on rho against the run from 1.001 U0.
+    Samples: 48 single entries of U0 (random field and cell, size the mean
+    |U| of the field), steps h1 = 1e-4 and h2 = h1/4.  The oracle's branch
+    signature (every comparison of the method, in order) of U0 +- h v is
+    compared with that of U0: a sample whose signature changes crosses a
+    limiter or Riemann-solver kink and is left out.  On the others the
+    central-difference remainder is O(h^2): r(h2) <= r(h1)/8 + f(h2) (a
+    factor 16 in exact arithmetic), where f(h) = 4 eps dx^2 sum|rho_N -
+    rho_T| |rho_N| / (h |<g, v>|) bounds the rounding of the difference
+    quotient (a worst case; the measured rounding is far smaller).  At least
+    three samples must show the factor directly (r(h1) / r(h2) >= 8)."""
+    n, nsteps, every = 64, 20, 5
+    rng = np.random.default_rng(3)
+    shape = (n, n)
+    gf = lambda: workloads.gaussian_random_field(shape, rng, spectral_index=-3.0)
+    vel = [0.3 * gf() for _ in range(2)]
+    U0 = workloads.conserved_from_primitive(np.exp(0.2 * gf()), vel, 1.0 + 0.2 * gf())
+    g = H.make_grid(shape, bc=(P, P))
+    og = oracle.Grid(shape, bc=(P, P))
+    Ud = torch.from_numpy(U0).to(DEV)
+    dts, _ = AG.recorded_dts(Ud, g, nsteps)
+    dth = dts.cpu().numpy()
+    rhoT = AG.run_fixed(Ud * 1.001, g, dts)[0]
+    X = Ud.clone().requires_grad_(True)
+    UN = AG.rollout(X, g, nsteps, 0.4, every)
+    dx2 = (1.0 / n) ** 2
+    J = 0.5 * dx2 * ((UN[0] - rhoT) ** 2).sum()
+    J.backward()
+    grad = X.grad.cpu().numpy()
+    UNd = UN.detach()
+    bound = dx2 * float(((UNd[0] - rhoT).abs() * UNd[0].abs()).sum())
+
+    def Jof(Uh):
+        UNh = AG.run_fixed(torch.from_numpy(Uh).to(DEV), g, dts)
+        return 0.5 * dx2 * float(((UNh[0] - rhoT) ** 2).sum())
+
+    s0 = oracle.branch_signature(og, U0, dth)
+    h1, h2 = 1e-4, 2.5e-5
+    eps = np.finfo(np.float64).eps
+    pick = np.random.default_rng(7)
+    kink_free = quadratic = 0
+    for k in range(48):
+        f = int(pick.integers(0, 4))
+        i, j = (int(a) for a in pick.integers(0, n, 2))
+        v = np.zeros_like(U0)
+        v[f, i, j] = np.abs(U0[f]).mean()
+        if any(oracle.branch_signature(og, U0 + sg * h * v, dth) != s0
+               for h in (h1, h2) for sg in (1.0, -1.0)):
+            continue
+        kink_free += 1
+        pred = float(grad[f, i, j] * v[f, i, j])
+        r = [abs((Jof(U0 + h * v) - Jof(U0 - h * v)) / (2.0 * h) - pred) / abs(pred)
+             for h in (h1, h2)]
+        floor = [4.0 * eps * bound / (h * abs(pred)) for h in (h1, h2)]
+        log(f"  sample {k} (field {f}, cell {i},{j}): remainders {r[0]:.2e} {r[1]:.2e}, "
+            f"rounding floor {floor[0]:.1e} {floor[1]:.1e}")
+        assert r[1] <= r[0] / 8.0 + floor[1], (k, r, floor)
+        quadratic += r[0] >= 8.0 * r[1]
+    log(f"  {kink_free} kink-free samples of 48, {quadratic} with r(h1)/r(h2) >= 8")
+    assert kink_free >= 6 and quadratic >= 3

@@ -76,6 +76,16 @@ CASES = [
     ((16, 16, 16), (R, R)),
     ((40, 33, 70), (O, O, P, P, R, R)),
     ((5, 6, 7), (O, R, P, P, R, O)),
+    # the smallest grids the C ABI accepts: 2 to 4 cells per axis (a tile
+    # mostly overhang, ghosts that wrap or mirror onto the same cells)
+    ((2,), (O, O)),
+    ((3,), (R, R)),
+    ((4,), (P, P)),
+    ((2, 3), (P, P, R, R)),
+    ((4, 2), (R, O, O, R)),
+    ((3, 4, 2), (R, R, P, P, O, O)),
+    ((2, 2, 2), (P, P, P, P, P, P)),
+    ((4, 3, 4), (O, O, R, R, P, P)),
 ]
 
 
@@ -186,6 +196,88 @@ def test_blast_256_full_grid_one_step():
     nref, _ = oracle.cfl_dt(og, ref, 0.4)
     assert abs(d.item() - nref) <= 1e-13 * nref
     assert H.hard_status_read(work) == 0
+
+
+def region_errors(out, ref, hot):
+    """Per field: normwise max|g - o| / max|o| over the cells of `hot` and
+    over the rest separately (a field that is 0 throughout a region must be
+    exactly 0 there on the GPU too), and the relative L1 over the field."""
+    res = []
+    for v in range(out.shape[0]):
+        r = []
+        for m in (hot, ~hot):
+            o, g_ = ref[v][m], out[v][m]
+            den = np.abs(o).max() if o.size else 0.0
+            r.append(np.abs(g_ - o).max() / den if den > 0 else np.abs(g_).max())
+        res.append((r[0], r[1], field_rel_l1(out[v], ref[v])))
+    return res
+
+
+@pytest.mark.parametrize("n,steps", [(128, 20), (256, 4)])
+def test_blast_multi_step(n, steps):
+    """The blast recipe run by each side's own time loop (CFL dt each step,
+    fused into stage 2 on the GPU): the same dt sequence to 1e-13, and every
+    field within 1e-12 both in the shocked region (oracle p > 10 p0) and in
+    the low-energy background (E about 2.5e-5 there, so the normwise bar of
+    the whole field would hide errors of a few percent of it), and in
+    relative L1.  Cells the blast has not reached keep the initial state bit
+    for bit on the GPU too."""
+    log(f"blast {n}^3, {steps} steps")
+    U0 = workloads.blast_3d(n)
+    og = oracle.Grid((n, n, n), bc=(R, R))
+    ref, t_ref, ns, st, dts = oracle.run(og, U0, 0.4, 1e9, max_steps=steps, record_dts=True)
+    assert st == 0 and ns == steps
+    g = H.make_grid((n, n, n), bc=(R, R))
+    U = torch.from_numpy(U0).to(DEV)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    buf = torch.zeros(steps + 1, dtype=torch.float64, device=DEV)
+    H.hard_cfl_dt(g, U, 0.4, buf[0:1], work)
+    for k in range(steps):
+        H.hard_hydro_step(g, U, buf[k:k + 1], work, cfl=0.4, next_dt_dev=buf[k + 1:k + 2])
+    torch.cuda.synchronize()
+    assert H.hard_status_read(work) == 0
+    gdts = buf[:steps].cpu().numpy()
+    assert np.all(np.abs(gdts - dts) <= 1e-13 * dts), (gdts, dts)
+    out = U.cpu().numpy()
+    p0 = 1e-5
+    p_ref = 0.4 * (ref[4] - 0.5 * (ref[1] ** 2 + ref[2] ** 2 + ref[3] ** 2) / ref[0])
+    hot = p_ref > 10.0 * p0
+    untouched = np.all(ref == U0, axis=0)
+    log(f"  shocked cells {hot.sum()}, untouched cells {untouched.sum()}")
+    assert hot.sum() > 0 and untouched.sum() > 0
+    for v, (eh, eb, el1) in enumerate(region_errors(out, ref, hot)):
+        log(f"  field {v}: shocked {eh:.2e}, background {eb:.2e}, rel L1 {el1:.2e}")
+        assert eh <= TOL64 and eb <= TOL64 and el1 <= TOL64, (v, eh, eb, el1)
+    assert np.array_equal(out[:, untouched], U0[:, untouched])
+
+
+def test_adjoint_config_forward_fields_512():
+    """The forward run of the adjoint workload (2D 512^2 FP64 periodic,
+    turbulent-box recipe in 2D, 200 steps, CFL step each step) compared
+    field by field with the oracle's run: the same dt sequence to 1e-13,
+    every field within 1e-12 normwise and in relative L1."""
+    n, steps = 512, 200
+    log("adjoint-config forward 512^2, 200 steps")
+    U0 = workloads.turbulent_box(n, ndim=2, seed=4)
+    og = oracle.Grid((n, n), bc=(P, P))
+    ref, _, ns, st, dts = oracle.run(og, U0, 0.4, 1e9, max_steps=steps, record_dts=True)
+    assert st == 0 and ns == steps
+    g = H.make_grid((n, n), bc=(P, P))
+    U = torch.from_numpy(U0).to(DEV)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    buf = torch.zeros(steps + 1, dtype=torch.float64, device=DEV)
+    H.hard_cfl_dt(g, U, 0.4, buf[0:1], work)
+    for k in range(steps):
+        H.hard_hydro_step(g, U, buf[k:k + 1], work, cfl=0.4, next_dt_dev=buf[k + 1:k + 2])
+    torch.cuda.synchronize()
+    assert H.hard_status_read(work) == 0
+    gdts = buf[:steps].cpu().numpy()
+    assert np.all(np.abs(gdts - dts) <= 1e-13 * dts)
+    out = U.cpu().numpy()
+    for v in range(4):
+        e, e1 = field_rel_linf(out[v], ref[v]), field_rel_l1(out[v], ref[v])
+        log(f"  field {v}: rel Linf {e:.2e}, rel L1 {e1:.2e}")
+        assert e <= TOL64 and e1 <= TOL64, (v, e, e1)
 
 
 def test_status_flags_nonphysical():
