@@ -8,8 +8,12 @@ After the warmup steps the state is reset to the initial blast, so the timed
 steps are steps 1..K of the blast.
 
 Prints one JSON line: zone-updates/s, the HBM roofline of the dominant kernel
-(stage 2) from HIP events around each launch, and the CPU oracle timed on a
-bounded sample of the same workload on the host cores.
+(stage 2) from HIP events around each launch, the legs beside the FP64 step
+(the 1D Riemann run, the FP32 box, the batch, the adjoint, the WENO5-Z and
+radiation variants), each with its roofline and its accuracy, and the CPU
+oracle timed on bounded samples of each workload on the host cores.  The
+oracle runs only in that last leg, which also compares its results with the
+GPU's on the same samples (the accuracy figures of the other legs).
 """
 import argparse
 import json
@@ -19,11 +23,26 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the CPU baseline's OpenMP threads stay on neighbouring cores (read by the
+# OpenMP runtime when it starts, so before anything loads one)
+os.environ.setdefault("OMP_PROC_BIND", "close")
+# the CPUs this process may run on, read before any OpenMP runtime binds the
+# main thread to one of them
+CPU_MASK = sorted(os.sched_getaffinity(0))
 
 import numpy as np  # noqa: E402
 import torch  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TARGET_FRAC = 0.60  # the step's target fraction of the HBM roofline
+# VALU issue ceilings of MI355X (256 CUs x 4 SIMDs at 2.4 GHz): a wave64 FP64
+# instruction takes 4 cycles of a SIMD (16 lanes per cycle: 78.6 TFLOP/s
+# counting an FMA as 2), a wave64 FP32 instruction 2 cycles (32 lanes per
+# cycle: 157.3 TFLOP/s), in lane-instructions per second
+VALU_F64_LANES = 256 * 4 * 16 * 2.4e9
+VALU_F32_LANES = 256 * 4 * 32 * 2.4e9
+# stash of GPU results that the CPU-baseline leg compares with the oracle
+_ACC = {}
 # floating-point operations of one zone-update in 3D as the oracle evaluates
 # them (oracle.ops_per_zone_update: 485 add, 378 mul, 87 div, 13 sqrt, 118
 # compare, 64 abs); tests/test_oracle_opcount.py recomputes it
@@ -45,6 +64,11 @@ WENO_SOURCES = _csrc("weno.hip", "hydro_device.hpp", "launch.hpp")
 WENO_COUNTERS_FILE = os.path.join(ROOT, "profiles", "weno_pipeline_blast256_fp64_hbm_counters.md")
 RAD_SOURCES = _csrc("rad.hip", "stage.hip", "stage_tile.hpp", "hydro_device.hpp", "launch.hpp")
 RAD_COUNTERS_FILE = os.path.join(ROOT, "profiles", "rad_step_radiation256_fp64_hbm_counters.md")
+FP32_COUNTERS_FILE = os.path.join(ROOT, "profiles", "stage_kernel_turbulent512_fp32_hbm_counters.md")
+BATCHED_SOURCES = _csrc("batched.hip", "stage_tile.hpp", "hydro_device.hpp", "launch.hpp")
+BATCHED_COUNTERS_FILE = os.path.join(ROOT, "profiles", "batched_step_4096_fp32_hbm_counters.md")
+ADJ_SOURCES = _csrc("adjoint.hip", "stage.hip", "stage_tile.hpp", "hydro_device.hpp", "launch.hpp")
+ADJ_COUNTERS_FILE = os.path.join(ROOT, "profiles", "adjoint_rollout_512_fp64_hbm_counters.md")
 
 
 def code_hash(files):
@@ -149,14 +173,42 @@ def _time_steps(fn, steps, stream):
     return a.elapsed_time(b)
 
 
-def bench_fp32_turbulent(args, n=512, steps=50):
-    """512^3 periodic turbulent box, FP32 bulk, 50 steps with fused CFL dt."""
+def _time_stages(g, U, U1, dt, work, steps, stream):
+    """Times `steps` Heun steps as stage-1 + stage-2 launches (fused next dt)
+    with HIP events on the launch stream around each launch; returns (ms per
+    step over the whole run, per-launch ms of stage 1, of stage 2)."""
+    import paper_2509_08971_amd as H
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for k in range(steps):
+        evs[k][0].record(stream)
+        H.hard_hydro_stage(g, 1, U, None, U1, dt, work)
+        evs[k][1].record(stream)
+        H.hard_hydro_stage(g, 2, U1, U, U, dt, work, cfl=0.4, next_dt_dev=dt)
+        evs[k][2].record(stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    s1 = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    s2 = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    return start.elapsed_time(stop) / steps, s1, s2
+
+
+def bench_fp32_turbulent(args, n=512, steps=50, n_acc=128):
+    """512^3 periodic turbulent box, FP32 bulk, 50 steps with fused CFL dt;
+    the roofline of its stage-2 kernel; its error after 50 steps against the
+    FP64 GPU step on the full box, and (from the CPU leg) against the FP64
+    oracle on a 128^3 box of the same recipe."""
     import paper_2509_08971_amd as H
     import workloads
 
     log(f"bench: turbulent {n}^3 fp32, {steps} steps")
     U = workloads.turbulent_box_torch(n, ndim=3, seed=2, device="cuda", dtype=torch.float32)
     U0 = U.clone()
+    U1 = torch.empty_like(U)
     g = H.make_grid((n, n, n), bc=(H.PERIODIC, H.PERIODIC), dtype=torch.float32)
     work = H.workspace(H.hard_workspace_bytes(g))
     dt = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -166,13 +218,16 @@ def bench_fp32_turbulent(args, n=512, steps=50):
         H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=dt)
     U.copy_(U0)
     H.hard_cfl_dt(g, U, 0.4, dt, work)
-    ms = _time_steps(lambda: H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=dt), steps,
-                     stream)
+    ms, s1, s2 = _time_stages(g, U, U1, dt, work, steps, stream)
     flags = H.hard_status_read(work)
+    del U1
     N = n ** 3
-    zus = N * steps / (ms * 1e-3)
+    zus = N / (ms * 1e-3)
     bytes_step = 5 * 5 * 4 * N
-    log(f"  {ms / steps:.3f} ms/step, {zus / 1e9:.2f} G zu/s")
+    b2 = 3 * 5 * 4 * N
+    ach2 = b2 / (s2.mean() * 1e-3) / 1e9
+    log(f"  {ms:.3f} ms/step, {zus / 1e9:.2f} G zu/s, stage1 {s1.mean():.3f} ms, "
+        f"stage2 {s2.mean():.3f} ms")
     # accuracy against the plain FP64 step: the same initial state (the float
     # values widened) run in double with the fused CFL steps, then in float
     # with that dt sequence; per-field sum|f32 - f64| / sum|f64| at the end
@@ -181,21 +236,54 @@ def bench_fp32_turbulent(args, n=512, steps=50):
     U64 = U0.double()
     dts = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
     H.hard_cfl_dt(g64, U64, 0.4, dts[0:1], work64)
-    for s in range(steps):
-        H.hard_hydro_step(g64, U64, dts[s:s + 1], work64, cfl=0.4, next_dt_dev=dts[s + 1:s + 2])
+    for k in range(steps):
+        H.hard_hydro_step(g64, U64, dts[k:k + 1], work64, cfl=0.4, next_dt_dev=dts[k + 1:k + 2])
     U32 = U0.clone()
-    for s in range(steps):
-        H.hard_hydro_step(g, U32, dts[s:s + 1], work)
+    for k in range(steps):
+        H.hard_hydro_step(g, U32, dts[k:k + 1], work)
     err = [((U32[v].double() - U64[v]).abs().sum() / U64[v].abs().sum()).item() for v in range(5)]
     flags |= H.hard_status_read(work) | H.hard_status_read(work64)
-    del U64, work64, U32
+    del U64, work64, U32, U, U0, work
     log(f"  per-field rel L1 vs the FP64 step after {steps} steps: "
         + ", ".join(f"{e:.2e}" for e in err))
-    return {"value": zus, "unit": "zone-updates/s", "ms_per_step": ms / steps, "steps": steps,
+    # the 128^3 box of the same recipe: FP64 and FP32 GPU runs with one dt
+    # sequence (the FP64 run's), kept for the oracle comparison in the CPU leg
+    Ua = workloads.turbulent_box_torch(n_acc, ndim=3, seed=2, device="cuda", dtype=torch.float32)
+    ga32 = H.make_grid((n_acc,) * 3, bc=(H.PERIODIC, H.PERIODIC), dtype=torch.float32)
+    ga64 = H.make_grid((n_acc,) * 3, bc=(H.PERIODIC, H.PERIODIC), dtype=torch.float64)
+    wa32 = H.workspace(H.hard_workspace_bytes(ga32))
+    wa64 = H.workspace(H.hard_workspace_bytes(ga64))
+    A64 = Ua.double()
+    A0 = A64.cpu().numpy()
+    adt = torch.zeros(steps + 1, dtype=torch.float64, device="cuda")
+    H.hard_cfl_dt(ga64, A64, 0.4, adt[0:1], wa64)
+    for k in range(steps):
+        H.hard_hydro_step(ga64, A64, adt[k:k + 1], wa64, cfl=0.4, next_dt_dev=adt[k + 1:k + 2])
+    A32 = Ua.clone()
+    for k in range(steps):
+        H.hard_hydro_step(ga32, A32, adt[k:k + 1], wa32)
+    flags |= H.hard_status_read(wa32) | H.hard_status_read(wa64)
+    _ACC["fp32"] = {"n": n_acc, "U0": A0, "dts": adt[:steps].cpu().numpy(),
+                    "f32": A32.double().cpu().numpy(), "f64": A64.cpu().numpy()}
+    return {"value": zus, "unit": "zone-updates/s", "ms_per_step": ms, "steps": steps,
             "dtype": "f32 (internal energy, dt in f64)",
             "workload": f"3D {n}^3 periodic log-normal rho, p = 1, solenoidal u (rms Mach 0.5)",
-            "achieved_hbm_gbs": bytes_step / (ms / steps * 1e-3) / 1e9,
+            "achieved_hbm_gbs": bytes_step / (ms * 1e-3) / 1e9,
+            "roofline": {"bound": "hbm", "kernel": "stage_kernel<3,float,2> (stage 2)",
+                         "achieved": ach2, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach2 / HBM_PEAK_GBS, "target_frac": TARGET_FRAC,
+                         "traffic": measured_bytes(FP32_COUNTERS_FILE, "fp32-stage2",
+                                                   KERNEL_SOURCES),
+                         "algorithmic_bytes": b2, "per": "launch",
+                         "stage1_ms": float(s1.mean()), "stage2_ms": float(s2.mean()),
+                         "stage1_achieved": 2 * 5 * 4 * N / (s1.mean() * 1e-3) / 1e9},
+            "alu_beside": {"bound": "alu", "unit": "lane-instr/s", "peak_f32": VALU_F32_LANES,
+                           "peak_f64": VALU_F64_LANES,
+                           "note": "FP32 kernels also issue FP64 instructions (internal energy, "
+                                   "CFL sum); their VALU busy fraction is in the SQ counter "
+                                   "profile"},
             "rel_l1_vs_fp64_step_per_field": dict(zip(["rho", "m_x", "m_y", "m_z", "E"], err)),
+            "rel_l1_vs_oracle_per_field": None,
             "accuracy_bound": 1e-5, "status_flags": flags}
 
 
@@ -243,15 +331,34 @@ def bench_batched(args, steps=100):
         stream = torch.cuda.current_stream()
         ms = _time_steps(graph.replay, 1, stream)
         flags = H.hard_status_read(work)
+        # a subset of the problems after the timed 100 steps, for the oracle
+        # comparison in the CPU leg (every 320th 1D and every 104th 2D problem)
+        pick = list(range(0, 3072, 320)) + list(range(3072, 4096, 104))
+        Uh = U.cpu().numpy()
+        _ACC["batched"] = {"steps": steps, "pick": pick, "specs": [specs[p] for p in pick],
+                           "out": [Uh[offs[p]:offs[p] + (specs[p][0] + 2) * specs[p][1] ** specs[p][0]]
+                                   .astype(np.float64).reshape((specs[p][0] + 2,) +
+                                                               (specs[p][1],) * specs[p][0])
+                                   for p in pick]}
     finally:
         H.hard_batch_plan_destroy(plan)
     zus = cells * steps / (ms * 1e-3)
+    ach = bytes_step / (ms / steps * 1e-3) / 1e9
     log(f"  {ms / steps:.3f} ms/step, {zus / 1e9:.2f} G zu/s ({cells} cells)")
     return {"value": zus, "unit": "zone-updates/s", "ms_per_step": ms / steps, "steps": steps,
             "cells": cells, "problems": len(specs), "dtype": "f32 (internal energy, dt in f64)",
             "launch": f"{steps} steps x (2 persistent stage launches + 1 per-problem dt "
                       f"launch) replayed from one captured graph",
-            "achieved_hbm_gbs": bytes_step / (ms / steps * 1e-3) / 1e9, "status_flags": flags}
+            "achieved_hbm_gbs": ach,
+            "roofline": {"bound": "hbm", "kernel": "whole batched step (both persistent stage "
+                                                  "launches and the per-problem dt)",
+                         "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes": bytes_step,
+                         "traffic": measured_bytes(BATCHED_COUNTERS_FILE, "batched",
+                                                   BATCHED_SOURCES),
+                         "per": "step", "bytes_per_cell": "5 nvar w (60 B 1D, 80 B 2D)"},
+            "rel_l1_vs_oracle_per_field": None, "accuracy_bound": 1e-5,
+            "status_flags": flags}
 
 
 def bench_weno(args, n=256, steps=10):
@@ -280,16 +387,19 @@ def bench_weno(args, n=256, steps=10):
     # reads U^n): 2 + 6 + 5 (+1) words of nvar; both stages
     words = (2 + 6 + 5) + (2 + 6 + 6)
     pipe_bytes = words * 5 * 8
+    alg_bytes = 5 * 5 * 8  # one read and one write per stage, plus U^n in stage 2
     log(f"  {ms / steps:.3f} ms/step, {zus / 1e9:.2f} G zu/s")
     return {"value": zus, "unit": "zone-updates/s", "ms_per_step": ms / steps, "steps": steps,
             "dtype": "f64", "workload": f"3D {n}^3 FP64 point-energy blast, reflecting, CFL 0.4, "
                                          f"WENO5-Z + HLL (the paper's scheme) + SSP-RK2",
-            "pipeline_bytes_per_zone_update": pipe_bytes,
-            "roofline": {"bound": "hbm", "kernel": "whole WENO5-Z + HLL step (pipeline bytes)",
-                         "achieved": pipe_bytes * zus / 1e9, "peak": 8000.0, "unit": "GB/s",
-                         "frac": pipe_bytes * zus / 1e9 / 8000.0,
+            "roofline": {"bound": "hbm", "kernel": "whole WENO5-Z + HLL step",
+                         "achieved": alg_bytes * zus / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg_bytes * zus / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes": alg_bytes * N, "per": "step",
+                         "bytes_per_zone_update": alg_bytes,
                          "traffic": measured_bytes(WENO_COUNTERS_FILE, "weno", WENO_SOURCES),
-                         "algorithmic_bytes": pipe_bytes * N, "per": "step"},
+                         "pipeline_bytes_per_zone_update": pipe_bytes,
+                         "pipeline_achieved": pipe_bytes * zus / 1e9},
             "status_flags": flags}
 
 
@@ -322,17 +432,20 @@ def bench_rad(args, n=256, steps=20):
     # stage 1 (read 6 fields, write E_r) and stage 2 (also read E_r of U^n);
     # exchange + next dt (read 6 fields, write E and E_r)
     step_bytes = 8 * ((10 + 15) + (6 + 1) + (6 + 2) + (6 + 2))
+    alg_bytes = 5 * 6 * 8  # the per-stage design's 5 nvar w with nvar = 6
     log(f"  {ms / steps:.3f} ms/step, {zus / 1e9:.2f} G zu/s")
     return {"value": zus, "unit": "zone-updates/s", "ms_per_step": ms / steps, "steps": steps,
             "dtype": "f64", "workload": f"3D {n}^3 FP64 point-energy blast with the radiation "
                                          f"energy density (E_r = 1, kappa = 1e-9, mu = 0.6)",
-            "step_bytes_per_zone_update": step_bytes,
             "roofline": {"bound": "hbm", "kernel": "whole radiation step (stage kernels, E_r "
                                                   "advection, exchange)",
-                         "achieved": step_bytes * zus / 1e9, "peak": 8000.0, "unit": "GB/s",
-                         "frac": step_bytes * zus / 1e9 / 8000.0,
+                         "achieved": alg_bytes * zus / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg_bytes * zus / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes": alg_bytes * N, "per": "step",
+                         "bytes_per_zone_update": alg_bytes,
                          "traffic": measured_bytes(RAD_COUNTERS_FILE, "rad", RAD_SOURCES),
-                         "algorithmic_bytes": step_bytes * N, "per": "step"},
+                         "pass_bytes_per_zone_update": step_bytes,
+                         "pass_achieved": step_bytes * zus / 1e9},
             "status_flags": flags}
 
 
@@ -444,10 +557,25 @@ def bench_adjoint(args, n=512, nsteps=200, every=20):
     gradient()  # untimed: the allocator's first requests for the checkpoints and buffers
     torch.cuda.synchronize()
     t0 = _t.perf_counter()
-    gradient()
+    G = gradient()
     torch.cuda.synchronize()
     full = _t.perf_counter() - t0
     N = n * n
+    nvar, w = 4, 8
+    # algorithmic bytes per zone-update: the forward step (5 nvar w); in the
+    # backward pass the segment's forward recompute (5 nvar w), the stage-1
+    # recompute inside the adjoint call (2 nvar w), the product at U^1 (read
+    # U^1 and lam, write lam1: 3 nvar w) and at U^n (read U^n, lam1 and lam,
+    # write the new lam: 4 nvar w)
+    b_fwd = 5 * nvar * w
+    b_grad = (5 + 5 + 2 + 3 + 4) * nvar * w
+    ach_fwd = b_fwd * N * nsteps / fwd / 1e9
+    ach_grad = b_grad * N * nsteps / full / 1e9
+    # one seeded direction for the oracle's dual-number check in the CPU leg
+    v = torch.from_numpy(np.random.default_rng(11).standard_normal((4, n, n))).to("cuda")
+    _ACC["adjoint"] = {"n": n, "U0": U0.cpu().numpy(), "dts": dts.cpu().numpy(),
+                       "rhoT": rhoT.cpu().numpy(), "v": v.cpu().numpy(),
+                       "g_dot_v": float((G * v).sum().item())}
     log(f"  forward {fwd * 1e3:.1f} ms, forward+gradient {full * 1e3:.1f} ms")
     return {"forward_ms": fwd * 1e3, "gradient_ms": full * 1e3,
             "gradient_over_forward": full / fwd,
@@ -455,8 +583,182 @@ def bench_adjoint(args, n=512, nsteps=200, every=20):
             "gradient_zone_updates_per_s": N * nsteps / full,
             "workload": f"2D {n}^2 FP64 periodic, {nsteps} steps, checkpoints every {every}, "
                         f"loss on final rho against a perturbed-start target",
+            "roofline": {"bound": "hbm", "kernel": "whole forward + gradient (all launches)",
+                         "achieved": ach_grad, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach_grad / HBM_PEAK_GBS, "bytes_per_zone_update": b_grad,
+                         "algorithmic_bytes": b_grad * N * nsteps, "per": "gradient",
+                         "forward_achieved": ach_fwd,
+                         "traffic": measured_bytes(ADJ_COUNTERS_FILE, "adjoint", ADJ_SOURCES),
+                         "note": "8.4 MB states: cache-resident, bound by launches and the "
+                                 "adjoint's face arrays rather than by HBM"},
+            "dual_check": None,
             "timing": "host wall clock around the whole forward / forward+backward, after "
                       "one untimed forward+backward (allocator warm-up)"}
+
+
+def bench_riemann(args, n=1024, t_end=0.2, reps=5):
+    """The 1D two-state Riemann problem (1024 cells, FP64, seed 0, outflow,
+    CFL 0.4) run to t = 0.2 with the device time loop: wall time of the whole
+    run (launch-latency bound) and zone-updates/s."""
+    import paper_2509_08971_amd as H
+    import workloads
+
+    log(f"bench: 1D Riemann problem {n} cells fp64 to t = {t_end}")
+    g = H.make_grid((n,), bc=(H.OUTFLOW, H.OUTFLOW))
+    U0 = torch.from_numpy(workloads.random_two_state(n, seed=0)).to("cuda")
+    work = H.workspace(H.hard_workspace_bytes(g))
+    U = U0.clone()
+    H.hard_run(g, U, 0.4, t_end, work)
+    walls = []
+    for _ in range(reps):
+        U.copy_(U0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t, steps = H.hard_run(g, U, 0.4, t_end, work)
+        walls.append(time.perf_counter() - t0)
+    wall = sorted(walls)[len(walls) // 2]
+    log(f"  {steps} steps in {wall * 1e3:.2f} ms, {n * steps / wall / 1e6:.1f} M zu/s")
+    return {"value": n * steps / wall, "unit": "zone-updates/s", "wall_ms": wall * 1e3,
+            "steps": steps, "t_final": t, "dtype": "f64",
+            "workload": f"1D two-state Riemann problem, {n} cells, seed 0, outflow, CFL 0.4, "
+                        f"to t = {t_end}",
+            "timing": f"median of {reps} host wall-clock runs of hard_run (device time loop, "
+                      f"host sync every 64 steps)"}
+
+
+def phys_cores():
+    """(physical cores, logical CPUs) of this process's CPU affinity mask (as
+    it was at start-up), from the sysfs topology of each allowed CPU."""
+    cpus = CPU_MASK
+    cores = set()
+    for c in cpus:
+        base = f"/sys/devices/system/cpu/cpu{c}/topology/"
+        try:
+            with open(base + "physical_package_id") as f1, open(base + "core_id") as f2:
+                cores.add((f1.read().strip(), f2.read().strip()))
+        except OSError:
+            cores.add(("cpu", str(c)))
+    return len(cores), len(cpus)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        return "unknown CPU"
+
+
+def cpu_baseline(args, U0_host, gpu_two_steps, n):
+    """The oracle (plain C++ loops, OpenMP over the slowest axis) timed on the
+    host cores on bounded samples of each workload, and its results compared
+    with the GPU's on the same samples."""
+    import oracle
+    import workloads
+    from oracle.metrics import field_rel_l1, field_rel_linf
+
+    phys, logical = phys_cores()
+    threads = oracle.threads()
+    model = cpu_model()
+    out = {"unit": "zone-updates/s", "kind": "oracle", "cpu": model, "threads": threads,
+           "cores": min(threads, phys), "physical_cores_in_mask": phys,
+           "logical_cpus_in_mask": logical, "omp_proc_bind": os.environ.get("OMP_PROC_BIND")}
+    per = {}
+    # c1: two steps (CFL dt + step) of the blast from its initial state, all threads
+    log(f"cpu baseline: oracle on {threads} threads ({phys} physical cores, {model})")
+    og = oracle.Grid((n, n, n), bc=(oracle.REFLECT, oracle.REFLECT))
+    t0 = time.perf_counter()
+    Uc = U0_host
+    dts = []
+    for _ in range(2):
+        d, _ = oracle.cfl_dt(og, Uc, 0.4)
+        dts.append(d)
+        Uc, _ = oracle.step(og, Uc, d)
+    el = time.perf_counter() - t0
+    per["c1_blast"] = {"value": n ** 3 * 2 / el, "seconds": el,
+                       "sample": f"2 steps of the {n}^3 blast from its initial state"}
+    out["value"] = n ** 3 * 2 / el
+    out["sample"] = per["c1_blast"]["sample"] + f", {el:.1f} s on {threads} threads"
+    if gpu_two_steps is not None:
+        Ug, gdts = gpu_two_steps
+        per["c1_blast"]["gpu_vs_oracle"] = {
+            "dt_equal": [float(a) == float(b) for a, b in zip(gdts, dts)],
+            "rel_linf_per_field": [field_rel_linf(Ug[v], Uc[v]) for v in range(5)],
+            "rel_l1_per_field": [field_rel_l1(Ug[v], Uc[v]) for v in range(5)]}
+    del Uc
+    # c1 on one core: one step of the same recipe at 128^3
+    oracle.set_threads(1)
+    try:
+        m = 128
+        Us = workloads.blast_3d(m)
+        ogs = oracle.Grid((m, m, m), bc=(oracle.REFLECT, oracle.REFLECT))
+        t0 = time.perf_counter()
+        d, _ = oracle.cfl_dt(ogs, Us, 0.4)
+        oracle.step(ogs, Us, d)
+        el1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    out["single_core"] = {"value": m ** 3 / el1, "seconds": el1,
+                          "sample": f"1 step of the {m}^3 blast (same recipe) on 1 thread"}
+    # c2 recipe at 128^3: the FP64 oracle with the GPU FP64 run's dt sequence,
+    # against the GPU FP32 and FP64 runs of the same initial state
+    acc = _ACC.get("fp32")
+    if acc is not None:
+        m = acc["n"]
+        ogt = oracle.Grid((m, m, m), bc=(oracle.PERIODIC, oracle.PERIODIC))
+        t0 = time.perf_counter()
+        ref, st = oracle.steps(ogt, acc["U0"], acc["dts"])
+        el = time.perf_counter() - t0
+        per["c2_turbulent"] = {"value": m ** 3 * len(acc["dts"]) / el, "seconds": el,
+                               "sample": f"{len(acc['dts'])} steps of the {m}^3 turbulent box"}
+        acc["rel_l1_f32"] = [field_rel_l1(acc["f32"][v], ref[v]) for v in range(5)]
+        acc["rel_linf_f64"] = [field_rel_linf(acc["f64"][v], ref[v]) for v in range(5)]
+        acc["status"] = st
+    # c3: the batch subset, 100 steps each with the oracle's own CFL steps
+    acc = _ACC.get("batched")
+    if acc is not None:
+        t0 = time.perf_counter()
+        zu = 0
+        worst = [0.0] * 4
+        for spec, gout in zip(acc["specs"], acc["out"]):
+            nd, m, _ = spec
+            ogb = oracle.Grid((m,) * nd, bc=(oracle.OUTFLOW, oracle.OUTFLOW))
+            U0b = workloads.batch_problem_state(spec).astype(np.float32).astype(np.float64)
+            ref, _, ns, _ = oracle.run(ogb, U0b, 0.4, 1e9, max_steps=acc["steps"])
+            zu += m ** nd * ns
+            for v in range(nd + 2):
+                k = v if v < nd + 1 else 3
+                worst[k] = max(worst[k], field_rel_l1(gout[v], ref[v]))
+        el = time.perf_counter() - t0
+        per["c3_batched"] = {"value": zu / el, "seconds": el,
+                             "sample": f"{len(acc['specs'])} problems of the batch "
+                                       f"(every 320th 1D, every 104th 2D), {acc['steps']} steps"}
+        acc["worst_rel_l1"] = dict(zip(["rho", "m_x", "m_y", "E"], worst))
+    # c4: forward and dual-number directional derivative of the 512^2 rollout
+    acc = _ACC.get("adjoint")
+    if acc is not None:
+        m = acc["n"]
+        oga = oracle.Grid((m, m), bc=(oracle.PERIODIC, oracle.PERIODIC))
+        t0 = time.perf_counter()
+        UN, dUN, st = oracle.steps_tangent(oga, acc["U0"], acc["v"], acc["dts"])
+        el = time.perf_counter() - t0
+        per["c4_adjoint"] = {"value": m * m * len(acc["dts"]) / el, "seconds": el,
+                             "sample": f"{len(acc['dts'])} steps of the {m}^2 box with the "
+                                       f"dual-number derivative along one direction"}
+        dJ = (1.0 / m) ** 2 * float(((UN[0] - acc["rhoT"]) * dUN[0]).sum())
+        acc["dual"] = {"oracle_DvJ": dJ, "gpu_g_dot_v": acc["g_dot_v"],
+                       "rel_diff": abs(acc["g_dot_v"] - dJ) / abs(dJ), "bound": 1e-10,
+                       "status": st}
+    # c0: the 1D Riemann problem to t = 0.2
+    og0 = oracle.Grid((1024,), bc=(oracle.OUTFLOW, oracle.OUTFLOW))
+    U00 = workloads.random_two_state(1024, seed=0)
+    t0 = time.perf_counter()
+    _, _, ns, _ = oracle.run(og0, U00, 0.4, 0.2)
+    el = time.perf_counter() - t0
+    per["c0_riemann"] = {"value": 1024 * ns / el, "seconds": el, "steps": ns,
+                         "sample": "the whole run to t = 0.2"}
+    out["per_config"] = per
+    return out
 
 
 def main():
@@ -466,10 +768,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--only-main", action="store_true",
                     help="time only the FP64 blast (skip the FP32 and batched lines)")
-    ap.add_argument("--only-leg", choices=["fp32", "batched", "adjoint", "weno", "rad", "fld"],
+    ap.add_argument("--only-leg", choices=["riemann", "fp32", "batched", "adjoint", "weno", "rad",
+                                           "fld"],
                     help="only time one of the legs beside the FP64 step (prints its object)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
@@ -487,7 +789,8 @@ def main():
         print(json.dumps({"error": "the kernels run on one GPU; --gpus must be 1"}), flush=True)
         sys.exit(2)
     if args.only_leg:
-        legs = {"fp32": ("fp32_512_turbulent", bench_fp32_turbulent),
+        legs = {"riemann": ("c0_riemann_1024", bench_riemann),
+                "fp32": ("fp32_512_turbulent", bench_fp32_turbulent),
                 "batched": ("batched_4096", bench_batched),
                 "adjoint": ("adjoint_512", bench_adjoint),
                 "weno": ("weno5z_hll_256", bench_weno),
@@ -513,45 +816,41 @@ def main():
     dt = torch.zeros(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        H.hard_hydro_stage(g, 1, U, None, U1, dt, work)
-        if ev is not None:
-            ev[1].record(stream)
-        H.hard_hydro_stage(g, 2, U1, U, U, dt, work, cfl=0.4, next_dt_dev=dt)
-        if ev is not None:
-            ev[2].record(stream)
+    def reset():
+        U.copy_(U0)
+        H.hard_cfl_dt(g, U, 0.4, dt, work)
+        torch.cuda.synchronize()
 
     log(f"bench: blast {n}^3 fp64, warmup {args.warmup}, steps {args.steps}")
     H.hard_cfl_dt(g, U, 0.4, dt, work)
     for _ in range(args.warmup):
-        step()
+        H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=dt)
     torch.cuda.synchronize()
-    # reset to the initial state (untimed)
-    U.copy_(U0)
-    H.hard_cfl_dt(g, U, 0.4, dt, work)
-    torch.cuda.synchronize()
-
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    reset()  # the timed steps are steps 1..K of the blast (untimed reset)
     t0 = time.perf_counter()
-    start.record(stream)
-    for k in range(args.steps):
-        step(evs[k])
-    stop.record(stream)
-    torch.cuda.synchronize()
+    ms_per_step, s1, s2 = _time_stages(g, U, U1, dt, work, args.steps, stream)
     wall = time.perf_counter() - t0
-    ms_total = start.elapsed_time(stop)
     flags = H.hard_status_read(work)
-    s1 = np.array([e[0].elapsed_time(e[1]) for e in evs])
-    s2 = np.array([e[1].elapsed_time(e[2]) for e in evs])
-    ms_per_step = ms_total / args.steps
-    zus = N * args.steps / (ms_total * 1e-3)
+    zus = N / (ms_per_step * 1e-3)
     log(f"  {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f}), {zus / 1e9:.2f} G zu/s, "
         f"stage1 {s1.mean():.3f} ms, stage2 {s2.mean():.3f} ms, flags {flags}")
+    # the configuration's own 100 steps, when a different count was timed
+    ms100 = None
+    if args.steps != 100:
+        reset()
+        ms100 = _time_stages(g, U, U1, dt, work, 100, stream)[0]
+        log(f"  100 steps: {ms100:.3f} ms/step")
+    # two steps from the initial state, compared with the oracle in the CPU leg
+    two = None
+    if not args.no_cpu_baseline:
+        reset()
+        gdts = []
+        for _ in range(2):
+            gdts.append(dt.item())
+            H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=dt)
+        torch.cuda.synchronize()
+        two = (U.cpu().numpy(), gdts)
+    del U1
 
     b_stage2 = 3 * nvar * w * N  # read U1, read U^n, write U^{n+1}
     b_stage1 = 2 * nvar * w * N  # read U^n, write U1
@@ -578,6 +877,9 @@ def main():
                                f"MUSCL-minmod + HLLC + SSP-RK2 with fused CFL dt",
                    "cells": N, "parallelism": "single GPU"},
         "achieved_hbm_gbs_step": step_gbs,
+        "frac_step": step_gbs / HBM_PEAK_GBS,
+        "target_frac": TARGET_FRAC,
+        "ms_per_step_100_steps": ms100 if ms100 is not None else ms_per_step,
         "roofline": {"bound": "hbm", "kernel": "stage_kernel<3,double,2> (stage 2)",
                      "achieved": ach2, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach2 / HBM_PEAK_GBS,
@@ -587,68 +889,48 @@ def main():
                      "stage2_ms": float(s2.mean())},
         "status_flags": flags,
     }
-    # the VALU ceiling beside the byte roofline: one wave64 FP64 instruction
-    # per 4 cycles on each of 1024 SIMDs at 2.4 GHz = 39.3 T lane-instr/s
-    lane_peak = 256 * 4 * 16 * 2.4e9
-    alu = {"bound": "alu", "unit": "lane-instr/s", "peak": lane_peak,
+    # the VALU ceiling beside the byte roofline (FP64 issue rate)
+    alu = {"bound": "alu", "unit": "lane-instr/s", "peak": VALU_F64_LANES,
            "oracle_ops_per_zone_update": OPS_PER_ZU_3D}
     if valu:
         per_zu = valu[0] + valu[1]  # lane-instructions per zone-update, both stages
         alu.update({"valu_per_zone_update": per_zu, "achieved": zus * per_zu,
-                    "frac": zus * per_zu / lane_peak, "ceiling_zone_updates_per_s": lane_peak / per_zu})
+                    "frac": zus * per_zu / VALU_F64_LANES,
+                    "ceiling_zone_updates_per_s": VALU_F64_LANES / per_zu})
     out["alu_beside"] = alu
+    del U, U0, work
 
+    extras = {}
     if not args.only_main:
-        extras = {}
-        try:
-            extras["fp32_512_turbulent"] = bench_fp32_turbulent(args)
-        except Exception as e:  # reported, never hidden
-            extras["fp32_512_turbulent"] = {"error": repr(e)}
-        try:
-            extras["batched_4096"] = bench_batched(args)
-        except Exception as e:
-            extras["batched_4096"] = {"error": repr(e)}
-        try:
-            extras["adjoint_512"] = bench_adjoint(args)
-        except Exception as e:
-            extras["adjoint_512"] = {"error": repr(e)}
-        try:
-            extras["weno5z_hll_256"] = bench_weno(args)
-        except Exception as e:
-            extras["weno5z_hll_256"] = {"error": repr(e)}
-        try:
-            extras["radiation_256"] = bench_rad(args)
-        except Exception as e:
-            extras["radiation_256"] = {"error": repr(e)}
-        try:
-            extras["radiation_diffusion_256"] = bench_fld(args)
-        except Exception as e:
-            extras["radiation_diffusion_256"] = {"error": repr(e)}
+        legs = [("c0_riemann_1024", bench_riemann), ("fp32_512_turbulent", bench_fp32_turbulent),
+                ("batched_4096", bench_batched), ("adjoint_512", bench_adjoint),
+                ("weno5z_hll_256", bench_weno), ("radiation_256", bench_rad),
+                ("radiation_diffusion_256", bench_fld)]
+        for name, fn in legs:
+            try:
+                extras[name] = fn(args)
+            except Exception as e:  # reported, never hidden
+                extras[name] = {"error": repr(e)}
         out["beside_fp64_step"] = extras
 
     if not args.no_cpu_baseline:
-        import oracle
-
-        og = oracle.Grid((n, n, n), bc=(oracle.REFLECT, oracle.REFLECT))
-        ksteps = args.cpu_steps
-        log(f"cpu baseline: oracle, {ksteps} steps of the same blast on {oracle.threads()} threads")
-        dt0, _ = oracle.cfl_dt(og, U0_host, 0.4)
-        t0 = time.perf_counter()
-        Uc = U0_host
-        for _ in range(ksteps):
-            d, _ = oracle.cfl_dt(og, Uc, 0.4)
-            Uc, _ = oracle.step(og, Uc, d)
-        el = time.perf_counter() - t0
-        cpu = "unknown CPU"
-        try:
-            with open("/proc/cpuinfo") as f:
-                cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
-        except (OSError, StopIteration):
-            pass
-        out["cpu_baseline"] = {"value": N * ksteps / el, "unit": "zone-updates/s",
-                               "cores": oracle.threads(), "kind": "oracle",
-                               "sample": f"{ksteps} steps (CFL dt + step) of the {n}^3 blast from "
-                                         f"its initial state, {el:.1f} s, on {cpu}"}
+        out["cpu_baseline"] = cpu_baseline(args, U0_host, two, n)
+        # the oracle comparisons of the legs above, made in the CPU leg
+        if "rel_l1_f32" in _ACC.get("fp32", {}) and "fp32_512_turbulent" in extras:
+            a = _ACC["fp32"]
+            extras["fp32_512_turbulent"]["rel_l1_vs_oracle_per_field"] = {
+                "fields": dict(zip(["rho", "m_x", "m_y", "m_z", "E"], a["rel_l1_f32"])),
+                "fp64_gpu_rel_linf_per_field": a["rel_linf_f64"],
+                "sample": f"{a['n']}^3 box of the same recipe, {len(a['dts'])} steps, one dt "
+                          f"sequence (the FP64 GPU run's) for the FP32 GPU run and the oracle"}
+        if "worst_rel_l1" in _ACC.get("batched", {}) and "batched_4096" in extras:
+            a = _ACC["batched"]
+            extras["batched_4096"]["rel_l1_vs_oracle_per_field"] = {
+                "worst_over_subset": a["worst_rel_l1"],
+                "sample": f"{len(a['pick'])} problems after the timed {a['steps']} steps, against "
+                          f"the FP64 oracle from the same float-rounded start with its own CFL steps"}
+        if "dual" in _ACC.get("adjoint", {}) and "adjoint_512" in extras:
+            extras["adjoint_512"]["dual_check"] = _ACC["adjoint"]["dual"]
     print(json.dumps(out), flush=True)
 
 
