@@ -266,6 +266,16 @@ hard_status_t hard_adjoint_workspace_bytes(const hard_grid_t* g, size_t* bytes);
 hard_status_t hard_hydro_step_adjoint(const hard_grid_t* g, const void* U_n, const double* dt_dev,
                                       void* lam, void* work, size_t work_bytes, void* stream);
 
+/* hard_hydro_step_adjoint with the intermediate stage supplied: U_1 must be
+ * the stage-1 state of U_n for the same dt, U_1 = U_n + dt L(U_n), as
+ * hard_hydro_stage (stage 1) writes it (a checkpointed reverse pass has it
+ * from recomputing the step forward).  The call then skips its own stage-1
+ * recomputation; the result is the same.  U_1 is read only and must not
+ * alias lam. */
+hard_status_t hard_hydro_step_adjoint_given_u1(const hard_grid_t* g, const void* U_n,
+                                               const void* U_1, const double* dt_dev, void* lam,
+                                               void* work, size_t work_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Implicit radiation diffusion (rad = 1): one backward-Euler step of the
  * diffusion term of the radiation energy equation (section 2.2.1, equation

@@ -22,7 +22,8 @@ __all__ = [
     "hard_batch_plan_create", "hard_batch_plan_destroy", "hard_batch_offsets",
     "hard_batch_workspace_bytes", "hard_cfl_dt_batched", "hard_hydro_step_batched",
     "hard_run_batched", "batch_pack", "batch_unpack",
-    "hard_adjoint_workspace_bytes", "hard_hydro_step_adjoint", "workspace",
+    "hard_adjoint_workspace_bytes", "hard_hydro_step_adjoint", "hard_hydro_step_adjoint_given_u1",
+    "workspace",
     "hard_gmg_opts_t", "hard_gmg_levels", "hard_rad_diffuse_workspace_bytes", "hard_rad_diffuse",
     "hard_run_rhd",
     "PERIODIC", "OUTFLOW", "REFLECT", "F64", "F32", "FLD_EDDINGTON", "FLD_LEVERMORE",
@@ -113,6 +114,7 @@ def lib():
                                  _vp, _sz, _vp],
             "hard_adjoint_workspace_bytes": [_gp, ctypes.POINTER(_sz)],
             "hard_hydro_step_adjoint": [_gp, _vp, _vp, _vp, _vp, _sz, _vp],
+            "hard_hydro_step_adjoint_given_u1": [_gp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
             "hard_gmg_levels": [_gp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                 ctypes.POINTER(ctypes.c_int32)],
             "hard_rad_diffuse_workspace_bytes": [_gp, ctypes.POINTER(_sz)],
@@ -333,6 +335,12 @@ def hard_adjoint_workspace_bytes(g):
 def hard_hydro_step_adjoint(g, U_n, dt_dev, lam, work, stream=None):
     _check(lib().hard_hydro_step_adjoint(_grid(g), _ptr(U_n), _ptr(dt_dev), _ptr(lam), _ptr(work),
                                          work.numel(), _stream(stream)))
+
+
+def hard_hydro_step_adjoint_given_u1(g, U_n, U_1, dt_dev, lam, work, stream=None):
+    _check(lib().hard_hydro_step_adjoint_given_u1(_grid(g), _ptr(U_n), _ptr(U_1), _ptr(dt_dev),
+                                                  _ptr(lam), _ptr(work), work.numel(),
+                                                  _stream(stream)))
 
 
 def hard_gmg_levels(g):

@@ -5,15 +5,18 @@ with the CFL step of each state (the step sizes are recorded and then held
 fixed: the time-step selection is not differentiated), keeping the state
 every `every` steps.  Its backward pass walks the segments in reverse:
 it recomputes the states of one segment from its checkpoint with the
-recorded step sizes, then applies hard_hydro_step_adjoint step by step,
-last step first.  Every state update and every vector-Jacobian product runs
-in libhard's kernels; this module only sequences the calls and keeps the
-checkpoints.
+recorded step sizes (keeping each step's stage-1 state), then applies the
+adjoint of each step, last step first, with that stage-1 state
+(hard_hydro_step_adjoint_given_u1; the segment's last step, whose stage 1
+was not recomputed, through hard_hydro_step_adjoint).  Every state update
+and every vector-Jacobian product runs in libhard's kernels; this module
+only sequences the calls and keeps the checkpoints.
 """
 import torch
 
 from . import (hard_adjoint_workspace_bytes, hard_cfl_dt, hard_hydro_stage, hard_hydro_step,
-               hard_hydro_step_adjoint, hard_workspace_bytes, workspace)
+               hard_hydro_step_adjoint, hard_hydro_step_adjoint_given_u1, hard_workspace_bytes,
+               workspace)
 
 
 class HydroRollout(torch.autograd.Function):
@@ -47,20 +50,28 @@ class HydroRollout(torch.autograd.Function):
         dev = lam.device
         work = workspace(hard_workspace_bytes(grid), dev)
         awork = workspace(hard_adjoint_workspace_bytes(grid), dev)
-        U1 = torch.empty_like(lam)
         for seg in reversed(range(len(ckpts))):
             start = seg * every
             end = min(start + every, nsteps)
             states = [ckpts[seg]]
+            stage1 = []
             for n in range(start, end - 1):
-                # recompute the segment's states: stage 1 into a scratch state,
-                # stage 2 straight into the new state (no copy of U^n)
+                # recompute the segment's states, keeping each step's stage-1
+                # state for its adjoint (stage 2 writes the new state directly)
+                U1 = torch.empty_like(lam)
                 U = torch.empty_like(lam)
                 hard_hydro_stage(grid, 1, states[-1], None, U1, dts[n:n + 1], work)
                 hard_hydro_stage(grid, 2, U1, states[-1], U, dts[n:n + 1], work)
+                stage1.append(U1)
                 states.append(U)
             for n in reversed(range(start, end)):
-                hard_hydro_step_adjoint(grid, states[n - start], dts[n:n + 1], lam, awork)
+                k = n - start
+                if k < len(stage1):
+                    hard_hydro_step_adjoint_given_u1(grid, states[k], stage1[k], dts[n:n + 1], lam,
+                                                     awork)
+                else:  # the segment's last step: its stage 1 was not recomputed
+                    hard_hydro_step_adjoint(grid, states[k], dts[n:n + 1], lam, awork)
+            del states, stage1
         return lam, None, None, None, None
 
 

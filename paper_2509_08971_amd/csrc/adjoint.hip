@@ -255,32 +255,23 @@ __device__ __forceinline__ void hllc_vjp(const double* WL, const double* WR, dou
   WRb[NV - 1] += pRb;
 }
 
-// One face along `axis`: contributions of its flux adjoint to the primitive
-// adjoints of its four stencil cells, written to C[slot][var][face]
-// (primitive order, before any ghost fold; faces numbered x fastest).
+// Contributions of the flux adjoint of one face along `axis` to the
+// primitive adjoints of its four stencil cells f-2 .. f+1 (primitive order,
+// before any ghost fold): Cb[s][v] for cell f - 2 + s.  (cx, cy, cz) is a
+// cell of the face's line (its coordinate along `axis` is not used); the
+// flux adjoint is Fbar = scale (mu_f - mu_{f-1}) / dx, zero outside the
+// interior.
 template <int NDIM, int axis>
-__global__ __launch_bounds__(256) void adj_face(const double* __restrict__ X,
-                                                const double* __restrict__ mu,
-                                                const double* __restrict__ dt_dev, double factor,
-                                                AdjGeo g, double* __restrict__ C) {
+__device__ __forceinline__ void face_vjp(const double* __restrict__ X,
+                                         const double* __restrict__ mu, double scale,
+                                         const AdjGeo& g, int cx, int cy, int cz, int f,
+                                         double (&Cb)[4][NDIM + 2]) {
   constexpr int NV = NDIM + 2;
-  const double scale = factor * *dt_dev;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const long long N = (long long)nx * ny * nz;
   const int nd = g.n[axis];
-  // faces form a grid of n + 1 positions along `axis` and n along the others,
-  // x fastest (so that neighbouring threads touch neighbouring cells)
-  const int m0 = nx + (axis == 0), m1 = ny + (axis == 1);
-  const long long NF = (long long)m0 * m1 * (nz + (axis == 2));
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= NF) return;
-  int c0[3];
-  c0[0] = (int)(id % m0);
-  c0[1] = (int)((id / m0) % m1);
-  c0[2] = (int)(id / ((long long)m0 * m1));
-  const int f = c0[axis];
   auto cell = [&](int q, bool& flip) -> long long {
-    int c[3] = {c0[0], c0[1], c0[2]};
+    int c[3] = {cx, cy, cz};
     c[axis] = remap(q, nd, g.bc[axis][0], g.bc[axis][1], flip);
     return ((long long)c[2] * ny + c[1]) * nx + c[0];
   };
@@ -341,7 +332,6 @@ __global__ __launch_bounds__(256) void adj_face(const double* __restrict__ X,
     WRb[perm[k]] = Bb[k];
   }
   // face states -> stencil cells
-  double Cb[4][NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     Cb[0][v] = 0;
@@ -355,6 +345,30 @@ __global__ __launch_bounds__(256) void adj_face(const double* __restrict__ X,
     if (pr[v] == 1) { Cb[2][v] += srb; Cb[1][v] -= srb; }
     else if (pr[v] == 2) { Cb[3][v] += srb; Cb[2][v] -= srb; }
   }
+}
+
+// One face along `axis` per thread: its stencil contributions written to
+// C[slot][var][face] (faces numbered x fastest) for adj_gather.
+template <int NDIM, int axis>
+__global__ __launch_bounds__(256) void adj_face(const double* __restrict__ X,
+                                                const double* __restrict__ mu,
+                                                const double* __restrict__ dt_dev, double factor,
+                                                AdjGeo g, double* __restrict__ C) {
+  constexpr int NV = NDIM + 2;
+  const double scale = factor * *dt_dev;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  // faces form a grid of n + 1 positions along `axis` and n along the others,
+  // x fastest (so that neighbouring threads touch neighbouring cells)
+  const int m0 = nx + (axis == 0), m1 = ny + (axis == 1);
+  const long long NF = (long long)m0 * m1 * (nz + (axis == 2));
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= NF) return;
+  int c0[3];
+  c0[0] = (int)(id % m0);
+  c0[1] = (int)((id / m0) % m1);
+  c0[2] = (int)(id / ((long long)m0 * m1));
+  double Cb[4][NV];
+  face_vjp<NDIM, axis>(X, mu, scale, g, c0[0], c0[1], c0[2], c0[axis], Cb);
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -408,6 +422,24 @@ __global__ __launch_bounds__(256) void adj_gather(AdjGeo g, int axis, const doub
   for (int v = 0; v < NV; ++v) Wb[v * N + c] = accumulate ? Wb[v * N + c] + acc[v] : acc[v];
 }
 
+// Conserved adjoint (dW/dU)^T wb of the primitive adjoint wb at the state u.
+template <int NDIM>
+__device__ __forceinline__ void prim_to_cons_adjoint(const double* u, const double* wb,
+                                                     double gamma, double* ub) {
+  constexpr int NV = NDIM + 2;
+  const double rho = u[0], gm1 = gamma - 1.0;
+  double q = 0.0;
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) q += u[1 + d] * u[1 + d];
+  ub[0] = wb[0] + wb[NV - 1] * gm1 * 0.5 * q / (rho * rho);
+#pragma unroll
+  for (int d = 0; d < NDIM; ++d) {
+    ub[0] -= wb[1 + d] * u[1 + d] / (rho * rho);
+    ub[1 + d] = wb[1 + d] / rho - wb[NV - 1] * gm1 * u[1 + d] / rho;
+  }
+  ub[NV - 1] = wb[NV - 1] * gm1;
+}
+
 // out = c0 lam + c1 lam1 + (dW/dU)^T Wb at X (lam1 may be NULL).
 template <int NDIM>
 __global__ __launch_bounds__(256) void adj_final(const double* __restrict__ X,
@@ -417,24 +449,195 @@ __global__ __launch_bounds__(256) void adj_final(const double* __restrict__ X,
   constexpr int NV = NDIM + 2;
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
-  double u[NV], wb[NV];
+  double u[NV], wb[NV], ub[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     u[v] = X[v * N + c];
     wb[v] = Wb[v * N + c];
   }
-  const double rho = u[0], gm1 = gamma - 1.0;
-  double q = 0.0;
+  prim_to_cons_adjoint<NDIM>(u, wb, gamma, ub);
 #pragma unroll
-  for (int d = 0; d < NDIM; ++d) q += u[1 + d] * u[1 + d];
-  double ub[NV];
-  ub[0] = wb[0] + wb[NV - 1] * gm1 * 0.5 * q / (rho * rho);
-#pragma unroll
-  for (int d = 0; d < NDIM; ++d) {
-    ub[0] -= wb[1 + d] * u[1 + d] / (rho * rho);
-    ub[1 + d] = wb[1 + d] / rho - wb[NV - 1] * gm1 * u[1 + d] / rho;
+  for (int v = 0; v < NV; ++v) {
+    double r = c0 * lam[v * N + c] + ub[v];
+    if (lam1) r += c1 * lam1[v * N + c];
+    out[v * N + c] = r;
   }
-  ub[NV - 1] = wb[NV - 1] * gm1;
+}
+
+// ---------------------------------------------------------------------------
+// The whole product in one launch for 1D and 2D grids (adj_tile): one
+// workgroup per tile of TX x TY cells
+//   out = c0 lam + c1 lam1 + (dW/dU)^T (dL/dX)^T (factor dt mu)   at X.
+// It computes every face whose stencil reaches a cell of the tile (TX + 3
+// per row and axis, plus the up to four faces at the far end of a line
+// whose ghost cells fold into the tile), one face per thread and batch, and
+// adds each face's four stencil contributions to per-cell accumulators in
+// LDS in eight rounds (axis, face index mod 4): faces of one round touch
+// distinct cells.  Contributions to ghost positions are kept per (ghost,
+// face) pair and folded into their source cells afterwards, in the order
+// q = -2, -1, n, n + 1 (faces ascending), the normal velocity negated
+// across a reflecting wall.  No face array goes through memory.
+// ---------------------------------------------------------------------------
+template <int NDIM>
+struct AdjTileShape;
+template <>
+struct AdjTileShape<1> {
+  static constexpr int TX = 256, TY = 1;
+};
+template <>
+struct AdjTileShape<2> {
+  static constexpr int TX = 16, TY = 16;
+};
+
+// The six (ghost position, face) pairs of a line: (-2, 0), (-1, 0), (-1, 1),
+// (n, n-1), (n, n), (n+1, n); pair_of() maps a face and a ghost stencil slot
+// to its pair.
+__device__ __forceinline__ int pair_q(int k, int nd) {
+  return k == 0 ? -2 : (k <= 2 ? -1 : (k <= 4 ? nd : nd + 1));
+}
+__device__ __forceinline__ int pair_f(int k, int nd) {
+  return k <= 1 ? 0 : (k == 2 ? 1 : (k == 3 ? nd - 1 : nd));
+}
+__device__ __forceinline__ int pair_of(int q, int f, int nd) {
+  if (q == -2) return 0;
+  if (q == -1) return f == 0 ? 1 : 2;
+  if (q == nd) return f == nd - 1 ? 3 : 4;
+  return 5;
+}
+
+template <int NDIM>
+__global__ __launch_bounds__(256) void adj_tile(const double* __restrict__ X,
+                                                const double* __restrict__ mu,
+                                                const double* __restrict__ dt_dev, double factor,
+                                                AdjGeo g, const double* lam, double c0,
+                                                const double* lam1, double c1, double* out) {
+  constexpr int NV = NDIM + 2;
+  constexpr int TX = AdjTileShape<NDIM>::TX, TY = AdjTileShape<NDIM>::TY;
+  constexpr int SX = TX + 7, SY = TY + 7;         // face slots per line and axis
+  constexpr int NIX = TY * SX, NIY = NDIM == 2 ? TX * SY : 0;
+  constexpr int NI = NIX + NIY;
+  constexpr int NL = NDIM == 1 ? 1 : (TX > TY ? TX : TY);  // lines per axis, at most
+  __shared__ double acc[NV][TY][TX];
+  __shared__ double gbuf[NDIM][NL][6][NV];
+  const int tid = threadIdx.x;
+  const int nx = g.n[0], ny = g.n[1];
+  const long long N = (long long)nx * ny;
+  const int tiles_x = (nx + TX - 1) / TX;
+  const int x0 = (int)(blockIdx.x % tiles_x) * TX, y0 = (int)(blockIdx.x / tiles_x) * TY;
+  const double scale = factor * *dt_dev;
+  const int lx = tid % TX, ly = tid / TX;         // this thread's cell (TX * TY == 256)
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v][ly][lx] = 0.0;
+  __syncthreads();
+
+  // the face of item i: axis, line (row y or column x of the tile), face index
+  // f along the axis; false if the item carries no face
+  auto item = [&](int i, int& ax, int& line, int& f, bool& own) -> bool {
+    int slot, t0, T, nd, nother, origin_other;
+    if (i < NIX) {
+      ax = 0; line = i / SX; slot = i % SX;
+      t0 = x0; T = TX; nd = nx; nother = ny; origin_other = y0;
+    } else {
+      const int k = i - NIX;
+      ax = 1; line = k % TX; slot = k / TX;
+      t0 = y0; T = TY; nd = ny; nother = nx; origin_other = x0;
+    }
+    if (origin_other + line >= nother) return false;
+    const int t1 = t0 + T < nd ? t0 + T : nd;       // tile cells [t0, t1) along the axis
+    const int fa = t0 - 1 > 0 ? t0 - 1 : 0, fb = t1 + 1 < nd ? t1 + 1 : nd;
+    if (slot < T + 3) {
+      f = t0 - 1 + slot;
+      own = true;
+      return f >= fa && f <= fb;
+    }
+    // far-end faces whose ghost contributions fold into this tile
+    const int r = slot - (T + 3);
+    const int cand[4] = {0, 1, nd - 1, nd};
+    f = cand[r];
+    own = false;
+    if (f >= fa && f <= fb) return false;           // computed as an own face
+    for (int e = 0; e < r; ++e)
+      if (cand[e] == f) return false;               // duplicate (short lines)
+    bool need = false;
+    for (int k = 0; k < 6; ++k) {
+      if (pair_f(k, nd) != f) continue;
+      bool fl;
+      const int src = remap(pair_q(k, nd), nd, g.bc[ax][0], g.bc[ax][1], fl);
+      need = need || (src >= t0 && src < t1);
+    }
+    return need;
+  };
+
+  for (int base = 0; base < NI; base += 256) {
+    const int i = base + tid;
+    int ax = 0, line = 0, f = 0;
+    bool own = false;
+    const bool has = i < NI && item(i, ax, line, f, own);
+    double Cb[4][NV];
+    if (has) {
+      if (ax == 0) face_vjp<NDIM, 0>(X, mu, scale, g, 0, y0 + line, 0, f, Cb);
+      else if constexpr (NDIM == 2) face_vjp<NDIM, 1>(X, mu, scale, g, x0 + line, 0, 0, f, Cb);
+      // ghost contributions whose source cell lies in the tile
+      const int nd = g.n[ax], t0 = ax == 0 ? x0 : y0, T = ax == 0 ? TX : TY;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int q = f - 2 + s;
+        if (q >= 0 && q < nd) continue;
+        bool fl;
+        const int src = remap(q, nd, g.bc[ax][0], g.bc[ax][1], fl);
+        if (src < t0 || src >= t0 + T) continue;
+        const int k = pair_of(q, f, nd);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gbuf[ax][line][k][v] = Cb[s][v];
+      }
+    }
+    // direct contributions, round by round
+#pragma unroll
+    for (int r = 0; r < 4 * NDIM; ++r) {
+      if (has && own && ax == r / 4 && (f & 3) == (r & 3)) {
+        const int nd = g.n[ax], t0 = ax == 0 ? x0 : y0, T = ax == 0 ? TX : TY;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int q = f - 2 + s;
+          if (q < 0 || q >= nd || q < t0 || q >= t0 + T) continue;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            if (ax == 0) acc[v][line][q - t0] += Cb[s][v];
+            else acc[v][q - t0][line] += Cb[s][v];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ghost folds, then the conserved adjoint of this thread's cell
+  const int gx = x0 + lx, gy = y0 + ly;
+  if (gx >= nx || gy >= ny) return;
+  double wb[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) wb[v] = acc[v][ly][lx];
+#pragma unroll
+  for (int ax = 0; ax < NDIM; ++ax) {
+    const int nd = g.n[ax], j = ax == 0 ? gx : gy, line = ax == 0 ? ly : lx;
+    if (j >= 2 && j < nd - 2) continue;             // no ghost has this cell as its source
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      bool fl;
+      const int src = remap(pair_q(k, nd), nd, g.bc[ax][0], g.bc[ax][1], fl);
+      if (src != j) continue;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double val = gbuf[ax][line][k][v];
+        wb[v] += (fl && v == 1 + ax) ? -val : val;
+      }
+    }
+  }
+  const long long c = (long long)gy * nx + gx;
+  double u[NV], ub[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = X[v * N + c];
+  prim_to_cons_adjoint<NDIM>(u, wb, g.gamma, ub);
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     double r = c0 * lam[v * N + c] + ub[v];
@@ -493,8 +696,8 @@ static hipError_t adj_rhs(const Grid& G, const AdjGeo& g, const double* X, const
 }
 
 template <int NDIM>
-static hipError_t adj_step(const Grid& G, const double* Un, const double* dt_dev, double* lam,
-                           char* wb, const AdjLayout& L, hipStream_t s) {
+static hipError_t adj_step(const Grid& G, const double* Un, const double* U1, const double* dt_dev,
+                           double* lam, char* wb, const AdjLayout& L, hipStream_t s) {
   AdjGeo g;
   for (int d = 0; d < 3; ++d) {
     g.n[d] = G.n[d];
@@ -503,13 +706,28 @@ static hipError_t adj_step(const Grid& G, const double* Un, const double* dt_dev
     g.inv_dx[d] = G.inv_dx[d];
   }
   g.gamma = G.gamma;
-  double* U1 = reinterpret_cast<double*>(wb + L.u1);
   double* lam1 = reinterpret_cast<double*>(wb + L.lam1);
   double* Wbuf = reinterpret_cast<double*>(wb + L.wb);
   double* C = reinterpret_cast<double*>(wb + L.cbuf);
   const long long N = G.ncell;
   const unsigned nb = (unsigned)((N + 255) / 256);
   hipError_t e;
+  if constexpr (NDIM <= 2) {
+    // one fused launch per product (adj_tile)
+    using TS = AdjTileShape<NDIM>;
+    const unsigned tiles = (unsigned)(((G.n[0] + TS::TX - 1) / TS::TX) *
+                                      ((G.n[1] + TS::TY - 1) / TS::TY));
+    // lam1 = lam/2 + (dL/dU1)^T (dt lam / 2)
+    hipLaunchKernelGGL(adj_tile<NDIM>, dim3(tiles), dim3(256), 0, s, U1, (const double*)lam,
+                       dt_dev, 0.5, g, (const double*)lam, 0.5, (const double*)nullptr, 0.0, lam1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // lam0 = lam/2 + lam1 + (dL/dU)^T (dt lam1)
+    hipLaunchKernelGGL(adj_tile<NDIM>, dim3(tiles), dim3(256), 0, s, Un, (const double*)lam1,
+                       dt_dev, 1.0, g, (const double*)lam, 0.5, (const double*)lam1, 1.0, lam);
+    return hipGetLastError();
+  }
+  // 3D: face kernels with their contributions through the workspace, a
+  // gather per axis and the final map
   // lam1 = lam/2 + (dL/dU1)^T (dt lam / 2)
   if ((e = adj_rhs<NDIM>(G, g, U1, lam, dt_dev, 0.5, C, Wbuf, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(adj_final<NDIM>, dim3(nb), dim3(256), 0, s, (const double*)U1,
@@ -541,8 +759,12 @@ hard_status_t hard_adjoint_workspace_bytes(const hard_grid_t* g, size_t* bytes) 
   return ok();
 }
 
-hard_status_t hard_hydro_step_adjoint(const hard_grid_t* g, const void* U_n, const double* dt_dev,
-                                      void* lam, void* work, size_t work_bytes, void* stream) {
+// Shared body of the two adjoint entry points: U_1 is the stage-1 state of
+// U_n for this dt (NULL: recomputed into the workspace by the forward stage
+// kernel).
+static hard_status_t adjoint_step(const hard_grid_t* g, const void* U_n, const void* U_1,
+                                  const double* dt_dev, void* lam, void* work, size_t work_bytes,
+                                  void* stream, const char* name) {
   Grid G;
   hard_status_t st = check_grid(g, &G);
   if (st) return st;
@@ -552,40 +774,58 @@ hard_status_t hard_hydro_step_adjoint(const hard_grid_t* g, const void* U_n, con
   if ((st = check_ptr(U_n, 8, "U_n"))) return st;
   if ((st = check_ptr(lam, 8, "lam"))) return st;
   if ((st = check_ptr(dt_dev, 8, "dt_dev"))) return st;
+  if (U_1 && (st = check_ptr(U_1, 8, "U_1"))) return st;
   AdjLayout L = adj_layout(G);
   if ((st = check_work(work, work_bytes, L.total))) return st;
   hipStream_t s = (hipStream_t)stream;
   char* wb = static_cast<char*>(work);
   hipError_t e;
-  // recompute U1 = U + dt L(U) with the forward stage kernel
-  StageArgs a;
-  std::memset(&a, 0, sizeof a);
-  for (int d = 0; d < 3; ++d) {
-    a.n[d] = G.n[d];
-    a.dx[d] = G.dx[d];
-    a.inv_dx[d] = G.inv_dx[d];
-    a.dx_pow2 = G.dx_pow2;
-    a.bc[d][0] = G.bc[d][0];
-    a.bc[d][1] = G.bc[d][1];
+  const double* U1 = static_cast<const double*>(U_1);
+  if (!U1) {
+    // recompute U1 = U + dt L(U) with the forward stage kernel
+    StageArgs a;
+    std::memset(&a, 0, sizeof a);
+    for (int d = 0; d < 3; ++d) {
+      a.n[d] = G.n[d];
+      a.dx[d] = G.dx[d];
+      a.inv_dx[d] = G.inv_dx[d];
+      a.dx_pow2 = G.dx_pow2;
+      a.bc[d][0] = G.bc[d][0];
+      a.bc[d][1] = G.bc[d][1];
+    }
+    a.gamma = G.gamma;
+    a.dt = dt_dev;
+    a.ctl = reinterpret_cast<Control*>(wb + L.ctl);
+    a.cz = stage_cz_override();
+    a.src = U_n;
+    a.un = U_n;
+    a.dst = wb + L.u1;
+    if ((e = launch_stage(G.ndim, G.dtype, a, 1, s)) != hipSuccess) return hip_fail(e, name);
+    U1 = reinterpret_cast<const double*>(wb + L.u1);
   }
-  a.gamma = G.gamma;
-  a.dt = dt_dev;
-  a.ctl = reinterpret_cast<Control*>(wb + L.ctl);
-  a.cz = stage_cz_override();
-  a.src = U_n;
-  a.un = U_n;
-  a.dst = wb + L.u1;
-  if ((e = launch_stage(G.ndim, G.dtype, a, 1, s)) != hipSuccess)
-    return hip_fail(e, "hard_hydro_step_adjoint stage 1");
   const double* Un = static_cast<const double*>(U_n);
   double* lm = static_cast<double*>(lam);
   switch (G.ndim) {
-    case 1: e = adj_step<1>(G, Un, dt_dev, lm, wb, L, s); break;
-    case 2: e = adj_step<2>(G, Un, dt_dev, lm, wb, L, s); break;
-    default: e = adj_step<3>(G, Un, dt_dev, lm, wb, L, s); break;
+    case 1: e = adj_step<1>(G, Un, U1, dt_dev, lm, wb, L, s); break;
+    case 2: e = adj_step<2>(G, Un, U1, dt_dev, lm, wb, L, s); break;
+    default: e = adj_step<3>(G, Un, U1, dt_dev, lm, wb, L, s); break;
   }
-  if (e != hipSuccess) return hip_fail(e, "hard_hydro_step_adjoint");
+  if (e != hipSuccess) return hip_fail(e, name);
   return ok();
+}
+
+hard_status_t hard_hydro_step_adjoint(const hard_grid_t* g, const void* U_n, const double* dt_dev,
+                                      void* lam, void* work, size_t work_bytes, void* stream) {
+  return adjoint_step(g, U_n, nullptr, dt_dev, lam, work, work_bytes, stream,
+                      "hard_hydro_step_adjoint");
+}
+
+hard_status_t hard_hydro_step_adjoint_given_u1(const hard_grid_t* g, const void* U_n,
+                                               const void* U_1, const double* dt_dev, void* lam,
+                                               void* work, size_t work_bytes, void* stream) {
+  if (!U_1) return fail(HARD_ERR_INVALID_ARG, "U_1 is NULL");
+  return adjoint_step(g, U_n, U_1, dt_dev, lam, work, work_bytes, stream,
+                      "hard_hydro_step_adjoint_given_u1");
 }
 
 }  // extern "C"

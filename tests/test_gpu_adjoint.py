@@ -64,6 +64,29 @@ def test_one_step_adjoint_dot_product(n, bc):
         assert abs(lhs - rhs) <= 1e-10 * scale, (trial, lhs, rhs)
 
 
+@pytest.mark.parametrize("n,bc", [((40, 32), (P, P, R, R)), ((16, 12, 10), (P, P, R, R, O, O)),
+                                  ((64,), (O, O))])
+def test_adjoint_given_stage_state_equals_recomputed(n, bc):
+    """hard_hydro_step_adjoint_given_u1 with the stage-1 state from
+    hard_hydro_stage gives the same bits as hard_hydro_step_adjoint, which
+    recomputes that stage itself."""
+    U0, rng = smooth_state(n, 8)
+    g = H.make_grid(n, bc=bc)
+    U = torch.from_numpy(U0).to(DEV)
+    dt = torch.zeros(1, dtype=torch.float64, device=DEV)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    H.hard_cfl_dt(g, U, 0.4, dt, work)
+    U1 = torch.empty_like(U)
+    H.hard_hydro_stage(g, 1, U, None, U1, dt, work)
+    aw = H.workspace(H.hard_adjoint_workspace_bytes(g))
+    lam = torch.from_numpy(rng.standard_normal(U0.shape)).to(DEV)
+    a, b = lam.clone(), lam.clone()
+    H.hard_hydro_step_adjoint(g, U, dt, a, aw)
+    H.hard_hydro_step_adjoint_given_u1(g, U, U1, dt, b, aw)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def c4_state(n, seed=4):
     return workloads.turbulent_box(n, ndim=2, seed=seed)
 
