@@ -179,14 +179,10 @@ hipError_t launch_scheme_stage(const Grid& G, const WorkLayout& L, char* wb, con
 RadArgs rad_args(const Grid& G, const StageArgs& a) {
   RadArgs r;
   std::memset(&r, 0, sizeof r);
-  r.src = a.src;
-  r.un = a.un;
   r.dst = a.dst;
   r.dt = a.dt;
   for (int d = 0; d < 3; ++d) {
     r.n[d] = a.n[d];
-    r.bc[d][0] = a.bc[d][0];
-    r.bc[d][1] = a.bc[d][1];
     r.dx[d] = a.dx[d];
     r.inv_dx[d] = a.inv_dx[d];
   }
@@ -302,6 +298,7 @@ hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_de
   a.slots = reinterpret_cast<double*>(wb + L.slots);
   a.nslots = L.nslots;
   a.cz = stage_cz_override();
+  a.rad = G.rad;  // E_r is advected by the same stage kernels
   void* U1 = wb + L.stage;
   // stage 1: U1 = U + dt L(U)
   a.src = U;
@@ -310,8 +307,6 @@ hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_de
   a.fuse_cfl = 0;
   hipError_t e = launch_scheme_stage(G, L, wb, a, 1, s);
   if (e != hipSuccess) return hip_fail(e, "hard_hydro_step stage 1");
-  if (G.rad && (e = launch_rad_advect(G.ndim, G.dtype, rad_args(G, a), 1, s)) != hipSuccess)
-    return hip_fail(e, "hard_hydro_step radiation stage 1");
   // stage 2: U = (U + (U1 + dt L(U1))) / 2, optionally with the next dt
   // (with radiation the next dt comes after the exchange instead)
   a.src = U1;
@@ -323,8 +318,6 @@ hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_de
   if (e != hipSuccess) return hip_fail(e, "hard_hydro_step stage 2");
   if (G.rad) {
     RadArgs r = rad_args(G, a);
-    if ((e = launch_rad_advect(G.ndim, G.dtype, r, 2, s)) != hipSuccess)
-      return hip_fail(e, "hard_hydro_step radiation stage 2");
     r.fuse_cfl = next_dt_dev != nullptr;
     if ((e = launch_rad_source(G.ndim, G.dtype, r, s)) != hipSuccess)
       return hip_fail(e, "hard_hydro_step radiation exchange");

@@ -234,6 +234,19 @@ __device__ __forceinline__ void hllc(R rL, R unL, const R* utL, R pL, R rR, R un
   F[NT + 2] = Ep * un + (S * q) * (Ep + r * d * Ss);
 }
 
+// Rusanov (local Lax-Friedrichs) flux of the radiation energy density E_r at
+// a face, from the face states in face order (rho, u_n, u_t..., p, E_r):
+// the mean of E_r u_n on the two sides minus half the larger signal speed
+// |u_n| + c of the two hydro face states times the jump of E_r.
+template <typename R, int NH>
+__device__ __forceinline__ R rusanov_er(const R* A, const R* B, R gam) {
+  const R cL = sound_speed(gam * A[NH - 1], A[0]);
+  const R cR = sound_speed(gam * B[NH - 1], B[0]);
+  const R sL = fabs(A[1]) + cL, sR = fabs(B[1]) + cR;
+  const R sm = sL >= sR ? sL : sR;
+  return R(0.5) * (A[NH] * A[1] + B[NH] * B[1]) - R(0.5) * sm * (B[NH] - A[NH]);
+}
+
 // MUSCL-minmod face states from four cell states along the face normal
 // (cells i-1, i | i+1, i+2 around face i+1/2 are w0, w1 | w2, w3).
 template <typename R>

@@ -23,6 +23,7 @@ struct StageArgs {
   int fuse_cfl;          // stage 2: fold the CFL max of U^{n+1} into the pass
   int tiles_x, tiles_y;  // filled by the launcher
   int cz;                // walk positions per workgroup (z in 3D, y in 2D), 0 = default
+  int rad;               // 1: field ndim + 2 is E_r, advected in the same pass
   Control* ctl;          // workspace control block
   double* next_dt;       // fused CFL output (stage 2)
   double* slots;         // fused CFL: one signal-sum max per workgroup
@@ -68,15 +69,13 @@ struct WenoArgs {
 
 hipError_t launch_weno_stage(int ndim, int dtype, const WenoArgs& a, int stage, hipStream_t s);
 
-// Radiation energy density (rad.hip): the E_r part of a Heun stage, and the
-// exchange with the fluid after stage 2 (with the fused next dt).
+// Radiation energy density (rad.hip): the exchange with the fluid after
+// stage 2 (with the fused next dt).  The advection of E_r runs in the stage
+// kernels (StageArgs::rad).
 struct RadArgs {
-  const void* src;
-  const void* un;
-  void* dst;          // stage output (rad_advect); the state after the step (rad_source)
+  void* dst;          // the state after the step, updated in place
   const double* dt;
   int n[3];
-  int bc[3][2];
   double dx[3];
   double inv_dx[3];
   int dx_pow2;
@@ -90,7 +89,6 @@ struct RadArgs {
   int nslots;
 };
 
-hipError_t launch_rad_advect(int ndim, int dtype, const RadArgs& a, int stage, hipStream_t s);
 hipError_t launch_rad_source(int ndim, int dtype, const RadArgs& a, hipStream_t s);
 
 // Standalone CFL dt (reads U once).

@@ -15,16 +15,17 @@
 namespace hard {
 
 // Minimum waves per SIMD the register allocator must allow: 3 for the FP64
-// 3D kernels (their natural footprint sits just above the 168-VGPR limit of
-// 3 waves), no constraint otherwise.
+// 3D hydro kernels (their natural footprint sits just above the 168-VGPR
+// limit of 3 waves), no constraint otherwise (the FP64 3D kernels carrying
+// E_r hold 2 waves per SIMD by their LDS anyway).
 #ifndef HARD_STAGE_WAVES
-#define HARD_STAGE_WAVES(NDIM, R) ((NDIM) == 3 && sizeof(R) == 8 ? 3 : 1)
+#define HARD_STAGE_WAVES(NDIM, R, RAD) ((NDIM) == 3 && sizeof(R) == 8 && !(RAD) ? 3 : 1)
 #endif
 
-template <int NDIM, typename R, int STAGE, int TX, int TY, int NTHR>
-__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(HARD_STAGE_WAVES(NDIM, R), 8)))
+template <int NDIM, typename R, int STAGE, int TX, int TY, int NTHR, bool RAD>
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(HARD_STAGE_WAVES(NDIM, R, RAD), 8)))
 void stage_kernel(StageArgs a) {
-  __shared__ R lds[TileShape<NDIM, R, TX, TY>::lds_elems];
+  __shared__ R lds[TileShape<NDIM, R, TX, TY, RAD>::lds_elems];
   int L = xcd_tile(blockIdx.x, gridDim.x);
   const int tile_x = L % a.tiles_x;
   L /= a.tiles_x;
@@ -52,7 +53,7 @@ void stage_kernel(StageArgs a) {
   t.fuse_cfl = STAGE == 2 && a.fuse_cfl;
   unsigned flags = 0;
   double smax = 0.0;
-  run_tile<NDIM, R, STAGE, TX, TY, NTHR, NDIM == 3>(t, lds, flags, smax);
+  run_tile<NDIM, R, STAGE, TX, TY, NTHR, NDIM == 3, RAD>(t, lds, flags, smax);
   block_finish<NTHR>(flags, smax, STAGE == 2 && a.fuse_cfl, a.ctl, a.slots + blockIdx.x);
 }
 
@@ -86,10 +87,16 @@ static hipError_t launch_stage_t(const StageArgs& a0, int stage, int cz_default,
   const bool fuse = stage == 2 && a.fuse_cfl;
   if (nb >= (1LL << 31) || (fuse && nb > a.nslots)) return hipErrorInvalidValue;
   dim3 grid((unsigned)nb), block(NTHR);
-  if (stage == 1)
-    hipLaunchKernelGGL((stage_kernel<NDIM, R, 1, TX, TY, NTHR>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((stage_kernel<NDIM, R, 2, TX, TY, NTHR>), grid, block, 0, s, a);
+  if (a.rad) {
+    if (stage == 1)
+      hipLaunchKernelGGL((stage_kernel<NDIM, R, 1, TX, TY, NTHR, true>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((stage_kernel<NDIM, R, 2, TX, TY, NTHR, true>), grid, block, 0, s, a);
+  } else if (stage == 1) {
+    hipLaunchKernelGGL((stage_kernel<NDIM, R, 1, TX, TY, NTHR, false>), grid, block, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((stage_kernel<NDIM, R, 2, TX, TY, NTHR, false>), grid, block, 0, s, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !fuse) return e;
   return launch_cfl_final(a.slots, (int)nb, a.cfl, a.next_dt, s);

@@ -59,9 +59,12 @@ __device__ __forceinline__ void stream_store(R* p, R v) {
   else *p = v;
 }
 
-template <int NDIM, typename R, int TX, int TY>
+// RAD: the state carries the radiation energy density E_r as field NDIM + 2,
+// advected in the same pass (see rusanov_er).
+template <int NDIM, typename R, int TX, int TY, bool RAD = false>
 struct TileShape {
-  static constexpr int NV = NDIM + 2;
+  static constexpr int NH = NDIM + 2;            // hydro fields
+  static constexpr int NV = NH + (RAD ? 1 : 0);  // fields carried through the tile
   static constexpr int PD = NDIM == 3 ? 2 : 1;  // dimensions of the plane in LDS
   static constexpr int LX = TX + 4;
   static constexpr int LY = PD == 2 ? TY + 4 : 1;
@@ -82,10 +85,11 @@ struct TileShape {
 // workgroup must call it (it contains barriers).  NTHR (>= TX*TY) is the
 // workgroup size; threads beyond TX*TY own no cell but take part in the face
 // and halo loops (a row of 63 cells has exactly 64 faces, one per lane).
-template <int NDIM, typename R, int STAGE, int TX, int TY, int NTHR = TX * TY, bool NTS = false>
+template <int NDIM, typename R, int STAGE, int TX, int TY, int NTHR = TX * TY, bool NTS = false,
+          bool RAD = false>
 __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& flags, double& smax) {
-  using S = TileShape<NDIM, R, TX, TY>;
-  constexpr int NV = S::NV, PD = S::PD, LX = S::LX, LXY = S::LXY;
+  using S = TileShape<NDIM, R, TX, TY, RAD>;
+  constexpr int NV = S::NV, NH = S::NH, PD = S::PD, LX = S::LX, LXY = S::LXY;
   constexpr int NFX = S::NFX, NF = S::NF, NHALO = S::NHALO;
   constexpr bool WALK = NDIM >= 2;
   constexpr int WA = NDIM - 1;          // walk axis
@@ -147,15 +151,24 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
 #pragma unroll
     for (int v = 0; v < NV; ++v) Uc[v] = src[v * N + c];
   };
-  // primitive state of this thread's column from conserved values
+  // primitive state of this thread's column from conserved values (E_r, if
+  // carried, is its own primitive)
   auto col_prim = [&](const R* Uc, bool fw, R* W) {
     to_primitive<R, NDIM>(Uc, W, gm1);
+    if constexpr (RAD) W[NH] = Uc[NH];
     if (fx_) W[1] = -W[1];
     if (PD == 2 && fy_) W[2] = -W[2];
     if (WALK && fw) W[1 + WA] = -W[1 + WA];
   };
-  // variable order of a face normal to the walk axis: (rho, u_n, u_t..., p)
-  constexpr int wperm[5] = {0, 1 + WA, 1, NDIM == 3 ? 2 : NV - 1, NV - 1};
+  // variable order of a face normal to the walk axis: (rho, u_n, u_t..., p
+  // [, E_r])
+  constexpr int wperm[6] = {0, 1 + WA, 1, NDIM == 3 ? 2 : NH - 1, NDIM == 3 ? NH - 1 : NH, NH};
+  // flux of a face from its states in face order: HLLC for the hydro fields,
+  // the Rusanov flux of E_r beside it
+  auto face_flux = [&](const R* A, const R* B, R* Fn) {
+    hllc_ordered<R, NH>(A, B, gam, inv_gm1, Fn);
+    if constexpr (RAD) Fn[NH] = rusanov_er<R, NH>(A, B, gam);
+  };
 
   // walk-axis register window: P0 = position w, P1 = w+1, S0 = slope at w,
   // Fm = flux through the face w-1/2; conserved values Ucur (w) and Uc1 (w+1)
@@ -191,7 +204,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
       A[k] = Pm1[q] + R(0.5) * sm1;
       B[k] = P0[q] - R(0.5) * S0[q];
     }
-    hllc_ordered<R, NV>(A, B, gam, inv_gm1, Fn);
+    face_flux(A, B, Fn);
 #pragma unroll
     for (int k = 0; k < NV; ++k) fz_set(wperm[k], Fn[k]);
   }
@@ -249,6 +262,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
     if (has_halo) {
       R Wh[NV];
       to_primitive<R, NDIM>(Hc, Wh, gm1);
+      if constexpr (RAD) Wh[NH] = Hc[NH];
       if (hflx) Wh[1] = -Wh[1];
       if (PD == 2 && hfly) Wh[2] = -Wh[2];
 #pragma unroll
@@ -262,7 +276,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
 #pragma unroll
       for (int v = 0; v < NV; ++v) Ws[v * LXY + (ty + OY) * LX + tx + 2] = P0[v];
     }
-    if (inside) flags |= cell_flags<R, NV>(Ucur, P0[NV - 1]);
+    if (inside) flags |= cell_flags<R, NV>(Ucur, P0[NH - 1]);
     __syncthreads();
 
     // ---- 2. in-plane faces.  Each owner thread takes the low x face of
@@ -281,7 +295,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
         const R* wp = Ws + sv * LXY + base;
         muscl_pair(wp[0], wp[stride], wp[2 * stride], wp[3 * stride], WL[v], WR[v]);
       }
-      hllc_ordered<R, NV>(WL, WR, gam, inv_gm1, Fn);
+      face_flux(WL, WR, Fn);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const int sv = (PD == 2 && YF && (v == 1 || v == 2)) ? 3 - v : v;
@@ -322,7 +336,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
               const R* wp = Ws + sv * LXY + base;
               muscl_pair(wp[0], wp[stride], wp[2 * stride], wp[3 * stride], WL[v], WR[v]);
             }
-            hllc_ordered<R, NV>(WL, WR, gam, inv_gm1, Fn);
+            face_flux(WL, WR, Fn);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
               const int sv = (PD == 2 && yf && (v == 1 || v == 2)) ? 3 - v : v;
@@ -371,7 +385,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
         A[k] = P0[q] + R(0.5) * S0[q];
         B[k] = P1[q] - R(0.5) * S1[q];
       }
-      hllc_ordered<R, NV>(A, B, gam, inv_gm1, Fn);
+      face_flux(A, B, Fn);
 #pragma unroll
       for (int k = 0; k < NV; ++k) Fp[wperm[k]] = Fn[k];
 #pragma unroll
