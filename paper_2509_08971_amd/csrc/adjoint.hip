@@ -111,7 +111,8 @@ __device__ __forceinline__ void hllc_vjp(const double* WL, const double* WR, dou
     v[t] = W[2 + t];
     q = q + v[t] * v[t];
   }
-  const double E = p / gm1 + 0.5 * r * q;
+  const double igm1 = 1.0 / gm1;
+  const double E = p * igm1 + 0.5 * r * q;
   const double S = left ? SL : SR;
   const double mn = r * u;
 
@@ -138,10 +139,13 @@ __device__ __forceinline__ void hllc_vjp(const double* WL, const double* WR, dou
   ub += mnb * r;
 
   if (star) {
+    // the reverse sweep makes no branch decision: it uses reciprocals formed
+    // once (within an ulp of the divisions they replace)
     const double d = S - u;
-    const double rr = d / (S - Ss);
+    const double id = 1.0 / d, iS = 1.0 / (S - Ss);
+    const double rr = d * iS;
     const double fac = r * rr;
-    const double X = r * Ss + p / d;
+    const double X = r * Ss + p * id;
     double US[NV], UK[NV];
     US[0] = fac;
     US[1] = fac * Ss;
@@ -173,12 +177,12 @@ __device__ __forceinline__ void hllc_vjp(const double* WL, const double* WR, dou
     ub -= USbE * rr * X;
     rb += Xb * Ss;
     Ssb += Xb * r;
-    pb += Xb / d;
-    db -= Xb * p / (d * d);
+    pb += Xb * id;
+    db -= Xb * p * id * id;
     rb += facb * rr;
     rrb += facb * r;
-    db += rrb / (S - Ss);
-    const double tS = -rrb * d / ((S - Ss) * (S - Ss));
+    db += rrb * iS;
+    const double tS = -rrb * d * iS * iS;
     Sb += tS;
     Ssb -= tS;
     // UK: adjoint -S Fb
@@ -196,7 +200,7 @@ __device__ __forceinline__ void hllc_vjp(const double* WL, const double* WR, dou
     ub -= db;
   }
   // E = p/(gamma-1) + r q / 2
-  pb += Eb / gm1;
+  pb += Eb * igm1;
   rb += Eb * 0.5 * q;
   const double qb = Eb * 0.5 * r;
   ub += 2.0 * u * qb;
@@ -220,8 +224,9 @@ __device__ __forceinline__ void hllc_vjp(const double* WL, const double* WR, dou
     for (int t = 0; t < NT; ++t) WRb[2 + t] += vb[t];
   }
   // S* = num / den
-  const double numb = Ssb / den;
-  const double denb = -Ssb * Ss / den;
+  const double iden = 1.0 / den;
+  const double numb = Ssb * iden;
+  const double denb = -Ssb * Ss * iden;
   pRb += numb;
   pLb -= numb;
   rLb += numb * uL * dLp;
@@ -243,10 +248,12 @@ __device__ __forceinline__ void hllc_vjp(const double* WL, const double* WR, dou
   if (pickL) { uLb += SLb; cLb -= SLb; } else { uRb += SLb; cRb -= SLb; }
   if (pickR) { uLb += SRb; cLb += SRb; } else { uRb += SRb; cRb += SRb; }
   // c = sqrt(g p / r)
-  pLb += cLb * g / (2.0 * cL * rL);
-  rLb -= cLb * g * pL / (2.0 * cL * rL * rL);
-  pRb += cRb * g / (2.0 * cR * rR);
-  rRb -= cRb * g * pR / (2.0 * cR * rR * rR);
+  // dc/dp = g / (2 c r), dc/dr = -c / (2 r) (c^2 = g p / r)
+  const double hL = cLb / (2.0 * cL * rL), hR = cRb / (2.0 * cR * rR);
+  pLb += hL * g;
+  rLb -= hL * cL * cL;
+  pRb += hR * g;
+  rRb -= hR * cR * cR;
   WLb[0] += rLb;
   WLb[1] += uLb;
   WLb[NV - 1] += pLb;
