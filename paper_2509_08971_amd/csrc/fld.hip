@@ -456,8 +456,6 @@ __global__ __launch_bounds__(256) void fld_setup(FldLevel L, FldCommon cm, const
   block_finish<256>(flags, 0.0, false, ctl, nullptr);
 }
 
-// The finest x back into the state's E_r field (rounded to float for a
-// float state).
 // fld_setup for FP64 3D states with nx a multiple of 4: four cells of a row
 // per thread (x = i0 .. i0 + 3, i0 a multiple of 4).  E and rho come as
 // 16-byte pairs, the six neighbour values per cell from the row itself, one
@@ -538,6 +536,8 @@ __global__ __launch_bounds__(256) void fld_setup_quad(FldLevel L, FldCommon cm, 
   block_finish<256>(flags, 0.0, false, ctl, nullptr);
 }
 
+// The finest x back into the state's E_r field (rounded to float for a
+// float state).
 template <int NDIM, typename R>
 __global__ __launch_bounds__(256) void fld_store(FldLevel L, R* E) {
   int p[3];
