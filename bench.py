@@ -405,9 +405,9 @@ def bench_weno(args, n=256, steps=10):
 
 def bench_rad(args, n=256, steps=20):
     """The 256^3 FP64 blast carrying the radiation energy density (uniform
-    E_r = 1, kappa = 1e-9 cm^2/g, mu = 0.6): the hydro stage kernels, the
-    Rusanov advection of E_r in both stages and the heating/cooling exchange
-    with the fused next dt."""
+    E_r = 1, kappa = 1e-9 cm^2/g, mu = 0.6): the stage kernels carrying E_r
+    as a sixth field (its Rusanov flux beside HLLC) and the heating/cooling
+    exchange with the fused next dt."""
     import paper_2509_08971_amd as H
     import workloads
 
@@ -427,18 +427,17 @@ def bench_rad(args, n=256, steps=20):
     flags = H.hard_status_read(work)
     N = n ** 3
     zus = N * steps / (ms * 1e-3)
-    # algorithmic bytes per zone-update: hydro stage 1 (read U^n, write U^1:
-    # 2 x 5 words) and stage 2 (read U^1, U^n, write: 3 x 5); E_r advection
-    # stage 1 (read 6 fields, write E_r) and stage 2 (also read E_r of U^n);
-    # exchange + next dt (read 6 fields, write E and E_r)
-    step_bytes = 8 * ((10 + 15) + (6 + 1) + (6 + 2) + (6 + 2))
+    # the kernels' own passes per zone-update: stage 1 (read U^n, write U^1:
+    # 2 x 6 words), stage 2 (read U^1 and U^n, write: 3 x 6), the exchange
+    # and next dt (read 6 fields, write E and E_r)
+    step_bytes = 8 * ((12 + 18) + (6 + 2))
     alg_bytes = 5 * 6 * 8  # the per-stage design's 5 nvar w with nvar = 6
     log(f"  {ms / steps:.3f} ms/step, {zus / 1e9:.2f} G zu/s")
     return {"value": zus, "unit": "zone-updates/s", "ms_per_step": ms / steps, "steps": steps,
             "dtype": "f64", "workload": f"3D {n}^3 FP64 point-energy blast with the radiation "
                                          f"energy density (E_r = 1, kappa = 1e-9, mu = 0.6)",
-            "roofline": {"bound": "hbm", "kernel": "whole radiation step (stage kernels, E_r "
-                                                  "advection, exchange)",
+            "roofline": {"bound": "hbm", "kernel": "whole radiation step (stage kernels "
+                                                  "carrying E_r, exchange)",
                          "achieved": alg_bytes * zus / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": alg_bytes * zus / 1e9 / HBM_PEAK_GBS,
                          "algorithmic_bytes": alg_bytes * N, "per": "step",
@@ -563,12 +562,13 @@ def bench_adjoint(args, n=512, nsteps=200, every=20):
     N = n * n
     nvar, w = 4, 8
     # algorithmic bytes per zone-update: the forward step (5 nvar w); in the
-    # backward pass the segment's forward recompute (5 nvar w), the stage-1
-    # recompute inside the adjoint call (2 nvar w), the product at U^1 (read
-    # U^1 and lam, write lam1: 3 nvar w) and at U^n (read U^n, lam1 and lam,
-    # write the new lam: 4 nvar w)
+    # backward pass the segment's forward recompute, which keeps each step's
+    # stage-1 state (5 nvar w for all but the segment's last step), the
+    # stage-1 recompute of that last step inside its adjoint call (2 nvar w),
+    # the product at U^1 (read U^1 and lam, write lam1: 3 nvar w) and at U^n
+    # (read U^n, lam1 and lam, write the new lam: 4 nvar w)
     b_fwd = 5 * nvar * w
-    b_grad = (5 + 5 + 2 + 3 + 4) * nvar * w
+    b_grad = (5 + 5 * (every - 1) / every + 2 / every + 3 + 4) * nvar * w
     ach_fwd = b_fwd * N * nsteps / fwd / 1e9
     ach_grad = b_grad * N * nsteps / full / 1e9
     # one seeded direction for the oracle's dual-number check in the CPU leg
@@ -589,8 +589,8 @@ def bench_adjoint(args, n=512, nsteps=200, every=20):
                          "algorithmic_bytes": b_grad * N * nsteps, "per": "gradient",
                          "forward_achieved": ach_fwd,
                          "traffic": measured_bytes(ADJ_COUNTERS_FILE, "adjoint", ADJ_SOURCES),
-                         "note": "8.4 MB states: cache-resident, bound by launches and the "
-                                 "adjoint's face arrays rather than by HBM"},
+                         "note": "8.4 MB states: cache-resident; the reverse sweep is "
+                                 "bound by its FP64 arithmetic rather than by HBM"},
             "dual_check": None,
             "timing": "host wall clock around the whole forward / forward+backward, after "
                       "one untimed forward+backward (allocator warm-up)"}
