@@ -3,11 +3,12 @@
 //
 // The plan cuts every problem into work items (1D: rows of 63 cells; 2D:
 // 63-cell row segments walking a range of rows; 3D: x-y tiles walking a
-// range of z planes) and lays all items of all problems out as one list,
-// most expensive first (longest-processing-time order).  Each stage is one
-// persistent launch sized to the resident capacity of the machine; workgroup
-// b runs items b, b + G, b + 2G, ... of the list (static striding: no shared
-// counter, no atomics to hand out work).  The item body is the single-grid
+// range of z planes).  Each stage is one persistent launch sized to the
+// resident capacity of the machine, and the plan deals the items to its
+// workgroups by the longest-processing-time rule: most expensive item first,
+// each to the workgroup with the least work so far.  Workgroup b runs the
+// contiguous run [start[b], start[b+1]) of the item list (no shared counter,
+// no atomics to hand out work).  The item body is the single-grid
 // tile body (stage_tile.hpp).  In stage 2 each item stores the CFL signal
 // max of its cells into its own slot; a small kernel then reduces the slots
 // of each problem into the problem's next dt.  Nothing needs clearing
@@ -20,8 +21,11 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <functional>
+#include <queue>
 #include <sstream>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hard.h"
@@ -57,6 +61,7 @@ struct BatchArgs {
   const BatchProblem* probs;
   const WorkItem* items;
   int nitems;
+  const int* start;  // stage kernels: workgroup b runs items [start[b], start[b+1])
   double* dt;        // per-problem dt (read)
   double* slot;      // per-item CFL signal max (written when the item computes it)
   Control* ctl;      // status bits
@@ -147,7 +152,8 @@ __global__ __launch_bounds__(BT12) void batched_stage_12(BatchArgs a) {
   constexpr int L2 = TileShape<2, R, ROW, 1>::lds_elems;
   __shared__ R lds[L1 > L2 ? L1 : L2];
   const bool do_cfl = STAGE == 2 && a.fuse_cfl;
-  for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+  const int i1 = a.start[blockIdx.x + 1];
+  for (int it = a.start[blockIdx.x]; it < i1; ++it) {
     const WorkItem w = a.items[it];
     const BatchProblem P = a.probs[w.prob];
     TileArgs t = tile_args(a, P, sizeof(R));
@@ -171,7 +177,8 @@ void batched_stage_3(BatchArgs a) {
   constexpr int TX = kTiles3D[TS][0], TY = kTiles3D[TS][1];
   __shared__ R lds[TileShape<3, R, TX, TY>::lds_elems];
   const bool do_cfl = STAGE == 2 && a.fuse_cfl;
-  for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+  const int i1 = a.start[blockIdx.x + 1];
+  for (int it = a.start[blockIdx.x]; it < i1; ++it) {
     const WorkItem w = a.items[it];
     const BatchProblem P = a.probs[w.prob];
     TileArgs t = tile_args(a, P, sizeof(R));
@@ -300,6 +307,8 @@ struct hard_batch_plan {
   BatchProblem* d_probs = nullptr;
   WorkItem* d_items12 = nullptr;
   WorkItem* d_items3 = nullptr;
+  int* d_start12 = nullptr;  // grid12 + 1 item offsets, one run per workgroup
+  int* d_start3 = nullptr;
   int grid12 = 0, grid3 = 0;
   // workspace layout
   size_t ws_ctl = 0, ws_active = 0, ws_slot = 0, ws_t = 0, ws_steps = 0, ws_stage = 0,
@@ -336,6 +345,36 @@ static void read_tune_cache(const char* path, hard_batch_plan* P) {
   }
 }
 
+// Longest-processing-time dealing of work items to G workgroups: the items
+// in decreasing cost (ties in list order), each to the workgroup with the
+// least cost so far (ties: the lowest index).  Returns the items grouped by
+// workgroup and the G + 1 run offsets.
+struct CostedItem {
+  double c;
+  WorkItem w;
+};
+static void deal_items(std::vector<CostedItem>& v, int G, std::vector<WorkItem>& items,
+                       std::vector<int>& start) {
+  std::stable_sort(v.begin(), v.end(),
+                   [](const CostedItem& a, const CostedItem& b) { return a.c > b.c; });
+  using Load = std::pair<double, int>;
+  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+  for (int b = 0; b < G; ++b) heap.push({0.0, b});
+  std::vector<int> owner(v.size()), count(G, 0);
+  for (size_t i = 0; i < v.size(); ++i) {
+    const Load l = heap.top();
+    heap.pop();
+    owner[i] = l.second;
+    ++count[l.second];
+    heap.push({l.first + v[i].c, l.second});
+  }
+  start.assign(G + 1, 0);
+  for (int b = 0; b < G; ++b) start[b + 1] = start[b] + count[b];
+  std::vector<int> pos(start.begin(), start.end() - 1);
+  items.resize(v.size());
+  for (size_t i = 0; i < v.size(); ++i) items[pos[owner[i]]++] = v[i].w;
+}
+
 static hard_status_t batch_common(const hard_batch_plan_t* P, const void* U, const double* dt,
                                   void* work, size_t work_bytes, BatchArgs* a) {
   if (!P) return fail(HARD_ERR_INVALID_ARG, "plan is NULL");
@@ -368,6 +407,7 @@ static hipError_t launch_batched_stage(const hard_batch_plan_t* P, BatchArgs a, 
     BatchArgs b = a;
     b.items = P->d_items12;
     b.nitems = P->nitems12;
+    b.start = P->d_start12;
     hipLaunchKernelGGL((batched_stage_12<R, STAGE>), dim3(P->grid12), dim3(BT12), 0, s, b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -376,6 +416,7 @@ static hipError_t launch_batched_stage(const hard_batch_plan_t* P, BatchArgs a, 
     BatchArgs b = a;
     b.items = P->d_items3;
     b.nitems = P->nitems3;
+    b.start = P->d_start3;
     switch (P->tile3d) {
       case 0: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 0>), dim3(P->grid3), dim3(BT3), 0, s, b); break;
       case 1: hipLaunchKernelGGL((batched_stage_3<R, STAGE, 1>), dim3(P->grid3), dim3(BT3), 0, s, b); break;
@@ -403,8 +444,7 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
   read_tune_cache(tune_cache, P);
   const int TX3 = kTiles3D[P->tile3d][0], TY3 = kTiles3D[P->tile3d][1];
   std::vector<BatchProblem> probs(nprob);
-  struct Cost { double c; WorkItem w; };
-  std::vector<Cost> c12, c3;
+  std::vector<CostedItem> c12, c3;
   P->offsets.resize(nprob + 1);
   long long off = 0, nslot = 0;
   for (int p = 0; p < nprob; ++p) {
@@ -434,25 +474,25 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
       B.inv_dx[d] = G.inv_dx[d];
     }
     B.dx_pow2 = G.dx_pow2;
-    double cells;  // cells of one work item, for the cost order
+    int nwalk;  // walk positions of the problem (1 in 1D)
     if (G.ndim == 1) {
       B.tiles_x = (G.n[0] + ROW - 1) / ROW;
       B.tiles_y = 1;
       B.walk = 1;
       B.nchunk = 1;
-      cells = ROW;
+      nwalk = 1;
     } else if (G.ndim == 2) {
       B.tiles_x = (G.n[0] + ROW - 1) / ROW;
       B.tiles_y = 1;
       B.walk = P->walk2d;
       B.nchunk = (G.n[1] + B.walk - 1) / B.walk;
-      cells = (double)ROW * std::min(B.walk, G.n[1]);
+      nwalk = G.n[1];
     } else {
       B.tiles_x = (G.n[0] + TX3 - 1) / TX3;
       B.tiles_y = (G.n[1] + TY3 - 1) / TY3;
       B.walk = P->cz;
       B.nchunk = (G.n[2] + B.walk - 1) / B.walk;
-      cells = (double)TX3 * TY3 * std::min(B.walk, G.n[2]);
+      nwalk = G.n[2];
     }
     B.ntiles = B.tiles_x * B.tiles_y * B.nchunk;
     B.slot0 = (int)nslot;
@@ -461,8 +501,16 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
       delete P;
       return fail(HARD_ERR_INVALID_ARG, "batch has more than 2^30 work items");
     }
-    const double cost = cells * G.ndim;  // faces per cell ~ ndim
-    for (int t = 0; t < B.ntiles; ++t) (G.ndim == 3 ? c3 : c12).push_back({cost, {p, t}});
+    // Cost of an item in walk positions of its tile: a wave takes a row (or
+    // a workgroup a plane) in about the same time however many of its lanes
+    // hold cells, so the cost is the positions the item walks, plus two for
+    // its set-up and prologue (four positions loaded, one face computed).
+    const int per_chunk = B.tiles_x * B.tiles_y;
+    for (int t = 0; t < B.ntiles; ++t) {
+      const int chunk = t / per_chunk;
+      const double cost = std::min(B.walk, nwalk - chunk * B.walk) + 2.0;
+      (G.ndim == 3 ? c3 : c12).push_back({cost, {p, t}});
+    }
     // keep every problem 256-byte aligned
     long long elems = (long long)G.nvar * G.ncell;
     long long align = 256 / P->wsize;
@@ -470,16 +518,8 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
   }
   P->offsets[nprob] = off;
   P->total_elems = off;
-  auto lpt = [](std::vector<Cost>& v) {
-    std::stable_sort(v.begin(), v.end(), [](const Cost& a, const Cost& b) { return a.c > b.c; });
-  };
-  lpt(c12);
-  lpt(c3);
-  std::vector<WorkItem> i12, i3;
-  for (auto& c : c12) i12.push_back(c.w);
-  for (auto& c : c3) i3.push_back(c.w);
-  P->nitems12 = (int)i12.size();
-  P->nitems3 = (int)i3.size();
+  P->nitems12 = (int)c12.size();
+  P->nitems3 = (int)c3.size();
   // persistent grids: the resident capacity of the machine for the stage-2
   // kernel (the larger register footprint), at most one workgroup per item
   int dev = 0, ncu = 256;
@@ -498,16 +538,24 @@ hard_status_t hard_batch_plan_create(const hard_grid_t* grids, int32_t nprob,
   occ3 = std::max(1, std::min(occ3, 8));
   P->grid12 = std::max(1, std::min(P->nitems12, ncu * occ12));
   P->grid3 = std::max(1, std::min(P->nitems3, ncu * occ3));
+  std::vector<WorkItem> i12, i3;
+  std::vector<int> s12, s3;
+  deal_items(c12, P->grid12, i12, s12);
+  deal_items(c3, P->grid3, i3, s3);
   hipError_t e;
   if ((e = hipMalloc(&P->d_probs, sizeof(BatchProblem) * nprob)) != hipSuccess ||
       (e = hipMalloc(&P->d_items12, sizeof(WorkItem) * std::max(1, P->nitems12))) != hipSuccess ||
-      (e = hipMalloc(&P->d_items3, sizeof(WorkItem) * std::max(1, P->nitems3))) != hipSuccess) {
+      (e = hipMalloc(&P->d_items3, sizeof(WorkItem) * std::max(1, P->nitems3))) != hipSuccess ||
+      (e = hipMalloc(&P->d_start12, sizeof(int) * (P->grid12 + 1))) != hipSuccess ||
+      (e = hipMalloc(&P->d_start3, sizeof(int) * (P->grid3 + 1))) != hipSuccess) {
     hard_batch_plan_destroy(P);
     return hip_fail(e, "hard_batch_plan_create alloc");
   }
   if ((e = hipMemcpy(P->d_probs, probs.data(), sizeof(BatchProblem) * nprob, hipMemcpyHostToDevice)) != hipSuccess ||
       (P->nitems12 && (e = hipMemcpy(P->d_items12, i12.data(), sizeof(WorkItem) * P->nitems12, hipMemcpyHostToDevice)) != hipSuccess) ||
-      (P->nitems3 && (e = hipMemcpy(P->d_items3, i3.data(), sizeof(WorkItem) * P->nitems3, hipMemcpyHostToDevice)) != hipSuccess)) {
+      (P->nitems3 && (e = hipMemcpy(P->d_items3, i3.data(), sizeof(WorkItem) * P->nitems3, hipMemcpyHostToDevice)) != hipSuccess) ||
+      (e = hipMemcpy(P->d_start12, s12.data(), sizeof(int) * (P->grid12 + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(P->d_start3, s3.data(), sizeof(int) * (P->grid3 + 1), hipMemcpyHostToDevice)) != hipSuccess) {
     hard_batch_plan_destroy(P);
     return hip_fail(e, "hard_batch_plan_create copy");
   }
@@ -529,6 +577,8 @@ hard_status_t hard_batch_plan_destroy(hard_batch_plan_t* P) {
   if (P->d_probs) (void)hipFree(P->d_probs);
   if (P->d_items12) (void)hipFree(P->d_items12);
   if (P->d_items3) (void)hipFree(P->d_items3);
+  if (P->d_start12) (void)hipFree(P->d_start12);
+  if (P->d_start3) (void)hipFree(P->d_start3);
   delete P;
   return ok();
 }
