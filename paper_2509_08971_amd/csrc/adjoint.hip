@@ -434,15 +434,17 @@ template <int NDIM>
 __device__ __forceinline__ void prim_to_cons_adjoint(const double* u, const double* wb,
                                                      double gamma, double* ub) {
   constexpr int NV = NDIM + 2;
+  // derivatives only (no branch depends on them): one reciprocal of rho
   const double rho = u[0], gm1 = gamma - 1.0;
+  const double ir = 1.0 / rho, ir2 = ir * ir;
   double q = 0.0;
 #pragma unroll
   for (int d = 0; d < NDIM; ++d) q += u[1 + d] * u[1 + d];
-  ub[0] = wb[0] + wb[NV - 1] * gm1 * 0.5 * q / (rho * rho);
+  ub[0] = wb[0] + wb[NV - 1] * gm1 * 0.5 * q * ir2;
 #pragma unroll
   for (int d = 0; d < NDIM; ++d) {
-    ub[0] -= wb[1 + d] * u[1 + d] / (rho * rho);
-    ub[1 + d] = wb[1 + d] / rho - wb[NV - 1] * gm1 * u[1 + d] / rho;
+    ub[0] -= wb[1 + d] * u[1 + d] * ir2;
+    ub[1 + d] = wb[1 + d] * ir - wb[NV - 1] * gm1 * u[1 + d] * ir;
   }
   ub[NV - 1] = wb[NV - 1] * gm1;
 }
@@ -522,7 +524,10 @@ __global__ __launch_bounds__(256) void adj_tile(const double* __restrict__ X,
   constexpr int TX = AdjTileShape<NDIM>::TX, TY = AdjTileShape<NDIM>::TY;
   constexpr int SX = TX + 7, SY = TY + 7;         // face slots per line and axis
   constexpr int NIX = TY * SX, NIY = NDIM == 2 ? TX * SY : 0;
-  constexpr int NI = NIX + NIY;
+  // the y items start on a wave boundary, so that no wave computes faces of
+  // both axes (the two face routines would run one after the other)
+  constexpr int NIXP = (NIX + 63) / 64 * 64;
+  constexpr int NI = NIXP + NIY;
   constexpr int NL = NDIM == 1 ? 1 : (TX > TY ? TX : TY);  // lines per axis, at most
   __shared__ double acc[NV][TY][TX];
   __shared__ double gbuf[NDIM][NL][6][NV];
@@ -541,11 +546,12 @@ __global__ __launch_bounds__(256) void adj_tile(const double* __restrict__ X,
   // f along the axis; false if the item carries no face
   auto item = [&](int i, int& ax, int& line, int& f, bool& own) -> bool {
     int slot, t0, T, nd, nother, origin_other;
-    if (i < NIX) {
+    if (i < NIXP) {
+      if (i >= NIX) return false;
       ax = 0; line = i / SX; slot = i % SX;
       t0 = x0; T = TX; nd = nx; nother = ny; origin_other = y0;
     } else {
-      const int k = i - NIX;
+      const int k = i - NIXP;
       ax = 1; line = k % TX; slot = k / TX;
       t0 = y0; T = TY; nd = ny; nother = nx; origin_other = x0;
     }
