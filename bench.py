@@ -173,6 +173,19 @@ def _time_steps(fn, steps, stream):
     return a.elapsed_time(b)
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate on this GPU (GB/s, bytes read plus bytes
+    written), the median of `reps` timed copies of `nbytes` after one warm-up:
+    the practical streaming ceiling beside the published HBM peak."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    stream = torch.cuda.current_stream()
+    times = sorted(_time_steps(lambda: b.copy_(a), 1, stream) for _ in range(reps))
+    del a, b
+    return 2 * nbytes / (times[len(times) // 2] * 1e-3) / 1e9
+
+
 def _time_stages(g, U, U1, dt, work, steps, stream):
     """Times `steps` Heun steps as stage-1 + stage-2 launches (fused next dt)
     with HIP events on the launch stream around each launch; returns (ms per
@@ -859,6 +872,8 @@ def main():
     step_gbs = (b_stage1 + b_stage2) / (ms_per_step * 1e-3) / 1e9
     traffic = measured_traffic() if n == 256 else None
     valu = measured_valu() if n == 256 else None
+    copy_gbs = copy_bandwidth()
+    log(f"  device copy {copy_gbs:.0f} GB/s; stage 2 at {ach2 / copy_gbs:.2f} of it")
 
     out = {
         "metric": "zone-updates/s",
@@ -880,6 +895,14 @@ def main():
         "frac_step": step_gbs / HBM_PEAK_GBS,
         "target_frac": TARGET_FRAC,
         "ms_per_step_100_steps": ms100 if ms100 is not None else ms_per_step,
+        # the same rates against the copy rate measured on this GPU, and the
+        # step against the strict lower bound of both stages blocked in time
+        # (read U^n, write U^{n+1}: 2 nvar w per zone-update)
+        "copy_gbs": copy_gbs,
+        "frac_of_copy_stage2": ach2 / copy_gbs,
+        "frac_of_copy_step": step_gbs / copy_gbs,
+        "temporal_bound_bytes_per_zone_update": 2 * nvar * w,
+        "frac_step_at_temporal_bound": zus * 2 * nvar * w / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": "stage_kernel<3,double,2> (stage 2)",
                      "achieved": ach2, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach2 / HBM_PEAK_GBS,
