@@ -366,6 +366,101 @@ def test_turbulent_512_fp32_full_size_sampled():
         assert rel <= TOL32, (v, rel)
 
 
+def random_state_torch(n, seed, dtype=torch.float64):
+    """Random positive state on the device (rho, p in [0.3, 1.5], |u| < 0.25),
+    array order (nvar, n_z, n_y, n_x); drawn with torch's seeded generator."""
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(seed)
+    shape = tuple(reversed(n))
+    nd = len(n)
+    U = torch.empty((nd + 2,) + shape, dtype=dtype, device=DEV)
+    rho = 0.3 + 1.2 * torch.rand(shape, generator=gen, dtype=torch.float64, device=DEV)
+    ke = torch.zeros(shape, dtype=torch.float64, device=DEV)
+    U[0] = rho
+    for d in range(nd):
+        u = 0.5 * torch.rand(shape, generator=gen, dtype=torch.float64, device=DEV) - 0.25
+        U[1 + d] = rho * u
+        ke += 0.5 * rho * u * u
+        del u
+    p = 0.3 + 1.2 * torch.rand(shape, generator=gen, dtype=torch.float64, device=DEV)
+    U[nd + 1] = p / (workloads.GAMMA - 1.0) + ke
+    return U
+
+
+# long, tall and thin grids, and a 3D FP64 grid whose fields lie more than
+# 4 GiB apart (545 M cells: byte offsets of fields 1..4 beyond 2^32)
+EXTREME = [
+    ((1 << 24,), (O, O)),
+    ((64, 1 << 18), (P, P, R, R)),
+    ((2, 3, 1 << 20), (R, R, P, P, O, O)),
+    ((1024, 1024, 520), (P, P, R, R, O, O)),
+]
+
+
+@pytest.mark.parametrize("n,bc", EXTREME)
+def test_extreme_shapes_sampled(n, bc):
+    """One FP64 step (hard_hydro_step with the fused dt) on grids at the far
+    ends of the accepted shapes, checked on sampled cells: a cell's new value
+    depends only on the cells within 4 of it, so the oracle steps a window
+    around each sample -- 9 cells along an axis (wrapped on periodic axes,
+    centres at least 4 cells from non-periodic walls), or the whole axis
+    with its own boundaries when it has at most 9 cells -- and the window's
+    copy of the sample must match to 1e-12 of the field's largest sampled
+    value."""
+    log(f"extreme shape {n} bc {bc}")
+    nd = len(n)
+    U = random_state_torch(n, seed=23)
+    U0 = U.clone()
+    g = H.make_grid(n, bc=bc)
+    work = H.workspace(H.hard_workspace_bytes(g))
+    dt = torch.zeros(1, dtype=torch.float64, device=DEV)
+    H.hard_cfl_dt(g, U, 0.4, dt, work)
+    dtv = dt.item()
+    H.hard_hydro_step(g, U, dt, work, cfl=0.4, next_dt_dev=dt)
+    torch.cuda.synchronize()
+    assert H.hard_status_read(work) == 0
+    assert math.isfinite(dt.item()) and dt.item() > 0.0
+    rng = np.random.default_rng(29)
+    got, ref = [], []
+    for _ in range(24):
+        idx, wbc, centre = [], [], []
+        for d in range(nd):
+            nn, lo, hi = n[d], bc[2 * d], bc[2 * d + 1]
+            if nn <= 9:
+                idx.append(np.arange(nn))
+                wbc += [lo, hi]
+                centre.append(int(rng.integers(0, nn)))
+            else:
+                if lo == P:
+                    c = int(rng.integers(0, nn))
+                else:
+                    c = int(rng.integers(4, nn - 4))
+                idx.append((c + np.arange(-4, 5)) % nn)
+                wbc += [O, O]
+                centre.append(4)
+        win = U0
+        # gather the window axis by axis (array axes are reversed: x last)
+        for d in range(nd):
+            ax = 1 + (nd - 1 - d)
+            win = torch.index_select(win, ax, torch.from_numpy(idx[d]).to(DEV))
+        win = win.cpu().numpy()
+        wshape = tuple(len(i) for i in idx)
+        og = oracle.Grid(wshape, bc=tuple(wbc), dx=tuple(1.0 / nn for nn in n))
+        out, st = oracle.step(og, win, dtv)
+        assert st == 0
+        pos = tuple(reversed(centre))
+        ref.append(out[(slice(None),) + pos])
+        gidx = tuple(int(idx[d][centre[d]]) for d in reversed(range(nd)))
+        got.append(U[(slice(None),) + gidx].cpu().numpy())
+    got, ref = np.array(got), np.array(ref)
+    for v in range(nd + 2):
+        scale = np.abs(ref[:, v]).max()
+        err = np.abs(got[:, v] - ref[:, v]).max() / scale
+        assert err <= TOL64, (v, err)
+    del U, U0, work
+    torch.cuda.empty_cache()
+
+
 def test_single_grid_step_graph_replay():
     """hard_hydro_step (with the fused next dt) captured in a graph: every
     replay equals the same steps run eagerly, bit for bit, with eager work
