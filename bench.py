@@ -611,8 +611,9 @@ def bench_adjoint(args, n=512, nsteps=200, every=20):
 
 def bench_riemann(args, n=1024, t_end=0.2, reps=5):
     """The 1D two-state Riemann problem (1024 cells, FP64, seed 0, outflow,
-    CFL 0.4) run to t = 0.2 with the device time loop: wall time of the whole
-    run (launch-latency bound) and zone-updates/s."""
+    CFL 0.4) run to t = 0.2 with hard_run, whose loop runs in one resident
+    workgroup for a grid this small: wall time of the whole run and
+    zone-updates/s."""
     import paper_2509_08971_amd as H
     import workloads
 
@@ -635,8 +636,8 @@ def bench_riemann(args, n=1024, t_end=0.2, reps=5):
             "steps": steps, "t_final": t, "dtype": "f64",
             "workload": f"1D two-state Riemann problem, {n} cells, seed 0, outflow, CFL 0.4, "
                         f"to t = {t_end}",
-            "timing": f"median of {reps} host wall-clock runs of hard_run (device time loop, "
-                      f"host sync every 64 steps)"}
+            "timing": f"median of {reps} host wall-clock runs of hard_run (the whole time "
+                      f"loop in one resident workgroup, up to 1024 steps per launch)"}
 
 
 def phys_cores():

@@ -190,8 +190,11 @@ hard_status_t hard_hydro_stage(const hard_grid_t* g, int32_t stage, const void* 
  * t_end - t); stops when t >= t_end (1 - 1e-14) or after max_steps steps.
  * The loop runs on the device in batches (t, dt and the stop flag live in
  * the workspace; steps after the end are exact no-ops with dt = 0); the host
- * synchronises once per batch.  Writes the final t and the number of steps
- * taken; returns HARD_ERR_NONPHYSICAL if the status word has bits set. */
+ * synchronises once per batch.  A 1D MUSCL-HLLC grid of at most 2048 cells
+ * without radiation runs the loop in one resident workgroup, up to 1024
+ * steps per launch, with the same result bit for bit.  Writes the final t
+ * and the number of steps taken; returns HARD_ERR_NONPHYSICAL if the status
+ * word has bits set. */
 hard_status_t hard_run(const hard_grid_t* g, void* U, double cfl, double t_end, int64_t max_steps,
                        double* t_out, int64_t* steps_out, void* work, size_t work_bytes,
                        void* stream);

@@ -396,8 +396,33 @@ hard_status_t hard_run(const hard_grid_t* g, void* U, double cfl, double t_end,
                       ctl, reinterpret_cast<double*>(static_cast<char*>(work) + L.slots), L.nslots,
                       s)) != hipSuccess)
     return hip_fail(e, "hard_run cfl");
-  const int batch = 64;
   int done = 0;
+  if (G.ndim == 1 && G.n[0] <= RUN1D_MAX && G.scheme == HARD_SCHEME_MUSCL_HLLC && !G.rad) {
+    // small 1D grids: the whole loop in one resident workgroup, 1024 steps
+    // per launch
+    Run1dArgs r;
+    std::memset(&r, 0, sizeof r);
+    r.U = U;
+    r.n = G.n[0];
+    r.bc[0] = G.bc[0][0];
+    r.bc[1] = G.bc[0][1];
+    r.dx = G.dx[0];
+    r.inv_dx = G.inv_dx[0];
+    r.dx_pow2 = G.dx_pow2;
+    r.gamma = G.gamma;
+    r.cfl = cfl;
+    r.t_end = t_end;
+    r.max_steps = max_steps;
+    r.chunk = 1024;
+    r.ctl = ctl;
+    while (!done) {
+      if ((e = launch_run1d(G.dtype, r, s)) != hipSuccess) return hip_fail(e, "hard_run 1D loop");
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hard_run sync");
+      if ((e = hipMemcpy(&done, &ctl->done, sizeof done, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hard_run read");
+    }
+  }
+  const int batch = 64;
   while (!done) {
     for (int i = 0; i < batch; ++i) {
       if ((e = launch_time_control(ctl, t_end, max_steps, s)) != hipSuccess)

@@ -91,6 +91,24 @@ struct RadArgs {
 
 hipError_t launch_rad_source(int ndim, int dtype, const RadArgs& a, hipStream_t s);
 
+// The time loop of hard_run for 1D grids of at most RUN1D_MAX cells in one
+// workgroup (run1d.hip): up to `chunk` steps per launch; t, steps, the next
+// dt, done and the status bits carried in the control block.
+constexpr int RUN1D_THREADS = 1024;
+constexpr int RUN1D_MAX = 2 * RUN1D_THREADS;
+struct Run1dArgs {
+  void* U;
+  int n;
+  int bc[2];
+  double dx, inv_dx;
+  int dx_pow2;
+  double gamma, cfl, t_end;
+  long long max_steps;
+  int chunk;
+  Control* ctl;
+};
+hipError_t launch_run1d(int dtype, const Run1dArgs& a, hipStream_t s);
+
 // Standalone CFL dt (reads U once).
 hipError_t launch_cfl(int ndim, int dtype, const int* n, const double* dx, const double* inv_dx,
                       int dx_pow2, double gamma, const void* U, double cfl, double* dt,
