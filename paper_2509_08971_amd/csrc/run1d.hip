@@ -59,15 +59,17 @@ __global__ __launch_bounds__(RUN1D_THREADS) void run1d_kernel(Run1dArgs a) {
         flags |= cell_flags<R, NV>(Src[k], P[NV - 1]);
 #pragma unroll
         for (int v = 0; v < NV; ++v) W[v][c + 2] = P[v];
-      }
-    }
-    __syncthreads();
-    if (tid < 4) {  // ghost cells -2, -1, n, n+1 from their source cells
-      const int q = tid < 2 ? tid - 2 : n + tid - 2;
-      bool flip;
-      const int s = remap(q, n, a.bc[0], a.bc[1], flip);
+        if (c < 2 || c >= n - 2) {
+          // the ghost cells -2, -1, n, n+1 whose source this cell is
+          for (int gi = 0; gi < 4; ++gi) {
+            const int q = gi < 2 ? gi - 2 : n + gi - 2;
+            bool flip;
+            if (remap(q, n, a.bc[0], a.bc[1], flip) != c) continue;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) W[v][q + 2] = (v == 1 && flip) ? -W[v][s + 2] : W[v][s + 2];
+            for (int v = 0; v < NV; ++v) W[v][q + 2] = (v == 1 && flip) ? -P[v] : P[v];
+          }
+        }
+      }
     }
     __syncthreads();
     for (int f = tid; f <= n; f += NT) {
@@ -94,8 +96,9 @@ __global__ __launch_bounds__(RUN1D_THREADS) void run1d_kernel(Run1dArgs a) {
         }
       }
     }
-    // W and F are rewritten by the next stage
-    __syncthreads();
+    // no barrier here: the next stage writes W, whose last reads came before
+    // the barrier above, and F only after its own first barrier, which every
+    // thread passes after this update
   };
 
   for (int it = 0; it < a.chunk; ++it) {
@@ -134,7 +137,7 @@ __global__ __launch_bounds__(RUN1D_THREADS) void run1d_kernel(Run1dArgs a) {
 #pragma unroll
     for (int i = 0; i < NT / 64; ++i) m = fmax(m, red[i]);
     dtn = a.cfl / m;
-    __syncthreads();  // red is rewritten by the next step
+    // red is written again only after the next step's four barriers
   }
 
 #pragma unroll
