@@ -47,9 +47,10 @@ void stage_kernel(StageArgs a) {
   t.dt = *a.dt;
   t.x0 = tile_x * TX;
   t.y0 = tile_y * TY;
+  constexpr bool WALK = TileShape<NDIM, R, TX, TY, RAD>::WALK;
   const int nwalk = NDIM == 3 ? a.n[2] : (NDIM == 2 ? a.n[1] : 1);
-  t.w0 = NDIM >= 2 ? chunk * a.cz : 0;
-  t.w1 = NDIM >= 2 ? min(t.w0 + a.cz, nwalk) : 1;
+  t.w0 = WALK ? chunk * a.cz : 0;
+  t.w1 = WALK ? min(t.w0 + a.cz, nwalk) : 1;
   t.fuse_cfl = STAGE == 2 && a.fuse_cfl;
   unsigned flags = 0;
   double smax = 0.0;
@@ -66,11 +67,12 @@ void stage_kernel(StageArgs a) {
 template <int NDIM, int TX, int TY>
 static long long stage_shape(const int* n, int cz_in, int cz_default, int& tiles_x, int& tiles_y,
                              int& cz) {
+  constexpr bool walk = NDIM == 3 || (NDIM == 2 && TY == 1);
   tiles_x = (n[0] + TX - 1) / TX;
-  tiles_y = NDIM == 3 ? (n[1] + TY - 1) / TY : 1;
+  tiles_y = (NDIM == 3 || TY > 1) ? (n[1] + TY - 1) / TY : 1;
   long long nchunk = 1;
   cz = 1;
-  if (NDIM >= 2) {
+  if (walk) {
     const int nwalk = NDIM == 3 ? n[2] : n[1];
     cz = cz_in > 0 ? cz_in : cz_default;
     nchunk = (nwalk + cz - 1) / cz;
@@ -126,9 +128,19 @@ static int chunk_2d(int nx, int ny, int tx) {
   return (int)(c < 4 ? 4 : (c > 64 ? 64 : c));
 }
 
+// 2D grids of at most PLANE_2D_MAX cells: 32 x 8 tiles that do not walk
+// (one workgroup per tile, four waves, every face of the tile from LDS).  The
+// walk cuts such a grid into a few hundred workgroups of one or two waves,
+// each stepping through a handful of rows.
+#ifndef HARD_PLANE_2D_MAX
+#define HARD_PLANE_2D_MAX (1 << 20)
+#endif
+constexpr long long PLANE_2D_MAX = HARD_PLANE_2D_MAX;
+
 template <typename R>
 static hipError_t launch_stage_2d(const StageArgs& a, int stage, hipStream_t s) {
   const int nx = a.n[0], ny = a.n[1];
+  if ((long long)nx * ny <= PLANE_2D_MAX) return launch_stage_t<2, R, 32, 8, 256>(a, stage, 1, s);
   if (nx >= 1024) return launch_stage_t<2, R, 255, 1, 256>(a, stage, chunk_2d(nx, ny, 255), s);
   if (nx >= 256) return launch_stage_t<2, R, 127, 1, 128>(a, stage, chunk_2d(nx, ny, 127), s);
   return launch_stage_t<2, R, 63, 1, 64>(a, stage, chunk_2d(nx, ny, 63), s);
@@ -140,6 +152,7 @@ long long stage_launch_blocks(int ndim, int dtype, const int* n) {
   switch (ndim) {
     case 1: return stage_shape<1, 255, 1>(n, cz, 1, tx, ty, c);
     case 2:
+      if ((long long)n[0] * n[1] <= PLANE_2D_MAX) return stage_shape<2, 32, 8>(n, cz, 1, tx, ty, c);
       if (n[0] >= 1024) return stage_shape<2, 255, 1>(n, cz, chunk_2d(n[0], n[1], 255), tx, ty, c);
       if (n[0] >= 256) return stage_shape<2, 127, 1>(n, cz, chunk_2d(n[0], n[1], 127), tx, ty, c);
       return stage_shape<2, 63, 1>(n, cz, chunk_2d(n[0], n[1], 63), tx, ty, c);

@@ -4,7 +4,9 @@
 //
 // A tile is a plane of cells held in LDS that walks along the last axis:
 //   1D: a row of TX cells in x (no walk);
-//   2D: a row of TX cells in x walking along y over [w0, w1);
+//   2D: a row of TX cells in x walking along y over [w0, w1) (TY = 1), or a
+//       TX x TY tile in x-y that does not walk (TY > 1: small grids, which
+//       the walk would cut into too few waves);
 //   3D: a TX x TY tile in x-y walking along z over [w0, w1).
 // For each position of the walk it
 //   1. puts the primitive states of the plane plus a two-cell halo in LDS
@@ -65,7 +67,8 @@ template <int NDIM, typename R, int TX, int TY, bool RAD = false>
 struct TileShape {
   static constexpr int NH = NDIM + 2;            // hydro fields
   static constexpr int NV = NH + (RAD ? 1 : 0);  // fields carried through the tile
-  static constexpr int PD = NDIM == 3 ? 2 : 1;  // dimensions of the plane in LDS
+  static constexpr int PD = (NDIM == 3 || TY > 1) ? 2 : 1;  // dimensions of the plane in LDS
+  static constexpr bool WALK = NDIM == 3 || (NDIM == 2 && TY == 1);
   static constexpr int LX = TX + 4;
   static constexpr int LY = PD == 2 ? TY + 4 : 1;
   static constexpr int LXY = LX * LY;
@@ -75,9 +78,9 @@ struct TileShape {
   static constexpr int NHALO = PD == 2 ? 4 * (TX + TY) : 4;
   // FP64 3D: the flux through the face below each cell along the walk axis
   // lives in LDS instead of registers (10 VGPRs fewer at the peak)
-  static constexpr bool FZ_LDS = PD == 2 && sizeof(R) == 8;
+  static constexpr bool FZ_LDS = WALK && PD == 2 && sizeof(R) == 8;
   static constexpr int lds_elems = NV * (LXY + NF) + (FZ_LDS ? NV * TX * TY : 0);
-  static_assert(PD == 2 || TY == 1, "1D and 2D planes are one row");
+  static_assert(NDIM >= 2 || TY == 1, "1D planes are one row");
 };
 
 // Runs one tile; ORs status bits into `flags` and maxes the CFL signal sum of
@@ -91,7 +94,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
   using S = TileShape<NDIM, R, TX, TY, RAD>;
   constexpr int NV = S::NV, NH = S::NH, PD = S::PD, LX = S::LX, LXY = S::LXY;
   constexpr int NFX = S::NFX, NF = S::NF, NHALO = S::NHALO;
-  constexpr bool WALK = NDIM >= 2;
+  constexpr bool WALK = S::WALK;
   constexpr int WA = NDIM - 1;          // walk axis
   constexpr int OY = PD == 2 ? 2 : 0;   // LDS row of the tile's first row
   constexpr int NT = NTHR;
