@@ -119,6 +119,20 @@ static hipError_t launch_stage_t(const StageArgs& a0, int stage, int cz_default,
 #endif
 constexpr int STAGE_CZ_3D = HARD_STAGE_CZ_3D;
 
+// z planes per workgroup of a 3D grid: STAGE_CZ_3D, halved while the launch
+// would have fewer than about 1500 workgroups, down to 4 (each chunk loads
+// four planes beyond its own).  Per step on periodic boxes (FP64, us), cz =
+// 32 / 16 / 8 / 4: 64^3 198 / 107 / 62 / 39; 128^3 228 / 179 / 177 / 179;
+// 192^3 563 / 508 / 521 / 539; 256^3 1045 / 1060 / 1078 / 1144.
+template <int TX, int TY>
+static int chunk_3d(const int* n) {
+  const long long tiles = (long long)((n[0] + TX - 1) / TX) * ((n[1] + TY - 1) / TY);
+  const long long want = tiles * n[2] / 1536;
+  int cz = STAGE_CZ_3D;
+  while (cz > 4 && cz > want) cz >>= 1;
+  return cz;
+}
+
 // 2D grids: rows of 255, 127 or 63 cells (one face per thread per row) and
 // enough walk chunks to give the machine a few thousand workgroups.
 static int chunk_2d(int nx, int ny, int tx) {
@@ -157,8 +171,8 @@ long long stage_launch_blocks(int ndim, int dtype, const int* n) {
       if (n[0] >= 256) return stage_shape<2, 127, 1>(n, cz, chunk_2d(n[0], n[1], 127), tx, ty, c);
       return stage_shape<2, 63, 1>(n, cz, chunk_2d(n[0], n[1], 63), tx, ty, c);
     default:
-      return dtype == 0 ? stage_shape<3, HARD_TILE64>(n, cz, STAGE_CZ_3D, tx, ty, c)
-                        : stage_shape<3, HARD_TILE32>(n, cz, STAGE_CZ_3D, tx, ty, c);
+      return dtype == 0 ? stage_shape<3, HARD_TILE64>(n, cz, chunk_3d<HARD_TILE64>(n), tx, ty, c)
+                        : stage_shape<3, HARD_TILE32>(n, cz, chunk_3d<HARD_TILE32>(n), tx, ty, c);
   }
 }
 
@@ -167,13 +181,13 @@ hipError_t launch_stage(int ndim, int dtype, const StageArgs& a, int stage, hipS
     switch (ndim) {
       case 1: return launch_stage_t<1, double, 255, 1, 256>(a, stage, 1, s);
       case 2: return launch_stage_2d<double>(a, stage, s);
-      case 3: return launch_stage_t<3, double, HARD_TILE64, 256>(a, stage, STAGE_CZ_3D, s);
+      case 3: return launch_stage_t<3, double, HARD_TILE64, 256>(a, stage, chunk_3d<HARD_TILE64>(a.n), s);
     }
   } else {
     switch (ndim) {
       case 1: return launch_stage_t<1, float, 255, 1, 256>(a, stage, 1, s);
       case 2: return launch_stage_2d<float>(a, stage, s);
-      case 3: return launch_stage_t<3, float, HARD_TILE32, 256>(a, stage, STAGE_CZ_3D, s);
+      case 3: return launch_stage_t<3, float, HARD_TILE32, 256>(a, stage, chunk_3d<HARD_TILE32>(a.n), s);
     }
   }
   return hipErrorInvalidValue;
