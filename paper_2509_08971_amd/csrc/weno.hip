@@ -195,17 +195,21 @@ __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
     idx = (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (idx >= nface) return;
   }
+  // the face count of an axis is below 2^32 (fewer than 2^31 cells), so the
+  // index splits in 32-bit unsigned arithmetic
   if constexpr (AX == 0) {
-    f = (int)(idx % (nx + 1));
-    long long r = idx / (nx + 1);
-    j = (int)(r % ny);
-    k = (int)(r / ny);
+    const unsigned u = (unsigned)idx, mx = (unsigned)nx + 1u;
+    f = (int)(u % mx);
+    const unsigned r = u / mx;
+    j = (int)(r % (unsigned)ny);
+    k = (int)(r / (unsigned)ny);
     i = 0;
   } else if constexpr (AX == 1) {
-    i = (int)(idx % nx);
-    long long r = idx / nx;
-    f = (int)(r % (ny + 1));
-    k = (int)(r / (ny + 1));
+    const unsigned u = (unsigned)idx, my = (unsigned)ny + 1u;
+    i = (int)(u % (unsigned)nx);
+    const unsigned r = u / (unsigned)nx;
+    f = (int)(r % my);
+    k = (int)(r / my);
     j = 0;
   }
   const R* W = static_cast<const R*>(a.W);
@@ -254,12 +258,13 @@ __global__ __launch_bounds__(256) void weno_update(WenoArgs a) {
   const long long N = (long long)nx * ny * nz;
   const bool fuse = STAGE == 2 && a.fuse_cfl;
   double smax = 0.0;
-  // grid-stride with a bounded grid: one pair of CFL atomics per workgroup
+  // grid-stride with a bounded grid: one CFL slot per workgroup
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
        c += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(c % nx);
-    const long long r = c / nx;
-    const int j = (int)(r % ny), k = (int)(r / ny);
+    // fewer than 2^31 cells: the cell index splits in 32-bit unsigned arithmetic
+    const unsigned cu = (unsigned)c, r = cu / (unsigned)nx;
+    const int i = (int)(cu % (unsigned)nx);
+    const int j = (int)(r % (unsigned)ny), k = (int)(r / (unsigned)ny);
     const R* src = static_cast<const R*>(a.src);
     const R* un = static_cast<const R*>(a.un);
     R* dst = static_cast<R*>(a.dst);
@@ -325,9 +330,10 @@ __global__ __launch_bounds__(256) void weno_update_pair(WenoArgs a) {
   double smax = 0.0;
   for (long long c = 2 * ((long long)blockIdx.x * blockDim.x + threadIdx.x); c < N;
        c += 2 * (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(c % nx);
-    const long long r = c / nx;
-    const int j = (int)(r % ny), k = (int)(r / ny);
+    // fewer than 2^31 cells: the cell index splits in 32-bit unsigned arithmetic
+    const unsigned cu = (unsigned)c, r = cu / (unsigned)nx;
+    const int i = (int)(cu % (unsigned)nx);
+    const int j = (int)(r % (unsigned)ny), k = (int)(r / (unsigned)ny);
     const long long fx = ((long long)k * ny + j) * (nx + 1) + i;
     const long long fy = ((long long)k * (ny + 1) + j) * nx + i;
     const long long fz = c;
