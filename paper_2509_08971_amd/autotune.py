@@ -4,7 +4,7 @@ Times hard_hydro_step_batched on the caller's own set of grids for each
 candidate setting and writes the fastest to a tune-cache text file that
 hard_batch_plan_create reads, one "key = value" per line:
 
-  walk2d = 32          rows per 2D work item
+  walk2d = 64          rows per 2D work item
   tile3d_f64 = 16x16   x-y tile of 3D problems (tile3d_f32 for float)
   cz = 32              planes per 3D work item
 
@@ -26,7 +26,7 @@ TILES_3D = ("16x16", "32x8", "8x32")
 
 def default_candidates(dtype):
     k3 = "tile3d_f64" if dtype == torch.float64 else "tile3d_f32"
-    return {"walk2d": ("16", "32", "64"), k3: TILES_3D, "cz": ("16", "32", "64")}
+    return {"walk2d": ("32", "64", "128"), k3: TILES_3D, "cz": ("16", "32", "64")}
 
 
 def _time_setting(grids, states, dtype, setting, steps, cfl, device):

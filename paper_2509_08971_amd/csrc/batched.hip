@@ -299,7 +299,7 @@ struct hard_batch_plan {
   double gamma = 0;
   int wsize = 8;
   int tile3d = 0;   // index into kTiles3D (x-y tile of 3D problems)
-  int walk2d = 32;  // rows per 2D work item
+  int walk2d = 64;  // rows per 2D work item
   int cz = 32;      // planes per 3D work item
   std::vector<int64_t> offsets;
   long long total_elems = 0;
@@ -318,7 +318,7 @@ struct hard_batch_plan {
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Tile choices from a tune cache, lines "key = value":
-//   walk2d = 32          rows per 2D work item
+//   walk2d = 64          rows per 2D work item
 //   tile3d_f64 = 16x16   x-y tile of 3D problems (tile3d_f32 for float)
 //   cz = 32              planes per 3D work item
 static void read_tune_cache(const char* path, hard_batch_plan* P) {
