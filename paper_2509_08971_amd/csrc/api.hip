@@ -175,29 +175,6 @@ hipError_t launch_scheme_stage(const Grid& G, const WorkLayout& L, char* wb, con
   return launch_weno_stage(G.ndim, G.dtype, w, stage, s);
 }
 
-// Radiation arguments of a stage from the hydro stage arguments.
-RadArgs rad_args(const Grid& G, const StageArgs& a) {
-  RadArgs r;
-  std::memset(&r, 0, sizeof r);
-  r.dst = a.dst;
-  r.dt = a.dt;
-  for (int d = 0; d < 3; ++d) {
-    r.n[d] = a.n[d];
-    r.dx[d] = a.dx[d];
-    r.inv_dx[d] = a.inv_dx[d];
-  }
-  r.dx_pow2 = a.dx_pow2;
-  r.gamma = a.gamma;
-  r.kappa = G.kappa;
-  r.mu = G.mu;
-  r.cfl = a.cfl;
-  r.ctl = a.ctl;
-  r.next_dt = a.next_dt;
-  r.slots = a.slots;
-  r.nslots = a.nslots;
-  return r;
-}
-
 int stage_cz_override() {
   static int v = [] {
     const char* e = std::getenv("HARD_STAGE_CZ");
@@ -299,6 +276,8 @@ hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_de
   a.nslots = L.nslots;
   a.cz = stage_cz_override();
   a.rad = G.rad;  // E_r is advected by the same stage kernels
+  a.kappa = G.kappa;
+  a.mu = G.mu;
   void* U1 = wb + L.stage;
   // stage 1: U1 = U + dt L(U)
   a.src = U;
@@ -307,21 +286,17 @@ hard_status_t hard_hydro_step(const hard_grid_t* g, void* U, const double* dt_de
   a.fuse_cfl = 0;
   hipError_t e = launch_scheme_stage(G, L, wb, a, 1, s);
   if (e != hipSuccess) return hip_fail(e, "hard_hydro_step stage 1");
-  // stage 2: U = (U + (U1 + dt L(U1))) / 2, optionally with the next dt
-  // (with radiation the next dt comes after the exchange instead)
+  // stage 2: U = (U + (U1 + dt L(U1))) / 2, with radiation followed cell by
+  // cell by the heating/cooling exchange, optionally with the next dt (of
+  // the state after the exchange)
   a.src = U1;
   a.un = U;
   a.dst = U;
-  a.fuse_cfl = next_dt_dev != nullptr && !G.rad;
+  a.fuse_cfl = next_dt_dev != nullptr;
+  a.exchange = G.rad;
   a.next_dt = next_dt_dev;
   e = launch_scheme_stage(G, L, wb, a, 2, s);
   if (e != hipSuccess) return hip_fail(e, "hard_hydro_step stage 2");
-  if (G.rad) {
-    RadArgs r = rad_args(G, a);
-    r.fuse_cfl = next_dt_dev != nullptr;
-    if ((e = launch_rad_source(G.ndim, G.dtype, r, s)) != hipSuccess)
-      return hip_fail(e, "hard_hydro_step radiation exchange");
-  }
   return ok();
 }
 

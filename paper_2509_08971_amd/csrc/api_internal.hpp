@@ -46,8 +46,6 @@ hard_status_t check_work(void* work, size_t have, size_t need);
 hard_status_t check_cfl(double cfl);
 WorkLayout layout_of(const Grid& g);
 struct StageArgs;
-struct RadArgs;
-RadArgs rad_args(const Grid& G, const StageArgs& a);
 hipError_t launch_scheme_stage(const Grid& G, const WorkLayout& L, char* wb, const StageArgs& a,
                                int stage, hipStream_t s);
 

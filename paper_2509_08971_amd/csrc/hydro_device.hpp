@@ -272,6 +272,69 @@ __device__ __forceinline__ void hllc_ordered(const R* WL, const R* WR, R gam, R 
   hllc<R, NT>(WL[0], WL[1], utL, WL[NV - 1], WR[0], WR[1], utR, WR[NV - 1], gam, inv_gm1, F);
 }
 
+// Heating and cooling of the radiation field (section 2.2.1, the heating
+// rate qdot = c kappa rho (E_r - a T^4)) over one step: backward Euler for the
+// fluid temperature, solved by Newton iterations from an upper bound; plain
+// IEEE arithmetic, so the iteration count and result are those of a plain
+// evaluation.  CGS constants (CODATA 2018): speed of light, radiation
+// constant a = 4 sigma/c, Boltzmann constant, atomic mass unit.
+constexpr double RC_LIGHT = 2.99792458e10;
+constexpr double RA_RAD = 4.0 * 5.670374419e-5 / 2.99792458e10;
+constexpr double RK_B = 1.380649e-16;
+constexpr double RM_U = 1.66053906660e-24;
+
+// Backward-Euler exchange of one cell; returns the new (E_fluid, E_r).
+// e + E_r is conserved; the kinetic energy is untouched.
+__device__ __forceinline__ void exchange(double rho, double ke, double& Ef, double& Er, double dt,
+                                         double gamma, double kappa, double mu) {
+#pragma clang fp contract(off)
+  const double q = RC_LIGHT * kappa * rho;
+  const double dq = dt * q;
+  if (!(dq > 0.0)) return;
+  const double e = Ef - ke;
+  const double Cv = rho * RK_B / (mu * RM_U * (gamma - 1.0));
+  const double W = e + Er;
+  const double t1 = W / Cv;
+  const double t2 = sqrt(sqrt((W * (1.0 + dq) - Er) / (dq * RA_RAD)));
+  double T = t1 < t2 ? t1 : t2;
+  for (int it = 0; it < 200; ++it) {
+    const double T3 = T * T * T;
+    const double f = Cv * T + (Er + dq * RA_RAD * (T3 * T)) / (1.0 + dq) - W;
+    const double fp = Cv + 4.0 * dq * RA_RAD * T3 / (1.0 + dq);
+    const double Tn = T - f / fp;
+    if (!(Tn < T)) break;
+    T = Tn;
+  }
+  const double e_new = Cv * T;
+  Ef = Ef + (e_new - e);
+  Er = W - e_new;
+}
+
+// The exchange applied to one new cell state U (conserved, as stored,
+// E_r in field NDIM + 2): in double on the stored values, the kinetic energy
+// from the momenta; changed energies are rounded back to R.  Returns the
+// status bits (non-finite energies).
+template <typename R, int NDIM>
+__device__ __forceinline__ unsigned exchange_cell(R* U, double dt, double gamma, double kappa,
+                                                  double mu) {
+#pragma clang fp contract(off)
+  constexpr int NH = NDIM + 2;
+  const double rho = (double)U[0];
+  double m2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < NDIM; ++k) {
+    const double m = (double)U[1 + k];
+    m2 = k == 0 ? m * m : m2 + m * m;
+  }
+  const double ke = 0.5 * m2 / rho;
+  double Ef = (double)U[NH - 1], Er = (double)U[NH];
+  const double Ef0 = Ef, Er0 = Er;
+  exchange(rho, ke, Ef, Er, dt, gamma, kappa, mu);
+  if (Ef != Ef0) U[NH - 1] = R(Ef);
+  if (Er != Er0) U[NH] = R(Er);
+  return (!isfinite(Er) || !isfinite(Ef)) ? FLAG_NONFINITE : 0u;
+}
+
 // Wave64 reductions
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll

@@ -24,6 +24,9 @@ struct StageArgs {
   int tiles_x, tiles_y;  // filled by the launcher
   int cz;                // walk positions per workgroup (z in 3D, y in 2D), 0 = default
   int rad;               // 1: field ndim + 2 is E_r, advected in the same pass
+  int exchange;          // stage 2 with rad: the heating/cooling exchange of each
+                         // new cell state before it is stored (and before its CFL)
+  double kappa, mu;      // opacity and mean molecular weight (exchange)
   Control* ctl;          // workspace control block
   double* next_dt;       // fused CFL output (stage 2)
   double* slots;         // fused CFL: one signal-sum max per workgroup
@@ -68,28 +71,6 @@ struct WenoArgs {
 };
 
 hipError_t launch_weno_stage(int ndim, int dtype, const WenoArgs& a, int stage, hipStream_t s);
-
-// Radiation energy density (rad.hip): the exchange with the fluid after
-// stage 2 (with the fused next dt).  The advection of E_r runs in the stage
-// kernels (StageArgs::rad).
-struct RadArgs {
-  void* dst;          // the state after the step, updated in place
-  const double* dt;
-  int n[3];
-  double dx[3];
-  double inv_dx[3];
-  int dx_pow2;
-  double gamma;
-  double kappa, mu;
-  double cfl;
-  int fuse_cfl;
-  Control* ctl;
-  double* next_dt;
-  double* slots;
-  int nslots;
-};
-
-hipError_t launch_rad_source(int ndim, int dtype, const RadArgs& a, hipStream_t s);
 
 // The time loop of hard_run for 1D grids of at most RUN1D_MAX cells in one
 // workgroup (run1d.hip): up to `chunk` steps per launch; t, steps, the next

@@ -52,6 +52,9 @@ void stage_kernel(StageArgs a) {
   t.w0 = WALK ? chunk * a.cz : 0;
   t.w1 = WALK ? min(t.w0 + a.cz, nwalk) : 1;
   t.fuse_cfl = STAGE == 2 && a.fuse_cfl;
+  t.exchange = STAGE == 2 && RAD && a.exchange;
+  t.kappa = a.kappa;
+  t.mu = a.mu;
   unsigned flags = 0;
   double smax = 0.0;
   run_tile<NDIM, R, STAGE, TX, TY, NTHR, NDIM == 3, RAD>(t, lds, flags, smax);

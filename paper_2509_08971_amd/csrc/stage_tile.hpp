@@ -41,6 +41,9 @@ struct TileArgs {
   int x0, y0;       // tile origin (y0: 3D only)
   int w0, w1;       // walk range (y in 2D, z in 3D; [0, 1) in 1D)
   int fuse_cfl;     // stage 2: accumulate the CFL signal max of the output
+  int exchange;     // stage 2 with RAD: the heating/cooling exchange of each
+                    // new cell state before it is stored
+  double kappa, mu;
 };
 
 // Streams that no other workgroup reads again within the launch -- the
@@ -411,6 +414,11 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
         } else {
           Out[v] = R(0.5) * (Un0[v] + (Ucur[v] + dt * l));
         }
+      }
+      // RAD, stage 2: the heating/cooling exchange of the new state before
+      // it is stored (and before its CFL signal)
+      if constexpr (RAD && STAGE == 2) {
+        if (a.exchange) flags |= exchange_cell<R, NDIM>(Out, a.dt, a.gamma, a.kappa, a.mu);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) stream_store<NTS>(dst + v * N + cidx, Out[v]);
