@@ -240,15 +240,22 @@ __global__ __launch_bounds__(NTHR) void batched_cfl(BatchArgs a, int tx3, int ty
   }
 }
 
-// dt of every problem from its items' slots: cfl / max(slot).
-__global__ void batched_dt_final(int nprob, const BatchProblem* probs, const double* slot,
-                                 double cfl, double* dt) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nprob) return;
+// dt of every problem from its items' slots: cfl / max(slot), one wave per
+// problem (a problem's slots are contiguous; the max does not depend on the
+// order it is taken in).
+constexpr int DT_FINAL_THREADS = 256;
+__global__ __launch_bounds__(DT_FINAL_THREADS) void batched_dt_final(int nprob,
+                                                                     const BatchProblem* probs,
+                                                                     const double* slot,
+                                                                     double cfl, double* dt) {
+  const int p = blockIdx.x * (DT_FINAL_THREADS / 64) + (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (p >= nprob) return;  // the whole wave
   const int s0 = probs[p].slot0, ns = probs[p].ntiles;
   double m = 0.0;
-  for (int i = 0; i < ns; ++i) m = fmax(m, slot[s0 + i]);
-  dt[p] = cfl / m;
+  for (int i = lane; i < ns; i += 64) m = fmax(m, slot[s0 + i]);
+  m = wave_max(m);
+  if (lane == 0) dt[p] = cfl / m;
 }
 
 // Per-problem time control of hard_run_batched: clip dt so each problem
@@ -394,8 +401,9 @@ static hard_status_t batch_common(const hard_batch_plan_t* P, const void* U, con
 
 static hipError_t launch_dt_final(const hard_batch_plan_t* P, const BatchArgs& a, double cfl,
                                   hipStream_t s) {
-  const int nb = (P->nprob + 255) / 256;
-  hipLaunchKernelGGL(batched_dt_final, dim3(nb), dim3(256), 0, s, P->nprob,
+  constexpr int per_block = DT_FINAL_THREADS / 64;
+  const int nb = (P->nprob + per_block - 1) / per_block;
+  hipLaunchKernelGGL(batched_dt_final, dim3(nb), dim3(DT_FINAL_THREADS), 0, s, P->nprob,
                      (const BatchProblem*)P->d_probs, (const double*)a.slot, cfl, a.dt);
   return hipGetLastError();
 }
