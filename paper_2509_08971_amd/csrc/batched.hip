@@ -128,6 +128,9 @@ __device__ __forceinline__ TileArgs tile_args(const BatchArgs& a, const BatchPro
   }
   t.dx_pow2 = P.dx_pow2;
   t.gamma = a.gamma;
+  t.exchange = 0;  // batched problems carry no radiation field
+  t.kappa = 0.0;
+  t.mu = 1.0;
   return t;
 }
 
