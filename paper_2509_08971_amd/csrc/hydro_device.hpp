@@ -386,8 +386,7 @@ __device__ __forceinline__ double signal_sum(const double* U, const double* dx,
 // plain IEEE evaluation (so dt equals that of a plain evaluation bit for
 // bit).  FP32 states: the same formula in double with the refined
 // reciprocal of rho and the refined reciprocal square root, within about
-// 1e-15 relative of the IEEE value for a third of the FP64 instructions
-// (which in the FP32 kernels issue at half the FP32 rate).
+// 1e-15 relative of the IEEE value for a third of the FP64 instructions.
 template <typename R, int NDIM>
 __device__ __forceinline__ double cfl_signal(const double* U, const double* dx,
                                              const double* inv_dx, int dx_pow2, double gamma) {
