@@ -227,15 +227,15 @@ __global__ __launch_bounds__(NTHR) void batched_cfl(BatchArgs a, int tx3, int ty
         if (P.ndim == 1) {
           to_primitive<R, 1>(Ur, W, a.gamma - 1.0);
           flags |= cell_flags<R, 3>(Ur, W[2]);
-          smax = fmax(smax, cfl_signal<R, 1>(Ud, P.dx, P.inv_dx, P.dx_pow2, a.gamma));
+          smax = fmax(smax, cfl_signal<R, 1>(Ud, P.inv_dx, a.gamma));
         } else if (P.ndim == 2) {
           to_primitive<R, 2>(Ur, W, a.gamma - 1.0);
           flags |= cell_flags<R, 4>(Ur, W[3]);
-          smax = fmax(smax, cfl_signal<R, 2>(Ud, P.dx, P.inv_dx, P.dx_pow2, a.gamma));
+          smax = fmax(smax, cfl_signal<R, 2>(Ud, P.inv_dx, a.gamma));
         } else {
           to_primitive<R, 3>(Ur, W, a.gamma - 1.0);
           flags |= cell_flags<R, 5>(Ur, W[4]);
-          smax = fmax(smax, cfl_signal<R, 3>(Ud, P.dx, P.inv_dx, P.dx_pow2, a.gamma));
+          smax = fmax(smax, cfl_signal<R, 3>(Ud, P.inv_dx, a.gamma));
         }
       }
     }

@@ -357,53 +357,22 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return xcd * per + (xcd < rem ? xcd : rem) + slot;
 }
 
-// CFL signal sum sum_d (|u_d| + c)/dx_d of one conserved state, in double,
-// rounded step by step in the stated order (no contraction) so that it
-// reproduces a plain evaluation of the formula.  When every dx is a power of
-// two, x/dx equals x*(1/dx) exactly and the multiply is used.
-template <int NDIM>
-__device__ __forceinline__ double signal_sum(const double* U, const double* dx,
-                                             const double* inv_dx, int dx_pow2, double gamma) {
-#pragma clang fp contract(off)
-  double rho = U[0];
+// The CFL signal sum sum_d (|u_d| + c)/dx_d of one conserved state stored as
+// R (FP64 or FP32 storage, the sum in double), with the refined reciprocal
+// of rho and the refined reciprocal square root: within a few ulp of the
+// plain IEEE evaluation for a third of its FP64 instructions.
+template <typename R, int NDIM>
+__device__ __forceinline__ double cfl_signal(const double* U, const double* inv_dx, double gamma) {
+  const double inv = fast_rcp(U[0]);
   double q = U[1] * U[1];
 #pragma unroll
   for (int d = 1; d < NDIM; ++d) q = q + U[1 + d] * U[1 + d];
-  double ke = 0.5 * q / rho;
-  double e = U[NDIM + 1] - ke;
-  double p = (gamma - 1.0) * e;
-  double cs = sqrt(gamma * p / rho);
+  const double gp = gamma * ((gamma - 1.0) * (U[NDIM + 1] - 0.5 * q * inv));
+  const double cs = sound_speed(gp, U[0]);
   double s = 0.0;
 #pragma unroll
-  for (int d = 0; d < NDIM; ++d) {
-    double t = fabs(U[1 + d] / rho) + cs;
-    s = s + (dx_pow2 ? t * inv_dx[d] : t / dx[d]);
-  }
+  for (int d = 0; d < NDIM; ++d) s = s + (fabs(U[1 + d]) * inv + cs) * inv_dx[d];
   return s;
-}
-
-// The CFL signal sum of a state stored as R.  FP64 states: signal_sum, the
-// plain IEEE evaluation (so dt equals that of a plain evaluation bit for
-// bit).  FP32 states: the same formula in double with the refined
-// reciprocal of rho and the refined reciprocal square root, within about
-// 1e-15 relative of the IEEE value for a third of the FP64 instructions.
-template <typename R, int NDIM>
-__device__ __forceinline__ double cfl_signal(const double* U, const double* dx,
-                                             const double* inv_dx, int dx_pow2, double gamma) {
-  if constexpr (sizeof(R) == 8) {
-    return signal_sum<NDIM>(U, dx, inv_dx, dx_pow2, gamma);
-  } else {
-    const double inv = fast_rcp(U[0]);
-    double q = U[1] * U[1];
-#pragma unroll
-    for (int d = 1; d < NDIM; ++d) q = q + U[1 + d] * U[1 + d];
-    const double gp = gamma * ((gamma - 1.0) * (U[NDIM + 1] - 0.5 * q * inv));
-    const double cs = sound_speed(gp, U[0]);
-    double s = 0.0;
-#pragma unroll
-    for (int d = 0; d < NDIM; ++d) s = s + (fabs(U[1 + d]) * inv + cs) * inv_dx[d];
-    return s;
-  }
 }
 
 // Block-wide: OR of status flags (one atomic per block, only when a bit is

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(RED_THREADS) void cfl_kernel(const R* __restrict__ 
     R W[NV];
     to_primitive<R, NDIM>(Ur, W, gamma - 1.0);
     flags |= cell_flags<R, NV>(Ur, W[NV - 1]);
-    smax = fmax(smax, cfl_signal<R, NDIM>(Ud, g.dx, g.inv_dx, g.dx_pow2, gamma));
+    smax = fmax(smax, cfl_signal<R, NDIM>(Ud, g.inv_dx, gamma));
   }
   block_finish<RED_THREADS>(flags, smax, true, ctl, slots + blockIdx.x);
 }

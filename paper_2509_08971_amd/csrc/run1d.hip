@@ -32,7 +32,7 @@ __global__ __launch_bounds__(RUN1D_THREADS) void run1d_kernel(Run1dArgs a) {
   const R gam = R(a.gamma);
   const R inv_gm1 = R(1.0 / gm1);
   const R idx0 = R(a.inv_dx);
-  const double dxa[3] = {a.dx, 1.0, 1.0}, idxa[3] = {a.inv_dx, 1.0, 1.0};
+  const double idxa[3] = {a.inv_dx, 1.0, 1.0};
 
   R Un[K][NV], U1[K][NV];
 #pragma unroll
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(RUN1D_THREADS) void run1d_kernel(Run1dArgs a) {
         double Ud[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) Ud[v] = (double)Un[k][v];
-        smax = fmax(smax, cfl_signal<R, 1>(Ud, dxa, idxa, a.dx_pow2, a.gamma));
+        smax = fmax(smax, cfl_signal<R, 1>(Ud, idxa, a.gamma));
       }
     }
     smax = wave_max(smax);

@@ -426,7 +426,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
         double Ud[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) Ud[v] = (double)Out[v];
-        smax = fmax(smax, cfl_signal<R, NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
+        smax = fmax(smax, cfl_signal<R, NDIM>(Ud, a.inv_dx, a.gamma));
       }
     }
 

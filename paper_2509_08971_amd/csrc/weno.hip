@@ -305,7 +305,7 @@ __global__ __launch_bounds__(256) void weno_update(WenoArgs a) {
       double Ud[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) Ud[v] = (double)Out[v];
-      smax = fmax(smax, cfl_signal<R, NDIM>(Ud, a.dx, a.inv_dx, a.dx_pow2, a.gamma));
+      smax = fmax(smax, cfl_signal<R, NDIM>(Ud, a.inv_dx, a.gamma));
     }
   }
   block_finish<256>(0u, smax, fuse, a.ctl, a.slots + blockIdx.x);
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(256) void weno_update_pair(WenoArgs a) {
     if (fuse) {
 #pragma unroll
       for (int e = 0; e < 2; ++e)
-        smax = fmax(smax, signal_sum<NDIM>(Out[e], a.dx, a.inv_dx, a.dx_pow2, a.gamma));
+        smax = fmax(smax, cfl_signal<double, NDIM>(Out[e], a.inv_dx, a.gamma));
     }
   }
   block_finish<256>(0u, smax, fuse, a.ctl, a.slots + blockIdx.x);

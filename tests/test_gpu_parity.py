@@ -2,10 +2,10 @@
 
 Tolerances: FP64 per field max|g - o| / max|o| <= 1e-12; FP32 bulk per field
 sum|g - o| / sum|o| <= 1e-5 against the FP64 oracle run on the same
-(float-rounded) input.  dt: the standalone GPU CFL step equals the oracle's
-bit for bit on the same input (both evaluate the same operations with IEEE
-division and square root and no contraction), and so does the CFL step
-fused into stage 2.
+(float-rounded) input.  dt: the GPU's CFL signal takes refined reciprocals
+where the oracle divides, so the standalone GPU CFL step is within DT_TOL
+(a few ulp) of the oracle's on the same input, and the CFL step fused into
+stage 2 equals the standalone one bit for bit.
 """
 import math
 
@@ -25,6 +25,7 @@ P, O, R = 0, 1, 2
 DEV = "cuda"
 TOL64 = 1e-12
 TOL32 = 1e-5
+DT_TOL = 4e-15  # relative; the largest deviation seen is 1.05e-15 (about 5 ulp)
 
 
 def log(*a):
@@ -90,7 +91,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("n,bc", CASES)
-def test_cfl_dt_bitwise(n, bc):
+def test_cfl_dt_vs_oracle(n, bc):
     log("cfl", n, bc)
     U0 = random_state(n, 1)
     g = H.make_grid(n, bc=bc)
@@ -100,7 +101,7 @@ def test_cfl_dt_bitwise(n, bc):
     got = H.hard_cfl_dt(g, U, 0.4, dt, work, want_host=True)
     ref, st = oracle.cfl_dt(oracle.Grid(n, bc=bc), U0, 0.4)
     assert st == 0
-    assert got == ref, (got, ref)
+    assert abs(got - ref) <= DT_TOL * ref, (got, ref)
 
 
 @pytest.mark.parametrize("n,bc", CASES)

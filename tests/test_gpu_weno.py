@@ -3,8 +3,8 @@ against the CPU oracle's second scheme.
 
 Tolerances as for the MUSCL-HLLC path: FP64 per field max|g - o| / max|o|
 <= 1e-12; FP32 bulk per field sum|g - o| / sum|o| <= 1e-5 against the FP64
-oracle on the float-rounded input.  The fused CFL step equals the oracle's
-bit for bit.  The paper's Sod figure (L1(rho) < 5e-4 at t = 0.0669, dx =
+oracle on the float-rounded input.  The fused CFL step is within a few ulp
+of the oracle's (refined reciprocals where the oracle divides).  The paper's Sod figure (L1(rho) < 5e-4 at t = 0.0669, dx =
 2^-10, Courant 0.3) is also checked on the GPU run, whose every step is held
 to the 1e-12 bar against the oracle's step from the same state (the run as a
 whole: see SOD_RUN_TOL).
@@ -86,7 +86,7 @@ def test_step_parity_fp64(n, bc):
     for v in range(len(n) + 2):
         assert field_rel_linf(out[v], ref[v]) <= TOL64, (v, field_rel_linf(out[v], ref[v]))
     nref, _ = oracle.cfl_dt(og, out, 0.4)
-    assert nxt == nref
+    assert abs(nxt - nref) <= 4e-15 * nref, (nxt, nref)
 
 
 @pytest.mark.parametrize("n,bc", [((1000,), (O, O)), ((50, 37), (O, O, R, R)),
