@@ -86,8 +86,8 @@ typedef int32_t hard_status_t;
  * Each Heun stage advects E_r with the fluid velocity through the local
  * Lax-Friedrichs (Rusanov) flux of its MUSCL-minmod face states (section
  * 2.2.2), with the signal speed max(|u_L| + c_L, |u_R| + c_R) of the hydro
- * face states; E_r does not act on the hydro fields.  After stage 2 every
- * cell exchanges energy between the fluid and the radiation by the heating
+ * face states; E_r does not act on the hydro fields.  Stage 2 then lets every
+ * new cell state exchange energy between the fluid and the radiation by the heating
  * rate qdot = c kappa rho (E_r - a T^4) (equation "heating-cooling"), T =
  * (gamma - 1) e mu m_u / (rho k_B), integrated by backward Euler (Newton on
  * the new temperature; e + E_r is conserved); the fused next dt is that of
@@ -134,8 +134,9 @@ hard_status_t hard_workspace_init(void* work, size_t work_bytes, void* stream);
 
 /* CFL time step (section 3.5; the formula is this library's reading):
  *     dt = cfl / max_i sum_d (|u_{d,i}| + c_i) / dx_d
- * over the interior cells of U, c = sqrt(gamma p / rho).  Writes dt to the
- * device double *dt_dev.  If dt_host is not NULL the call synchronises the
+ * over the interior cells of U, c = sqrt(gamma p / rho), evaluated in double
+ * with refined reciprocals of rho and of the square root (within a few ulp
+ * of a plain IEEE evaluation).  Writes dt to the device double *dt_dev.  If dt_host is not NULL the call synchronises the
  * stream, copies dt to *dt_host and returns HARD_ERR_NONPHYSICAL if the
  * status word has any bit set.  0 < cfl <= 1. */
 hard_status_t hard_cfl_dt(const hard_grid_t* g, const void* U, double cfl, double* dt_dev,
