@@ -284,6 +284,11 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
     }
     if (inside) flags |= cell_flags<R, NV>(Ucur, P0[NH - 1]);
     __syncthreads();
+    // The in-plane faces are the phase every wave of the workgroup waits on
+    // at the next barrier: they issue at a raised priority over the waves of
+    // the other workgroups on the SIMD, which are between barriers of their
+    // own (measured 1.4% faster per FP64 step, 0.8% FP32).
+    __builtin_amdgcn_s_setprio(2);
 
     // ---- 2. in-plane faces.  Each owner thread takes the low x face of
     // its cell (and, in 3D, the low y face); the far faces (x = TX of every
@@ -377,6 +382,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, R* lds, unsigned& fl
       }
     }
 
+    __builtin_amdgcn_s_setprio(0);
     // ---- 3. face w+1/2 from the register window
     R Fp[NV];
     R P2[NV];
