@@ -522,12 +522,18 @@ __global__ __launch_bounds__(256) void adj_tile(const double* __restrict__ X,
                                                 const double* lam1, double c1, double* out) {
   constexpr int NV = NDIM + 2;
   constexpr int TX = AdjTileShape<NDIM>::TX, TY = AdjTileShape<NDIM>::TY;
-  constexpr int SX = TX + 7, SY = TY + 7;         // face slots per line and axis
-  constexpr int NIX = TY * SX, NIY = NDIM == 2 ? TX * SY : 0;
-  // the y items start on a wave boundary, so that no wave computes faces of
-  // both axes (the two face routines would run one after the other)
-  constexpr int NIXP = (NIX + 63) / 64 * 64;
-  constexpr int NI = NIXP + NIY;
+  // own faces t0 - 1 .. t0 + T + 1 of every line, x items then y items, then
+  // the far-end faces (four per line and axis), which only tiles at a grid
+  // edge iterate.  Each region starts on a wave boundary, so that no wave
+  // computes faces of both axes (the two face routines would run one after
+  // the other) and interior tiles issue no lane for a far-end slot.
+  constexpr int OX = TX + 3, OY = TY + 3;
+  constexpr int NOX = TY * OX, NOY = NDIM == 2 ? TX * OY : 0;
+  constexpr int NOXP = (NOX + 63) / 64 * 64;
+  constexpr int NOWN = NOXP + NOY;
+  constexpr int FAR0 = (NOWN + 63) / 64 * 64;
+  constexpr int NFX = TY * 4, NFXP = (NFX + 63) / 64 * 64, NFY = NDIM == 2 ? TX * 4 : 0;
+  constexpr int NI = FAR0 + NFXP + NFY;
   constexpr int NL = NDIM == 1 ? 1 : (TX > TY ? TX : TY);  // lines per axis, at most
   __shared__ double acc[NV][TY][TX];
   __shared__ double gbuf[NDIM][NL][6][NV];
@@ -545,14 +551,29 @@ __global__ __launch_bounds__(256) void adj_tile(const double* __restrict__ X,
   // the face of item i: axis, line (row y or column x of the tile), face index
   // f along the axis; false if the item carries no face
   auto item = [&](int i, int& ax, int& line, int& f, bool& own) -> bool {
-    int slot, t0, T, nd, nother, origin_other;
-    if (i < NIXP) {
-      if (i >= NIX) return false;
-      ax = 0; line = i / SX; slot = i % SX;
+    int slot;
+    if (i < FAR0) {
+      if (i < NOXP) {
+        if (i >= NOX) return false;
+        ax = 0; line = i / OX; slot = i % OX;
+      } else {
+        const int k = i - NOXP;
+        if (k >= NOY) return false;
+        ax = 1; line = k % TX; slot = k / TX;
+      }
+    } else if (i < FAR0 + NFXP) {
+      const int k = i - FAR0;
+      if (k >= NFX) return false;
+      ax = 0; line = k / 4; slot = OX + k % 4;
+    } else {
+      const int k = i - FAR0 - NFXP;
+      if (k >= NFY) return false;
+      ax = 1; line = k % TX; slot = OY + k / TX;
+    }
+    int t0, T, nd, nother, origin_other;
+    if (ax == 0) {
       t0 = x0; T = TX; nd = nx; nother = ny; origin_other = y0;
     } else {
-      const int k = i - NIXP;
-      ax = 1; line = k % TX; slot = k / TX;
       t0 = y0; T = TY; nd = ny; nother = nx; origin_other = x0;
     }
     if (origin_other + line >= nother) return false;
@@ -581,11 +602,16 @@ __global__ __launch_bounds__(256) void adj_tile(const double* __restrict__ X,
     return need;
   };
 
-  for (int base = 0; base < NI; base += 256) {
+  // a ghost's source cell is one of 0, 1, nd - 2, nd - 1: only a tile that
+  // holds one of them (along either axis) has far-end faces to compute
+  bool edge = x0 < 2 || x0 + TX > nx - 2;
+  if constexpr (NDIM == 2) edge = edge || y0 < 2 || y0 + TY > ny - 2;
+  const int ni = edge ? NI : NOWN;
+  for (int base = 0; base < ni; base += 256) {
     const int i = base + tid;
     int ax = 0, line = 0, f = 0;
     bool own = false;
-    const bool has = i < NI && item(i, ax, line, f, own);
+    const bool has = i < ni && item(i, ax, line, f, own);
     double Cb[4][NV];
     if (has) {
       if (ax == 0) face_vjp<NDIM, 0>(X, mu, scale, g, 0, y0 + line, 0, f, Cb);
@@ -604,9 +630,13 @@ __global__ __launch_bounds__(256) void adj_tile(const double* __restrict__ X,
         for (int v = 0; v < NV; ++v) gbuf[ax][line][k][v] = Cb[s][v];
       }
     }
-    // direct contributions, round by round
+    // direct contributions, round by round; the rounds of an axis with no
+    // own item in this batch are skipped (uniform over the workgroup)
+    const bool xr = base < NOX;
+    const bool yr = NDIM == 2 && base + 256 > NOXP && base < NOXP + NOY;
 #pragma unroll
     for (int r = 0; r < 4 * NDIM; ++r) {
+      if (!(r < 4 ? xr : yr)) continue;
       if (has && own && ax == r / 4 && (f & 3) == (r & 3)) {
         const int nd = g.n[ax], t0 = ax == 0 ? x0 : y0, T = ax == 0 ? TX : TY;
 #pragma unroll
@@ -623,6 +653,10 @@ __global__ __launch_bounds__(256) void adj_tile(const double* __restrict__ X,
       __syncthreads();
     }
   }
+
+  // the last batch may have run no round: its ghost contributions must be
+  // visible before the folds
+  __syncthreads();
 
   // ghost folds, then the conserved adjoint of this thread's cell
   const int gx = x0 + lx, gy = y0 + ly;
