@@ -3,17 +3,23 @@
 // (Harten, Lax and van Leer 1983; Davis wave speeds), inside the same Heun
 // stages as the MUSCL-HLLC path.  Three ghost layers per side.
 //
-// This path is a plain pipeline per stage, not the fused tile kernel:
+// This path is a pipeline per stage, not the fused tile kernel:
 //   weno_prim    one thread per cell: primitives W of the stage source into
 //                the workspace (and the status bits);
-//   weno_face    one thread per face, one launch per axis: six W cells along
-//                the axis (ghosts by index remap), WENO5-Z left and right
-//                states, HLL flux into a per-axis face array;
-//   weno_update  grid-stride over the cells: L(U) = -sum_d (F+ - F-)/dx_d in the order
-//                x, y, z, the stage combine, and in stage 2 the fused CFL step.
+//   weno_face    one thread per face, one launch per axis (x, and y in 2D and
+//                3D): six W cells along the axis (ghosts by index remap),
+//                WENO5-Z left and right states, HLL flux into a per-axis
+//                face array;
+//   weno_update  (1D, 2D) grid-stride over the cells: L(U) = -sum_d
+//                (F+ - F-)/dx_d in the order x, y, the stage combine, and in
+//                stage 2 the fused CFL step;
+//   weno_zwalk   (3D) the z faces and the update in one pass: each thread
+//                walks a z column, computes the z faces from a register
+//                window of W and updates each cell with the x and y fluxes
+//                from their arrays; no z face array exists.
 // Bytes per cell and stage: the fused MUSCL kernel moves 2-3 nvar words; this
-// pipeline about 6 + 4 ndim nvar words (W and the face arrays round-trip
-// through memory).
+// pipeline 2 + 2 (ndim - 1) + 5 (+ 1 in stage 2) nvar words in 3D (W and the
+// x and y face arrays round-trip through memory).
 //
 // Arithmetic: the face kernels are bound by FP64 instruction issue (about
 // 1100 VALU instructions per face, 0.8 of issue busy), so the WENO5-Z
@@ -23,8 +29,6 @@
 // plain IEEE division, no contraction, in the order of the formulas.  On the
 // paper's Sod run (503 steps) every step stays within 5e-16 of the oracle's
 // step from the same state and the whole run within 1e-11.
-
-#include <type_traits>
 
 #include "hydro_device.hpp"
 #include "launch.hpp"
@@ -164,18 +168,11 @@ __global__ __launch_bounds__(256) void weno_prim(WenoArgs a) {
   if ((threadIdx.x & 63) == 0 && flags) atomicOr(&a.ctl->flags, flags);
 }
 
-// Faces along axis AX: face f (0..n_AX) lies between cells f-1 and f.
-// Linear face index (the layout of the face array), x fastest: AX = 0:
-// (f, j, k); AX = 1: (i, f, k); AX = 2: (i, j, f).
-//
-// Along x and y a block takes 256 consecutive faces of that layout: the six
-// cells of a face lie in its own row or plane, which the L2 holds.  Along z
-// they lie in six planes, and in layout order a W plane is needed again
-// about six planes of work later (16 MB at 256^2 cells a plane, beyond one
-// XCD's 4 MB L2), so the z faces go by tile columns instead: a block takes
-// a 64 x 4 (i, j) tile of one face plane, and the blocks of one tile column
-// follow each other plane by plane.
-constexpr int WENO_ZTX = 64, WENO_ZTY = 4;
+// Faces along axis AX (x or y): face f (0..n_AX) lies between cells f-1 and
+// f.  Linear face index (the layout of the face array), x fastest: AX = 0:
+// (f, j, k); AX = 1: (i, f, k).  A block takes 256 consecutive faces of that
+// layout: the six cells of a face lie in its own row or plane, which the L2
+// holds.  The z faces are computed inside weno_zwalk.
 
 template <typename R, int NDIM, int AX>
 __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
@@ -183,22 +180,10 @@ __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const long long N = (long long)nx * ny * nz;
   const long long nface = N / a.n[AX] * (a.n[AX] + 1);
-  long long idx;
+  static_assert(AX < 2, "z faces are computed by weno_zwalk");
   int i, j, k, f;
-  if constexpr (AX == 2) {
-    const long long b = xcd_tile(blockIdx.x, gridDim.x);
-    const int tx = (nx + WENO_ZTX - 1) / WENO_ZTX;
-    f = (int)(b % (nz + 1));
-    const long long r = b / (nz + 1);
-    i = (int)(r % tx) * WENO_ZTX + (int)(threadIdx.x % WENO_ZTX);
-    j = (int)(r / tx) * WENO_ZTY + (int)(threadIdx.x / WENO_ZTX);
-    k = 0;
-    if (i >= nx || j >= ny) return;
-    idx = ((long long)f * ny + j) * nx + i;
-  } else {
-    idx = (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (idx >= nface) return;
-  }
+  const long long idx = (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (idx >= nface) return;
   // the face count of an axis is below 2^32 (fewer than 2^31 cells), so the
   // index splits in 32-bit unsigned arithmetic
   if constexpr (AX == 0) {
@@ -223,7 +208,7 @@ __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
   for (int s = 0; s < 6; ++s) {
     bool flip;
     const int q = remap(f - 3 + s, a.n[AX], a.bc[AX][0], a.bc[AX][1], flip);
-    const int ii = AX == 0 ? q : i, jj = AX == 1 ? q : j, kk = AX == 2 ? q : k;
+    const int ii = AX == 0 ? q : i, jj = AX == 1 ? q : j, kk = k;
     const long long cell = ((long long)kk * ny + jj) * nx + ii;
 #pragma unroll
     for (int v = 0; v < NV; ++v) c[s][v] = W[v * N + cell];
@@ -311,73 +296,112 @@ __global__ __launch_bounds__(256) void weno_update(WenoArgs a) {
   block_finish<256>(0u, smax, fuse, a.ctl, a.slots + blockIdx.x);
 }
 
-// weno_update for FP64 3D grids with nx even: two cells of a row per thread
-// (x = i, i + 1 with i even) and 16-byte loads of the cell-centred arrays and
-// of the y and z face arrays (a pair of x faces rows of nx + 1 is not always
-// 16-byte aligned, so the three x faces come as 8-byte loads).  The update
-// loads every word once and the L1 data path, not HBM, bounded the one-cell
-// form: 18 accesses per field and two cells there, 10 here.  Per cell the
-// arithmetic is weno_update's, in the same order.
-template <int STAGE>
-__global__ __launch_bounds__(256) void weno_update_pair(WenoArgs a) {
-#pragma clang fp contract(off)
+
+// 3D: the z faces fused into the stage update.  A work unit is a 64 x 4
+// (i, j) tile of columns and a chunk of WENO_ZCHUNK cells along z; each
+// thread walks its column with the six cells of the current z face in a
+// register window (one new cell loaded per face) and carries the flux of
+// the face below the current cell from the previous position, so no z face
+// array goes through memory (the face at a chunk's upper end is computed by
+// both chunks that share it).  The x and y face fluxes come from their
+// arrays.  The face arithmetic is weno_face's and the update's
+// weno_update's, in the same order.  Grid-stride over the units, one CFL
+// slot per workgroup.  Against a z face kernel plus a separate update: 4.44
+// against 5.27 ms per step of the 256^3 blast, the same bits; chunks of 16
+// or 64 cells 4.62 and 4.52 ms, loading the next window cell one face ahead
+// 4.48 ms.
+constexpr int WENO_ZTX = 64, WENO_ZTY = 4, WENO_ZCHUNK = 32;
+
+template <typename R, int STAGE>
+__global__ __launch_bounds__(256) void weno_zwalk(WenoArgs a, long long units) {
   constexpr int NDIM = 3, NV = 5;
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-  const long long N = (long long)nx * ny * nz;
+  const long long N = (long long)nx * ny * nz, NXY = (long long)nx * ny;
   const bool fuse = STAGE == 2 && a.fuse_cfl;
-  const double* src = static_cast<const double*>(a.src);
-  const double* un = static_cast<const double*>(a.un);
-  double* dst = static_cast<double*>(a.dst);
-  const double dt = *a.dt;
+  const int tilesx = (nx + WENO_ZTX - 1) / WENO_ZTX;
+  const int nchunk = (nz + WENO_ZCHUNK - 1) / WENO_ZCHUNK;
   const long long nf0 = (long long)(nx + 1) * ny * nz, nf1 = (long long)nx * (ny + 1) * nz;
-  const long long nf2 = (long long)nx * ny * (nz + 1);
+  const R* W = static_cast<const R*>(a.W);
+  const R* src = static_cast<const R*>(a.src);
+  const R* un = static_cast<const R*>(a.un);
+  R* dst = static_cast<R*>(a.dst);
+  const R* Fx = static_cast<const R*>(a.F[0]);
+  const R* Fy = static_cast<const R*>(a.F[1]);
+  const R dt = R(*a.dt);
+  const R gam = R(a.gamma), gm1 = R(a.gamma - 1.0);
+  // face order of a z face: (rho, u_z, u_x, u_y, p)
+  constexpr int perm[NV] = {0, 3, 1, 2, 4};
   double smax = 0.0;
-  for (long long c = 2 * ((long long)blockIdx.x * blockDim.x + threadIdx.x); c < N;
-       c += 2 * (long long)gridDim.x * blockDim.x) {
-    // fewer than 2^31 cells: the cell index splits in 32-bit unsigned arithmetic
-    const unsigned cu = (unsigned)c, r = cu / (unsigned)nx;
-    const int i = (int)(cu % (unsigned)nx);
-    const int j = (int)(r % (unsigned)ny), k = (int)(r / (unsigned)ny);
-    const long long fx = ((long long)k * ny + j) * (nx + 1) + i;
-    const long long fy = ((long long)k * (ny + 1) + j) * nx + i;
-    const long long fz = c;
-    double Out[2][NV];
+  for (long long u = xcd_tile(blockIdx.x, gridDim.x); u < units; u += gridDim.x) {
+    const int ch = (int)(u % nchunk);
+    const long long t = u / nchunk;
+    const int i = (int)(t % tilesx) * WENO_ZTX + (int)(threadIdx.x % WENO_ZTX);
+    const int j = (int)(t / tilesx) * WENO_ZTY + (int)(threadIdx.x / WENO_ZTX);
+    if (i >= nx || j >= ny) continue;
+    const int k0 = ch * WENO_ZCHUNK, k1 = min(k0 + WENO_ZCHUNK, nz);
+    const long long col = (long long)j * nx + i;
+    auto load_cell = [&](int q, R* out) {
+      bool flip;
+      const int kk = remap(q, nz, a.bc[2][0], a.bc[2][1], flip);
+      const long long cell = (long long)kk * NXY + col;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double* Fx = static_cast<const double*>(a.F[0]) + v * nf0;
-      const double* Fy = static_cast<const double*>(a.F[1]) + v * nf1;
-      const double* Fz = static_cast<const double*>(a.F[2]) + v * nf2;
-      const double x0 = Fx[fx], x1 = Fx[fx + 1], x2 = Fx[fx + 2];
-      const double2 y0 = *reinterpret_cast<const double2*>(Fy + fy);
-      const double2 y1 = *reinterpret_cast<const double2*>(Fy + fy + nx);
-      const double2 z0 = *reinterpret_cast<const double2*>(Fz + fz);
-      const double2 z1 = *reinterpret_cast<const double2*>(Fz + fz + (long long)nx * ny);
-      const double2 u = *reinterpret_cast<const double2*>(src + v * N + c);
-      double2 uo = make_double2(0.0, 0.0);
-      if (STAGE == 2) uo = *reinterpret_cast<const double2*>(un + v * N + c);
-      const double dfs[2][3] = {{x1 - x0, y1.x - y0.x, z1.x - z0.x}, {x2 - x1, y1.y - y0.y, z1.y - z0.y}};
-      const double us[2] = {u.x, u.y}, uos[2] = {uo.x, uo.y};
+      for (int v = 0; v < NV; ++v) out[v] = W[v * N + cell];
+      if (flip) out[3] = -out[3];
+    };
+    R c[6][NV], Fm[NV];
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        double l = 0.0;
+    for (int s = 1; s < 6; ++s) load_cell(k0 - 4 + s, c[s]);
+    for (int f = k0; f <= k1; ++f) {
+      // window: cells f - 3 .. f + 2
 #pragma unroll
-        for (int d = 0; d < NDIM; ++d) {
-          const double df = dfs[e][d];
-          l = l - (a.dx_pow2 ? df * a.inv_dx[d] : df / a.dx[d]);
-        }
-        if (STAGE == 1)
-          Out[e][v] = us[e] + dt * l;
-        else
-          Out[e][v] = 0.5 * (uos[e] + (us[e] + dt * l));
+      for (int s = 0; s < 5; ++s)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) c[s][v] = c[s + 1][v];
+      load_cell(f + 2, c[5]);
+      R WL[NV], WR[NV], Fo[NV], Fn[NV];
+#pragma unroll
+      for (int m = 0; m < NV; ++m) {
+        const int v = perm[m];
+        WL[m] = weno5z<R>(c[0][v], c[1][v], c[2][v], c[3][v], c[4][v]);
+        WR[m] = weno5z<R>(c[5][v], c[4][v], c[3][v], c[2][v], c[1][v]);
       }
-    }
+      hll_ordered<R, NV>(WL, WR, gam, gm1, Fo);
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-      *reinterpret_cast<double2*>(dst + v * N + c) = make_double2(Out[0][v], Out[1][v]);
-    if (fuse) {
+      for (int m = 0; m < NV; ++m) Fn[perm[m]] = Fo[m];
+      if (f > k0) {
+#pragma clang fp contract(off)
+        const int k = f - 1;
+        const long long cidx = (long long)k * NXY + col;
+        const long long fx = ((long long)k * ny + j) * (nx + 1) + i;
+        const long long fy = ((long long)k * (ny + 1) + j) * nx + i;
+        R Out[NV];
 #pragma unroll
-      for (int e = 0; e < 2; ++e)
-        smax = fmax(smax, cfl_signal<double, NDIM>(Out[e], a.inv_dx, a.gamma));
+        for (int v = 0; v < NV; ++v) {
+          const R dfs[3] = {Fx[v * nf0 + fx + 1] - Fx[v * nf0 + fx],
+                            Fy[v * nf1 + fy + nx] - Fy[v * nf1 + fy], Fn[v] - Fm[v]};
+          R l = R(0);
+#pragma unroll
+          for (int d = 0; d < NDIM; ++d) {
+            const R df = dfs[d];
+            l = l - (a.dx_pow2 ? df * R(a.inv_dx[d]) : df / R(a.dx[d]));
+          }
+          const R uc = src[v * N + cidx];
+          if (STAGE == 1)
+            Out[v] = uc + dt * l;
+          else
+            Out[v] = R(0.5) * (un[v * N + cidx] + (uc + dt * l));
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dst[v * N + cidx] = Out[v];
+        if (fuse) {
+          double Ud[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Ud[v] = (double)Out[v];
+          smax = fmax(smax, cfl_signal<R, NDIM>(Ud, a.inv_dx, a.gamma));
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Fm[v] = Fn[v];
     }
   }
   block_finish<256>(0u, smax, fuse, a.ctl, a.slots + blockIdx.x);
@@ -387,37 +411,34 @@ template <typename R, int NDIM>
 static hipError_t weno_stage_t(const WenoArgs& a, int stage, hipStream_t s) {
   const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
   const unsigned nb = (unsigned)((N + 255) / 256);
+  const bool fuse = stage == 2 && a.fuse_cfl;
   hipLaunchKernelGGL((weno_prim<R, NDIM>), dim3(nb), dim3(256), 0, s, a);
   auto faces = [&](int d) { return (unsigned)((N / a.n[d] * (a.n[d] + 1) + 255) / 256); };
   hipLaunchKernelGGL((weno_face<R, NDIM, 0>), dim3(faces(0)), dim3(256), 0, s, a);
   if constexpr (NDIM >= 2) hipLaunchKernelGGL((weno_face<R, NDIM, 1>), dim3(faces(1)), dim3(256), 0, s, a);
-  if constexpr (NDIM >= 3) {
-    const unsigned zt = (unsigned)((a.n[0] + WENO_ZTX - 1) / WENO_ZTX) *
-                        (unsigned)((a.n[1] + WENO_ZTY - 1) / WENO_ZTY) * (unsigned)(a.n[2] + 1);
-    hipLaunchKernelGGL((weno_face<R, NDIM, 2>), dim3(zt), dim3(256), 0, s, a);
-  }
-  const unsigned nbu = nb < 2048u ? nb : 2048u;
-  const bool pair = std::is_same<R, double>::value && NDIM == 3 && a.n[0] % 2 == 0 &&
-                    ((uintptr_t)a.src | (uintptr_t)a.un | (uintptr_t)a.dst) % 16 == 0;
-  const bool fuse = stage == 2 && a.fuse_cfl;
-  unsigned nbx = nbu;
-  if (pair) {
-    const unsigned np = (unsigned)((N / 2 + 255) / 256), nbp = np < 2048u ? np : 2048u;
-    nbx = nbp;
-    if (fuse && (int)nbx > a.nslots) return hipErrorInvalidValue;
+  unsigned ng;
+  if constexpr (NDIM == 3) {
+    const long long units = (long long)((a.n[0] + WENO_ZTX - 1) / WENO_ZTX) *
+                            ((a.n[1] + WENO_ZTY - 1) / WENO_ZTY) *
+                            ((a.n[2] + WENO_ZCHUNK - 1) / WENO_ZCHUNK);
+    const long long cap = fuse ? a.nslots : GRID_STRIDE_MAX_BLOCKS;
+    if (cap < 1) return hipErrorInvalidValue;
+    ng = (unsigned)(units < cap ? units : cap);
     if (stage == 1)
-      hipLaunchKernelGGL((weno_update_pair<1>), dim3(nbp), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((weno_zwalk<R, 1>), dim3(ng), dim3(256), 0, s, a, units);
     else
-      hipLaunchKernelGGL((weno_update_pair<2>), dim3(nbp), dim3(256), 0, s, a);
-  } else if (stage == 1) {
-    hipLaunchKernelGGL((weno_update<R, NDIM, 1>), dim3(nbu), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((weno_zwalk<R, 2>), dim3(ng), dim3(256), 0, s, a, units);
   } else {
-    if (fuse && (int)nbx > a.nslots) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((weno_update<R, NDIM, 2>), dim3(nbu), dim3(256), 0, s, a);
+    ng = nb < 2048u ? nb : 2048u;
+    if (fuse && (int)ng > a.nslots) return hipErrorInvalidValue;
+    if (stage == 1)
+      hipLaunchKernelGGL((weno_update<R, NDIM, 1>), dim3(ng), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((weno_update<R, NDIM, 2>), dim3(ng), dim3(256), 0, s, a);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !fuse) return e;
-  return launch_cfl_final(a.slots, (int)nbx, a.cfl, a.next_dt, s);
+  return launch_cfl_final(a.slots, (int)ng, a.cfl, a.next_dt, s);
 }
 
 hipError_t launch_weno_stage(int ndim, int dtype, const WenoArgs& a, int stage, hipStream_t s) {

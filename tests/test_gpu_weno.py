@@ -69,8 +69,11 @@ CASES = [
     ((37, 21, 19), (P, P, R, R, O, O)),
     ((16, 16, 16), (R, R)),
     ((5, 6, 7), (O, R, P, P, R, O)),
-    # even nx in 3D FP64: the two-cells-per-thread update
     ((24, 13, 11), (O, R, P, P, R, O)), ((4, 5, 6), (R, O, O, R, P, P)),
+    # 3D: z columns walked in chunks of 32 cells by 64 x 4 column tiles;
+    # several chunks (the face between two chunks computed by both), ragged
+    # tiles in x and y, every boundary kind at a chunk end
+    ((70, 9, 70), (R, O, P, P, O, R)), ((8, 6, 65), (P, P, O, R, R, R)),
 ]
 
 
@@ -90,7 +93,8 @@ def test_step_parity_fp64(n, bc):
 
 
 @pytest.mark.parametrize("n,bc", [((1000,), (O, O)), ((50, 37), (O, O, R, R)),
-                                  ((37, 21, 19), (P, P, R, R, O, O))])
+                                  ((37, 21, 19), (P, P, R, R, O, O)),
+                                  ((70, 9, 70), (R, O, P, P, O, R))])
 def test_step_parity_fp32(n, bc):
     log("weno fp32", n, bc)
     U0 = random_state(n, 4).astype(np.float32).astype(np.float64)
@@ -198,9 +202,8 @@ def test_turbulent_64_periodic_one_step():
 
 
 def test_aligned_and_unaligned_states_give_the_same_bits():
-    """The FP64 3D update takes two cells per thread with 16-byte accesses
-    when the states are 16-byte aligned, one cell otherwise: the same step,
-    bit for bit, and the same fused dt."""
+    """A state that starts 8 bytes past a 16-byte boundary gives the same
+    step, bit for bit, and the same fused dt as an aligned one."""
     n, bc = (24, 13, 11), (O, R, P, P, R, O)
     log("weno aligned vs unaligned state", n, bc)
     U0 = random_state(n, 8)
