@@ -40,8 +40,11 @@ def smooth_state(n, seed):
     return workloads.conserved_from_primitive(np.exp(0.2 * gf()), vel, 1.0 + 0.2 * gf()), rng
 
 
+# (600,) and (70, 52) hold tiles away from every edge (256-cell rows, 16 x 16
+# tiles), which compute no far-end face, beside edge tiles that do
 @pytest.mark.parametrize("n,bc", [((64,), (O, O)), ((48,), (R, R)), ((40, 32), (P, P, R, R)),
-                                  ((32, 24), (O, O, P, P)), ((16, 12, 10), (P, P, R, R, O, O))])
+                                  ((32, 24), (O, O, P, P)), ((16, 12, 10), (P, P, R, R, O, O)),
+                                  ((600,), (R, O)), ((70, 52), (R, O, O, R))])
 def test_one_step_adjoint_dot_product(n, bc):
     log("adjoint dot product", n, bc)
     U0, rng = smooth_state(n, 3)
