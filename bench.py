@@ -376,9 +376,9 @@ def bench_batched(args, steps=100):
 
 def bench_weno(args, n=256, steps=10):
     """The paper's own face scheme (WENO5-Z + HLL) on the 256^3 FP64 blast:
-    the same step, as a pipeline per stage (primitives, the x and y face-flux
-    kernels, then the z faces and the update, with the fused CFL step, in
-    one z-walking kernel)."""
+    the same step, as a pipeline per stage (the x face-flux kernel, which
+    also stores the primitives, the y face-flux kernel, then the z faces and
+    the update, with the fused CFL step, in one z-walking kernel)."""
     import paper_2509_08971_amd as H
     import workloads
 
@@ -396,10 +396,10 @@ def bench_weno(args, n=256, steps=10):
     flags = H.hard_status_read(work)
     N = n ** 3
     zus = N * steps / (ms * 1e-3)
-    # pipeline words per cell and stage: prim (read U, write W), x and y
+    # pipeline words per cell and stage: x faces (read U, write W and F), y
     # faces (read W, write F), z walk (read W, the x and y F, src, write dst;
-    # stage 2 also reads U^n): 2 + 4 + 5 (+1) words of nvar; both stages
-    words = (2 + 4 + 5) + (2 + 4 + 6)
+    # stage 2 also reads U^n): 3 + 2 + 5 (+1) words of nvar; both stages
+    words = (3 + 2 + 5) + (3 + 2 + 6)
     pipe_bytes = words * 5 * 8
     alg_bytes = 5 * 5 * 8  # one read and one write per stage, plus U^n in stage 2
     log(f"  {ms / steps:.3f} ms/step, {zus / 1e9:.2f} G zu/s")

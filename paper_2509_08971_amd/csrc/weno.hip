@@ -4,12 +4,13 @@
 // stages as the MUSCL-HLLC path.  Three ghost layers per side.
 //
 // This path is a pipeline per stage, not the fused tile kernel:
-//   weno_prim    one thread per cell: primitives W of the stage source into
-//                the workspace (and the status bits);
-//   weno_face    one thread per face, one launch per axis (x, and y in 2D and
-//                3D): six W cells along the axis (ghosts by index remap),
-//                WENO5-Z left and right states, HLL flux into a per-axis
-//                face array;
+//   weno_xface   one thread per x face: the primitives of the stage source
+//                for a run of rows in LDS (each cell's also stored to W for
+//                the other axes, with the status bits), then six cells along
+//                x (ghosts by index remap), WENO5-Z left and right states,
+//                HLL flux into the x face array;
+//   weno_face    (2D, 3D) the same for the y faces, the six cells read from
+//                W;
 //   weno_update  (1D, 2D) grid-stride over the cells: L(U) = -sum_d
 //                (F+ - F-)/dx_d in the order x, y, the stage combine, and in
 //                stage 2 the fused CFL step;
@@ -18,8 +19,8 @@
 //                window of W and updates each cell with the x and y fluxes
 //                from their arrays; no z face array exists.
 // Bytes per cell and stage: the fused MUSCL kernel moves 2-3 nvar words; this
-// pipeline 2 + 2 (ndim - 1) + 5 (+ 1 in stage 2) nvar words in 3D (W and the
-// x and y face arrays round-trip through memory).
+// pipeline 3 + 2 + 5 (+ 1 in stage 2) nvar words in 3D (W and the x and y
+// face arrays round-trip through memory).
 //
 // Arithmetic: the face kernels are bound by FP64 instruction issue (about
 // 1100 VALU instructions per face, 0.8 of issue busy), so the WENO5-Z
@@ -147,32 +148,96 @@ __device__ __forceinline__ void primitives_plain(const R* u, double gamma, R* w)
   w[NDIM + 1] = R((gamma - 1.0) * e);
 }
 
+// x faces with the primitives of their stencils computed in the same pass
+// (no separate primitive pass over the grid).  A block takes 256 consecutive faces of the x-face
+// layout (f, j, k).  Face t of the block reads the six cells f - 3 .. f + 2
+// of its row from LDS slots p(t) .. p(t) + 5, p(t) = t + 6 (r - r0) with r
+// its row and r0 the block's first row: consecutive faces of a row share
+// five slots, and each row starts six slots after the previous one.  Every
+// slot is filled once: each face thread fills the slot of cell f (a ghost
+// past the row's end by index remap, with the wall flip), the block's first
+// face of a row also cells f - 3 .. f - 1, its last face cells f + 1 and
+// f + 2.  The thread of face f < nx also stores the primitives of cell f to
+// W (read by the y faces and the z walk) and its status bits.  Rows of at
+// least 4 faces (nx >= 3) bound the rows a block touches to 65.
+constexpr int WENO_XSLOTS = 256 + 5 + 6 * 64;
+
 template <typename R, int NDIM>
-__global__ __launch_bounds__(256) void weno_prim(WenoArgs a) {
+__global__ __launch_bounds__(256) void weno_xface(WenoArgs a) {
   constexpr int NV = NDIM + 2;
-  const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
-  const long long c = (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  __shared__ R S[NV][WENO_XSLOTS];
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const long long N = (long long)nx * ny * nz;
+  const long long nface = N / nx * (nx + 1);
+  const unsigned mx = (unsigned)nx + 1u;
+  const long long base = (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x;
+  const long long idx = base + threadIdx.x;
+  const bool live = idx < nface;
+  // the face count is below 2^32 (fewer than 2^31 cells): 32-bit splits
+  const unsigned r0 = (unsigned)base / mx;
+  const unsigned u = (unsigned)(live ? idx : base);
+  const int f = (int)(u % mx);
+  const unsigned r = u / mx;               // row (j, k) = (r % ny, r / ny)
+  const int p = (int)threadIdx.x + 6 * (int)(r - r0);
+  const R* U = static_cast<const R*>(a.src);
+  R* W = static_cast<R*>(a.W);
   unsigned flags = 0;
-  if (c < N) {
-    const R* U = static_cast<const R*>(a.src);
-    R* W = static_cast<R*>(a.W);
-    R u[NV], w[NV];
+  auto fill = [&](int q, int slot, bool own) {
+    bool flip;
+    const int qq = remap(q, nx, a.bc[0][0], a.bc[0][1], flip);
+    const long long cell = (long long)r * nx + qq;
+    R uc[NV], w[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = U[v * N + c];
-    primitives_plain<R, NDIM>(u, a.gamma, w);
-    flags = cell_flags<R, NV>(u, w[NV - 1]);
+    for (int v = 0; v < NV; ++v) uc[v] = U[v * N + cell];
+    primitives_plain<R, NDIM>(uc, a.gamma, w);
+    if (own) {
+      flags = cell_flags<R, NV>(uc, w[NV - 1]);
+      if constexpr (NDIM >= 2) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) W[v * N + c] = w[v];
+        for (int v = 0; v < NV; ++v) W[v * N + cell] = w[v];
+      }
+    }
+    if (flip) w[1] = -w[1];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) S[v][slot] = w[v];
+  };
+  if (live) {
+    fill(f, p + 3, f < nx);
+    if (f == 0 || idx == base)
+      for (int s = 0; s < 3; ++s) fill(f - 3 + s, p + s, false);
+    if (f == nx || idx == base + (long long)blockDim.x - 1 || idx == nface - 1)
+      for (int s = 4; s < 6; ++s) fill(f - 3 + s, p + s, false);
+  }
+  __syncthreads();
+  if (live) {
+    R c[6][NV];
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) c[s][v] = S[v][p + s];
+    // face states ordered (rho, u_x, u_y, u_z, p): the x faces need no swap
+    R WL[NV], WR[NV], Fn[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      WL[v] = weno5z<R>(c[0][v], c[1][v], c[2][v], c[3][v], c[4][v]);
+      WR[v] = weno5z<R>(c[5][v], c[4][v], c[3][v], c[2][v], c[1][v]);
+    }
+    const R gam = R(a.gamma), gm1 = R(a.gamma - 1.0);
+    hll_ordered<R, NV>(WL, WR, gam, gm1, Fn);
+    R* F = static_cast<R*>(a.F[0]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v * nface + idx] = Fn[v];
   }
   flags = wave_or(flags);
   if ((threadIdx.x & 63) == 0 && flags) atomicOr(&a.ctl->flags, flags);
 }
 
-// Faces along axis AX (x or y): face f (0..n_AX) lies between cells f-1 and
-// f.  Linear face index (the layout of the face array), x fastest: AX = 0:
-// (f, j, k); AX = 1: (i, f, k).  A block takes 256 consecutive faces of that
-// layout: the six cells of a face lie in its own row or plane, which the L2
-// holds.  The z faces are computed inside weno_zwalk.
+
+// y faces (2D and 3D): face f (0..ny) lies between cells f-1 and f.  Linear
+// face index (the layout of the face array), x fastest: (i, f, k).  A block
+// takes 256 consecutive faces of that layout: the six cells of a face lie in
+// its own plane, which the L2 holds.  The x faces are computed by
+// weno_xface, the z faces inside weno_zwalk.
 
 template <typename R, int NDIM, int AX>
 __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
@@ -180,20 +245,13 @@ __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const long long N = (long long)nx * ny * nz;
   const long long nface = N / a.n[AX] * (a.n[AX] + 1);
-  static_assert(AX < 2, "z faces are computed by weno_zwalk");
+  static_assert(AX == 1, "x faces: weno_xface; z faces: weno_zwalk");
   int i, j, k, f;
   const long long idx = (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (idx >= nface) return;
   // the face count of an axis is below 2^32 (fewer than 2^31 cells), so the
   // index splits in 32-bit unsigned arithmetic
-  if constexpr (AX == 0) {
-    const unsigned u = (unsigned)idx, mx = (unsigned)nx + 1u;
-    f = (int)(u % mx);
-    const unsigned r = u / mx;
-    j = (int)(r % (unsigned)ny);
-    k = (int)(r / (unsigned)ny);
-    i = 0;
-  } else if constexpr (AX == 1) {
+  {
     const unsigned u = (unsigned)idx, my = (unsigned)ny + 1u;
     i = (int)(u % (unsigned)nx);
     const unsigned r = u / (unsigned)nx;
@@ -208,8 +266,7 @@ __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
   for (int s = 0; s < 6; ++s) {
     bool flip;
     const int q = remap(f - 3 + s, a.n[AX], a.bc[AX][0], a.bc[AX][1], flip);
-    const int ii = AX == 0 ? q : i, jj = AX == 1 ? q : j, kk = k;
-    const long long cell = ((long long)kk * ny + jj) * nx + ii;
+    const long long cell = ((long long)k * ny + q) * nx + i;
 #pragma unroll
     for (int v = 0; v < NV; ++v) c[s][v] = W[v * N + cell];
     if (flip) c[s][1 + AX] = -c[s][1 + AX];
@@ -412,9 +469,9 @@ static hipError_t weno_stage_t(const WenoArgs& a, int stage, hipStream_t s) {
   const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
   const unsigned nb = (unsigned)((N + 255) / 256);
   const bool fuse = stage == 2 && a.fuse_cfl;
-  hipLaunchKernelGGL((weno_prim<R, NDIM>), dim3(nb), dim3(256), 0, s, a);
+  if (a.n[0] < 3) return hipErrorInvalidValue;  // weno_xface's slot bound
   auto faces = [&](int d) { return (unsigned)((N / a.n[d] * (a.n[d] + 1) + 255) / 256); };
-  hipLaunchKernelGGL((weno_face<R, NDIM, 0>), dim3(faces(0)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((weno_xface<R, NDIM>), dim3(faces(0)), dim3(256), 0, s, a);
   if constexpr (NDIM >= 2) hipLaunchKernelGGL((weno_face<R, NDIM, 1>), dim3(faces(1)), dim3(256), 0, s, a);
   unsigned ng;
   if constexpr (NDIM == 3) {
