@@ -246,19 +246,14 @@ __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
   const long long N = (long long)nx * ny * nz;
   const long long nface = N / a.n[AX] * (a.n[AX] + 1);
   static_assert(AX == 1, "x faces: weno_xface; z faces: weno_zwalk");
-  int i, j, k, f;
   const long long idx = (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (idx >= nface) return;
   // the face count of an axis is below 2^32 (fewer than 2^31 cells), so the
   // index splits in 32-bit unsigned arithmetic
-  {
-    const unsigned u = (unsigned)idx, my = (unsigned)ny + 1u;
-    i = (int)(u % (unsigned)nx);
-    const unsigned r = u / (unsigned)nx;
-    f = (int)(r % my);
-    k = (int)(r / my);
-    j = 0;
-  }
+  const unsigned u = (unsigned)idx, my = (unsigned)ny + 1u;
+  const int i = (int)(u % (unsigned)nx);
+  const unsigned r = u / (unsigned)nx;
+  const int f = (int)(r % my), k = (int)(r / my);
   const R* W = static_cast<const R*>(a.W);
   // six cells f-3 .. f+2 along AX, primitives with the wall flip applied
   R c[6][NV];
