@@ -74,6 +74,9 @@ CASES = [
     # several chunks (the face between two chunks computed by both), ragged
     # tiles in x and y, every boundary kind at a chunk end
     ((70, 9, 70), (R, O, P, P, O, R)), ((8, 6, 65), (P, P, O, R, R, R)),
+    # the shortest x rows (4 and 5 faces): a block of 256 x faces spans up to
+    # 64 rows of LDS slots in weno_xface, starting mid-row for nx = 4
+    ((3, 40, 35), (R, R, O, O, P, P)), ((4, 7, 33), (P, P, R, O, O, R)),
 ]
 
 
