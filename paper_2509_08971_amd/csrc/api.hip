@@ -123,8 +123,9 @@ WorkLayout layout_of(const Grid& g) {
   if (g.scheme == HARD_SCHEME_WENO5Z_HLL) {
     w.weno_w = w.total;
     w.total += align256((size_t)g.nvar * g.ncell * g.wsize);
-    // face arrays of x and y; the z faces of a 3D grid never leave registers
-    for (int d = 0; d < g.ndim && d < 2; ++d) {
+    // face arrays of every axis but the last (x in 1D too); the faces of
+    // the last axis of a 2D or 3D grid never leave registers
+    for (int d = 0; d < (g.ndim == 1 ? 1 : g.ndim - 1); ++d) {
       w.weno_f[d] = w.total;
       w.total += align256((size_t)g.nvar * (g.ncell / g.n[d]) * (g.n[d] + 1) * g.wsize);
     }

@@ -9,18 +9,17 @@
 //                the other axes, with the status bits), then six cells along
 //                x (ghosts by index remap), WENO5-Z left and right states,
 //                HLL flux into the x face array;
-//   weno_face    (2D, 3D) the same for the y faces, the six cells read from
-//                W;
-//   weno_update  (1D, 2D) grid-stride over the cells: L(U) = -sum_d
-//                (F+ - F-)/dx_d in the order x, y, the stage combine, and in
-//                stage 2 the fused CFL step;
-//   weno_zwalk   (3D) the z faces and the update in one pass: each thread
-//                walks a z column, computes the z faces from a register
-//                window of W and updates each cell with the x and y fluxes
-//                from their arrays; no z face array exists.
+//   weno_face    (3D) the same for the y faces, the six cells read from W;
+//   weno_walk    (2D, 3D) the faces of the last axis and the update in one
+//                pass: each thread walks a column along that axis, computes
+//                its faces from a register window of W and updates each
+//                cell with the other axes' fluxes from their arrays; no face
+//                array of the last axis exists;
+//   weno_update  (1D) grid-stride over the cells: L(U) = -(F+ - F-)/dx, the
+//                stage combine, and in stage 2 the fused CFL step.
 // Bytes per cell and stage: the fused MUSCL kernel moves 2-3 nvar words; this
-// pipeline 3 + 2 + 5 (+ 1 in stage 2) nvar words in 3D (W and the x and y
-// face arrays round-trip through memory).
+// pipeline 3 + 2 + 5 (+ 1 in stage 2) nvar words in 3D, 3 + 4 (+ 1) in 2D
+// (W and the face arrays of the other axes round-trip through memory).
 //
 // Arithmetic: the face kernels are bound by FP64 instruction issue (about
 // 1100 VALU instructions per face, 0.8 of issue busy), so the WENO5-Z
@@ -232,12 +231,12 @@ __global__ __launch_bounds__(256) void weno_xface(WenoArgs a) {
   if ((threadIdx.x & 63) == 0 && flags) atomicOr(&a.ctl->flags, flags);
 }
 
-
-// y faces (2D and 3D): face f (0..ny) lies between cells f-1 and f.  Linear
-// face index (the layout of the face array), x fastest: (i, f, k).  A block
-// takes 256 consecutive faces of that layout: the six cells of a face lie in
-// its own plane, which the L2 holds.  The x faces are computed by
-// weno_xface, the z faces inside weno_zwalk.
+// y faces of a 3D grid: face f (0..ny) lies between cells f-1 and f.
+// Linear face index (the layout of the face array), x fastest: (i, f, k).
+// A block takes 256 consecutive faces of that layout: the six cells of a
+// face lie in its own plane, which the L2 holds.  The x faces are computed
+// by weno_xface, the z faces (and the y faces of a 2D grid) inside
+// weno_walk.
 
 template <typename R, int NDIM, int AX>
 __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
@@ -245,7 +244,7 @@ __global__ __launch_bounds__(256) void weno_face(WenoArgs a) {
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const long long N = (long long)nx * ny * nz;
   const long long nface = N / a.n[AX] * (a.n[AX] + 1);
-  static_assert(AX == 1, "x faces: weno_xface; z faces: weno_zwalk");
+  static_assert(AX == 1 && NDIM == 3, "x faces: weno_xface; the last axis: weno_walk");
   const long long idx = (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (idx >= nface) return;
   // the face count of an axis is below 2^32 (fewer than 2^31 cells), so the
@@ -349,29 +348,35 @@ __global__ __launch_bounds__(256) void weno_update(WenoArgs a) {
 }
 
 
-// 3D: the z faces fused into the stage update.  A work unit is a 64 x 4
-// (i, j) tile of columns and a chunk of WENO_ZCHUNK cells along z; each
-// thread walks its column with the six cells of the current z face in a
-// register window (one new cell loaded per face) and carries the flux of
-// the face below the current cell from the previous position, so no z face
-// array goes through memory (the face at a chunk's upper end is computed by
-// both chunks that share it).  The x and y face fluxes come from their
-// arrays.  The face arithmetic is weno_face's and the update's
-// weno_update's, in the same order.  Grid-stride over the units, one CFL
-// slot per workgroup.  Against a z face kernel plus a separate update: 4.44
-// against 5.27 ms per step of the 256^3 blast, the same bits; chunks of 16
-// or 64 cells 4.62 and 4.52 ms, loading the next window cell one face ahead
-// 4.48 ms.
-constexpr int WENO_ZTX = 64, WENO_ZTY = 4, WENO_ZCHUNK = 32;
+// 2D and 3D: the faces of the last axis (y in 2D, z in 3D) fused into the
+// stage update.  A work unit is a tile of columns along that axis (64 x 4
+// (i, j) columns in 3D, 256 i columns in 2D) and a chunk of WENO_WCHUNK
+// cells along it (WENO_WCHUNK, halved while the launch would have fewer
+// than about 1500 units, down to 4); each thread walks its column with the six cells of the
+// current face in a register window (one new cell loaded per face) and
+// carries the flux of the face below the current cell from the previous
+// position, so no face array of that axis goes through memory (the face at
+// a chunk's upper end is computed by both chunks that share it).  The other
+// axes' face fluxes come from their arrays.  The face arithmetic is
+// weno_face's and the update's weno_update's, in the same order.
+// Grid-stride over the units, one CFL slot per workgroup.  In 3D, against a
+// z face kernel plus a separate update: 4.44 against 5.27 ms per step of the
+// 256^3 blast, the same bits; chunks of 16 or 64 cells 4.62 and 4.52 ms,
+// loading the next window cell one face ahead 4.48 ms.
+constexpr int WENO_ZTX = 64, WENO_ZTY = 4, WENO_WCHUNK = 32;
 
-template <typename R, int STAGE>
-__global__ __launch_bounds__(256) void weno_zwalk(WenoArgs a, long long units) {
-  constexpr int NDIM = 3, NV = 5;
+template <typename R, int NDIM, int STAGE>
+__global__ __launch_bounds__(256) void weno_walk(WenoArgs a, long long units, int wchunk) {
+  static_assert(NDIM >= 2, "1D grids use weno_update");
+  constexpr int NV = NDIM + 2, WA = NDIM - 1;
+  constexpr int CX = NDIM == 3 ? WENO_ZTX : 256, CY = NDIM == 3 ? WENO_ZTY : 1;
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-  const long long N = (long long)nx * ny * nz, NXY = (long long)nx * ny;
+  const int nw = a.n[WA];
+  const long long N = (long long)nx * ny * nz;
+  const long long WS = NDIM == 3 ? (long long)nx * ny : nx;  // stride along the walk axis
   const bool fuse = STAGE == 2 && a.fuse_cfl;
-  const int tilesx = (nx + WENO_ZTX - 1) / WENO_ZTX;
-  const int nchunk = (nz + WENO_ZCHUNK - 1) / WENO_ZCHUNK;
+  const int tilesx = (nx + CX - 1) / CX;
+  const int nchunk = (nw + wchunk - 1) / wchunk;
   const long long nf0 = (long long)(nx + 1) * ny * nz, nf1 = (long long)nx * (ny + 1) * nz;
   const R* W = static_cast<const R*>(a.W);
   const R* src = static_cast<const R*>(a.src);
@@ -381,24 +386,24 @@ __global__ __launch_bounds__(256) void weno_zwalk(WenoArgs a, long long units) {
   const R* Fy = static_cast<const R*>(a.F[1]);
   const R dt = R(*a.dt);
   const R gam = R(a.gamma), gm1 = R(a.gamma - 1.0);
-  // face order of a z face: (rho, u_z, u_x, u_y, p)
-  constexpr int perm[NV] = {0, 3, 1, 2, 4};
+  // face order along the walk axis: (rho, u_w, the other velocities, p)
+  constexpr int perm3[5] = {0, 3, 1, 2, 4}, perm2[4] = {0, 2, 1, 3};
   double smax = 0.0;
   for (long long u = xcd_tile(blockIdx.x, gridDim.x); u < units; u += gridDim.x) {
     const int ch = (int)(u % nchunk);
     const long long t = u / nchunk;
-    const int i = (int)(t % tilesx) * WENO_ZTX + (int)(threadIdx.x % WENO_ZTX);
-    const int j = (int)(t / tilesx) * WENO_ZTY + (int)(threadIdx.x / WENO_ZTX);
+    const int i = (int)(t % tilesx) * CX + (int)(threadIdx.x % CX);
+    const int j = NDIM == 3 ? (int)(t / tilesx) * CY + (int)(threadIdx.x / CX) : 0;
     if (i >= nx || j >= ny) continue;
-    const int k0 = ch * WENO_ZCHUNK, k1 = min(k0 + WENO_ZCHUNK, nz);
+    const int k0 = ch * wchunk, k1 = min(k0 + wchunk, nw);
     const long long col = (long long)j * nx + i;
     auto load_cell = [&](int q, R* out) {
       bool flip;
-      const int kk = remap(q, nz, a.bc[2][0], a.bc[2][1], flip);
-      const long long cell = (long long)kk * NXY + col;
+      const int kk = remap(q, nw, a.bc[WA][0], a.bc[WA][1], flip);
+      const long long cell = (long long)kk * WS + col;
 #pragma unroll
       for (int v = 0; v < NV; ++v) out[v] = W[v * N + cell];
-      if (flip) out[3] = -out[3];
+      if (flip) out[1 + WA] = -out[1 + WA];
     };
     R c[6][NV], Fm[NV];
 #pragma unroll
@@ -413,24 +418,28 @@ __global__ __launch_bounds__(256) void weno_zwalk(WenoArgs a, long long units) {
       R WL[NV], WR[NV], Fo[NV], Fn[NV];
 #pragma unroll
       for (int m = 0; m < NV; ++m) {
-        const int v = perm[m];
+        const int v = NDIM == 3 ? perm3[m] : perm2[m];
         WL[m] = weno5z<R>(c[0][v], c[1][v], c[2][v], c[3][v], c[4][v]);
         WR[m] = weno5z<R>(c[5][v], c[4][v], c[3][v], c[2][v], c[1][v]);
       }
       hll_ordered<R, NV>(WL, WR, gam, gm1, Fo);
 #pragma unroll
-      for (int m = 0; m < NV; ++m) Fn[perm[m]] = Fo[m];
+      for (int m = 0; m < NV; ++m) Fn[NDIM == 3 ? perm3[m] : perm2[m]] = Fo[m];
       if (f > k0) {
 #pragma clang fp contract(off)
-        const int k = f - 1;
-        const long long cidx = (long long)k * NXY + col;
-        const long long fx = ((long long)k * ny + j) * (nx + 1) + i;
+        const int k = f - 1;  // the cell below face f along the walk axis
+        const long long cidx = (long long)k * WS + col;
+        // x face (i, j, k) in 3D, (i, k) in 2D; y face (i, k, j) ... of a 3D grid
+        const long long fx = NDIM == 3 ? ((long long)k * ny + j) * (nx + 1) + i
+                                       : (long long)k * (nx + 1) + i;
         const long long fy = ((long long)k * (ny + 1) + j) * nx + i;
         R Out[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          const R dfs[3] = {Fx[v * nf0 + fx + 1] - Fx[v * nf0 + fx],
-                            Fy[v * nf1 + fy + nx] - Fy[v * nf1 + fy], Fn[v] - Fm[v]};
+          R dfs[NDIM];
+          dfs[0] = Fx[v * nf0 + fx + 1] - Fx[v * nf0 + fx];
+          if constexpr (NDIM == 3) dfs[1] = Fy[v * nf1 + fy + nx] - Fy[v * nf1 + fy];
+          dfs[NDIM - 1] = Fn[v] - Fm[v];
           R l = R(0);
 #pragma unroll
           for (int d = 0; d < NDIM; ++d) {
@@ -462,25 +471,28 @@ __global__ __launch_bounds__(256) void weno_zwalk(WenoArgs a, long long units) {
 template <typename R, int NDIM>
 static hipError_t weno_stage_t(const WenoArgs& a, int stage, hipStream_t s) {
   const long long N = (long long)a.n[0] * a.n[1] * a.n[2];
-  const unsigned nb = (unsigned)((N + 255) / 256);
   const bool fuse = stage == 2 && a.fuse_cfl;
   if (a.n[0] < 3) return hipErrorInvalidValue;  // weno_xface's slot bound
   auto faces = [&](int d) { return (unsigned)((N / a.n[d] * (a.n[d] + 1) + 255) / 256); };
   hipLaunchKernelGGL((weno_xface<R, NDIM>), dim3(faces(0)), dim3(256), 0, s, a);
-  if constexpr (NDIM >= 2) hipLaunchKernelGGL((weno_face<R, NDIM, 1>), dim3(faces(1)), dim3(256), 0, s, a);
+  if constexpr (NDIM == 3) hipLaunchKernelGGL((weno_face<R, NDIM, 1>), dim3(faces(1)), dim3(256), 0, s, a);
   unsigned ng;
-  if constexpr (NDIM == 3) {
-    const long long units = (long long)((a.n[0] + WENO_ZTX - 1) / WENO_ZTX) *
-                            ((a.n[1] + WENO_ZTY - 1) / WENO_ZTY) *
-                            ((a.n[2] + WENO_ZCHUNK - 1) / WENO_ZCHUNK);
+  if constexpr (NDIM >= 2) {
+    const int cx = NDIM == 3 ? WENO_ZTX : 256, cy = NDIM == 3 ? WENO_ZTY : 1;
+    const int nw = a.n[NDIM - 1];
+    const long long cols = (long long)((a.n[0] + cx - 1) / cx) * (NDIM == 3 ? (a.n[1] + cy - 1) / cy : 1);
+    int wchunk = WENO_WCHUNK;
+    while (wchunk > 4 && cols * ((nw + wchunk - 1) / wchunk) < 1536) wchunk /= 2;
+    const long long units = cols * ((nw + wchunk - 1) / wchunk);
     const long long cap = fuse ? a.nslots : GRID_STRIDE_MAX_BLOCKS;
     if (cap < 1) return hipErrorInvalidValue;
     ng = (unsigned)(units < cap ? units : cap);
     if (stage == 1)
-      hipLaunchKernelGGL((weno_zwalk<R, 1>), dim3(ng), dim3(256), 0, s, a, units);
+      hipLaunchKernelGGL((weno_walk<R, NDIM, 1>), dim3(ng), dim3(256), 0, s, a, units, wchunk);
     else
-      hipLaunchKernelGGL((weno_zwalk<R, 2>), dim3(ng), dim3(256), 0, s, a, units);
+      hipLaunchKernelGGL((weno_walk<R, NDIM, 2>), dim3(ng), dim3(256), 0, s, a, units, wchunk);
   } else {
+    const unsigned nb = (unsigned)((N + 255) / 256);
     ng = nb < 2048u ? nb : 2048u;
     if (fuse && (int)ng > a.nslots) return hipErrorInvalidValue;
     if (stage == 1)

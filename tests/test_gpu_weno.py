@@ -74,6 +74,9 @@ CASES = [
     # several chunks (the face between two chunks computed by both), ragged
     # tiles in x and y, every boundary kind at a chunk end
     ((70, 9, 70), (R, O, P, P, O, R)), ((8, 6, 65), (P, P, O, R, R, R)),
+    # 2D: y columns walked in chunks (32 cells, fewer on small grids) by tiles
+    # of 256 x columns; several column tiles and chunks
+    ((300, 70), (R, O, P, P)),
     # the shortest x rows (4 and 5 faces): a block of 256 x faces spans up to
     # 64 rows of LDS slots in weno_xface, starting mid-row for nx = 4
     ((3, 40, 35), (R, R, O, O, P, P)), ((4, 7, 33), (P, P, R, O, O, R)),
@@ -97,7 +100,7 @@ def test_step_parity_fp64(n, bc):
 
 @pytest.mark.parametrize("n,bc", [((1000,), (O, O)), ((50, 37), (O, O, R, R)),
                                   ((37, 21, 19), (P, P, R, R, O, O)),
-                                  ((70, 9, 70), (R, O, P, P, O, R))])
+                                  ((70, 9, 70), (R, O, P, P, O, R)), ((513, 40), (P, P, O, R))])
 def test_step_parity_fp32(n, bc):
     log("weno fp32", n, bc)
     U0 = random_state(n, 4).astype(np.float32).astype(np.float64)
