@@ -80,6 +80,8 @@ CASES = [
     # the shortest x rows (4 and 5 faces): a block of 256 x faces spans up to
     # 64 rows of LDS slots in weno_xface, starting mid-row for nx = 4
     ((3, 40, 35), (R, R, O, O, P, P)), ((4, 7, 33), (P, P, R, O, O, R)),
+    # the fewest cells along the walked axis (one chunk shorter than the window)
+    ((6, 5, 3), (O, R, P, P, R, R)), ((7, 3), (R, O, P, P)),
 ]
 
 
